@@ -1,0 +1,225 @@
+"""ctypes wrapper of the FP64 CPU oracle (liblbfs_oracle.so).
+
+TEST INFRASTRUCTURE: imported only by the tests, the smoke check and the CPU-baseline
+leg of the benchmark. The HIP product never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liblbfs_oracle.so")
+
+HE, P, MX, MY, CC, PHI, S, T, FL, FMGX, FMGY, MUC = range(12)
+FIELDS = dict(He=HE, p=P, Mx=MX, My=MY, C=CC, phi=PHI, S=S, T=T, Fl=FL,
+              Fmgx=FMGX, Fmgy=FMGY, muc=MUC)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int),
+        ("dx", C.c_double), ("dt", C.c_double), ("dt_stream", C.c_double),
+        ("rho", C.c_double * 3), ("mu", C.c_double * 3), ("cp", C.c_double * 3),
+        ("lam", C.c_double * 3), ("chi", C.c_double * 3),
+        ("latent", C.c_double), ("t_melt", C.c_double), ("t_init", C.c_double),
+        ("mu0", C.c_double), ("h0", C.c_double), ("angle_deg", C.c_double),
+        ("grav", C.c_double * 2),
+        ("sigma", C.c_double), ("xi", C.c_double), ("mobility", C.c_double), ("tau_g", C.c_double),
+        ("drop_cx", C.c_double), ("drop_cy", C.c_double), ("drop_r", C.c_double),
+        ("init_kind", C.c_int), ("c_init", C.c_double),
+        ("periodic", C.c_int * 2),
+        ("tbc", C.c_int * 4), ("tval", C.c_double * 4), ("mbc", C.c_int * 4),
+        ("sweeps", C.c_int), ("omega", C.c_double),
+        ("init_omega", C.c_double), ("init_tol", C.c_double),
+        ("init_max", C.c_int), ("init_check", C.c_int),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "t", "step", "liquid_fraction", "solid_ratio", "volume", "volume0",
+        "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat")]
+
+
+def build(force: bool = False) -> str:
+    src = os.path.join(HERE, "lbfs_oracle.c")
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+                               "-o", LIB, src, "-lm"])
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_new.restype = C.c_void_p
+        L.orc_new.argtypes = [C.POINTER(Params)]
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_init.argtypes = [C.c_void_p]
+        L.orc_init.restype = C.c_int
+        L.orc_step.argtypes = [C.c_void_p, C.c_int]
+        L.orc_rhs.argtypes = [C.c_void_p, dp]
+        L.orc_face_fluxes.argtypes = [C.c_void_p, dp, dp]
+        L.orc_get.argtypes = [C.c_void_p, C.c_int, dp]
+        L.orc_set.argtypes = [C.c_void_p, C.c_int, dp]
+        L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Obs)]
+        L.orc_mag_sweeps.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_mag_sweeps.restype = C.c_double
+        L.orc_mag_residual.argtypes = [C.c_void_p]
+        L.orc_mag_residual.restype = C.c_double
+        L.orc_lattice.argtypes = [dp, dp, dp]
+        L.orc_enthalpy_state.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp, dp]
+        L.orc_equilibria.argtypes = [C.POINTER(Params)] + [C.c_double] * 9 + [dp, dp, dp]
+        L.orc_params_from_dimless.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+_TBC = {"adiabatic": 0, "fixed": 1}
+_MBC = {"insulating": 0, "fixed": 1}
+
+
+def make_params(prob: dict) -> Params:
+    """Oracle parameter block from a workload description (Eq. 50 conversions here)."""
+    p = Params()
+    p.nx, p.ny = int(prob["nx"]), int(prob["ny"])
+    p.dx = float(prob["dx"])
+    p.dt = float(prob["dt"])
+    p.dt_stream = float(prob.get("dt_stream", 0.5 * p.dx)) or 0.5 * p.dx
+    for name in ("rho", "mu", "cp", "lam", "chi"):
+        arr = getattr(p, name)
+        for k in range(3):
+            arr[k] = float(prob[name][k])
+    p.t_melt = float(prob.get("t_melt", 0.0))
+    p.t_init = float(prob.get("t_init", 0.0))
+    p.mu0 = float(prob.get("mu0", 1.0))
+    p.angle_deg = float(prob.get("angle_deg", 0.0))
+    p.grav[0], p.grav[1] = [float(g) for g in prob.get("grav", [0.0, 0.0])]
+    p.sigma, p.xi = float(prob["sigma"]), float(prob["xi"])
+    p.mobility, p.tau_g = float(prob["mobility"]), float(prob["tau_g"])
+    p.drop_cx, p.drop_cy, p.drop_r = [float(v) for v in prob["drop"]]
+    p.init_kind = 0 if prob.get("init_kind", "droplet") == "droplet" else 1
+    p.c_init = float(prob.get("c_init", 1.0))
+    p.periodic[0], p.periodic[1] = [int(v) for v in prob.get("periodic", [0, 0])]
+    for k in range(4):
+        p.tbc[k] = _TBC[prob["thermal_bc"][k]]
+        p.tval[k] = float(prob["thermal_val"][k])
+        p.mbc[k] = _MBC[prob["mag_bc"][k]]
+    p.sweeps = int(prob.get("sweeps", 4))
+    p.omega = float(prob.get("omega", 1.0))
+    p.init_omega = float(prob.get("init_omega", 0.0))
+    p.init_tol = float(prob.get("init_tol", 1e-12))
+    p.init_max = int(prob.get("init_max", 200000))
+    p.init_check = int(prob.get("init_check", 50))
+    if "latent" in prob and "h0" in prob:
+        p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
+    else:
+        # Eq. 50: Ste = Cp_l (Tm - Tw) / L and Bo_m = mu0 H0^2 D / sigma, D = 2 R
+        lib().orc_params_from_dimless(C.byref(p), float(prob["ste"]), float(prob["t_wall"]),
+                                      float(prob["bo_m"]))
+        if "latent" in prob:
+            p.latent = float(prob["latent"])
+        if "h0" in prob:
+            p.h0 = float(prob["h0"])
+    return p
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Oracle:
+    """One FP64 CPU solve of a workload description."""
+
+    def __init__(self, prob: dict, init: bool = True):
+        self.prob = prob
+        self.params = make_params(prob)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        self._h = lib().orc_new(C.byref(self.params))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+        self.init_sweeps = lib().orc_init(self._h) if init else 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_free(h)
+            self._h = None
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    def step(self, n: int = 1) -> None:
+        lib().orc_step(self._h, int(n))
+
+    def rhs(self) -> np.ndarray:
+        out = np.zeros(5 * self.n)
+        lib().orc_rhs(self._h, _dp(out))
+        return out.reshape(5, self.ny, self.nx)
+
+    def face_fluxes(self):
+        fx = np.zeros(5 * (self.nx + 1) * self.ny)
+        fy = np.zeros(5 * self.nx * (self.ny + 1))
+        lib().orc_face_fluxes(self._h, _dp(fx), _dp(fy))
+        return fx.reshape(5, self.ny, self.nx + 1), fy.reshape(5, self.ny + 1, self.nx)
+
+    def get(self, name: str) -> np.ndarray:
+        out = np.zeros(self.n)
+        lib().orc_get(self._h, FIELDS[name], _dp(out))
+        return out.reshape(self.ny, self.nx)
+
+    def set(self, name: str, arr) -> None:
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtype=np.float64), (self.ny, self.nx)))
+        lib().orc_set(self._h, FIELDS[name], _dp(a))
+
+    def set_state(self, state: dict) -> None:
+        for k, v in state.items():
+            self.set(k, v)
+
+    def set_time(self, t: float, step: float) -> None:
+        lib().orc_set_time(self._h, float(t), float(step))
+
+    def observe(self) -> dict:
+        o = Obs()
+        lib().orc_observe(self._h, C.byref(o))
+        return {n: getattr(o, n) for n, _ in Obs._fields_}
+
+    def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
+        return lib().orc_mag_sweeps(self._h, int(n), float(omega))
+
+    def mag_residual(self) -> float:
+        return lib().orc_mag_residual(self._h)
+
+
+def lattice():
+    ex, ey, w = np.zeros(9), np.zeros(9), np.zeros(9)
+    lib().orc_lattice(_dp(ex), _dp(ey), _dp(w))
+    return ex, ey, w
+
+
+def enthalpy_state(prob: dict, He: float, Cval: float):
+    p = make_params(prob)
+    T, Fl = C.c_double(), C.c_double()
+    lib().orc_enthalpy_state(C.byref(p), float(He), float(Cval), C.byref(T), C.byref(Fl))
+    return T.value, Fl.value
+
+
+def equilibria(prob: dict, pr, rho, u, v, Cval, muc, He, T, cp):
+    p = make_params(prob)
+    f, g, h = np.zeros(9), np.zeros(9), np.zeros(9)
+    lib().orc_equilibria(C.byref(p), pr, rho, u, v, Cval, muc, He, T, cp, _dp(f), _dp(g), _dp(h))
+    return f, g, h
+
