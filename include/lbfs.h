@@ -1,0 +1,182 @@
+/*
+ * lbfs.h -- C ABI of the MI355X (gfx950) enthalpy lattice Boltzmann flux solver (LBFS)
+ * for a ferrofluid droplet freezing on a cold wall in a uniform magnetic field
+ * (Zhou, Yang, Wang, Wu, Niu, arXiv 2511.10257).
+ *
+ * One time step (Table 1 of the paper, "computational procedure"):
+ *   1. magnetic potential: the compact system that the magnetic LBFS of Sec. 3.1
+ *      (Eqs. 12-18) reaches at delta_t = dx/2, i.e. Eq. 4 with face permeabilities,
+ *      relaxed by `sweeps` red-black Gauss-Seidel/SOR sweeps (warm started);
+ *   2. Kelvin force F_mg = (mu0 chi / 2) grad |H|^2 (Eq. 6), held over the stages;
+ *   3. three stages of strong-stability-preserving third-order Runge-Kutta (Eq. 46)
+ *      on W = (He, p, rho cs^2 u, rho cs^2 v, C) (Eq. 39), each stage computing the
+ *      LBFS face fluxes (Eq. 44 reconstruction, Eq. 45 compatibility, star
+ *      distributions Eqs. 16/22/32/33, moments Eq. 43) and the sources (Eq. 41);
+ *   4. Eq. 8 (liquid fraction and temperature) after the step (Table 1 (d)), the
+ *      lagged dFs/dt of Eqs. 9-10 and FP64 reductions of the observables.
+ * Lattice units: c = 1, cs^2 = 1/3, streaming step delta_t = dx/2.
+ *
+ * Conventions
+ *  - Every function returns an int status (LBFS_OK or a negative LBFS_E_*), except
+ *    lbfs_state_bytes (0 on invalid parameters), lbfs_strerror and lbfs_destroy.
+ *  - The caller owns the parameter block, every host buffer and the device buffer
+ *    passed to lbfs_init (it must stay allocated until lbfs_destroy). The library owns
+ *    the handle. The HIP stream is borrowed; all device work is enqueued on it.
+ *  - Fields are nx*ny arrays, row-major (index j*nx + i), cell (i,j) centred at
+ *    ((i+1/2)dx, (j+1/2)dx). Host arrays exchanged through the ABI are FP64.
+ *  - A handle is not thread safe: use one handle per host thread.
+ *  - Precision is fixed at init; observables are always FP64.
+ */
+#ifndef LBFS_H
+#define LBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBFS_ABI_VERSION 1u
+
+enum {
+    LBFS_OK = 0,
+    LBFS_E_INVAL = -1,     /* invalid argument or parameter block           */
+    LBFS_E_NOMEM = -2,     /* buffer too small / batch budget exhausted     */
+    LBFS_E_NONFINITE = -3, /* the last reduction saw a non-finite value     */
+    LBFS_E_DEVICE = -4,    /* a HIP call failed                             */
+    LBFS_E_STATE = -5,     /* call out of order (e.g. step before init)     */
+    LBFS_E_ABI = -6        /* abi_version mismatch                          */
+};
+
+typedef enum { LBFS_FP32 = 0, LBFS_FP64 = 1 } lbfs_precision;
+
+/* walls: 0 = west (x = 0), 1 = east (x = nx dx), 2 = south (y = 0), 3 = north */
+enum { LBFS_TBC_ADIABATIC = 0, LBFS_TBC_FIXED = 1 };     /* thermal wall condition  */
+enum { LBFS_MBC_INSULATING = 0, LBFS_MBC_FIXED = 1 };    /* magnetic wall condition:
+                                                            fixed = potential of the
+                                                            applied uniform field  */
+enum { LBFS_INIT_DROPLET = 0, LBFS_INIT_UNIFORM = 1 };
+
+/* Problem statement (plain data, copied at init). Phase-indexed arrays are
+   [solid, liquid, gas]; Eq. 11 mixes them with the solid fraction Fs and the
+   clamped order parameter. */
+typedef struct lbfs_params {
+    uint32_t abi_version;     /* = LBFS_ABI_VERSION                                 */
+    int32_t nx, ny;           /* cells, each >= 4                                   */
+    int32_t precision;        /* lbfs_precision                                     */
+    double dx;                /* cell size                                          */
+    double dt;                /* Runge-Kutta time step                              */
+    double dt_stream;         /* streaming step delta_t; 0 or dx/2 (only dx/2 is supported) */
+    double rho[3], mu[3], cp[3], lambda[3], chi[3];
+    double latent;            /* latent heat L (Eq. 7)                              */
+    double t_melt;            /* Ts = Tl = Tm (Eq. 8)                               */
+    double t_init;            /* initial temperature                                */
+    double mu0;               /* vacuum permeability (Eq. 2)                        */
+    double h0;                /* applied field strength                             */
+    double field_angle_deg;   /* direction of the applied field, from +x            */
+    double gravity[2];        /* F_g = rho g (Eq. 9)                                */
+    double sigma, xi;         /* interfacial tension, interface thickness (Sec. 2)  */
+    double mobility;          /* M_c (Eq. 10)                                       */
+    double tau_g;             /* phase-field relaxation parameter, > 1/2            */
+    double drop_cx, drop_cy, drop_radius;   /* initial droplet (Fig. 8)             */
+    int32_t init_kind;        /* LBFS_INIT_*                                        */
+    double c_init;            /* order parameter of LBFS_INIT_UNIFORM               */
+    int32_t periodic[2];      /* periodic x / y (then the walls of that axis are unused) */
+    int32_t thermal_bc[4];    /* LBFS_TBC_* per wall                                */
+    double thermal_val[4];    /* wall temperatures of fixed walls                   */
+    int32_t mag_bc[4];        /* LBFS_MBC_* per wall                                */
+    int32_t sweeps;           /* red-black sweeps per step                          */
+    double sor_omega;         /* relaxation factor of the per-step sweeps (0, 2)    */
+    double init_omega;        /* SOR factor of the initial solve, <= 0: automatic   */
+    double init_tol;          /* relative residual target of the initial solve      */
+    int32_t init_max;         /* sweep cap of the initial solve                     */
+    int32_t init_check;       /* sweeps between residual checks of the initial solve */
+} lbfs_params;
+
+typedef struct lbfs_observables {
+    double t;                 /* simulated time                                     */
+    double liquid_fraction;   /* sum(Ct Fl) / sum(Ct), Ct = clamp(C, 0, 1)          */
+    double solid_ratio;       /* Q_L of Eq. 51: sum(Fs dA) / A0                     */
+    double volume;            /* sum(Ct dA)                                         */
+    double volume0;           /* A0: volume at initialisation                       */
+    double mag_residual;      /* ||r||_2 of the magnetic system after the sweeps    */
+    double umax;              /* max |u| over all cells                             */
+    double umax_drop;         /* max |u| over cells with Ct >= 1/2                  */
+    double height;            /* sum(Ct dx) along the column containing drop_cx     */
+    double wall_heat;         /* sum over the south wall of -lambda dT/dy dx (fixed wall) */
+    int64_t step;
+    int32_t nonfinite;        /* 1 if a conserved value was not finite              */
+} lbfs_observables;
+
+/* field ids for lbfs_read_field / lbfs_write_field */
+enum {
+    LBFS_FIELD_HE = 0, LBFS_FIELD_P = 1, LBFS_FIELD_MX = 2, LBFS_FIELD_MY = 3,
+    LBFS_FIELD_C = 4,         /* conserved: He, p, rho cs^2 u, rho cs^2 v, C        */
+    LBFS_FIELD_PHI = 5,       /* magnetic potential phi_m (full, Eq. 3)             */
+    LBFS_FIELD_S = 6,         /* lagged dFs/dt                                      */
+    LBFS_FIELD_T = 7,         /* temperature, Eq. 8 (read only)                     */
+    LBFS_FIELD_FL = 8         /* liquid fraction, Eq. 8 (read only)                 */
+};
+
+typedef struct lbfs_solver lbfs_solver;
+typedef struct lbfs_batch lbfs_batch;
+
+/* Fill p with the defaults of the synthetic freezing-droplet workload for an nx x ny
+   box (property ratios of the paper's Sec. 5 table, lattice values stable for the
+   explicit scheme). */
+int lbfs_params_default(lbfs_params* p, int32_t nx, int32_t ny, int32_t precision);
+
+/* Eq. 50: set latent = Cp_l (Tm - t_wall) / ste and h0 = sqrt(bo_m sigma / (mu0 D)),
+   D = 2 drop_radius; also sets the south wall to the fixed temperature t_wall and the
+   field direction. */
+int lbfs_params_from_dimless(lbfs_params* p, double ste, double t_wall, double bo_m,
+                             double angle_deg);
+
+/* Bytes of device memory one solver needs for these parameters; 0 if invalid. */
+size_t lbfs_state_bytes(const lbfs_params* p);
+
+/* Validate p, carve the state out of dev_buf (>= lbfs_state_bytes(p) bytes, caller
+   owned), initialise the fields (droplet or uniform) and converge the magnetic
+   potential. stream is a hipStream_t (NULL = default stream). Synchronous. */
+int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
+              lbfs_solver** out);
+
+/* Enqueue nsteps time steps on the stream (asynchronous). */
+int lbfs_step(lbfs_solver* s, int32_t nsteps);
+
+/* Synchronise the stream and return the observables of the last step. Returns
+   LBFS_E_NONFINITE (with o filled) when the step produced a non-finite value. */
+int lbfs_observe(lbfs_solver* s, lbfs_observables* o);
+
+/* One evaluation of R(W) (Eq. 46) for the current state, with the Kelvin force of the
+   current potential and the stored lagged dFs/dt; host_R is 5*nx*ny FP64,
+   field-major (He, p, Mx, My, C). Synchronous. */
+int lbfs_rhs(lbfs_solver* s, double* host_R);
+
+/* Run nsweeps red-black sweeps of the magnetic system with factor omega on the
+   current state; *residual receives ||r||_2 afterwards. Synchronous. */
+int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* residual);
+
+/* Copy a field to / from a host FP64 array of n = nx*ny values. Synchronous. */
+int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n);
+int lbfs_write_field(lbfs_solver* s, int32_t field, const double* host, size_t n);
+
+/* Set the clock (time and step count) of the solver. */
+int lbfs_set_time(lbfs_solver* s, double t, int64_t step);
+
+/* Checkpoint: raw state in the native precision plus clock; resume is bitwise. */
+size_t lbfs_checkpoint_bytes(const lbfs_solver* s);
+int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes);
+int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
+
+/* Release the handle (the device buffer stays the caller's). NULL is allowed. */
+void lbfs_destroy(lbfs_solver* s);
+
+/* Static description of a status code. */
+const char* lbfs_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,81 @@
+// lbfs_internal.hpp -- structures shared by the host ABI and the gfx950 kernels.
+//
+// Every kernel works on a list of tiles; a tile names the instance it belongs to and
+// its origin. One solver is a list of one instance; a batch is the same kernels over
+// the tiles of many instances, so a batched instance computes exactly what it
+// computes alone.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfs {
+
+// stage tile shapes (cells); one thread per cell
+constexpr int STAGE_TX_F32 = 16, STAGE_TY_F32 = 16;
+constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8;
+// magnetic tile shape (cells); one thread per cell
+constexpr int MAG_TX = 64, MAG_TY = 4;
+
+// per-tile partial sums written by the last Runge-Kutta stage (FP64)
+enum { PART_CT = 0, PART_CTFL, PART_FS, PART_UMAX, PART_NONFINITE, PART_UDROP, PART_HEIGHT,
+       PART_HEAT, NPART };
+// per-instance results written by the reduction (FP64)
+enum { RES_CT = 0, RES_CTFL, RES_FS, RES_UMAX, RES_NONFINITE, RES_UDROP, RES_HEIGHT, RES_HEAT,
+       RES_MAGR2, NRES };
+
+struct Tile {
+    int32_t inst;    // instance index
+    int32_t x0, y0;  // origin (cells)
+    int32_t idx;     // tile index inside its instance (partials slot)
+};
+
+// Per-instance descriptor, resident in device memory. Field pointers are typed by
+// the instance precision (float or double); parameters are kept in FP64 and
+// converted once per workgroup.
+struct DevInst {
+    void* W[5];      // state at the start of the step: He, p, Mx, My, C
+    void* W1[5];     // stage-1 output (also the R(W) output of the rhs call)
+    void* W2[5];     // stage-2 output
+    void* phi;       // potential minus the applied-field potential
+    void* S;         // lagged dFs/dt
+    void* mu;        // magnetic permeability (scratch of the sweeps)
+    double* part;    // [ntile_stage][NPART]
+    double* mpart;   // [ntile_mag]
+    double* result;  // [NRES]
+    int32_t nx, ny, pitch;
+    int32_t per_x, per_y;
+    int32_t tbc[4], mbc[4];
+    int32_t ntile_stage, ntile_mag;
+    int32_t col_height;  // column of the height observable
+    int32_t heat_on;     // south wall is a fixed-temperature wall
+    double tval[4];
+    double rho[3], mu_[3], lam[3], cp[3], chi[3];
+    double latent, tm, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;
+    double grav[2];
+    double vc;       // 1 - rho_s / rho_l
+};
+
+// launchers (lbfs_kernels.hip); all enqueue on `stream`, return hipError_t
+template <typename T>
+hipError_t launch_stage(int stage, const DevInst* insts, const Tile* tiles, int ntiles,
+                        hipStream_t stream);
+template <typename T>
+hipError_t launch_mag_mu(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
+template <typename T>
+hipError_t launch_mag_pass(int color, double omega, const DevInst* insts, const Tile* tiles, int ntiles,
+                           hipStream_t stream);
+template <typename T>
+hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
+template <typename T>
+hipError_t launch_mag_residual(const DevInst* insts, const Tile* tiles, int ntiles,
+                               hipStream_t stream);
+hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream);
+template <typename T>
+hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,
+                              double c_init, double t_init, double cx, double cy, double r,
+                              hipStream_t stream);
+template <typename T>
+hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
+
+}  // namespace lbfs

@@ -1,0 +1,850 @@
+// lbfs_kernels.hip -- gfx950 kernels of the enthalpy LBFS time step.
+//
+// Kernels (all driven by tile lists, see lbfs_internal.hpp):
+//   k_stage<T,TX,TY,STAGE>  fused Runge-Kutta stage: LDS-staged halo of the cell
+//                           fields, Eq. 8 / Eq. 11 derived fields, chemical potential,
+//                           central gradients, Kelvin force, LBFS fluxes of every face
+//                           of the tile, sources (Eq. 41), residual (Eq. 42) and the
+//                           SSP-RK3 combination (Eq. 46); the last stage also applies
+//                           Eq. 8 for the lagged dFs/dt and writes FP64 partial sums.
+//   k_mag_mu / k_mag_pass / k_mag_residual
+//                           permeability (Eq. 2 with Eq. 11), one colour of a
+//                           red-black sweep of the compact magnetic system, residual.
+//   k_reduce                fixed-order FP64 reduction of the partials per instance.
+//   k_init_fields, k_derived
+//
+// The path is a stencil: a few hundred flops per face over ~70 bytes per cell and
+// stage, no dense contraction, so no MFMA. Fields are SoA with a padded row pitch;
+// the stage kernel reads each tile plus a 3-cell halo once into LDS.
+#include "lbfs_internal.hpp"
+
+namespace lbfs {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T c) { return c < T(0) ? T(0) : (c > T(1) ? T(1) : c); }
+
+// Eq. 11: property of the solid / liquid / gas mixture
+template <typename T>
+__device__ __forceinline__ T mix3(const double* g, T fs, T ct)
+{
+    return fs * T(g[0]) + (T(1) - fs) * ct * T(g[1]) + (T(1) - fs) * (T(1) - ct) * T(g[2]);
+}
+
+// Eq. 8 with Ts = Tl = Tm, local latent heat Ct L and branch heat capacities of the
+// solid-gas and liquid-gas mixtures
+template <typename T>
+__device__ __forceinline__ void enthalpy_state(const DevInst& I, T He, T C, T& Tt, T& Fl)
+{
+    const T ct = clamp01(C);
+    const T cps = ct * T(I.cp[0]) + (T(1) - ct) * T(I.cp[2]);
+    const T cpl = ct * T(I.cp[1]) + (T(1) - ct) * T(I.cp[2]);
+    const T tm = T(I.tm);
+    const T Hes = cps * tm;
+    const T Hel = cpl * tm + ct * T(I.latent);
+    if (He > Hel) {
+        Fl = T(1);
+        Tt = tm + (He - Hel) / cpl;
+    } else if (He >= Hes && Hel > Hes) {
+        Fl = (He - Hes) / (Hel - Hes);
+        Tt = tm;
+    } else {
+        Fl = T(0);
+        Tt = He / cps;
+    }
+}
+
+template <typename T>
+struct Prim {
+    T p, u, v, rho, C, Tt, He, mu, lam, cp, fs;
+};
+
+template <typename T>
+__device__ __forceinline__ Prim<T> primitives(const DevInst& I, T He, T p, T Mx, T My, T C)
+{
+    Prim<T> q;
+    T Fl;
+    enthalpy_state<T>(I, He, C, q.Tt, Fl);
+    const T ct = clamp01(C);
+    q.fs = ct * (T(1) - Fl);
+    q.rho = mix3<T>(I.rho, q.fs, ct);
+    q.mu = mix3<T>(I.mu_, q.fs, ct);
+    q.lam = mix3<T>(I.lam, q.fs, ct);
+    q.cp = mix3<T>(I.cp, q.fs, ct);
+    const T inv = T(3) / q.rho;   // 1 / (rho cs^2)
+    q.u = Mx * inv;
+    q.v = My * inv;
+    q.p = p;
+    q.C = C;
+    q.He = He;
+    return q;
+}
+
+// Source cell of grid coordinate g along an axis of n cells: itself, the periodic
+// image, or the mirror cell across the wall (then `wall` names it). Coordinates
+// further than the 3-cell halo from the domain (only in tiles of tiny domains) are
+// clamped: their values never reach an output.
+__device__ __forceinline__ int map_axis(int g, int n, int periodic, int wlo, int whi, int& wall)
+{
+    int s = g;
+    wall = -1;
+    if (g < 0) {
+        if (periodic) s = g + n;
+        else { s = -1 - g; wall = wlo; }
+    } else if (g >= n) {
+        if (periodic) s = g - n;
+        else { s = 2 * n - 1 - g; wall = whi; }
+    }
+    return s < 0 ? 0 : (s >= n ? n - 1 : s);
+}
+
+// ------------------------------------------------------------- face flux
+
+// Inputs of one side of a face, in the face frame (n = normal from L to R,
+// t = tangential): values and (d/dn, d/dt) of p, u_n, u_t, rho, C, mu_c, T, He.
+enum { V_P = 0, V_UN, V_UT, V_RHO, V_C, V_MUC, V_T, V_HE, NV };
+
+template <typename T>
+struct Side {
+    T v[NV], gn[NV], gt[NV];
+    T mu, lam, cp;
+};
+
+// LBFS fluxes through one face with delta_t = dx/2 (h = dx/2). The nine points
+// x_f - e_a delta_t of Eq. 44 are the two cell centres (a with e_n = +-1, e_t = 0),
+// points on the cell axes half a cell off the face line (diagonals) and points on
+// the face line (e_n = 0, averaged over both sides). The flux is evaluated as
+// moments: with Gamma_a = e.u + 1.5 (e.u)^2 - 0.5 u^2,
+//   f_eq,a = w (p + rho Gamma), f_eqm,a = w (p + rho_f Gamma)   (Eq. 28, f^{eq-m})
+//   g_eq,a = w 3 (Q mu_c + C e.u)  (a > 0)                      (Eq. 29)
+//   h_eq,a = w (Cp_ref T + 3 Cp_f T Gamma) (+ He - Cp_ref T at a = 0)   (Eq. 20)
+// Eq. 45 gives the face state; the star distributions (Eqs. 16, 22, 32, 33 with the
+// viscous sign) give F = (3/2 - tau) M_eq(face) + (tau - 1/2) M(surrounding), where
+// M_eq(face) are the closed-form moments of the face equilibria (D2Q9 identities).
+// Output: F[0] He, F[1] p, F[2] normal momentum, F[3] tangential momentum, F[4] C.
+template <typename T>
+__device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, const Side<T>& R,
+                                          T F[5])
+{
+    const T h = T(0.5) * T(I.dx);
+    // reconstructions at the nine points, per variable
+    T rc[NV][9];
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        const T m = T(0.5) * ((L.v[k] + h * L.gn[k]) + (R.v[k] - h * R.gn[k]));
+        const T gt = T(0.5) * (L.gt[k] + R.gt[k]);
+        rc[k][0] = m;
+        rc[k][1] = L.v[k];
+        rc[k][2] = m - h * gt;
+        rc[k][3] = R.v[k];
+        rc[k][4] = m + h * gt;
+        rc[k][5] = L.v[k] - h * L.gt[k];
+        rc[k][6] = R.v[k] - h * R.gt[k];
+        rc[k][7] = R.v[k] + h * R.gt[k];
+        rc[k][8] = L.v[k] + h * L.gt[k];
+    }
+    const T rho_f = rc[V_RHO][0];
+    const T mu_f = T(0.5) * (L.mu + R.mu);
+    const T lam_f = T(0.5) * (L.lam + R.lam);
+    const T cp_f = T(0.5) * (L.cp + R.cp);
+    const T cpref = T(I.cpref);
+    const T Q = T(I.qg);
+    const T tau_f = T(0.5) + T(3) * mu_f / (rho_f * T(I.dts));
+    const T tau_h = T(0.5) + T(3) * lam_f / (rho_f * cpref * T(I.dts));
+    const T tau_g = T(I.tau_g);
+
+    // (e_n, e_t) of the nine points in the face frame and their weights
+    constexpr int EN[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int ET[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const T WA[9] = {T(4.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0),
+                     T(1.0 / 36.0), T(1.0 / 36.0), T(1.0 / 36.0), T(1.0 / 36.0)};
+    T S0 = 0, Sn = 0, St = 0, Mnn = 0, Mnt = 0, Cs = 0, Gn = 0, Hs = 0, Hn = 0;
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        const T un = rc[V_UN][a], ut = rc[V_UT][a];
+        const T eu = T(EN[a]) * un + T(ET[a]) * ut;
+        const T gam = eu + T(1.5) * eu * eu - T(0.5) * (un * un + ut * ut);
+        const T A = WA[a] * (rc[V_P][a] + rc[V_RHO][a] * gam);
+        const T B = WA[a] * (rc[V_P][a] + rho_f * gam);
+        const T Hq = WA[a] * (cpref * rc[V_T][a] + T(3) * cp_f * rc[V_T][a] * gam);
+        S0 += A;
+        Hs += Hq;
+        if (EN[a] != 0) {
+            Sn += T(EN[a]) * A;
+            Mnn += B;                      // e_n^2 = 1
+            Hn += T(EN[a]) * Hq;
+        }
+        if (ET[a] != 0) St += T(ET[a]) * A;
+        if (EN[a] != 0 && ET[a] != 0) Mnt += T(EN[a] * ET[a]) * B;
+        if (a > 0) {
+            const T Gq = WA[a] * T(3) * (Q * rc[V_MUC][a] + rc[V_C][a] * eu);
+            Cs += Gq;
+            if (EN[a] != 0) Gn += T(EN[a]) * Gq;
+        }
+    }
+    // Eq. 45: face state
+    const T p_f = S0;
+    const T un_f = T(3) * Sn / rho_f;
+    const T ut_f = T(3) * St / rho_f;
+    const T C_f = rc[V_C][0] - T(3) * Q * T(5.0 / 9.0) * rc[V_MUC][0] + Cs;
+    const T He_f = rc[V_HE][0] - cpref * rc[V_T][0] + Hs;
+    T T_f, Fl_f;
+    enthalpy_state<T>(I, He_f, C_f, T_f, Fl_f);
+    // Eqs. 40 and 43 through the star distributions
+    F[1] = Sn;
+    F[2] = (T(1.5) - tau_f) * (p_f + rho_f * un_f * un_f) * T(1.0 / 3.0) + (tau_f - T(0.5)) * Mnn;
+    F[3] = (T(1.5) - tau_f) * (rho_f * un_f * ut_f) * T(1.0 / 3.0) + (tau_f - T(0.5)) * Mnt;
+    F[4] = (T(1.5) - tau_g) * C_f * un_f + (tau_g - T(0.5)) * Gn;
+    F[0] = (T(1.5) - tau_h) * cp_f * T_f * un_f + (tau_h - T(0.5)) * Hn;
+}
+
+// ------------------------------------------------------------- stage kernel
+
+enum { Q_P = 0, Q_U, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_MU, Q_LAM, Q_CP, Q_PHI, NQ };
+
+template <typename T, int TX, int TY>
+struct StageLds {
+    static constexpr int RX = TX + 6, RY = TY + 6, NR = RX * RY;   // tile + 3
+    static constexpr int GX = TX + 2, GY = TY + 2, NG = GX * GY;   // tile + 1
+    static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    T q[NQ][NR];
+    T muc[NR];          // valid on tile + 2
+    T g[NV][2][NG];     // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He
+    T h2[NG];           // |H|^2
+    T fx[5][NFX];
+    T fy[5][NFY];
+    double red[NPART][TX * TY / 64];
+};
+
+// gather one side of a face from LDS; axis 0: x-face (n = x, t = y), 1: y-face
+template <typename T, typename L>
+__device__ __forceinline__ void gather_side(const L& s, int r, int gidx, int axis, Side<T>& o)
+{
+    const int in = axis == 0 ? 0 : 1, it = 1 - in;
+    o.v[V_P] = s.q[Q_P][r];
+    o.v[V_UN] = axis == 0 ? s.q[Q_U][r] : s.q[Q_V][r];
+    o.v[V_UT] = axis == 0 ? s.q[Q_V][r] : s.q[Q_U][r];
+    o.v[V_RHO] = s.q[Q_RHO][r];
+    o.v[V_C] = s.q[Q_C][r];
+    o.v[V_MUC] = s.muc[r];
+    o.v[V_T] = s.q[Q_T][r];
+    o.v[V_HE] = s.q[Q_HE][r];
+    // gradient slots: 0 p, 1 u, 2 v, 3 rho, 4 C, 5 muc, 6 T, 7 He
+    const int slot[NV] = {0, axis == 0 ? 1 : 2, axis == 0 ? 2 : 1, 3, 4, 5, 6, 7};
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        o.gn[k] = s.g[slot[k]][in][gidx];
+        o.gt[k] = s.g[slot[k]][it][gidx];
+    }
+    o.mu = s.q[Q_MU][r];
+    o.lam = s.q[Q_LAM][r];
+    o.cp = s.q[Q_CP][r];
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ __forceinline__ double wave_max(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// FP64 observables of one cell of the state Wn (He, p, Mx, My, C): clamped order
+// parameter, Ct Fl, Fs, |u|, non-finite flag, |u| inside the drop, height column and
+// heat into a fixed south wall (-lambda dT/dy over the half cell, times dx).
+template <typename T>
+__device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int gx, int gy, double* pr)
+{
+    T T1, Fl1;
+    enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
+    const T ct1 = clamp01(Wn[4]);
+    const T fs1 = ct1 * (T(1) - Fl1);
+    const T rho1 = mix3<T>(I.rho, fs1, ct1);
+    const double u1 = double(Wn[2]) * 3.0 / double(rho1), v1 = double(Wn[3]) * 3.0 / double(rho1);
+    const double um = sqrt(u1 * u1 + v1 * v1);
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 5; k++) finite = finite && isfinite(double(Wn[k]));
+    pr[PART_CT] = double(ct1);
+    pr[PART_CTFL] = double(ct1) * double(Fl1);
+    pr[PART_FS] = double(fs1);
+    pr[PART_UMAX] = um;
+    pr[PART_NONFINITE] = finite ? 0.0 : 1.0;
+    pr[PART_UDROP] = ct1 >= T(0.5) ? um : 0.0;
+    pr[PART_HEIGHT] = gx == I.col_height ? double(ct1) : 0.0;
+    pr[PART_HEAT] = 0.0;
+    if (gy == 0 && I.heat_on) {
+        const double lam1 = double(mix3<T>(I.lam, fs1, ct1));
+        pr[PART_HEAT] = -lam1 * (double(T1) - I.tval[2]) / (0.5 * I.dx) * I.dx;
+    }
+}
+
+__device__ __forceinline__ bool part_is_max(int k)
+{
+    return k == PART_UMAX || k == PART_NONFINITE || k == PART_UDROP;
+}
+
+// fixed-order workgroup reduction of the per-thread partials into out[NPART]
+template <int NT>
+__device__ __forceinline__ void block_partials(const double* pr, double (*red)[NT / 64], int tid, double* out)
+{
+    const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+    for (int k = 0; k < NPART; k++) {
+        const double w = part_is_max(k) ? wave_max(pr[k]) : wave_sum(pr[k]);
+        if (lane == 0) red[k][wave] = w;
+    }
+    __syncthreads();
+    if (tid < NPART) {
+        const int k = tid;
+        double acc = red[k][0];
+        for (int w = 1; w < NT / 64; w++) acc = part_is_max(k) ? fmax(acc, red[k][w]) : acc + red[k][w];
+        out[k] = acc;
+    }
+}
+
+template <typename T, int TX, int TY, int STAGE>
+__global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ insts,
+                                                  const Tile* __restrict__ tiles)
+{
+    using L = StageLds<T, TX, TY>;
+    constexpr int NT = TX * TY;
+    __shared__ L s;
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int tid = threadIdx.x;
+    const int x0 = tile.x0, y0 = tile.y0;
+    const int nx = I.nx, ny = I.ny, pitch = I.pitch;
+    const T dx = T(I.dx);
+    const T inv2dx = T(1) / (T(2) * dx);
+
+    T* const* Wbase = reinterpret_cast<T* const*>(I.W);
+    T* const* Win = STAGE == 2 ? reinterpret_cast<T* const*>(I.W1)
+                  : STAGE == 3 ? reinterpret_cast<T* const*>(I.W2) : Wbase;
+    const T* __restrict__ phi = reinterpret_cast<const T*>(I.phi);
+
+    // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image)
+    for (int r = tid; r < L::NR; r += NT) {
+        const int lx = r % L::RX, ly = r / L::RX;
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        int wx, wy;
+        const int sx = map_axis(gx, nx, I.per_x, 0, 1, wx);
+        const int sy = map_axis(gy, ny, I.per_y, 2, 3, wy);
+        const size_t o = (size_t)sy * pitch + sx;
+        Prim<T> q = primitives<T>(I, Win[0][o], Win[1][o], Win[2][o], Win[3][o], Win[4][o]);
+        T ph = phi[o];
+        if (wx >= 0) {
+            q.u = -q.u;
+            q.v = -q.v;
+            if (I.tbc[wx]) q.Tt = T(2) * T(I.tval[wx]) - q.Tt;
+            ph = I.mbc[wx] ? -ph : ph - T(I.h0x) * T(sx - gx) * dx;
+        }
+        if (wy >= 0) {
+            q.u = -q.u;
+            q.v = -q.v;
+            if (I.tbc[wy]) q.Tt = T(2) * T(I.tval[wy]) - q.Tt;
+            ph = I.mbc[wy] ? -ph : ph - T(I.h0y) * T(sy - gy) * dx;
+        }
+        s.q[Q_P][r] = q.p;
+        s.q[Q_U][r] = q.u;
+        s.q[Q_V][r] = q.v;
+        s.q[Q_RHO][r] = q.rho;
+        s.q[Q_C][r] = q.C;
+        s.q[Q_T][r] = q.Tt;
+        s.q[Q_HE][r] = q.He;
+        s.q[Q_MU][r] = q.mu;
+        s.q[Q_LAM][r] = q.lam;
+        s.q[Q_CP][r] = q.cp;
+        s.q[Q_PHI][r] = ph;
+    }
+    __syncthreads();
+
+    // ---- B: chemical potential on tile + 2 (mu_c = 2 beta C (C-1)(2C-1) - kappa lap C)
+    {
+        const T beta = T(I.beta), kappa = T(I.kappa), idx2 = T(1) / (dx * dx);
+        for (int r = tid; r < L::NR; r += NT) {
+            const int lx = r % L::RX, ly = r / L::RX;
+            if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
+            const T* C = s.q[Q_C];
+            const T c = C[r];
+            const T lap = (C[r + 1] + C[r - 1] + C[r + L::RX] + C[r - L::RX] - T(4) * c) * idx2;
+            s.muc[r] = T(2) * beta * c * (c - T(1)) * (T(2) * c - T(1)) - kappa * lap;
+        }
+    }
+    __syncthreads();
+
+    // ---- C: central gradients and |H|^2 on tile + 1
+    const T h0x = T(I.h0x), h0y = T(I.h0y);
+    for (int gi = tid; gi < L::NG; gi += NT) {
+        const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
+        const int r = ly * L::RX + lx;
+        const T* src[NV] = {s.q[Q_P], s.q[Q_U], s.q[Q_V], s.q[Q_RHO], s.q[Q_C], s.muc, s.q[Q_T], s.q[Q_HE]};
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            s.g[k][0][gi] = (src[k][r + 1] - src[k][r - 1]) * inv2dx;
+            s.g[k][1][gi] = (src[k][r + L::RX] - src[k][r - L::RX]) * inv2dx;
+        }
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
+        const bool wally = !I.per_y && (gy < 0 || gy >= ny);
+        if (!wallx && !wally) {
+            const T* P = s.q[Q_PHI];
+            const T Hx = h0x - (P[r + 1] - P[r - 1]) * inv2dx;
+            const T Hy = h0y - (P[r + L::RX] - P[r - L::RX]) * inv2dx;
+            s.h2[gi] = Hx * Hx + Hy * Hy;
+        }
+    }
+    __syncthreads();
+    // |H|^2 of wall ghosts mirrors the interior cell
+    for (int gi = tid; gi < L::NG; gi += NT) {
+        const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
+        const bool wally = !I.per_y && (gy < 0 || gy >= ny);
+        if (!wallx && !wally) continue;
+        int mx = gx, my = gy;
+        if (wallx) mx = gx < 0 ? -1 - gx : 2 * nx - 1 - gx;
+        if (wally) my = gy < 0 ? -1 - gy : 2 * ny - 1 - gy;
+        int mlx = mx - (x0 - 3) - 2, mly = my - (y0 - 3) - 2;
+        mlx = mlx < 0 ? 0 : (mlx >= L::GX ? L::GX - 1 : mlx);
+        mly = mly < 0 ? 0 : (mly >= L::GY ? L::GY - 1 : mly);
+        const int mg = mly * L::GX + mlx;
+        const bool mwx = !I.per_x && (mx < 0 || mx >= nx);
+        const bool mwy = !I.per_y && (my < 0 || my >= ny);
+        s.h2[gi] = (mwx || mwy) ? T(0) : s.h2[mg];
+    }
+
+    // ---- D: LBFS fluxes of all faces of the tile
+    for (int f = tid; f < L::NFX + L::NFY; f += NT) {
+        const bool xf = f < L::NFX;
+        const int fi = xf ? f : f - L::NFX;
+        int cx, cy, lxL, lyL, lxR, lyR;   // tile coords of L and R cells
+        if (xf) {
+            cx = fi % (TX + 1); cy = fi / (TX + 1);
+            lxL = cx - 1; lyL = cy; lxR = cx; lyR = cy;
+        } else {
+            cx = fi % TX; cy = fi / TX;
+            lxL = cx; lyL = cy - 1; lxR = cx; lyR = cy;
+        }
+        const int rL = (lyL + 3) * L::RX + (lxL + 3), rR = (lyR + 3) * L::RX + (lxR + 3);
+        const int gL = (lyL + 1) * L::GX + (lxL + 1), gR = (lyR + 1) * L::GX + (lxR + 1);
+        Side<T> SL, SR;
+        gather_side<T>(s, rL, gL, xf ? 0 : 1, SL);
+        gather_side<T>(s, rR, gR, xf ? 0 : 1, SR);
+        T F[5];
+        face_flux<T>(I, SL, SR, F);
+        // walls: no mass or order-parameter flux; heat through the half cell
+        const int gface = xf ? x0 + cx : y0 + cy;
+        const int nax = xf ? nx : ny;
+        const bool per = xf ? I.per_x : I.per_y;
+        if (!per && (gface == 0 || gface == nax)) {
+            const bool lo = gface == 0;
+            const int wall = xf ? (lo ? 0 : 1) : (lo ? 2 : 3);
+            const int rc = lo ? rR : rL;
+            F[1] = T(0);
+            F[4] = T(0);
+            if (I.tbc[wall]) {
+                const T k = s.q[Q_LAM][rc] / s.q[Q_RHO][rc];
+                const T Tc = s.q[Q_T][rc], Tw = T(I.tval[wall]);
+                F[0] = lo ? -k * (Tc - Tw) / (T(0.5) * dx) : -k * (Tw - Tc) / (T(0.5) * dx);
+            } else {
+                F[0] = T(0);
+            }
+        }
+        if (xf) {
+            s.fx[0][fi] = F[0]; s.fx[1][fi] = F[1]; s.fx[2][fi] = F[2]; s.fx[3][fi] = F[3]; s.fx[4][fi] = F[4];
+        } else {
+            s.fy[0][fi] = F[0]; s.fy[1][fi] = F[1]; s.fy[2][fi] = F[3]; s.fy[3][fi] = F[2]; s.fy[4][fi] = F[4];
+        }
+    }
+    __syncthreads();
+
+    // ---- E: residual, sources, Runge-Kutta stage
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool inside = gx < nx && gy < ny;
+    double pr[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (inside) {
+        const size_t o = (size_t)gy * pitch + gx;
+        const int r = (ly + 3) * L::RX + (lx + 3);
+        const int gi = (ly + 1) * L::GX + (lx + 1);
+        const T dt = T(I.dt);
+        const T cs2 = T(1.0 / 3.0);
+        // Kelvin force from the step-start state (Eq. 6)
+        T Cn, Hen;
+        if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
+        else { Cn = Wbase[4][o]; Hen = Wbase[0][o]; }
+        T Tn, Fln;
+        enthalpy_state<T>(I, Hen, Cn, Tn, Fln);
+        const T ctn = clamp01(Cn);
+        const T chi = mix3<T>(I.chi, ctn * (T(1) - Fln), ctn);
+        const T kmg = T(0.5) * T(I.mu0) * chi;
+        const T fmx = kmg * (s.h2[gi + 1] - s.h2[gi - 1]) * inv2dx;
+        const T fmy = kmg * (s.h2[gi + L::GX] - s.h2[gi - L::GX]) * inv2dx;
+        // stage-state cell fields
+        const T* U = s.q[Q_U];
+        const T* V = s.q[Q_V];
+        const T* RH = s.q[Q_RHO];
+        const T divu = (U[r + 1] - U[r - 1]) * inv2dx + (V[r + L::RX] - V[r - L::RX]) * inv2dx;
+        const T drx = (RH[r + 1] - RH[r - 1]) * inv2dx, dry = (RH[r + L::RX] - RH[r - L::RX]) * inv2dx;
+        const T dmx = (s.muc[r + 1] - s.muc[r - 1]) * inv2dx;
+        const T dmy = (s.muc[r + L::RX] - s.muc[r - L::RX]) * inv2dx;
+        const T c = s.q[Q_C][r], rho = RH[r], u = U[r], v = V[r];
+        T Tc, Flc;
+        enthalpy_state<T>(I, s.q[Q_HE][r], c, Tc, Flc);
+        const T fs = clamp01(c) * (T(1) - Flc);
+        const T Sv = reinterpret_cast<const T*>(I.S)[o];
+        const T vc = T(I.vc);
+        T src[5];
+        src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
+        src[1] = cs2 * (u * drx + v * dry) + rho * cs2 * vc * Sv;
+        src[2] = cs2 * (-c * dmx + fmx + rho * T(I.grav[0]) - rho * u * fs / dt);
+        src[3] = cs2 * (-c * dmy + fmy + rho * T(I.grav[1]) - rho * v * fs / dt);
+        src[4] = c * vc * Sv;
+        const int fW = ly * (TX + 1) + lx, fS = ly * TX + lx;
+        T Rk[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) {
+            const T div = (s.fx[k][fW + 1] - s.fx[k][fW] + s.fy[k][fS + TX] - s.fy[k][fS]) / dx;
+            Rk[k] = -div + src[k];
+        }
+        if (STAGE == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) reinterpret_cast<T*>(I.W1[k])[o] = Rk[k];
+        } else if (STAGE == 1) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) reinterpret_cast<T*>(I.W1[k])[o] = Win[k][o] + dt * Rk[k];
+        } else if (STAGE == 2) {
+#pragma unroll
+            for (int k = 0; k < 5; k++)
+                reinterpret_cast<T*>(I.W2[k])[o] = T(0.75) * Wbase[k][o] + T(0.25) * (Win[k][o] + dt * Rk[k]);
+        } else {
+            T Wn[5];
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                Wn[k] = Wbase[k][o] * T(1.0 / 3.0) + T(2.0 / 3.0) * (Win[k][o] + dt * Rk[k]);
+                Wbase[k][o] = Wn[k];
+            }
+            // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
+            T T1, Fl1;
+            enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
+            const T ct1 = clamp01(Wn[4]);
+            reinterpret_cast<T*>(I.S)[o] = -ct1 * (Fl1 - Fln) / dt;
+            cell_partials<T>(I, Wn, gx, gy, pr);
+        }
+    }
+    if (STAGE == 3) block_partials<NT>(pr, s.red, tid, I.part + (size_t)tile.idx * NPART);
+}
+
+template <typename T>
+hipError_t launch_stage(int stage, const DevInst* insts, const Tile* tiles, int ntiles,
+                        hipStream_t stream)
+{
+    constexpr bool f32 = sizeof(T) == 4;
+    constexpr int TX = f32 ? STAGE_TX_F32 : STAGE_TX_F64;
+    constexpr int TY = f32 ? STAGE_TY_F32 : STAGE_TY_F64;
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid(ntiles), block(TX * TY);
+    switch (stage) {
+    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, 0>), grid, block, 0, stream, insts, tiles); break;
+    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, 1>), grid, block, 0, stream, insts, tiles); break;
+    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, 2>), grid, block, 0, stream, insts, tiles); break;
+    default: hipLaunchKernelGGL((k_stage<T, TX, TY, 3>), grid, block, 0, stream, insts, tiles); break;
+    }
+    return hipGetLastError();
+}
+
+// Observables of the current state (used at initialisation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_partials(const DevInst* __restrict__ insts,
+                                                        const Tile* __restrict__ tiles, int TX, int TY)
+{
+    __shared__ double red[NPART][4];
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    double pr[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = threadIdx.x; c < TX * TY; c += 256) {
+        const int gx = tile.x0 + c % TX, gy = tile.y0 + c / TX;
+        if (gx >= I.nx || gy >= I.ny) continue;
+        const size_t o = (size_t)gy * I.pitch + gx;
+        T Wn[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) Wn[k] = reinterpret_cast<const T*>(I.W[k])[o];
+        double q[NPART];
+        cell_partials<T>(I, Wn, gx, gy, q);
+#pragma unroll
+        for (int k = 0; k < NPART; k++) pr[k] = part_is_max(k) ? fmax(pr[k], q[k]) : pr[k] + q[k];
+    }
+    block_partials<256>(pr, red, threadIdx.x, I.part + (size_t)tile.idx * NPART);
+}
+
+template <typename T>
+hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
+{
+    constexpr bool f32 = sizeof(T) == 4;
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_state_partials<T>), dim3(ntiles), dim3(256), 0, stream, insts, tiles,
+                       f32 ? STAGE_TX_F32 : STAGE_TX_F64, f32 ? STAGE_TY_F32 : STAGE_TY_F64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- magnetics
+
+template <typename T>
+__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_mu(const DevInst* __restrict__ insts,
+                                                          const Tile* __restrict__ tiles)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    if (gx >= I.nx || gy >= I.ny) return;
+    const size_t o = (size_t)gy * I.pitch + gx;
+    const T He = reinterpret_cast<const T*>(I.W[0])[o], C = reinterpret_cast<const T*>(I.W[4])[o];
+    T Tt, Fl;
+    enthalpy_state<T>(I, He, C, Tt, Fl);
+    const T ct = clamp01(C);
+    reinterpret_cast<T*>(I.mu)[o] = T(I.mu0) * (T(1) + mix3<T>(I.chi, ct * (T(1) - Fl), ct));
+}
+
+// Sum over the four faces of w_f (phi'_nb + phi0_nb - phi0_c) and w_f: face weight
+// mean(mu); 2 mu_c to a fixed-potential wall half a cell away (phi' = 0 there); no
+// term at an insulating wall. phi0 is the applied-field potential -(h0x x + h0y y).
+template <typename T, typename Acc>
+__device__ __forceinline__ void mag_faces(const DevInst& I, int gx, int gy, Acc& num, Acc& den)
+{
+    const T* __restrict__ mu = reinterpret_cast<const T*>(I.mu);
+    const T* __restrict__ ph = reinterpret_cast<const T*>(I.phi);
+    const int pitch = I.pitch;
+    const size_t o = (size_t)gy * pitch + gx;
+    const T muc = mu[o];
+    const T hx = T(I.h0x) * T(I.dx), hy = T(I.h0y) * T(I.dx);
+    num = Acc(0);
+    den = Acc(0);
+    const int DI[4] = {-1, 1, 0, 0}, DJ[4] = {0, 0, -1, 1};
+    const T D0[4] = {hx, -hx, hy, -hy};
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        int ii = gx + DI[d], jj = gy + DJ[d];
+        const bool per = d < 2 ? I.per_x : I.per_y;
+        bool inside = ii >= 0 && ii < I.nx && jj >= 0 && jj < I.ny;
+        if (!inside && per) {
+            ii = (ii + I.nx) % I.nx;
+            jj = (jj + I.ny) % I.ny;
+            inside = true;
+        }
+        if (inside) {
+            const size_t q = (size_t)jj * pitch + ii;
+            const T w = T(0.5) * (muc + mu[q]);
+            num += Acc(w) * (Acc(ph[q]) + Acc(D0[d]));
+            den += Acc(w);
+        } else if (I.mbc[d]) {
+            const T w = T(2) * muc;
+            num += Acc(w) * Acc(T(0.5) * D0[d]);
+            den += Acc(w);
+        }
+    }
+}
+
+template <typename T, int COLOR>
+__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_pass(const DevInst* __restrict__ insts,
+                                                            const Tile* __restrict__ tiles, double omega)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    if (gx >= I.nx || gy >= I.ny || ((gx + gy) & 1) != COLOR) return;
+    T num, den;
+    mag_faces<T, T>(I, gx, gy, num, den);
+    if (den > T(0)) {
+        T* ph = reinterpret_cast<T*>(I.phi);
+        const size_t o = (size_t)gy * I.pitch + gx;
+        const T om = T(omega);
+        ph[o] = (T(1) - om) * ph[o] + om * num / den;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_residual(const DevInst* __restrict__ insts,
+                                                                const Tile* __restrict__ tiles)
+{
+    __shared__ double red[MAG_TX * MAG_TY / 64];
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    double r2 = 0.0;
+    if (gx < I.nx && gy < I.ny) {
+        double num, den;
+        mag_faces<T, double>(I, gx, gy, num, den);
+        const double r = num - den * double(reinterpret_cast<const T*>(I.phi)[(size_t)gy * I.pitch + gx]);
+        r2 = r * r;
+    }
+    r2 = wave_sum(r2);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = r2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int w = 0; w < MAG_TX * MAG_TY / 64; w++) acc += red[w];
+        I.mpart[tile.idx] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_mag_mu(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_mag_mu<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mag_pass(int color, double omega, const DevInst* insts, const Tile* tiles, int ntiles,
+                           hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (color == 0)
+        hipLaunchKernelGGL((k_mag_pass<T, 0>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles, omega);
+    else
+        hipLaunchKernelGGL((k_mag_pass<T, 1>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles, omega);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mag_residual(const DevInst* insts, const Tile* tiles, int ntiles,
+                               hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_mag_residual<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- reduction
+
+__global__ __launch_bounds__(256) void k_reduce(const DevInst* __restrict__ insts)
+{
+    __shared__ double red[NRES][4];
+    const DevInst& I = insts[blockIdx.x];
+    const int tid = threadIdx.x;
+    double acc[NRES] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = tid; t < I.ntile_stage; t += 256) {
+        const double* p = I.part + (size_t)t * NPART;
+        acc[RES_CT] += p[PART_CT];
+        acc[RES_CTFL] += p[PART_CTFL];
+        acc[RES_FS] += p[PART_FS];
+        acc[RES_UMAX] = fmax(acc[RES_UMAX], p[PART_UMAX]);
+        acc[RES_NONFINITE] = fmax(acc[RES_NONFINITE], p[PART_NONFINITE]);
+        acc[RES_UDROP] = fmax(acc[RES_UDROP], p[PART_UDROP]);
+        acc[RES_HEIGHT] += p[PART_HEIGHT];
+        acc[RES_HEAT] += p[PART_HEAT];
+    }
+    for (int t = tid; t < I.ntile_mag; t += 256) acc[RES_MAGR2] += I.mpart[t];
+#pragma unroll
+    for (int k = 0; k < NRES; k++) {
+        const bool isMax = k == RES_UMAX || k == RES_NONFINITE || k == RES_UDROP;
+        const double w = isMax ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (tid % 64 == 0) red[k][tid / 64] = w;
+    }
+    __syncthreads();
+    if (tid < NRES) {
+        const int k = tid;
+        const bool isMax = k == RES_UMAX || k == RES_NONFINITE || k == RES_UDROP;
+        double a = red[k][0];
+        for (int w = 1; w < 4; w++) a = isMax ? fmax(a, red[k][w]) : a + red[k][w];
+        I.result[k] = a;
+    }
+}
+
+hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(ninst), dim3(256), 0, stream, insts);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- init / derived
+
+// Initial fields: order parameter (tanh droplet of width xi, Fig. 8, or uniform), the
+// enthalpy of temperature t_init by the inverse of Eq. 8, fluid at rest, potential of
+// the applied field (phi' = 0), no lagged source.
+template <typename T>
+__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_init_fields(const DevInst* __restrict__ insts,
+                                                               const Tile* __restrict__ tiles,
+                                                               int kind, double c_init, double t_init,
+                                                               double cx, double cy, double rad)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    if (gx >= I.nx || gy >= I.ny) return;
+    const size_t o = (size_t)gy * I.pitch + gx;
+    const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx;
+    double C = c_init;
+    if (kind == 0) {
+        const double r = sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy));
+        C = 0.5 * (1.0 + tanh(2.0 * (rad - r) / I.xi));
+    }
+    const double ct = C < 0.0 ? 0.0 : (C > 1.0 ? 1.0 : C);
+    const double cps = ct * I.cp[0] + (1.0 - ct) * I.cp[2];
+    const double cpl = ct * I.cp[1] + (1.0 - ct) * I.cp[2];
+    const double He = t_init >= I.tm ? cpl * t_init + ct * I.latent : cps * t_init;
+    reinterpret_cast<T*>(I.W[0])[o] = T(He);
+    reinterpret_cast<T*>(I.W[1])[o] = T(0);
+    reinterpret_cast<T*>(I.W[2])[o] = T(0);
+    reinterpret_cast<T*>(I.W[3])[o] = T(0);
+    reinterpret_cast<T*>(I.W[4])[o] = T(C);
+    reinterpret_cast<T*>(I.S)[o] = T(0);
+    reinterpret_cast<T*>(I.phi)[o] = T(0);
+}
+
+// Temperature and liquid fraction (Eq. 8) of the current state into W1[0], W1[1].
+template <typename T>
+__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_derived(const DevInst* __restrict__ insts,
+                                                           const Tile* __restrict__ tiles)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const DevInst& I = insts[tile.inst];
+    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    if (gx >= I.nx || gy >= I.ny) return;
+    const size_t o = (size_t)gy * I.pitch + gx;
+    T Tt, Fl;
+    enthalpy_state<T>(I, reinterpret_cast<const T*>(I.W[0])[o], reinterpret_cast<const T*>(I.W[4])[o], Tt, Fl);
+    reinterpret_cast<T*>(I.W1[0])[o] = Tt;
+    reinterpret_cast<T*>(I.W1[1])[o] = Fl;
+}
+
+template <typename T>
+hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,
+                              double c_init, double t_init, double cx, double cy, double r,
+                              hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_init_fields<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles,
+                       kind, c_init, t_init, cx, cy, r);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_derived<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
+    return hipGetLastError();
+}
+
+#define LBFS_INSTANTIATE(T)                                                                          \
+    template hipError_t launch_stage<T>(int, const DevInst*, const Tile*, int, hipStream_t);        \
+    template hipError_t launch_mag_mu<T>(const DevInst*, const Tile*, int, hipStream_t);            \
+    template hipError_t launch_mag_pass<T>(int, double, const DevInst*, const Tile*, int, hipStream_t); \
+    template hipError_t launch_state_partials<T>(const DevInst*, const Tile*, int, hipStream_t);    \
+    template hipError_t launch_mag_residual<T>(const DevInst*, const Tile*, int, hipStream_t);      \
+    template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
+                                              double, double, double, hipStream_t);                 \
+    template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);
+
+LBFS_INSTANTIATE(float)
+LBFS_INSTANTIATE(double)
+
+}  // namespace lbfs

@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in include/lbfs.h (argument marshalling only).
+
+Every step of the solver runs in the gfx950 kernels of liblbfs.so; PyTorch only
+provides the device buffer and the stream. Importing works without a GPU (the
+host-only calls such as lbfs_state_bytes can be used for validation); creating a
+Solver needs the built library and a ROCm device and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbfs.so")
+
+LBFS_ABI_VERSION = 1
+LBFS_OK, LBFS_E_INVAL, LBFS_E_NOMEM, LBFS_E_NONFINITE, LBFS_E_DEVICE, LBFS_E_STATE, LBFS_E_ABI = (
+    0, -1, -2, -3, -4, -5, -6)
+LBFS_FP32, LBFS_FP64 = 0, 1
+FIELDS = dict(He=0, p=1, Mx=2, My=3, C=4, phi=5, S=6, T=7, Fl=8)
+
+# every symbol include/lbfs.h declares
+EXPORTS = (
+    "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
+    "lbfs_step", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
+    "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
+    "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
+)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
+        ("dx", C.c_double), ("dt", C.c_double), ("dt_stream", C.c_double),
+        ("rho", C.c_double * 3), ("mu", C.c_double * 3), ("cp", C.c_double * 3),
+        ("lambda_", C.c_double * 3), ("chi", C.c_double * 3),
+        ("latent", C.c_double), ("t_melt", C.c_double), ("t_init", C.c_double),
+        ("mu0", C.c_double), ("h0", C.c_double), ("field_angle_deg", C.c_double),
+        ("gravity", C.c_double * 2), ("sigma", C.c_double), ("xi", C.c_double),
+        ("mobility", C.c_double), ("tau_g", C.c_double),
+        ("drop_cx", C.c_double), ("drop_cy", C.c_double), ("drop_radius", C.c_double),
+        ("init_kind", C.c_int32), ("c_init", C.c_double),
+        ("periodic", C.c_int32 * 2), ("thermal_bc", C.c_int32 * 4), ("thermal_val", C.c_double * 4),
+        ("mag_bc", C.c_int32 * 4), ("sweeps", C.c_int32), ("sor_omega", C.c_double),
+        ("init_omega", C.c_double), ("init_tol", C.c_double), ("init_max", C.c_int32),
+        ("init_check", C.c_int32),
+    ]
+
+
+class Observables(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("liquid_fraction", C.c_double), ("solid_ratio", C.c_double),
+        ("volume", C.c_double), ("volume0", C.c_double), ("mag_residual", C.c_double),
+        ("umax", C.c_double), ("umax_drop", C.c_double), ("height", C.c_double),
+        ("wall_heat", C.c_double), ("step", C.c_int64), ("nonfinite", C.c_int32),
+    ]
+
+
+class LbfsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbfs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int32
+        sig = {
+            "lbfs_params_default": (C.c_int, [C.POINTER(Params), i32, i32, i32]),
+            "lbfs_params_from_dimless": (C.c_int, [C.POINTER(Params), C.c_double, C.c_double, C.c_double, C.c_double]),
+            "lbfs_state_bytes": (C.c_size_t, [C.POINTER(Params)]),
+            "lbfs_init": (C.c_int, [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "lbfs_step": (C.c_int, [vp, i32]),
+            "lbfs_observe": (C.c_int, [vp, C.POINTER(Observables)]),
+            "lbfs_rhs": (C.c_int, [vp, dp]),
+            "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
+            "lbfs_read_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
+            "lbfs_write_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
+            "lbfs_set_time": (C.c_int, [vp, C.c_double, C.c_int64]),
+            "lbfs_checkpoint_bytes": (C.c_size_t, [vp]),
+            "lbfs_save_state": (C.c_int, [vp, vp, C.c_size_t]),
+            "lbfs_load_state": (C.c_int, [vp, vp, C.c_size_t]),
+            "lbfs_destroy": (None, [vp]),
+            "lbfs_strerror": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().lbfs_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != LBFS_OK:
+        raise LbfsError(status, what)
+
+
+_TBC = {"adiabatic": 0, "fixed": 1}
+_MBC = {"insulating": 0, "fixed": 1}
+
+
+def make_params(prob: dict) -> Params:
+    """lbfs_params from a workload description (see workloads.py)."""
+    prec = LBFS_FP64 if prob.get("precision", "fp32") == "fp64" else LBFS_FP32
+    p = Params()
+    _check(lib().lbfs_params_default(C.byref(p), int(prob["nx"]), int(prob["ny"]), prec), "params_default")
+    p.dx = float(prob.get("dx", 1.0))
+    p.dt = float(prob.get("dt", 0.5))
+    p.dt_stream = float(prob.get("dt_stream", 0.0))
+    for name, key in (("rho", "rho"), ("mu", "mu"), ("cp", "cp"), ("lambda_", "lam"), ("chi", "chi")):
+        if key in prob:
+            arr = getattr(p, name)
+            for k in range(3):
+                arr[k] = float(prob[key][k])
+    for key in ("t_melt", "t_init", "mu0", "sigma", "xi", "mobility", "tau_g", "c_init",
+                "init_omega", "init_tol"):
+        if key in prob:
+            setattr(p, key, float(prob[key]))
+    if "grav" in prob:
+        p.gravity[0], p.gravity[1] = [float(g) for g in prob["grav"]]
+    if "drop" in prob:
+        p.drop_cx, p.drop_cy, p.drop_radius = [float(v) for v in prob["drop"]]
+    p.init_kind = 0 if prob.get("init_kind", "droplet") == "droplet" else 1
+    if "periodic" in prob:
+        p.periodic[0], p.periodic[1] = [int(v) for v in prob["periodic"]]
+    for k in range(4):
+        if "thermal_bc" in prob:
+            p.thermal_bc[k] = _TBC[prob["thermal_bc"][k]]
+        if "thermal_val" in prob:
+            p.thermal_val[k] = float(prob["thermal_val"][k])
+        if "mag_bc" in prob:
+            p.mag_bc[k] = _MBC[prob["mag_bc"][k]]
+    p.sweeps = int(prob.get("sweeps", 4))
+    p.sor_omega = float(prob.get("omega", 1.0))
+    for key in ("init_max", "init_check"):
+        if key in prob:
+            setattr(p, key, int(prob[key]))
+    angle = float(prob.get("angle_deg", p.field_angle_deg))
+    if "latent" in prob and "h0" in prob:
+        p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
+        p.field_angle_deg = angle
+    else:
+        # Eq. 50 conversions happen in the library; they also set the fixed south wall
+        tbc2, tval2 = p.thermal_bc[2], p.thermal_val[2]
+        _check(lib().lbfs_params_from_dimless(C.byref(p), float(prob["ste"]), float(prob["t_wall"]),
+                                              float(prob["bo_m"]), angle), "params_from_dimless")
+        p.thermal_bc[2], p.thermal_val[2] = tbc2, tval2
+        if "latent" in prob:
+            p.latent = float(prob["latent"])
+        if "h0" in prob:
+            p.h0 = float(prob["h0"])
+    return p
+
+
+def state_bytes(prob_or_params) -> int:
+    p = prob_or_params if isinstance(prob_or_params, Params) else make_params(prob_or_params)
+    return int(lib().lbfs_state_bytes(C.byref(p)))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """One LBFS solve resident on a ROCm device; state lives in a torch uint8 buffer."""
+
+    def __init__(self, prob, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the LBFS solver needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.params = prob if isinstance(prob, Params) else make_params(prob)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = int(lib().lbfs_state_bytes(C.byref(self.params)))
+        if nbytes == 0:
+            raise LbfsError(LBFS_E_INVAL, "lbfs_state_bytes")
+        self.device = torch.device(device)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().lbfs_init(C.byref(self.params), C.c_void_p(self.buffer.data_ptr()), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfs_init")
+        self._h = h
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lbfs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1) -> None:
+        _check(lib().lbfs_step(self._h, int(n)), "lbfs_step")
+
+    def observe(self, allow_nonfinite: bool = False) -> dict:
+        o = Observables()
+        st = lib().lbfs_observe(self._h, C.byref(o))
+        if not (st == LBFS_OK or (allow_nonfinite and st == LBFS_E_NONFINITE)):
+            _check(st, "lbfs_observe")
+        return {n: getattr(o, n) for n, _ in Observables._fields_}
+
+    def rhs(self) -> np.ndarray:
+        out = np.zeros(5 * self.n)
+        _check(lib().lbfs_rhs(self._h, _dp(out)), "lbfs_rhs")
+        return out.reshape(5, self.ny, self.nx)
+
+    def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
+        r = C.c_double()
+        _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
+        return r.value
+
+    def get(self, name: str) -> np.ndarray:
+        out = np.zeros(self.n)
+        _check(lib().lbfs_read_field(self._h, FIELDS[name], _dp(out), self.n), "lbfs_read_field")
+        return out.reshape(self.ny, self.nx)
+
+    def set(self, name: str, arr) -> None:
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtype=np.float64), (self.ny, self.nx)))
+        _check(lib().lbfs_write_field(self._h, FIELDS[name], _dp(a), self.n), "lbfs_write_field")
+
+    def set_state(self, state: dict) -> None:
+        for k, v in state.items():
+            self.set(k, v)
+
+    def set_time(self, t: float, step: int) -> None:
+        _check(lib().lbfs_set_time(self._h, float(t), int(step)), "lbfs_set_time")
+
+    def save(self) -> bytes:
+        nb = int(lib().lbfs_checkpoint_bytes(self._h))
+        buf = C.create_string_buffer(nb)
+        _check(lib().lbfs_save_state(self._h, buf, nb), "lbfs_save_state")
+        return buf.raw
+
+    def load(self, blob: bytes) -> None:
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().lbfs_load_state(self._h, buf, len(blob)), "lbfs_load_state")
+
