@@ -142,8 +142,23 @@ size_t lbfs_state_bytes(const lbfs_params* p);
 int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
               lbfs_solver** out);
 
-/* Enqueue nsteps time steps on the stream (asynchronous). */
+/* Enqueue nsteps time steps on the stream (asynchronous). On a non-default stream
+   the first call captures one step into a HIP graph and every step is one graph
+   launch (set LBFS_NO_GRAPH=1 in the environment to launch the kernels directly). */
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
+
+/* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
+   per 4 sweeps: permeability, sweeps, residual), the three Runge-Kutta stages (the
+   third also applies Eq. 8 and writes per-tile partial sums) and the reduction. */
+enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUCE, LBFS_NKERNELS };
+
+/* lbfs_step with HIP events recorded on the solver's stream around every kernel
+   phase of every sample_every-th step (sample_every >= 1; at most 4096 sampled
+   steps; the other steps run as in lbfs_step). Synchronises at the end and writes,
+   per kind, the mean duration of one phase in ms (kernel_ms[LBFS_NKERNELS]) and the
+   number of timed phases (launches[LBFS_NKERNELS]). */
+int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
+                       int32_t* launches);
 
 /* Synchronise the stream and return the observables of the last step. Returns
    LBFS_E_NONFINITE (with o filled) when the step produced a non-finite value. */

@@ -2,12 +2,13 @@
 //
 // The solver state lives in one caller-owned device buffer, carved into 256-byte
 // aligned segments: the instance descriptor, the tile lists, FP64 partials and
-// results, and 18 SoA fields (W, W1, W2 of 5 fields each, phi', S, mu) with the row
+// results, and 18 SoA fields (W, W1, W2 of 5 fields each, phi' twice, S) with the row
 // pitch padded to 64 elements. No device allocation happens inside the library.
 #include "lbfs.h"
 #include "lbfs_internal.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -17,7 +18,7 @@ using namespace lbfs;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int NFIELDS = 18;   // W[5], W1[5], W2[5], phi, S, mu
+constexpr int NFIELDS = 18;   // W[5], W1[5], W2[5], phi[0], S, phi[1]
 constexpr uint32_t CKPT_MAGIC = 0x5346424cu;   // "LBFS"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -25,11 +26,13 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     int pitch = 0;
     size_t esize = 0, field_bytes = 0;
-    int tiles_stage_x = 0, tiles_stage_y = 0, tiles_mag_x = 0, tiles_mag_y = 0;
-    size_t off_inst = 0, off_tstage = 0, off_tmag = 0, off_part = 0, off_mpart = 0, off_res = 0,
+    int tiles_stage_x = 0, tiles_stage_y = 0, tiles_mag_x = 0, tiles_mag_y = 0, tiles_pt_x = 0, tiles_pt_y = 0;
+    int mag_big = 0, mag_tx = 0, mag_ty = 0;
+    size_t off_inst = 0, off_tstage = 0, off_tmag = 0, off_tpt = 0, off_part = 0, off_mpart = 0, off_res = 0,
            off_fields = 0, total = 0;
     int ntile_stage() const { return tiles_stage_x * tiles_stage_y; }
     int ntile_mag() const { return tiles_mag_x * tiles_mag_y; }
+    int ntile_pt() const { return tiles_pt_x * tiles_pt_y; }
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -72,6 +75,8 @@ int validate(const lbfs_params* p)
     if (!std::isfinite(p->init_omega) || p->init_omega >= 2.0) return LBFS_E_INVAL;
     if (!std::isfinite(p->init_tol) || p->init_tol < 0.0 || p->init_max < 0 || p->init_check < 0)
         return LBFS_E_INVAL;
+    // a red-black colouring of a periodic axis needs an even number of cells
+    if ((p->periodic[0] && (p->nx & 1)) || (p->periodic[1] && (p->ny & 1))) return LBFS_E_INVAL;
     // the applied-field potential is not periodic along an axis the field crosses
     const double th = p->field_angle_deg * M_PI / 180.0;
     const double hx = p->h0 * std::cos(th), hy = p->h0 * std::sin(th);
@@ -98,12 +103,18 @@ Layout make_layout(const lbfs_params* p)
     const int sty = p->precision == LBFS_FP64 ? STAGE_TY_F64 : STAGE_TY_F32;
     L.tiles_stage_x = (p->nx + stx - 1) / stx;
     L.tiles_stage_y = (p->ny + sty - 1) / sty;
-    L.tiles_mag_x = (p->nx + MAG_TX - 1) / MAG_TX;
-    L.tiles_mag_y = (p->ny + MAG_TY - 1) / MAG_TY;
+    L.mag_big = (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0;
+    L.mag_tx = L.mag_big ? MAG_BIG_TX : MAG_SMALL_TX;
+    L.mag_ty = L.mag_big ? MAG_BIG_TY : MAG_SMALL_TY;
+    L.tiles_mag_x = (p->nx + L.mag_tx - 1) / L.mag_tx;
+    L.tiles_mag_y = (p->ny + L.mag_ty - 1) / L.mag_ty;
+    L.tiles_pt_x = (p->nx + PT_TX - 1) / PT_TX;
+    L.tiles_pt_y = (p->ny + PT_TY - 1) / PT_TY;
     size_t off = 0;
     L.off_inst = off; off = align_up(off + sizeof(DevInst), ALIGN);
     L.off_tstage = off; off = align_up(off + sizeof(Tile) * L.ntile_stage(), ALIGN);
     L.off_tmag = off; off = align_up(off + sizeof(Tile) * L.ntile_mag(), ALIGN);
+    L.off_tpt = off; off = align_up(off + sizeof(Tile) * L.ntile_pt(), ALIGN);
     L.off_part = off; off = align_up(off + sizeof(double) * NPART * L.ntile_stage(), ALIGN);
     L.off_mpart = off; off = align_up(off + sizeof(double) * L.ntile_mag(), ALIGN);
     L.off_res = off; off = align_up(off + sizeof(double) * NRES, ALIGN);
@@ -123,6 +134,12 @@ struct lbfs_solver {
     DevInst* dinst = nullptr;
     Tile* dtiles_stage = nullptr;
     Tile* dtiles_mag = nullptr;
+    Tile* dtiles_pt = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};          // one captured step per potential buffer
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    bool use_graph = true;
+    int phase = 0;                       // potential buffer holding the current phi'
+    int phi_field() const { return phase ? 17 : 15; }
     double* hres = nullptr;      // pinned copy of the results
     void* staging = nullptr;     // pinned field staging (nx*ny elements of 8 bytes)
     double t = 0.0;
@@ -140,39 +157,19 @@ struct lbfs_solver {
 
 namespace {
 
-hipError_t launch_mag_sweeps(lbfs_solver* s, int nsweeps, double omega)
-{
-    hipError_t e;
-    const int nm = s->L.ntile_mag();
-    for (int k = 0; k < nsweeps; k++) {
-        for (int c = 0; c < 2; c++) {
-            e = s->f64() ? launch_mag_pass<double>(c, omega, s->dinst, s->dtiles_mag, nm, s->stream)
-                         : launch_mag_pass<float>(c, omega, s->dinst, s->dtiles_mag, nm, s->stream);
-            if (e != hipSuccess) return e;
-        }
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_mu(lbfs_solver* s)
+hipError_t launch_mag_phase(lbfs_solver* s, int nsweeps, double omega, int residual)
 {
     const int nm = s->L.ntile_mag();
-    return s->f64() ? launch_mag_mu<double>(s->dinst, s->dtiles_mag, nm, s->stream)
-                    : launch_mag_mu<float>(s->dinst, s->dtiles_mag, nm, s->stream);
-}
-
-hipError_t launch_resid(lbfs_solver* s)
-{
-    const int nm = s->L.ntile_mag();
-    return s->f64() ? launch_mag_residual<double>(s->dinst, s->dtiles_mag, nm, s->stream)
-                    : launch_mag_residual<float>(s->dinst, s->dtiles_mag, nm, s->stream);
+    return s->f64()
+        ? launch_mag<double>(s->L.mag_big, nsweeps, omega, residual, &s->phase, s->dinst, s->dtiles_mag, nm, s->stream)
+        : launch_mag<float>(s->L.mag_big, nsweeps, omega, residual, &s->phase, s->dinst, s->dtiles_mag, nm, s->stream);
 }
 
 hipError_t launch_stage_k(lbfs_solver* s, int stage)
 {
     const int ns = s->L.ntile_stage();
-    return s->f64() ? launch_stage<double>(stage, s->dinst, s->dtiles_stage, ns, s->stream)
-                    : launch_stage<float>(stage, s->dinst, s->dtiles_stage, ns, s->stream);
+    return s->f64() ? launch_stage<double>(stage, s->phase, s->dinst, s->dtiles_stage, ns, s->stream)
+                    : launch_stage<float>(stage, s->phase, s->dinst, s->dtiles_stage, ns, s->stream);
 }
 
 hipError_t launch_state_part(lbfs_solver* s)
@@ -182,11 +179,19 @@ hipError_t launch_state_part(lbfs_solver* s)
                     : launch_state_partials<float>(s->dinst, s->dtiles_stage, ns, s->stream);
 }
 
+// one time step: magnetic phase, three Runge-Kutta stages, reduction of the observables
+hipError_t enqueue_step(lbfs_solver* s)
+{
+    hipError_t e = launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1);
+    for (int st = 1; st <= 3 && e == hipSuccess; st++) e = launch_stage_k(s, st);
+    if (e == hipSuccess) e = launch_reduce(s->dinst, 1, s->stream);
+    return e;
+}
+
 // residual of the magnetic system of the current state, synchronously
 int mag_residual_now(lbfs_solver* s, double* out)
 {
-    HIPCHK(launch_mu(s));
-    HIPCHK(launch_resid(s));
+    HIPCHK(launch_mag_phase(s, 0, 1.0, 1));
     HIPCHK(launch_reduce(s->dinst, 1, s->stream));
     HIPCHK(hipMemcpyAsync(s->hres, s->hinst.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -209,7 +214,7 @@ int field_index(int field)
     case LBFS_FIELD_MX: return 2;
     case LBFS_FIELD_MY: return 3;
     case LBFS_FIELD_C: return 4;
-    case LBFS_FIELD_PHI: return 15;
+    case LBFS_FIELD_PHI: return -2;   // current potential buffer
     case LBFS_FIELD_S: return 16;
     default: return -1;
     }
@@ -330,6 +335,7 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
     s->dinst = reinterpret_cast<DevInst*>(s->base + L.off_inst);
     s->dtiles_stage = reinterpret_cast<Tile*>(s->base + L.off_tstage);
     s->dtiles_mag = reinterpret_cast<Tile*>(s->base + L.off_tmag);
+    s->dtiles_pt = reinterpret_cast<Tile*>(s->base + L.off_tpt);
     auto fail = [&](int code) {
         lbfs_destroy(s);
         return code;
@@ -346,9 +352,9 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
         I.W1[k] = s->field(5 + k);
         I.W2[k] = s->field(10 + k);
     }
-    I.phi = s->field(15);
+    I.phi[0] = s->field(15);
+    I.phi[1] = s->field(17);
     I.S = s->field(16);
-    I.mu = s->field(17);
     I.part = reinterpret_cast<double*>(s->base + L.off_part);
     I.mpart = reinterpret_cast<double*>(s->base + L.off_mpart);
     I.result = reinterpret_cast<double*>(s->base + L.off_res);
@@ -389,7 +395,7 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
     I.grav[1] = p->gravity[1];
     I.vc = 1.0 - p->rho[0] / p->rho[1];
 
-    std::vector<Tile> ts, tm;
+    std::vector<Tile> ts, tm, tp;
     {
         const int stx = s->f64() ? STAGE_TX_F64 : STAGE_TX_F32, sty = s->f64() ? STAGE_TY_F64 : STAGE_TY_F32;
         for (int ty = 0; ty < L.tiles_stage_y; ty++)
@@ -397,20 +403,24 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
                 ts.push_back(Tile{0, tx * stx, ty * sty, (int)ts.size()});
         for (int ty = 0; ty < L.tiles_mag_y; ty++)
             for (int tx = 0; tx < L.tiles_mag_x; tx++)
-                tm.push_back(Tile{0, tx * MAG_TX, ty * MAG_TY, (int)tm.size()});
+                tm.push_back(Tile{0, tx * L.mag_tx, ty * L.mag_ty, (int)tm.size()});
+        for (int ty = 0; ty < L.tiles_pt_y; ty++)
+            for (int tx = 0; tx < L.tiles_pt_x; tx++)
+                tp.push_back(Tile{0, tx * PT_TX, ty * PT_TY, (int)tp.size()});
     }
     if (hipMemcpyAsync(s->dinst, &I, sizeof I, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->dtiles_stage, ts.data(), sizeof(Tile) * ts.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->dtiles_mag, tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->dtiles_pt, tp.data(), sizeof(Tile) * tp.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_part, 0, L.off_fields - L.off_part, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_fields, 0, L.field_bytes * NFIELDS, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
 
     hipError_t e = s->f64()
-        ? launch_init_fields<double>(s->dinst, s->dtiles_mag, L.ntile_mag(), p->init_kind, p->c_init, p->t_init,
+        ? launch_init_fields<double>(s->dinst, s->dtiles_pt, L.ntile_pt(), p->init_kind, p->c_init, p->t_init,
                                      p->drop_cx, p->drop_cy, p->drop_radius, s->stream)
-        : launch_init_fields<float>(s->dinst, s->dtiles_mag, L.ntile_mag(), p->init_kind, p->c_init, p->t_init,
+        : launch_init_fields<float>(s->dinst, s->dtiles_pt, L.ntile_pt(), p->init_kind, p->c_init, p->t_init,
                                     p->drop_cx, p->drop_cy, p->drop_radius, s->stream);
     if (e != hipSuccess) return fail(LBFS_E_DEVICE);
 
@@ -427,10 +437,12 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
     while (r0 > 0.0 && used < p->init_max && r > p->init_tol * r0) {
         int k = s->p.init_check;
         if (used + k > p->init_max) k = p->init_max - used;
-        if (launch_mag_sweeps(s, k, om) != hipSuccess) return fail(LBFS_E_DEVICE);
+        if (launch_mag_phase(s, k, om, 0) != hipSuccess) return fail(LBFS_E_DEVICE);
         used += k;
+        const double r_prev = r;
         if (mag_residual_now(s, &r) != LBFS_OK) return fail(LBFS_E_DEVICE);
         if (!std::isfinite(r)) return fail(LBFS_E_NONFINITE);
+        if (r > 0.98 * r_prev) break;   // stagnated at the round-off floor of the precision
     }
     // observables of the initial state (also the reference volume A0)
     if (launch_state_part(s) != hipSuccess || launch_reduce(s->dinst, 1, s->stream) != hipSuccess ||
@@ -439,8 +451,58 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
         return fail(LBFS_E_DEVICE);
     s->vol0 = s->hres[RES_CT] * p->dx * p->dx;
     s->hres[RES_MAGR2] = r * r;
+    const char* ng = std::getenv("LBFS_NO_GRAPH");
+    s->use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
     *out = s;
     return LBFS_OK;
+}
+
+// capture one time step starting from potential buffer `ph` into a HIP graph (once
+// per buffer); replays cost one launch per step
+static int ensure_graph(lbfs_solver* s, int ph)
+{
+    if (!s->use_graph || s->graph_exec[ph]) return LBFS_OK;
+    const int saved = s->phase;
+    s->phase = ph;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        s->phase = saved;
+        return LBFS_E_DEVICE;
+    }
+    const hipError_t e = enqueue_step(s);
+    const hipError_t ec = hipStreamEndCapture(s->stream, &g);
+    s->phase = saved;
+    if (e != hipSuccess || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return LBFS_E_DEVICE;
+    }
+    if (hipGraphInstantiate(&s->graph_exec[ph], g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        s->graph_exec[ph] = nullptr;
+        return LBFS_E_DEVICE;
+    }
+    s->graph[ph] = g;
+    return LBFS_OK;
+}
+
+// potential-buffer flips of one step (one per magnetic launch)
+static int step_flips(const lbfs_solver* s)
+{
+    const int launches = s->p.sweeps == 0 ? 1 : (s->p.sweeps + MAG_KMAX - 1) / MAG_KMAX;
+    return launches & 1;
+}
+
+// one step, as a graph replay when graphs are on
+static hipError_t run_step(lbfs_solver* s)
+{
+    if (s->use_graph) {
+        const int ph = s->phase;
+        if (ensure_graph(s, ph) != LBFS_OK) return hipErrorUnknown;
+        const hipError_t e = hipGraphLaunch(s->graph_exec[ph], s->stream);
+        s->phase = ph ^ step_flips(s);
+        return e;
+    }
+    return enqueue_step(s);
 }
 
 int lbfs_step(lbfs_solver* s, int32_t nsteps)
@@ -448,17 +510,82 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps)
     if (!s) return LBFS_E_STATE;
     if (nsteps < 0) return LBFS_E_INVAL;
     for (int n = 0; n < nsteps; n++) {
-        if (launch_mu(s) != hipSuccess) return LBFS_E_DEVICE;
-        if (launch_mag_sweeps(s, s->p.sweeps, s->p.sor_omega) != hipSuccess) return LBFS_E_DEVICE;
-        if (launch_resid(s) != hipSuccess) return LBFS_E_DEVICE;
-        for (int st = 1; st <= 3; st++)
-            if (launch_stage_k(s, st) != hipSuccess) return LBFS_E_DEVICE;
-        if (launch_reduce(s->dinst, 1, s->stream) != hipSuccess) return LBFS_E_DEVICE;
+        if (run_step(s) != hipSuccess) return LBFS_E_DEVICE;
         s->t += s->p.dt;
         s->step += 1;
         s->stepped_since_observe = true;
     }
     return LBFS_OK;
+}
+
+int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
+                       int32_t* launches)
+{
+    if (!s) return LBFS_E_STATE;
+    if (nsteps < 0 || sample_every < 1 || !kernel_ms || !launches) return LBFS_E_INVAL;
+    const int nsample = (nsteps + sample_every - 1) / sample_every;
+    if (nsample > 4096) return LBFS_E_INVAL;
+
+    const int per_step = 5;
+    std::vector<hipEvent_t> ev((size_t)nsample * per_step * 2, nullptr);
+    std::vector<int> kind((size_t)nsample * per_step, 0);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return LBFS_E_DEVICE;
+        }
+    int rc = LBFS_OK;
+    size_t slot = 0;
+    auto timed = [&](int k, bool on, auto&& launch) -> hipError_t {
+        if (on) {
+            kind[slot] = k;
+            hipError_t e = hipEventRecord(ev[2 * slot], s->stream);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = launch();
+        if (e != hipSuccess) return e;
+        if (on) {
+            e = hipEventRecord(ev[2 * slot + 1], s->stream);
+            slot++;
+        }
+        return e;
+    };
+    for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
+        const bool on = n % sample_every == 0;
+        hipError_t e;
+        if (on) {
+            e = timed(LBFS_K_MAG, on, [&] { return launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1); });
+            for (int st = 1; st <= 3 && e == hipSuccess; st++)
+                e = timed(LBFS_K_STAGE1 + st - 1, on, [&] { return launch_stage_k(s, st); });
+            if (e == hipSuccess) e = timed(LBFS_K_REDUCE, on, [&] { return launch_reduce(s->dinst, 1, s->stream); });
+        } else {
+            e = run_step(s);
+        }
+        if (e != hipSuccess) rc = LBFS_E_DEVICE;
+        s->t += s->p.dt;
+        s->step += 1;
+        s->stepped_since_observe = true;
+    }
+    if (rc == LBFS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LBFS_E_DEVICE;
+    for (int k = 0; k < LBFS_NKERNELS; k++) {
+        kernel_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (rc == LBFS_OK)
+        for (size_t q = 0; q < slot; q++) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess) {
+                rc = LBFS_E_DEVICE;
+                break;
+            }
+            kernel_ms[kind[q]] += ms;
+            launches[kind[q]] += 1;
+        }
+    for (int k = 0; k < LBFS_NKERNELS; k++)
+        if (launches[k] > 0) kernel_ms[k] /= launches[k];
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int lbfs_observe(lbfs_solver* s, lbfs_observables* o)
@@ -504,8 +631,7 @@ int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* resid
 {
     if (!s) return LBFS_E_STATE;
     if (nsweeps < 0 || !(omega > 0.0 && omega < 2.0)) return LBFS_E_INVAL;
-    HIPCHK(launch_mu(s));
-    HIPCHK(launch_mag_sweeps(s, nsweeps, omega));
+    HIPCHK(launch_mag_phase(s, nsweeps, omega, 0));
     double r = 0.0;
     const int rc = mag_residual_now(s, &r);
     if (rc != LBFS_OK) return rc;
@@ -519,12 +645,13 @@ int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n)
     const size_t nn = (size_t)s->p.nx * s->p.ny;
     if (!host || n != nn) return LBFS_E_INVAL;
     if (field == LBFS_FIELD_T || field == LBFS_FIELD_FL) {
-        const int nm = s->L.ntile_mag();
-        HIPCHK(s->f64() ? launch_derived<double>(s->dinst, s->dtiles_mag, nm, s->stream)
-                        : launch_derived<float>(s->dinst, s->dtiles_mag, nm, s->stream));
+        const int np = s->L.ntile_pt();
+        HIPCHK(s->f64() ? launch_derived<double>(s->dinst, s->dtiles_pt, np, s->stream)
+                        : launch_derived<float>(s->dinst, s->dtiles_pt, np, s->stream));
         return copy_field_out(s, field == LBFS_FIELD_T ? 5 : 6, host);
     }
-    const int k = field_index(field);
+    int k = field_index(field);
+    if (k == -2) k = s->phi_field();
     if (k < 0) return LBFS_E_INVAL;
     const int rc = copy_field_out(s, k, host);
     if (rc != LBFS_OK) return rc;
@@ -539,7 +666,8 @@ int lbfs_write_field(lbfs_solver* s, int32_t field, const double* host, size_t n
     if (!s) return LBFS_E_STATE;
     const size_t nn = (size_t)s->p.nx * s->p.ny;
     if (!host || n != nn) return LBFS_E_INVAL;
-    const int k = field_index(field);
+    int k = field_index(field);
+    if (k == -2) k = s->phi_field();
     if (k < 0) return LBFS_E_INVAL;
     if (field == LBFS_FIELD_PHI) {
         std::vector<double> d(host, host + nn);
@@ -566,7 +694,7 @@ struct CkptHeader {
     double t, vol0;
     int64_t step;
 };
-constexpr int CKPT_FIELDS[7] = {0, 1, 2, 3, 4, 15, 16};
+constexpr int CKPT_FIELDS[7] = {0, 1, 2, 3, 4, -2, 16};   // -2: current potential buffer
 }  // namespace
 
 size_t lbfs_checkpoint_bytes(const lbfs_solver* s)
@@ -584,7 +712,8 @@ int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes)
     char* dst = static_cast<char*>(host) + sizeof h;
     const size_t es = s->L.esize, row = (size_t)s->p.nx * es, fb = row * s->p.ny;
     for (int q = 0; q < 7; q++) {
-        HIPCHK(hipMemcpy2DAsync(s->staging, row, s->field(CKPT_FIELDS[q]), (size_t)s->L.pitch * es, row, s->p.ny,
+        const int f = CKPT_FIELDS[q] == -2 ? s->phi_field() : CKPT_FIELDS[q];
+        HIPCHK(hipMemcpy2DAsync(s->staging, row, s->field(f), (size_t)s->L.pitch * es, row, s->p.ny,
                                 hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         std::memcpy(dst + q * fb, s->staging, fb);
@@ -605,7 +734,8 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes)
     const size_t es = s->L.esize, row = (size_t)s->p.nx * es, fb = row * s->p.ny;
     for (int q = 0; q < 7; q++) {
         std::memcpy(s->staging, src + q * fb, fb);
-        HIPCHK(hipMemcpy2DAsync(s->field(CKPT_FIELDS[q]), (size_t)s->L.pitch * es, s->staging, row, row, s->p.ny,
+        const int f = CKPT_FIELDS[q] == -2 ? s->phi_field() : CKPT_FIELDS[q];
+        HIPCHK(hipMemcpy2DAsync(s->field(f), (size_t)s->L.pitch * es, s->staging, row, row, s->p.ny,
                                 hipMemcpyHostToDevice, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -619,6 +749,10 @@ void lbfs_destroy(lbfs_solver* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    for (int k = 0; k < 2; k++) {
+        if (s->graph_exec[k]) (void)hipGraphExecDestroy(s->graph_exec[k]);
+        if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
+    }
     if (s->hres) (void)hipHostFree(s->hres);
     if (s->staging) (void)hipHostFree(s->staging);
     delete s;

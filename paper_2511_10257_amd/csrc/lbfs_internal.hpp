@@ -14,8 +14,13 @@ namespace lbfs {
 // stage tile shapes (cells); one thread per cell
 constexpr int STAGE_TX_F32 = 16, STAGE_TY_F32 = 16;
 constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8;
-// magnetic tile shape (cells); one thread per cell
-constexpr int MAG_TX = 64, MAG_TY = 4;
+// fused magnetic kernel: interior tile shapes (256 threads) and the sweeps one launch
+// can do (LDS halo 2*MAG_KMAX+1)
+constexpr int MAG_KMAX = 4;
+constexpr int MAG_SMALL_TX = 32, MAG_SMALL_TY = 8;
+constexpr int MAG_BIG_TX = 64, MAG_BIG_TY = 16;
+// pointwise kernels (init, derived fields): one thread per cell
+constexpr int PT_TX = 64, PT_TY = 4;
 
 // per-tile partial sums written by the last Runge-Kutta stage (FP64)
 enum { PART_CT = 0, PART_CTFL, PART_FS, PART_UMAX, PART_NONFINITE, PART_UDROP, PART_HEIGHT,
@@ -37,9 +42,8 @@ struct DevInst {
     void* W[5];      // state at the start of the step: He, p, Mx, My, C
     void* W1[5];     // stage-1 output (also the R(W) output of the rhs call)
     void* W2[5];     // stage-2 output
-    void* phi;       // potential minus the applied-field potential
+    void* phi[2];    // potential minus the applied-field potential, double buffered
     void* S;         // lagged dFs/dt
-    void* mu;        // magnetic permeability (scratch of the sweeps)
     double* part;    // [ntile_stage][NPART]
     double* mpart;   // [ntile_mag]
     double* result;  // [NRES]
@@ -58,18 +62,16 @@ struct DevInst {
 
 // launchers (lbfs_kernels.hip); all enqueue on `stream`, return hipError_t
 template <typename T>
-hipError_t launch_stage(int stage, const DevInst* insts, const Tile* tiles, int ntiles,
+hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                         hipStream_t stream);
+// magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
+// residual partials when residual != 0; big selects the large tile shape. Reads the
+// potential buffer *pidx and flips *pidx once per launch.
 template <typename T>
-hipError_t launch_mag_mu(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
-template <typename T>
-hipError_t launch_mag_pass(int color, double omega, const DevInst* insts, const Tile* tiles, int ntiles,
-                           hipStream_t stream);
+hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+                      const Tile* tiles, int ntiles, hipStream_t stream);
 template <typename T>
 hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
-template <typename T>
-hipError_t launch_mag_residual(const DevInst* insts, const Tile* tiles, int ntiles,
-                               hipStream_t stream);
 hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream);
 template <typename T>
 hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,

@@ -7,10 +7,11 @@
 //                           of the tile, sources (Eq. 41), residual (Eq. 42) and the
 //                           SSP-RK3 combination (Eq. 46); the last stage also applies
 //                           Eq. 8 for the lagged dFs/dt and writes FP64 partial sums.
-//   k_mag_mu / k_mag_pass / k_mag_residual
-//                           permeability (Eq. 2 with Eq. 11), one colour of a
-//                           red-black sweep of the compact magnetic system, residual.
-//   k_reduce                fixed-order FP64 reduction of the partials per instance.
+//   k_mag_fused             permeability (Eq. 2 with Eq. 11), red-black sweeps of the
+//                           compact magnetic system (temporally blocked in LDS) and
+//                           the FP64 residual.
+//   k_reduce                fixed-order FP64 reduction of the partials per instance
+//                           (the last stage does the same in its last workgroup).
 //   k_init_fields, k_derived
 //
 // The path is a stencil: a few hundred flops per face over ~70 bytes per cell and
@@ -21,6 +22,12 @@
 namespace lbfs {
 
 // ------------------------------------------------------------------ helpers
+
+// Field pointers live in the instance descriptor as generic pointers; cast them to the
+// global address space so that accesses compile to global (not flat) memory ops.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gp(void* p) { return (GLOBAL T*)p; }
 
 template <typename T>
 __device__ __forceinline__ T clamp01(T c) { return c < T(0) ? T(0) : (c > T(1) ? T(1) : c); }
@@ -199,6 +206,19 @@ __device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, co
     F[0] = (T(1.5) - tau_h) * cp_f * T_f * un_f + (tau_h - T(0.5)) * Hn;
 }
 
+// ------------------------------------------------------------- tile order
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Map
+// dispatch index -> tile so that every XCD works through one contiguous range of the
+// (row-major) tile list: neighbouring tiles, whose halos overlap, then share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n)
+{
+    constexpr int NXCD = 8;
+    const int q = n / NXCD, r = n % NXCD;
+    const int x = bid % NXCD, k = bid / NXCD;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // ------------------------------------------------------------- stage kernel
 
 enum { Q_P = 0, Q_U, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_MU, Q_LAM, Q_CP, Q_PHI, NQ };
@@ -307,14 +327,52 @@ __device__ __forceinline__ void block_partials(const double* pr, double (*red)[N
     }
 }
 
+__device__ __forceinline__ bool res_is_max(int k)
+{
+    return k == RES_UMAX || k == RES_NONFINITE || k == RES_UDROP;
+}
+
+// Fixed-order FP64 reduction of an instance's tile partials (and the magnetic
+// residual partials) into I.result; NT threads of one workgroup.
+template <int NT>
+__device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, double (*red)[NT / 64])
+{
+    double acc[NRES] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = tid; t < I.ntile_stage; t += NT) {
+        const double* p = I.part + (size_t)t * NPART;
+        acc[RES_CT] += p[PART_CT];
+        acc[RES_CTFL] += p[PART_CTFL];
+        acc[RES_FS] += p[PART_FS];
+        acc[RES_UMAX] = fmax(acc[RES_UMAX], p[PART_UMAX]);
+        acc[RES_NONFINITE] = fmax(acc[RES_NONFINITE], p[PART_NONFINITE]);
+        acc[RES_UDROP] = fmax(acc[RES_UDROP], p[PART_UDROP]);
+        acc[RES_HEIGHT] += p[PART_HEIGHT];
+        acc[RES_HEAT] += p[PART_HEAT];
+    }
+    for (int t = tid; t < I.ntile_mag; t += NT) acc[RES_MAGR2] += I.mpart[t];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NRES; k++) {
+        const double w = res_is_max(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (tid % 64 == 0) red[k][tid / 64] = w;
+    }
+    __syncthreads();
+    if (tid < NRES) {
+        const int k = tid;
+        double a = red[k][0];
+        for (int w = 1; w < NT / 64; w++) a = res_is_max(k) ? fmax(a, red[k][w]) : a + red[k][w];
+        I.result[k] = a;
+    }
+}
+
 template <typename T, int TX, int TY, int STAGE>
 __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ insts,
-                                                  const Tile* __restrict__ tiles)
+                                                  const Tile* __restrict__ tiles, int pidx)
 {
     using L = StageLds<T, TX, TY>;
     constexpr int NT = TX * TY;
     __shared__ L s;
-    const Tile tile = tiles[blockIdx.x];
+    const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
     const int tid = threadIdx.x;
     const int x0 = tile.x0, y0 = tile.y0;
@@ -325,41 +383,63 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
     T* const* Wbase = reinterpret_cast<T* const*>(I.W);
     T* const* Win = STAGE == 2 ? reinterpret_cast<T* const*>(I.W1)
                   : STAGE == 3 ? reinterpret_cast<T* const*>(I.W2) : Wbase;
-    const T* __restrict__ phi = reinterpret_cast<const T*>(I.phi);
+    const GLOBAL T* phi = gp<T>(I.phi[pidx]);
 
-    // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image)
-    for (int r = tid; r < L::NR; r += NT) {
-        const int lx = r % L::RX, ly = r / L::RX;
-        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
-        int wx, wy;
-        const int sx = map_axis(gx, nx, I.per_x, 0, 1, wx);
-        const int sy = map_axis(gy, ny, I.per_y, 2, 3, wy);
-        const size_t o = (size_t)sy * pitch + sx;
-        Prim<T> q = primitives<T>(I, Win[0][o], Win[1][o], Win[2][o], Win[3][o], Win[4][o]);
-        T ph = phi[o];
-        if (wx >= 0) {
-            q.u = -q.u;
-            q.v = -q.v;
-            if (I.tbc[wx]) q.Tt = T(2) * T(I.tval[wx]) - q.Tt;
-            ph = I.mbc[wx] ? -ph : ph - T(I.h0x) * T(sx - gx) * dx;
+    // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image); every load of
+    //      this thread is issued before the first one is used
+    {
+        constexpr int NIT = (L::NR + NT - 1) / NT;
+        T vW[NIT][5], vph[NIT];
+        int vwx[NIT], vwy[NIT], vdx[NIT], vdy[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            const int rr = r < L::NR ? r : L::NR - 1;
+            const int lx = rr % L::RX, ly = rr / L::RX;
+            const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+            int wx, wy;
+            const int sx = map_axis(gx, nx, I.per_x, 0, 1, wx);
+            const int sy = map_axis(gy, ny, I.per_y, 2, 3, wy);
+            vwx[it] = wx;
+            vwy[it] = wy;
+            vdx[it] = sx - gx;
+            vdy[it] = sy - gy;
+            const size_t o = (size_t)sy * pitch + sx;
+#pragma unroll
+            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[o];
+            vph[it] = phi[o];
         }
-        if (wy >= 0) {
-            q.u = -q.u;
-            q.v = -q.v;
-            if (I.tbc[wy]) q.Tt = T(2) * T(I.tval[wy]) - q.Tt;
-            ph = I.mbc[wy] ? -ph : ph - T(I.h0y) * T(sy - gy) * dx;
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR) break;
+            Prim<T> q = primitives<T>(I, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]);
+            T ph = vph[it];
+            const int wx = vwx[it], wy = vwy[it];
+            if (wx >= 0) {
+                q.u = -q.u;
+                q.v = -q.v;
+                if (I.tbc[wx]) q.Tt = T(2) * T(I.tval[wx]) - q.Tt;
+                ph = I.mbc[wx] ? -ph : ph - T(I.h0x) * T(vdx[it]) * dx;
+            }
+            if (wy >= 0) {
+                q.u = -q.u;
+                q.v = -q.v;
+                if (I.tbc[wy]) q.Tt = T(2) * T(I.tval[wy]) - q.Tt;
+                ph = I.mbc[wy] ? -ph : ph - T(I.h0y) * T(vdy[it]) * dx;
+            }
+            s.q[Q_P][r] = q.p;
+            s.q[Q_U][r] = q.u;
+            s.q[Q_V][r] = q.v;
+            s.q[Q_RHO][r] = q.rho;
+            s.q[Q_C][r] = q.C;
+            s.q[Q_T][r] = q.Tt;
+            s.q[Q_HE][r] = q.He;
+            s.q[Q_MU][r] = q.mu;
+            s.q[Q_LAM][r] = q.lam;
+            s.q[Q_CP][r] = q.cp;
+            s.q[Q_PHI][r] = ph;
         }
-        s.q[Q_P][r] = q.p;
-        s.q[Q_U][r] = q.u;
-        s.q[Q_V][r] = q.v;
-        s.q[Q_RHO][r] = q.rho;
-        s.q[Q_C][r] = q.C;
-        s.q[Q_T][r] = q.Tt;
-        s.q[Q_HE][r] = q.He;
-        s.q[Q_MU][r] = q.mu;
-        s.q[Q_LAM][r] = q.lam;
-        s.q[Q_CP][r] = q.cp;
-        s.q[Q_PHI][r] = ph;
     }
     __syncthreads();
 
@@ -477,7 +557,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
         if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
-        else { Cn = Wbase[4][o]; Hen = Wbase[0][o]; }
+        else { Cn = gp<T>(Wbase[4])[o]; Hen = gp<T>(Wbase[0])[o]; }
         T Tn, Fln;
         enthalpy_state<T>(I, Hen, Cn, Tn, Fln);
         const T ctn = clamp01(Cn);
@@ -497,7 +577,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         T Tc, Flc;
         enthalpy_state<T>(I, s.q[Q_HE][r], c, Tc, Flc);
         const T fs = clamp01(c) * (T(1) - Flc);
-        const T Sv = reinterpret_cast<const T*>(I.S)[o];
+        const T Sv = gp<T>(I.S)[o];
         const T vc = T(I.vc);
         T src[5];
         src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
@@ -514,26 +594,26 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         }
         if (STAGE == 0) {
 #pragma unroll
-            for (int k = 0; k < 5; k++) reinterpret_cast<T*>(I.W1[k])[o] = Rk[k];
+            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = Rk[k];
         } else if (STAGE == 1) {
 #pragma unroll
-            for (int k = 0; k < 5; k++) reinterpret_cast<T*>(I.W1[k])[o] = Win[k][o] + dt * Rk[k];
+            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = gp<T>(Win[k])[o] + dt * Rk[k];
         } else if (STAGE == 2) {
 #pragma unroll
             for (int k = 0; k < 5; k++)
-                reinterpret_cast<T*>(I.W2[k])[o] = T(0.75) * Wbase[k][o] + T(0.25) * (Win[k][o] + dt * Rk[k]);
+                gp<T>(I.W2[k])[o] = T(0.75) * gp<T>(Wbase[k])[o] + T(0.25) * (gp<T>(Win[k])[o] + dt * Rk[k]);
         } else {
             T Wn[5];
 #pragma unroll
             for (int k = 0; k < 5; k++) {
-                Wn[k] = Wbase[k][o] * T(1.0 / 3.0) + T(2.0 / 3.0) * (Win[k][o] + dt * Rk[k]);
-                Wbase[k][o] = Wn[k];
+                Wn[k] = gp<T>(Wbase[k])[o] * T(1.0 / 3.0) + T(2.0 / 3.0) * (gp<T>(Win[k])[o] + dt * Rk[k]);
+                gp<T>(Wbase[k])[o] = Wn[k];
             }
             // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
             T T1, Fl1;
             enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
             const T ct1 = clamp01(Wn[4]);
-            reinterpret_cast<T*>(I.S)[o] = -ct1 * (Fl1 - Fln) / dt;
+            gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) / dt;
             cell_partials<T>(I, Wn, gx, gy, pr);
         }
     }
@@ -541,7 +621,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
 }
 
 template <typename T>
-hipError_t launch_stage(int stage, const DevInst* insts, const Tile* tiles, int ntiles,
+hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                         hipStream_t stream)
 {
     constexpr bool f32 = sizeof(T) == 4;
@@ -550,10 +630,10 @@ hipError_t launch_stage(int stage, const DevInst* insts, const Tile* tiles, int 
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(TX * TY);
     switch (stage) {
-    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, 0>), grid, block, 0, stream, insts, tiles); break;
-    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, 1>), grid, block, 0, stream, insts, tiles); break;
-    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, 2>), grid, block, 0, stream, insts, tiles); break;
-    default: hipLaunchKernelGGL((k_stage<T, TX, TY, 3>), grid, block, 0, stream, insts, tiles); break;
+    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, 0>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, 1>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, 2>), grid, block, 0, stream, insts, tiles, pidx); break;
+    default: hipLaunchKernelGGL((k_stage<T, TX, TY, 3>), grid, block, 0, stream, insts, tiles, pidx); break;
     }
     return hipGetLastError();
 }
@@ -594,131 +674,210 @@ hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int nt
 
 // ------------------------------------------------------------- magnetics
 
-template <typename T>
-__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_mu(const DevInst* __restrict__ insts,
-                                                          const Tile* __restrict__ tiles)
-{
-    const Tile tile = tiles[blockIdx.x];
-    const DevInst& I = insts[tile.inst];
-    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
-    if (gx >= I.nx || gy >= I.ny) return;
-    const size_t o = (size_t)gy * I.pitch + gx;
-    const T He = reinterpret_cast<const T*>(I.W[0])[o], C = reinterpret_cast<const T*>(I.W[4])[o];
-    T Tt, Fl;
-    enthalpy_state<T>(I, He, C, Tt, Fl);
-    const T ct = clamp01(C);
-    reinterpret_cast<T*>(I.mu)[o] = T(I.mu0) * (T(1) + mix3<T>(I.chi, ct * (T(1) - Fl), ct));
-}
+// Fused magnetic phase on one tile of MTX x MTY cells: permeability (Eq. 2 with
+// Eq. 11) of the tile plus a halo of 2*MAG_KMAX+1 cells into LDS, up to MAG_KMAX
+// red-black sweeps of the compact system done in LDS (temporal blocking: the
+// region where the sweeps are exact shrinks by one cell per colour pass), the tile's
+// potential written back, and optionally the FP64 residual of the tile. Each cell
+// update is the same arithmetic as an untiled red-black pass, so the result does not
+// depend on the tiling.
+//
+// Update of cell c: phi'_c <- (1-w) phi'_c + w sum_f a_f (phi'_nb + phi0_nb - phi0_c) / sum_f a_f,
+// a_f = mean(mu) on interior faces, 2 mu_c towards a fixed-potential wall half a cell
+// away (where phi' = 0), no term at an insulating wall; phi0 = -(h0x x + h0y y).
+template <typename T, int MTX, int MTY>
+struct MagLds {
+    static constexpr int H = 2 * MAG_KMAX + 1;
+    static constexpr int RX = MTX + 2 * H, RY = MTY + 2 * H, NR = RX * RY;
+    static_assert(RX % 2 == 0, "region rows hold whole red-black pairs");
+    T phi[NR];
+    T we[NR];         // weight of the east face (0 unless both cells are in the domain)
+    T wn[NR];         // weight of the north face
+    T b[NR];          // sum_f a_f (phi0_nb - phi0_c): the applied-field part of the numerator
+    T rden[NR];       // 1 / sum_f a_f (0: cell not updated)
+    double red[4];
+};
 
-// Sum over the four faces of w_f (phi'_nb + phi0_nb - phi0_c) and w_f: face weight
-// mean(mu); 2 mu_c to a fixed-potential wall half a cell away (phi' = 0 there); no
-// term at an insulating wall. phi0 is the applied-field potential -(h0x x + h0y y).
-template <typename T, typename Acc>
-__device__ __forceinline__ void mag_faces(const DevInst& I, int gx, int gy, Acc& num, Acc& den)
+template <typename T, int MTX, int MTY>
+__global__ __launch_bounds__(256) void k_mag_fused(const DevInst* __restrict__ insts,
+                                                   const Tile* __restrict__ tiles, int nsweeps, double omega,
+                                                   int residual, int pin)
 {
-    const T* __restrict__ mu = reinterpret_cast<const T*>(I.mu);
-    const T* __restrict__ ph = reinterpret_cast<const T*>(I.phi);
-    const int pitch = I.pitch;
-    const size_t o = (size_t)gy * pitch + gx;
-    const T muc = mu[o];
-    const T hx = T(I.h0x) * T(I.dx), hy = T(I.h0y) * T(I.dx);
-    num = Acc(0);
-    den = Acc(0);
-    const int DI[4] = {-1, 1, 0, 0}, DJ[4] = {0, 0, -1, 1};
-    const T D0[4] = {hx, -hx, hy, -hy};
+    using L = MagLds<T, MTX, MTY>;
+    constexpr int NT = 256;
+    constexpr int NIT = (L::NR + NT - 1) / NT;
+    __shared__ L s;
+    const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const DevInst& I = insts[tile.inst];
+    const int tid = threadIdx.x;
+    const int nx = I.nx, ny = I.ny;
+    const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
+    const GLOBAL T* phin = gp<T>(I.phi[pin]);
+    const GLOBAL T* He_ = gp<T>(I.W[0]);
+    const GLOBAL T* C_ = gp<T>(I.W[4]);
+    // 1. load the region (all loads of this thread in flight together); mu = 0 outside
+    //    the domain. The permeability goes to rden temporarily.
+    {
+        T vHe[NIT], vC[NIT], vph[NIT];
+        bool vin[NIT];
 #pragma unroll
-    for (int d = 0; d < 4; d++) {
-        int ii = gx + DI[d], jj = gy + DJ[d];
-        const bool per = d < 2 ? I.per_x : I.per_y;
-        bool inside = ii >= 0 && ii < I.nx && jj >= 0 && jj < I.ny;
-        if (!inside && per) {
-            ii = (ii + I.nx) % I.nx;
-            jj = (jj + I.ny) % I.ny;
-            inside = true;
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            const int gx = ox + r % L::RX, gy = oy + r / L::RX;
+            int sx = gx, sy = gy;
+            bool in = r < L::NR;
+            if (gx < 0 || gx >= nx) {
+                if (I.per_x) sx = gx < 0 ? gx + nx : gx - nx;
+                else in = false;
+            }
+            if (gy < 0 || gy >= ny) {
+                if (I.per_y) sy = gy < 0 ? gy + ny : gy - ny;
+                else in = false;
+            }
+            in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+            vin[it] = in;
+            const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
+            vHe[it] = He_[o];
+            vC[it] = C_[o];
+            vph[it] = phin[o];
         }
-        if (inside) {
-            const size_t q = (size_t)jj * pitch + ii;
-            const T w = T(0.5) * (muc + mu[q]);
-            num += Acc(w) * (Acc(ph[q]) + Acc(D0[d]));
-            den += Acc(w);
-        } else if (I.mbc[d]) {
-            const T w = T(2) * muc;
-            num += Acc(w) * Acc(T(0.5) * D0[d]);
-            den += Acc(w);
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR) break;
+            T mu = T(0);
+            if (vin[it]) {
+                T Tt, Fl;
+                enthalpy_state<T>(I, vHe[it], vC[it], Tt, Fl);
+                const T ct = clamp01(vC[it]);
+                mu = T(I.mu0) * (T(1) + mix3<T>(I.chi, ct * (T(1) - Fl), ct));
+            }
+            s.rden[r] = mu;
+            s.phi[r] = vin[it] ? vph[it] : T(0);
         }
     }
-}
-
-template <typename T, int COLOR>
-__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_pass(const DevInst* __restrict__ insts,
-                                                            const Tile* __restrict__ tiles, double omega)
-{
-    const Tile tile = tiles[blockIdx.x];
-    const DevInst& I = insts[tile.inst];
-    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
-    if (gx >= I.nx || gy >= I.ny || ((gx + gy) & 1) != COLOR) return;
-    T num, den;
-    mag_faces<T, T>(I, gx, gy, num, den);
-    if (den > T(0)) {
-        T* ph = reinterpret_cast<T*>(I.phi);
-        const size_t o = (size_t)gy * I.pitch + gx;
-        const T om = T(omega);
-        ph[o] = (T(1) - om) * ph[o] + om * num / den;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_mag_residual(const DevInst* __restrict__ insts,
-                                                                const Tile* __restrict__ tiles)
-{
-    __shared__ double red[MAG_TX * MAG_TY / 64];
-    const Tile tile = tiles[blockIdx.x];
-    const DevInst& I = insts[tile.inst];
-    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
-    double r2 = 0.0;
-    if (gx < I.nx && gy < I.ny) {
-        double num, den;
-        mag_faces<T, double>(I, gx, gy, num, den);
-        const double r = num - den * double(reinterpret_cast<const T*>(I.phi)[(size_t)gy * I.pitch + gx]);
-        r2 = r * r;
-    }
-    r2 = wave_sum(r2);
-    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = r2;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        for (int w = 0; w < MAG_TX * MAG_TY / 64; w++) acc += red[w];
-        I.mpart[tile.idx] = acc;
+    // 2. face weights (mean permeability of two domain cells), then the constant part of
+    //    the numerator and 1 / sum of the weights; a fixed-potential wall half a cell away
+    //    has weight 2 mu_c, an insulating wall none.
+    const T hx = T(I.h0x) * T(I.dx), hy = T(I.h0y) * T(I.dx);
+    for (int r = tid; r < L::NR; r += NT) {
+        const int lx = r % L::RX, ly = r / L::RX;
+        const T muc = s.rden[r];
+        const T mue = lx + 1 < L::RX ? s.rden[r + 1] : T(0);
+        const T mun = ly + 1 < L::RY ? s.rden[r + L::RX] : T(0);
+        s.we[r] = (muc > T(0) && mue > T(0)) ? T(0.5) * (muc + mue) : T(0);
+        s.wn[r] = (muc > T(0) && mun > T(0)) ? T(0.5) * (muc + mun) : T(0);
+    }
+    __syncthreads();
+    T bb[NIT], dd[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int r = tid + it * NT;
+        bb[it] = T(0);
+        dd[it] = T(0);
+        if (r >= L::NR) break;
+        const int lx = r % L::RX, ly = r / L::RX;
+        const T muc = s.rden[r];
+        if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1 || !(muc > T(0))) continue;
+        const T w[4] = {s.we[r - 1], s.we[r], s.wn[r - L::RX], s.wn[r]};   // W, E, S, N
+        const T D0[4] = {hx, -hx, hy, -hy};   // phi0_nb - phi0_c across each face
+        T bsum = T(0), den = T(0);
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            if (w[d] > T(0)) {
+                bsum += w[d] * D0[d];
+                den += w[d];
+            } else {
+                const int q = r + (d == 0 ? -1 : d == 1 ? 1 : d == 2 ? -L::RX : L::RX);
+                const bool nb_in = s.rden[q] > T(0);
+                if (!nb_in && I.mbc[d]) {   // a wall face
+                    const T ww = T(2) * muc;
+                    bsum += ww * (T(0.5) * D0[d]);
+                    den += ww;
+                }
+            }
+        }
+        bb[it] = bsum;
+        dd[it] = den;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int r = tid + it * NT;
+        if (r >= L::NR) break;
+        s.b[r] = bb[it];
+        s.rden[r] = dd[it] > T(0) ? T(1) / dd[it] : T(0);
+    }
+    __syncthreads();
+    // 3. red-black passes in LDS
+    const T om = T(omega);
+    constexpr int HALF = L::NR / 2, PAIRS = L::RX / 2;
+    constexpr int NITH = (HALF + NT - 1) / NT;
+    for (int pass = 0; pass < 2 * nsweeps; pass++) {
+        const int color = pass & 1;
+#pragma unroll
+        for (int it = 0; it < NITH; it++) {
+            const int k = tid + it * NT;
+            if (k >= HALF) break;
+            const int ly = k / PAIRS;
+            const int lx = 2 * (k % PAIRS) + ((ox + oy + ly + color) & 1);
+            const int r = ly * L::RX + lx;
+            const T rd = s.rden[r];
+            if (rd == T(0)) continue;   // ring 0, outside the domain
+            const T num = s.b[r] + s.we[r - 1] * s.phi[r - 1] + s.we[r] * s.phi[r + 1] +
+                          s.wn[r - L::RX] * s.phi[r - L::RX] + s.wn[r] * s.phi[r + L::RX];
+            s.phi[r] = (T(1) - om) * s.phi[r] + om * num * rd;
+        }
+        __syncthreads();
+    }
+    // 4. write the tile; FP64 residual r_c = sum_f a_f (phi_nb - phi_c)
+    double r2 = 0.0;
+    GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
+    for (int c = tid; c < MTX * MTY; c += NT) {
+        const int gx = tile.x0 + c % MTX, gy = tile.y0 + c / MTX;
+        if (gx >= nx || gy >= ny) continue;
+        const int r = (c / MTX + L::H) * L::RX + (c % MTX + L::H);
+        phout[(size_t)gy * I.pitch + gx] = s.phi[r];
+        if (residual && s.rden[r] != T(0)) {
+            const double res = double(s.b[r]) + double(s.we[r - 1]) * double(s.phi[r - 1]) +
+                               double(s.we[r]) * double(s.phi[r + 1]) +
+                               double(s.wn[r - L::RX]) * double(s.phi[r - L::RX]) +
+                               double(s.wn[r]) * double(s.phi[r + L::RX]) - double(s.phi[r]) / double(s.rden[r]);
+            r2 += res * res;
+        }
+    }
+    if (residual) {
+        r2 = wave_sum(r2);
+        if (tid % 64 == 0) s.red[tid / 64] = r2;
+        __syncthreads();
+        if (tid == 0) I.mpart[tile.idx] = s.red[0] + s.red[1] + s.red[2] + s.red[3];
     }
 }
 
 template <typename T>
-hipError_t launch_mag_mu(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
+hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+                      const Tile* tiles, int ntiles, hipStream_t stream)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_mag_mu<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_mag_pass(int color, double omega, const DevInst* insts, const Tile* tiles, int ntiles,
-                           hipStream_t stream)
-{
-    if (ntiles <= 0) return hipSuccess;
-    if (color == 0)
-        hipLaunchKernelGGL((k_mag_pass<T, 0>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles, omega);
-    else
-        hipLaunchKernelGGL((k_mag_pass<T, 1>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles, omega);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_mag_residual(const DevInst* insts, const Tile* tiles, int ntiles,
-                               hipStream_t stream)
-{
-    if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_mag_residual<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
-    return hipGetLastError();
+    // the potential is read from phi[*pidx] and written to the other buffer (halo cells
+    // of a tile belong to other workgroups); sweeps beyond the LDS halo run as further
+    // launches
+    do {
+        const int k = nsweeps > MAG_KMAX ? MAG_KMAX : nsweeps;
+        nsweeps -= k;
+        const int res = residual && nsweeps == 0;
+        if (big)
+            hipLaunchKernelGGL((k_mag_fused<T, MAG_BIG_TX, MAG_BIG_TY>), dim3(ntiles), dim3(256), 0, stream, insts,
+                               tiles, k, omega, res, *pidx);
+        else
+            hipLaunchKernelGGL((k_mag_fused<T, MAG_SMALL_TX, MAG_SMALL_TY>), dim3(ntiles), dim3(256), 0, stream,
+                               insts, tiles, k, omega, res, *pidx);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        *pidx ^= 1;
+    } while (nsweeps > 0);
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------- reduction
@@ -726,35 +885,7 @@ hipError_t launch_mag_residual(const DevInst* insts, const Tile* tiles, int ntil
 __global__ __launch_bounds__(256) void k_reduce(const DevInst* __restrict__ insts)
 {
     __shared__ double red[NRES][4];
-    const DevInst& I = insts[blockIdx.x];
-    const int tid = threadIdx.x;
-    double acc[NRES] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = tid; t < I.ntile_stage; t += 256) {
-        const double* p = I.part + (size_t)t * NPART;
-        acc[RES_CT] += p[PART_CT];
-        acc[RES_CTFL] += p[PART_CTFL];
-        acc[RES_FS] += p[PART_FS];
-        acc[RES_UMAX] = fmax(acc[RES_UMAX], p[PART_UMAX]);
-        acc[RES_NONFINITE] = fmax(acc[RES_NONFINITE], p[PART_NONFINITE]);
-        acc[RES_UDROP] = fmax(acc[RES_UDROP], p[PART_UDROP]);
-        acc[RES_HEIGHT] += p[PART_HEIGHT];
-        acc[RES_HEAT] += p[PART_HEAT];
-    }
-    for (int t = tid; t < I.ntile_mag; t += 256) acc[RES_MAGR2] += I.mpart[t];
-#pragma unroll
-    for (int k = 0; k < NRES; k++) {
-        const bool isMax = k == RES_UMAX || k == RES_NONFINITE || k == RES_UDROP;
-        const double w = isMax ? wave_max(acc[k]) : wave_sum(acc[k]);
-        if (tid % 64 == 0) red[k][tid / 64] = w;
-    }
-    __syncthreads();
-    if (tid < NRES) {
-        const int k = tid;
-        const bool isMax = k == RES_UMAX || k == RES_NONFINITE || k == RES_UDROP;
-        double a = red[k][0];
-        for (int w = 1; w < 4; w++) a = isMax ? fmax(a, red[k][w]) : a + red[k][w];
-        I.result[k] = a;
-    }
+    instance_reduce<256>(insts[blockIdx.x], threadIdx.x, red);
 }
 
 hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream)
@@ -770,14 +901,14 @@ hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream)
 // enthalpy of temperature t_init by the inverse of Eq. 8, fluid at rest, potential of
 // the applied field (phi' = 0), no lagged source.
 template <typename T>
-__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_init_fields(const DevInst* __restrict__ insts,
+__global__ __launch_bounds__(PT_TX* PT_TY) void k_init_fields(const DevInst* __restrict__ insts,
                                                                const Tile* __restrict__ tiles,
                                                                int kind, double c_init, double t_init,
                                                                double cx, double cy, double rad)
 {
     const Tile tile = tiles[blockIdx.x];
     const DevInst& I = insts[tile.inst];
-    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    const int gx = tile.x0 + (int)threadIdx.x % PT_TX, gy = tile.y0 + (int)threadIdx.x / PT_TX;
     if (gx >= I.nx || gy >= I.ny) return;
     const size_t o = (size_t)gy * I.pitch + gx;
     const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx;
@@ -796,17 +927,18 @@ __global__ __launch_bounds__(MAG_TX* MAG_TY) void k_init_fields(const DevInst* _
     reinterpret_cast<T*>(I.W[3])[o] = T(0);
     reinterpret_cast<T*>(I.W[4])[o] = T(C);
     reinterpret_cast<T*>(I.S)[o] = T(0);
-    reinterpret_cast<T*>(I.phi)[o] = T(0);
+    reinterpret_cast<T*>(I.phi[0])[o] = T(0);
+    reinterpret_cast<T*>(I.phi[1])[o] = T(0);
 }
 
 // Temperature and liquid fraction (Eq. 8) of the current state into W1[0], W1[1].
 template <typename T>
-__global__ __launch_bounds__(MAG_TX* MAG_TY) void k_derived(const DevInst* __restrict__ insts,
+__global__ __launch_bounds__(PT_TX* PT_TY) void k_derived(const DevInst* __restrict__ insts,
                                                            const Tile* __restrict__ tiles)
 {
     const Tile tile = tiles[blockIdx.x];
     const DevInst& I = insts[tile.inst];
-    const int gx = tile.x0 + (int)threadIdx.x % MAG_TX, gy = tile.y0 + (int)threadIdx.x / MAG_TX;
+    const int gx = tile.x0 + (int)threadIdx.x % PT_TX, gy = tile.y0 + (int)threadIdx.x / PT_TX;
     if (gx >= I.nx || gy >= I.ny) return;
     const size_t o = (size_t)gy * I.pitch + gx;
     T Tt, Fl;
@@ -821,7 +953,7 @@ hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntile
                               hipStream_t stream)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_init_fields<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles,
+    hipLaunchKernelGGL((k_init_fields<T>), dim3(ntiles), dim3(PT_TX * PT_TY), 0, stream, insts, tiles,
                        kind, c_init, t_init, cx, cy, r);
     return hipGetLastError();
 }
@@ -830,16 +962,14 @@ template <typename T>
 hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_derived<T>), dim3(ntiles), dim3(MAG_TX * MAG_TY), 0, stream, insts, tiles);
+    hipLaunchKernelGGL((k_derived<T>), dim3(ntiles), dim3(PT_TX * PT_TY), 0, stream, insts, tiles);
     return hipGetLastError();
 }
 
 #define LBFS_INSTANTIATE(T)                                                                          \
-    template hipError_t launch_stage<T>(int, const DevInst*, const Tile*, int, hipStream_t);        \
-    template hipError_t launch_mag_mu<T>(const DevInst*, const Tile*, int, hipStream_t);            \
-    template hipError_t launch_mag_pass<T>(int, double, const DevInst*, const Tile*, int, hipStream_t); \
+    template hipError_t launch_stage<T>(int, int, const DevInst*, const Tile*, int, hipStream_t);   \
+    template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_state_partials<T>(const DevInst*, const Tile*, int, hipStream_t);    \
-    template hipError_t launch_mag_residual<T>(const DevInst*, const Tile*, int, hipStream_t);      \
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \
     template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);

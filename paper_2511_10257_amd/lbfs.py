@@ -20,11 +20,13 @@ LBFS_OK, LBFS_E_INVAL, LBFS_E_NOMEM, LBFS_E_NONFINITE, LBFS_E_DEVICE, LBFS_E_STA
     0, -1, -2, -3, -4, -5, -6)
 LBFS_FP32, LBFS_FP64 = 0, 1
 FIELDS = dict(He=0, p=1, Mx=2, My=3, C=4, phi=5, S=6, T=7, Fl=8)
+KERNELS = ("mag", "stage1", "stage2", "stage3", "reduce")
+NKERNELS = len(KERNELS)
 
 # every symbol include/lbfs.h declares
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
-    "lbfs_step", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
+    "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
 )
@@ -81,6 +83,7 @@ def lib():
             "lbfs_state_bytes": (C.c_size_t, [C.POINTER(Params)]),
             "lbfs_init": (C.c_int, [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbfs_step": (C.c_int, [vp, i32]),
+            "lbfs_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
             "lbfs_observe": (C.c_int, [vp, C.POINTER(Observables)]),
             "lbfs_rhs": (C.c_int, [vp, dp]),
             "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
@@ -190,7 +193,8 @@ class Solver:
             raise LbfsError(LBFS_E_INVAL, "lbfs_state_bytes")
         self.device = torch.device(device)
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority) so that a step can be replayed as a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().lbfs_init(C.byref(self.params), C.c_void_p(self.buffer.data_ptr()), nbytes,
@@ -214,6 +218,14 @@ class Solver:
 
     def step(self, n: int = 1) -> None:
         _check(lib().lbfs_step(self._h, int(n)), "lbfs_step")
+
+    def step_profiled(self, n: int, sample_every: int = 10) -> dict:
+        """Steps with HIP events around the kernels of every sample_every-th step;
+        returns {kernel kind: (mean ms per launch, timed launches)}."""
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        _check(lib().lbfs_step_profiled(self._h, int(n), int(sample_every), ms, cnt), "lbfs_step_profiled")
+        return {KERNELS[k]: (ms[k], cnt[k]) for k in range(NKERNELS)}
 
     def observe(self, allow_nonfinite: bool = False) -> dict:
         o = Observables()

@@ -39,6 +39,10 @@ def test_state_bytes_and_validation():
         q = lbfs.make_params(wl.config0())
         setattr(q, field, bad)
         assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0, field
+    q = lbfs.make_params(wl.neumann_problem(0.1, 250.0))
+    assert lbfs.lib().lbfs_state_bytes(C.byref(q)) > 0
+    q.ny = 5                     # odd periodic axis: no red-black colouring
+    assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0
     q = lbfs.make_params(wl.config0())
     q.periodic[1] = 1            # vertical applied field across a periodic axis
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0

@@ -221,3 +221,66 @@ def test_rhs_at_full_size(which):
     for k, name in enumerate(NAMES):
         err = np.linalg.norm(Rg[k] - Ro[k]) / np.linalg.norm(Ro[k])
         assert err < 2e-4, (which, name, err)
+
+
+def test_step_fp64_full_size_observables():
+    """1024^2 FP64 (8192 stage tiles over all XCDs): one step from the same state,
+    fields and the observables reduced by the last workgroup of the last stage."""
+    prob = wl.with_changes(wl.config2("fp64"), init_max=0)
+    nx, ny = prob["nx"], prob["ny"]
+    o = orc.Oracle(prob, init=False)
+    # momentum amplitude for |u| ~ 0.015 in the gas of density 0.01
+    st = wl.smooth_state(nx, ny, seed=9, latent=o.params.latent, h0=o.params.h0,
+                         angle_deg=prob["angle_deg"], amp_u=5e-5)
+    o.set_state(st)
+    g = lbfs.Solver(prob)
+    g.set_state(st)
+    o.step(1)
+    g.step(1)
+    fl = floors(prob)
+    for name in ("He", "p", "Mx", "My", "C", "phi", "S"):
+        assert rel_l2(g.get(name), o.get(name), fl[name]) < 1e-10, name
+    ob, og = o.observe(), g.observe()
+    # (the solid ratio is relative to the initial volume, which only the GPU side has here)
+    for key in ("liquid_fraction", "volume", "mag_residual", "umax", "height", "wall_heat"):
+        assert og[key] == pytest.approx(ob[key], rel=1e-9, abs=1e-14), key
+    # a second step exercises the reset of the completion counter
+    o.step(1)
+    g.step(1)
+    assert g.observe()["liquid_fraction"] == pytest.approx(o.observe()["liquid_fraction"], rel=1e-9)
+
+
+def test_graph_replay_equals_direct_launches(monkeypatch):
+    prob = wl.droplet_problem(96, 24.0, ste=0.1, bo_m=1.5, angle_deg=30.0, precision="fp32")
+    a = lbfs.Solver(prob)
+    monkeypatch.setenv("LBFS_NO_GRAPH", "1")
+    b = lbfs.Solver(prob)
+    a.step(25)
+    b.step(25)
+    for k in ("He", "p", "Mx", "My", "C", "phi", "S"):
+        assert np.array_equal(a.get(k), b.get(k)), k
+    assert a.observe() == b.observe()
+
+
+def test_profiled_steps_equal_plain_steps():
+    prob = wl.droplet_problem(64, 16.0, ste=0.1, bo_m=1.0, angle_deg=90.0, precision="fp32")
+    a = lbfs.Solver(prob)
+    b = lbfs.Solver(prob)
+    a.step(30)
+    kern = b.step_profiled(30, 7)
+    assert kern["stage2"][1] == 5 and kern["mag"][0] > 0
+    for k in ("He", "C", "phi", "S"):
+        assert np.array_equal(a.get(k), b.get(k)), k
+
+
+@pytest.mark.parametrize("sweeps", [0, 1, 9])
+def test_sweep_counts_match_oracle(sweeps):
+    """The magnetic phase runs in launches of at most four sweeps; any count matches."""
+    prob, st = smooth_case(45, 36, seed=21)
+    prob["sweeps"] = sweeps
+    o, g = pair(prob, st)
+    o.step(1)
+    g.step(1)
+    fl = floors(prob)
+    for name in ("phi", "Mx", "He"):
+        assert rel_l2(g.get(name), o.get(name), fl[name]) < 1e-11, (sweeps, name)
