@@ -148,8 +148,9 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
 /* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
-   per 4 sweeps: permeability, sweeps, residual), the three Runge-Kutta stages (the
-   third also applies Eq. 8 and writes per-tile partial sums) and the reduction. */
+   per 4 sweeps: permeability, sweeps, residual) and the three Runge-Kutta stages
+   (the third also applies Eq. 8 and writes per-tile FP64 partial sums). REDUCE, the
+   reduction of those partials, runs in lbfs_observe and is not timed here. */
 enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUCE, LBFS_NKERNELS };
 
 /* lbfs_step with HIP events recorded on the solver's stream around every kernel

@@ -179,12 +179,12 @@ hipError_t launch_state_part(lbfs_solver* s)
                     : launch_state_partials<float>(s->dinst, s->dtiles_stage, ns, s->stream);
 }
 
-// one time step: magnetic phase, three Runge-Kutta stages, reduction of the observables
+// one time step: magnetic phase and three Runge-Kutta stages (the observables of the
+// state are summed when they are read)
 hipError_t enqueue_step(lbfs_solver* s)
 {
     hipError_t e = launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1);
     for (int st = 1; st <= 3 && e == hipSuccess; st++) e = launch_stage_k(s, st);
-    if (e == hipSuccess) e = launch_reduce(s->dinst, 1, s->stream);
     return e;
 }
 
@@ -526,7 +526,7 @@ int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, dou
     const int nsample = (nsteps + sample_every - 1) / sample_every;
     if (nsample > 4096) return LBFS_E_INVAL;
 
-    const int per_step = 5;
+    const int per_step = 4;
     std::vector<hipEvent_t> ev((size_t)nsample * per_step * 2, nullptr);
     std::vector<int> kind((size_t)nsample * per_step, 0);
     for (auto& e : ev)
@@ -558,7 +558,6 @@ int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, dou
             e = timed(LBFS_K_MAG, on, [&] { return launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1); });
             for (int st = 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, on, [&] { return launch_stage_k(s, st); });
-            if (e == hipSuccess) e = timed(LBFS_K_REDUCE, on, [&] { return launch_reduce(s->dinst, 1, s->stream); });
         } else {
             e = run_step(s);
         }
@@ -592,6 +591,8 @@ int lbfs_observe(lbfs_solver* s, lbfs_observables* o)
 {
     if (!s || !o) return s ? LBFS_E_INVAL : LBFS_E_STATE;
     if (s->stepped_since_observe) {
+        HIPCHK(launch_state_part(s));
+        HIPCHK(launch_reduce(s->dinst, 1, s->stream));
         HIPCHK(hipMemcpyAsync(s->hres, s->hinst.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         s->stepped_since_observe = false;

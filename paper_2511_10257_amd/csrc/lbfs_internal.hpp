@@ -11,18 +11,21 @@
 
 namespace lbfs {
 
-// stage tile shapes (cells); one thread per cell
-constexpr int STAGE_TX_F32 = 16, STAGE_TY_F32 = 16;
-constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8;
+// stage tile shapes (cells) and workgroup sizes: enough threads for the tile plus its
+// 3-cell halo (22 x 22 = 484 / 22 x 14 = 308) and for all faces of the tile
+// (544 / 280) in one round
+constexpr int STAGE_TX_F32 = 16, STAGE_TY_F32 = 16, STAGE_NT_F32 = 576;
+constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8, STAGE_NT_F64 = 320;
 // fused magnetic kernel: interior tile shapes (256 threads) and the sweeps one launch
 // can do (LDS halo 2*MAG_KMAX+1)
 constexpr int MAG_KMAX = 4;
-constexpr int MAG_SMALL_TX = 32, MAG_SMALL_TY = 8;
-constexpr int MAG_BIG_TX = 64, MAG_BIG_TY = 16;
+// (workgroup sizes: one round per colour pass over the 50 x 26 / 82 x 34 region)
+constexpr int MAG_SMALL_TX = 32, MAG_SMALL_TY = 8, MAG_SMALL_NT = 704;
+constexpr int MAG_BIG_TX = 64, MAG_BIG_TY = 16, MAG_BIG_NT = 1024;
 // pointwise kernels (init, derived fields): one thread per cell
 constexpr int PT_TX = 64, PT_TY = 4;
 
-// per-tile partial sums written by the last Runge-Kutta stage (FP64)
+// per-tile partial sums of the observables of a state (FP64)
 enum { PART_CT = 0, PART_CTFL, PART_FS, PART_UMAX, PART_NONFINITE, PART_UDROP, PART_HEIGHT,
        PART_HEAT, NPART };
 // per-instance results written by the reduction (FP64)

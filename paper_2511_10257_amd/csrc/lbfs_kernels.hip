@@ -1,12 +1,13 @@
 // lbfs_kernels.hip -- gfx950 kernels of the enthalpy LBFS time step.
 //
 // Kernels (all driven by tile lists, see lbfs_internal.hpp):
-//   k_stage<T,TX,TY,STAGE>  fused Runge-Kutta stage: LDS-staged halo of the cell
+//   k_stage<T,TX,TY,NT,ST>  fused Runge-Kutta stage: LDS-staged halo of the cell
 //                           fields, Eq. 8 / Eq. 11 derived fields, chemical potential,
 //                           central gradients, Kelvin force, LBFS fluxes of every face
 //                           of the tile, sources (Eq. 41), residual (Eq. 42) and the
 //                           SSP-RK3 combination (Eq. 46); the last stage also applies
-//                           Eq. 8 for the lagged dFs/dt and writes FP64 partial sums.
+//                           Eq. 8 for the lagged dFs/dt.
+//   k_state_partials        FP64 per-tile partial sums of the observables of a state.
 //   k_mag_fused             permeability (Eq. 2 with Eq. 11), red-black sweeps of the
 //                           compact magnetic system (temporally blocked in LDS) and
 //                           the FP64 residual.
@@ -223,7 +224,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int n)
 
 enum { Q_P = 0, Q_U, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_MU, Q_LAM, Q_CP, Q_PHI, NQ };
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, int NT>
 struct StageLds {
     static constexpr int RX = TX + 6, RY = TY + 6, NR = RX * RY;   // tile + 3
     static constexpr int GX = TX + 2, GY = TY + 2, NG = GX * GY;   // tile + 1
@@ -234,7 +235,6 @@ struct StageLds {
     T h2[NG];           // |H|^2
     T fx[5][NFX];
     T fy[5][NFY];
-    double red[NPART][TX * TY / 64];
 };
 
 // gather one side of a face from LDS; axis 0: x-face (n = x, t = y), 1: y-face
@@ -365,12 +365,14 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
     }
 }
 
-template <typename T, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ insts,
-                                                  const Tile* __restrict__ tiles, int pidx)
+// NT >= every per-tile work count (halo cells, gradient cells, faces), so each phase
+// is one round; the first TX*TY threads own the tile's cells.
+template <typename T, int TX, int TY, int NT, int STAGE>
+__global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
+                                              const Tile* __restrict__ tiles, int pidx)
 {
-    using L = StageLds<T, TX, TY>;
-    constexpr int NT = TX * TY;
+    using L = StageLds<T, TX, TY, NT>;
+    static_assert(NT % 64 == 0 && NT >= TX * TY, "whole waves, one thread per cell at least");
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
@@ -385,6 +387,20 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
                   : STAGE == 3 ? reinterpret_cast<T* const*>(I.W2) : Wbase;
     const GLOBAL T* phi = gp<T>(I.phi[pidx]);
 
+    // cell owned by this thread (phase E); its point values are fetched now so that the
+    // loads overlap the halo phases
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool inside = tid < TX * TY && gx < nx && gy < ny;
+    const size_t o = inside ? (size_t)gy * pitch + gx : 0;
+    T cWin[5], cWb[5], cS = T(0);
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        cWin[k] = STAGE >= 1 ? gp<T>(Win[k])[o] : T(0);
+        cWb[k] = STAGE >= 2 ? gp<T>(Wbase[k])[o] : T(0);
+    }
+    cS = gp<T>(I.S)[o];
+
     // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image); every load of
     //      this thread is issued before the first one is used
     {
@@ -395,19 +411,18 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             const int rr = r < L::NR ? r : L::NR - 1;
-            const int lx = rr % L::RX, ly = rr / L::RX;
-            const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+            const int hx = x0 - 3 + rr % L::RX, hy = y0 - 3 + rr / L::RX;
             int wx, wy;
-            const int sx = map_axis(gx, nx, I.per_x, 0, 1, wx);
-            const int sy = map_axis(gy, ny, I.per_y, 2, 3, wy);
+            const int sx = map_axis(hx, nx, I.per_x, 0, 1, wx);
+            const int sy = map_axis(hy, ny, I.per_y, 2, 3, wy);
             vwx[it] = wx;
             vwy[it] = wy;
-            vdx[it] = sx - gx;
-            vdy[it] = sy - gy;
-            const size_t o = (size_t)sy * pitch + sx;
+            vdx[it] = sx - hx;
+            vdy[it] = sy - hy;
+            const size_t oh = (size_t)sy * pitch + sx;
 #pragma unroll
-            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[o];
-            vph[it] = phi[o];
+            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            vph[it] = phi[oh];
         }
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
@@ -544,12 +559,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
     __syncthreads();
 
     // ---- E: residual, sources, Runge-Kutta stage
-    const int lx = tid % TX, ly = tid / TX;
-    const int gx = x0 + lx, gy = y0 + ly;
-    const bool inside = gx < nx && gy < ny;
-    double pr[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (inside) {
-        const size_t o = (size_t)gy * pitch + gx;
         const int r = (ly + 3) * L::RX + (lx + 3);
         const int gi = (ly + 1) * L::GX + (lx + 1);
         const T dt = T(I.dt);
@@ -557,7 +567,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
         if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
-        else { Cn = gp<T>(Wbase[4])[o]; Hen = gp<T>(Wbase[0])[o]; }
+        else { Cn = cWb[4]; Hen = cWb[0]; }
         T Tn, Fln;
         enthalpy_state<T>(I, Hen, Cn, Tn, Fln);
         const T ctn = clamp01(Cn);
@@ -577,7 +587,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
         T Tc, Flc;
         enthalpy_state<T>(I, s.q[Q_HE][r], c, Tc, Flc);
         const T fs = clamp01(c) * (T(1) - Flc);
-        const T Sv = gp<T>(I.S)[o];
+        const T Sv = cS;
         const T vc = T(I.vc);
         T src[5];
         src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
@@ -597,16 +607,16 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
             for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = Rk[k];
         } else if (STAGE == 1) {
 #pragma unroll
-            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = gp<T>(Win[k])[o] + dt * Rk[k];
+            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = cWin[k] + dt * Rk[k];
         } else if (STAGE == 2) {
 #pragma unroll
             for (int k = 0; k < 5; k++)
-                gp<T>(I.W2[k])[o] = T(0.75) * gp<T>(Wbase[k])[o] + T(0.25) * (gp<T>(Win[k])[o] + dt * Rk[k]);
+                gp<T>(I.W2[k])[o] = T(0.75) * cWb[k] + T(0.25) * (cWin[k] + dt * Rk[k]);
         } else {
             T Wn[5];
 #pragma unroll
             for (int k = 0; k < 5; k++) {
-                Wn[k] = gp<T>(Wbase[k])[o] * T(1.0 / 3.0) + T(2.0 / 3.0) * (gp<T>(Win[k])[o] + dt * Rk[k]);
+                Wn[k] = cWb[k] * T(1.0 / 3.0) + T(2.0 / 3.0) * (cWin[k] + dt * Rk[k]);
                 gp<T>(Wbase[k])[o] = Wn[k];
             }
             // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
@@ -614,10 +624,8 @@ __global__ __launch_bounds__(TX* TY) void k_stage(const DevInst* __restrict__ in
             enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
             const T ct1 = clamp01(Wn[4]);
             gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) / dt;
-            cell_partials<T>(I, Wn, gx, gy, pr);
         }
     }
-    if (STAGE == 3) block_partials<NT>(pr, s.red, tid, I.part + (size_t)tile.idx * NPART);
 }
 
 template <typename T>
@@ -627,13 +635,14 @@ hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* t
     constexpr bool f32 = sizeof(T) == 4;
     constexpr int TX = f32 ? STAGE_TX_F32 : STAGE_TX_F64;
     constexpr int TY = f32 ? STAGE_TY_F32 : STAGE_TY_F64;
+    constexpr int NT = f32 ? STAGE_NT_F32 : STAGE_NT_F64;
     if (ntiles <= 0) return hipSuccess;
-    dim3 grid(ntiles), block(TX * TY);
+    dim3 grid(ntiles), block(NT);
     switch (stage) {
-    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, 0>), grid, block, 0, stream, insts, tiles, pidx); break;
-    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, 1>), grid, block, 0, stream, insts, tiles, pidx); break;
-    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, 2>), grid, block, 0, stream, insts, tiles, pidx); break;
-    default: hipLaunchKernelGGL((k_stage<T, TX, TY, 3>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 0>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 1>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 2>), grid, block, 0, stream, insts, tiles, pidx); break;
+    default: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 3>), grid, block, 0, stream, insts, tiles, pidx); break;
     }
     return hipGetLastError();
 }
@@ -695,16 +704,16 @@ struct MagLds {
     T wn[NR];         // weight of the north face
     T b[NR];          // sum_f a_f (phi0_nb - phi0_c): the applied-field part of the numerator
     T rden[NR];       // 1 / sum_f a_f (0: cell not updated)
-    double red[4];
+    double red[16];
 };
 
-template <typename T, int MTX, int MTY>
-__global__ __launch_bounds__(256) void k_mag_fused(const DevInst* __restrict__ insts,
-                                                   const Tile* __restrict__ tiles, int nsweeps, double omega,
-                                                   int residual, int pin)
+template <typename T, int MTX, int MTY, int NT>
+__global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ insts,
+                                                  const Tile* __restrict__ tiles, int nsweeps, double omega,
+                                                  int residual, int pin)
 {
     using L = MagLds<T, MTX, MTY>;
-    constexpr int NT = 256;
+    static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
     constexpr int NIT = (L::NR + NT - 1) / NT;
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
@@ -851,7 +860,11 @@ __global__ __launch_bounds__(256) void k_mag_fused(const DevInst* __restrict__ i
         r2 = wave_sum(r2);
         if (tid % 64 == 0) s.red[tid / 64] = r2;
         __syncthreads();
-        if (tid == 0) I.mpart[tile.idx] = s.red[0] + s.red[1] + s.red[2] + s.red[3];
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int w = 0; w < NT / 64; w++) acc += s.red[w];
+            I.mpart[tile.idx] = acc;
+        }
     }
 }
 
@@ -868,11 +881,11 @@ hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pid
         nsweeps -= k;
         const int res = residual && nsweeps == 0;
         if (big)
-            hipLaunchKernelGGL((k_mag_fused<T, MAG_BIG_TX, MAG_BIG_TY>), dim3(ntiles), dim3(256), 0, stream, insts,
-                               tiles, k, omega, res, *pidx);
+            hipLaunchKernelGGL((k_mag_fused<T, MAG_BIG_TX, MAG_BIG_TY, MAG_BIG_NT>), dim3(ntiles), dim3(MAG_BIG_NT),
+                               0, stream, insts, tiles, k, omega, res, *pidx);
         else
-            hipLaunchKernelGGL((k_mag_fused<T, MAG_SMALL_TX, MAG_SMALL_TY>), dim3(ntiles), dim3(256), 0, stream,
-                               insts, tiles, k, omega, res, *pidx);
+            hipLaunchKernelGGL((k_mag_fused<T, MAG_SMALL_TX, MAG_SMALL_TY, MAG_SMALL_NT>), dim3(ntiles),
+                               dim3(MAG_SMALL_NT), 0, stream, insts, tiles, k, omega, res, *pidx);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         *pidx ^= 1;
