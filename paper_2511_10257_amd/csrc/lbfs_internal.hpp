@@ -12,9 +12,10 @@
 namespace lbfs {
 
 // stage tile shapes (cells) and workgroup sizes: enough threads for the tile plus its
-// 3-cell halo (22 x 22 = 484 / 22 x 14 = 308) and for all faces of the tile
-// (544 / 280) in one round
-constexpr int STAGE_TX_F32 = 16, STAGE_TY_F32 = 16, STAGE_NT_F32 = 576;
+// 3-cell halo (38 x 14 = 532 / 22 x 14 = 308) and for all faces of the tile
+// (552 / 280) in one round. FP32 tiles are 32 wide so that each half-wave works on
+// one contiguous LDS row (no bank conflicts between rows).
+constexpr int STAGE_TX_F32 = 32, STAGE_TY_F32 = 8, STAGE_NT_F32 = 576;
 constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8, STAGE_NT_F64 = 320;
 // fused magnetic kernel: interior tile shapes (256 threads) and the sweeps one launch
 // can do (LDS halo 2*MAG_KMAX+1)

@@ -51,16 +51,14 @@ __device__ __forceinline__ void enthalpy_state(const DevInst& I, T He, T C, T& T
     const T tm = T(I.tm);
     const T Hes = cps * tm;
     const T Hel = cpl * tm + ct * T(I.latent);
-    if (He > Hel) {
-        Fl = T(1);
-        Tt = tm + (He - Hel) / cpl;
-    } else if (He >= Hes && Hel > Hes) {
-        Fl = (He - Hes) / (Hel - Hes);
-        Tt = tm;
-    } else {
-        Fl = T(0);
-        Tt = He / cps;
-    }
+    // branch of Eq. 8, then the one quotient that branch needs
+    const bool liq = He > Hel;
+    const bool mushy = !liq && He >= Hes && Hel > Hes;
+    const T num = liq ? He - Hel : (mushy ? He - Hes : He);
+    const T den = liq ? cpl : (mushy ? Hel - Hes : cps);
+    const T q = num / den;
+    Fl = liq ? T(1) : (mushy ? q : T(0));
+    Tt = liq ? tm + q : (mushy ? tm : q);
 }
 
 template <typename T>
@@ -153,13 +151,15 @@ __device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, co
         rc[k][8] = L.v[k] + h * L.gt[k];
     }
     const T rho_f = rc[V_RHO][0];
+    const T irho_f = T(1) / rho_f;
     const T mu_f = T(0.5) * (L.mu + R.mu);
     const T lam_f = T(0.5) * (L.lam + R.lam);
     const T cp_f = T(0.5) * (L.cp + R.cp);
     const T cpref = T(I.cpref);
     const T Q = T(I.qg);
-    const T tau_f = T(0.5) + T(3) * mu_f / (rho_f * T(I.dts));
-    const T tau_h = T(0.5) + T(3) * lam_f / (rho_f * cpref * T(I.dts));
+    // tau_f = 1/2 + mu / (rho cs^2 delta_t), tau_h = 1/2 + lambda / (rho Cp,ref cs^2 delta_t)
+    const T tau_f = T(0.5) + mu_f * irho_f * T(3.0 / I.dts);
+    const T tau_h = T(0.5) + lam_f * irho_f * T(3.0 / (I.cpref * I.dts));
     const T tau_g = T(I.tau_g);
 
     // (e_n, e_t) of the nine points in the face frame and their weights
@@ -193,8 +193,8 @@ __device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, co
     }
     // Eq. 45: face state
     const T p_f = S0;
-    const T un_f = T(3) * Sn / rho_f;
-    const T ut_f = T(3) * St / rho_f;
+    const T un_f = T(3) * Sn * irho_f;
+    const T ut_f = T(3) * St * irho_f;
     const T C_f = rc[V_C][0] - T(3) * Q * T(5.0 / 9.0) * rc[V_MUC][0] + Cs;
     const T He_f = rc[V_HE][0] - cpref * rc[V_T][0] + Hs;
     T T_f, Fl_f;
@@ -563,6 +563,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         const int r = (ly + 3) * L::RX + (lx + 3);
         const int gi = (ly + 1) * L::GX + (lx + 1);
         const T dt = T(I.dt);
+        const T idt = T(1.0 / I.dt), idx = T(1.0 / I.dx);
         const T cs2 = T(1.0 / 3.0);
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
@@ -592,14 +593,14 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         T src[5];
         src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
         src[1] = cs2 * (u * drx + v * dry) + rho * cs2 * vc * Sv;
-        src[2] = cs2 * (-c * dmx + fmx + rho * T(I.grav[0]) - rho * u * fs / dt);
-        src[3] = cs2 * (-c * dmy + fmy + rho * T(I.grav[1]) - rho * v * fs / dt);
+        src[2] = cs2 * (-c * dmx + fmx + rho * T(I.grav[0]) - rho * u * fs * idt);
+        src[3] = cs2 * (-c * dmy + fmy + rho * T(I.grav[1]) - rho * v * fs * idt);
         src[4] = c * vc * Sv;
         const int fW = ly * (TX + 1) + lx, fS = ly * TX + lx;
         T Rk[5];
 #pragma unroll
         for (int k = 0; k < 5; k++) {
-            const T div = (s.fx[k][fW + 1] - s.fx[k][fW] + s.fy[k][fS + TX] - s.fy[k][fS]) / dx;
+            const T div = (s.fx[k][fW + 1] - s.fx[k][fW] + s.fy[k][fS + TX] - s.fy[k][fS]) * idx;
             Rk[k] = -div + src[k];
         }
         if (STAGE == 0) {
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             T T1, Fl1;
             enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
             const T ct1 = clamp01(Wn[4]);
-            gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) / dt;
+            gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) * idt;
         }
     }
 }
