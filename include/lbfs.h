@@ -186,8 +186,66 @@ size_t lbfs_checkpoint_bytes(const lbfs_solver* s);
 int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes);
 int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
 
-/* Release the handle (the device buffer stays the caller's). NULL is allowed. */
+/* Release the handle (the device buffer stays the caller's). NULL is allowed; a handle
+   owned by a batch (lbfs_batch_slot) is left alone. */
 void lbfs_destroy(lbfs_solver* s);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (different sizes, fields, Stefan and magnetic Bond numbers)
+ * advanced together: every kernel of a step runs once over the concatenated tiles of
+ * all live instances, so each instance computes exactly what it computes alone (the
+ * same fields, bit for bit) while the launches fill the GPU. Instances are admitted
+ * and retired between steps; their state is carved from one caller-owned device
+ * buffer by a first-fit allocator (no device allocation inside the library). All
+ * instances of a batch share the precision and the per-step magnetic sweeps.
+ * The batch's metadata (descriptors, tile lists, FP64 results) is carved from the same
+ * buffer and grows on admission. A batch handle is not thread safe. */
+
+/* Device bytes one admission takes from the batch buffer for these parameters
+   (its state; the shared metadata grows by about 1 KB per instance); 0 if invalid. */
+size_t lbfs_batch_instance_bytes(const lbfs_params* p);
+
+/* Create an empty batch of at most max_slots instances over dev_buf (bytes, caller
+   owned, alive until lbfs_batch_destroy). precision, sweeps and sor_omega are those
+   every admitted instance must have. stream as in lbfs_init. */
+int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, double sor_omega, void* dev_buf,
+                      size_t bytes, void* stream, lbfs_batch** out);
+
+/* Admit one problem: validate, carve its state, initialise it as lbfs_init does
+   (synchronous). *slot_out receives its slot. LBFS_E_NOMEM when no slot is free or the
+   buffer has no room for it (the batch is unchanged); LBFS_E_INVAL when p does not
+   share the batch's precision, sweeps or sor_omega. */
+int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out);
+
+/* Retire the instance in a slot (after the work already enqueued); its memory and slot
+   become free. */
+int lbfs_batch_retire(lbfs_batch* b, int32_t slot);
+
+/* Enqueue nsteps time steps of every live instance (asynchronous; one HIP graph
+   replay per step on a non-default stream, recaptured after admissions and
+   retirements). */
+int lbfs_batch_step(lbfs_batch* b, int32_t nsteps);
+
+/* lbfs_step_profiled for a batch: mean duration of each kernel phase over all live
+   instances. */
+int lbfs_batch_step_profiled(lbfs_batch* b, int32_t nsteps, int32_t sample_every, double* kernel_ms,
+                             int32_t* launches);
+
+/* Synchronise and fill out[max_slots] and live[max_slots] (1 for an occupied slot;
+   out[k] is zeroed for a free slot). One reduction launch covers all instances.
+   Returns LBFS_E_NONFINITE (outputs filled) if any live instance is non-finite. */
+int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live);
+
+/* Borrow the handle of a live slot for lbfs_read_field, lbfs_write_field, lbfs_rhs,
+   lbfs_observe, lbfs_save_state and lbfs_load_state. lbfs_step, lbfs_step_profiled and
+   lbfs_mag_sweeps on it return LBFS_E_STATE; it is valid until the slot is retired. */
+int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
+
+/* Live instances, cells they hold and free bytes of the buffer (largest free block). */
+int lbfs_batch_info(lbfs_batch* b, int32_t* live, int64_t* cells, size_t* largest_free);
+
+/* Retire everything and release the handle. NULL is allowed. */
+void lbfs_batch_destroy(lbfs_batch* b);
 
 /* Static description of a status code. */
 const char* lbfs_strerror(int status);

@@ -61,30 +61,36 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        dp = C.POINTER(C.c_double)
-        L.orc_new.restype = C.c_void_p
-        L.orc_new.argtypes = [C.POINTER(Params)]
-        L.orc_free.argtypes = [C.c_void_p]
-        L.orc_init.argtypes = [C.c_void_p]
-        L.orc_init.restype = C.c_int
-        L.orc_step.argtypes = [C.c_void_p, C.c_int]
-        L.orc_rhs.argtypes = [C.c_void_p, dp]
-        L.orc_face_fluxes.argtypes = [C.c_void_p, dp, dp]
-        L.orc_get.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_set.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_double]
-        L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Obs)]
-        L.orc_mag_sweeps.argtypes = [C.c_void_p, C.c_int, C.c_double]
-        L.orc_mag_sweeps.restype = C.c_double
-        L.orc_mag_residual.argtypes = [C.c_void_p]
-        L.orc_mag_residual.restype = C.c_double
-        L.orc_lattice.argtypes = [dp, dp, dp]
-        L.orc_enthalpy_state.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp, dp]
-        L.orc_equilibria.argtypes = [C.POINTER(Params)] + [C.c_double] * 9 + [dp, dp, dp]
-        L.orc_params_from_dimless.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double]
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path: str):
+    """Open a build of the oracle source (the FP64 library, or its operation-counting
+    build) and declare the argument types of its API."""
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_new.restype = C.c_void_p
+    L.orc_new.argtypes = [C.POINTER(Params)]
+    L.orc_free.argtypes = [C.c_void_p]
+    L.orc_init.argtypes = [C.c_void_p]
+    L.orc_init.restype = C.c_int
+    L.orc_step.argtypes = [C.c_void_p, C.c_int]
+    L.orc_rhs.argtypes = [C.c_void_p, dp]
+    L.orc_face_fluxes.argtypes = [C.c_void_p, dp, dp]
+    L.orc_get.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_set.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_double]
+    L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Obs)]
+    L.orc_mag_sweeps.argtypes = [C.c_void_p, C.c_int, C.c_double]
+    L.orc_mag_sweeps.restype = C.c_double
+    L.orc_mag_residual.argtypes = [C.c_void_p]
+    L.orc_mag_residual.restype = C.c_double
+    L.orc_lattice.argtypes = [dp, dp, dp]
+    L.orc_enthalpy_state.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp, dp]
+    L.orc_equilibria.argtypes = [C.POINTER(Params)] + [C.c_double] * 9 + [dp, dp, dp]
+    L.orc_params_from_dimless.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double]
+    return L
 
 
 _TBC = {"adiabatic": 0, "fixed": 1}
@@ -143,19 +149,20 @@ def _dp(a: np.ndarray):
 class Oracle:
     """One FP64 CPU solve of a workload description."""
 
-    def __init__(self, prob: dict, init: bool = True):
+    def __init__(self, prob: dict, init: bool = True, library=None):
         self.prob = prob
+        self._L = library if library is not None else lib()
         self.params = make_params(prob)
         self.nx, self.ny = self.params.nx, self.params.ny
-        self._h = lib().orc_new(C.byref(self.params))
+        self._h = self._L.orc_new(C.byref(self.params))
         if not self._h:
             raise ValueError("oracle rejected the parameters")
-        self.init_sweeps = lib().orc_init(self._h) if init else 0
+        self.init_sweeps = self._L.orc_init(self._h) if init else 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_free(h)
+            self._L.orc_free(h)
             self._h = None
 
     @property
@@ -163,45 +170,45 @@ class Oracle:
         return self.nx * self.ny
 
     def step(self, n: int = 1) -> None:
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
 
     def rhs(self) -> np.ndarray:
         out = np.zeros(5 * self.n)
-        lib().orc_rhs(self._h, _dp(out))
+        self._L.orc_rhs(self._h, _dp(out))
         return out.reshape(5, self.ny, self.nx)
 
     def face_fluxes(self):
         fx = np.zeros(5 * (self.nx + 1) * self.ny)
         fy = np.zeros(5 * self.nx * (self.ny + 1))
-        lib().orc_face_fluxes(self._h, _dp(fx), _dp(fy))
+        self._L.orc_face_fluxes(self._h, _dp(fx), _dp(fy))
         return fx.reshape(5, self.ny, self.nx + 1), fy.reshape(5, self.ny + 1, self.nx)
 
     def get(self, name: str) -> np.ndarray:
         out = np.zeros(self.n)
-        lib().orc_get(self._h, FIELDS[name], _dp(out))
+        self._L.orc_get(self._h, FIELDS[name], _dp(out))
         return out.reshape(self.ny, self.nx)
 
     def set(self, name: str, arr) -> None:
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtype=np.float64), (self.ny, self.nx)))
-        lib().orc_set(self._h, FIELDS[name], _dp(a))
+        self._L.orc_set(self._h, FIELDS[name], _dp(a))
 
     def set_state(self, state: dict) -> None:
         for k, v in state.items():
             self.set(k, v)
 
     def set_time(self, t: float, step: float) -> None:
-        lib().orc_set_time(self._h, float(t), float(step))
+        self._L.orc_set_time(self._h, float(t), float(step))
 
     def observe(self) -> dict:
         o = Obs()
-        lib().orc_observe(self._h, C.byref(o))
+        self._L.orc_observe(self._h, C.byref(o))
         return {n: getattr(o, n) for n, _ in Obs._fields_}
 
     def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
-        return lib().orc_mag_sweeps(self._h, int(n), float(omega))
+        return self._L.orc_mag_sweeps(self._h, int(n), float(omega))
 
     def mag_residual(self) -> float:
-        return lib().orc_mag_residual(self._h)
+        return self._L.orc_mag_residual(self._h)
 
 
 def lattice():

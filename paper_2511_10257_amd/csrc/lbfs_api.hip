@@ -8,8 +8,11 @@
 #include "lbfs_internal.hpp"
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -93,7 +96,9 @@ int validate(const lbfs_params* p)
     return LBFS_OK;
 }
 
-Layout make_layout(const lbfs_params* p)
+// small_mag: use the small magnetic tile shape whatever the grid size (instances of a
+// batch share one magnetic launch, hence one tile shape)
+Layout make_layout(const lbfs_params* p, bool small_mag = false)
 {
     Layout L;
     L.esize = p->precision == LBFS_FP64 ? 8 : 4;
@@ -103,7 +108,7 @@ Layout make_layout(const lbfs_params* p)
     const int sty = p->precision == LBFS_FP64 ? STAGE_TY_F64 : STAGE_TY_F32;
     L.tiles_stage_x = (p->nx + stx - 1) / stx;
     L.tiles_stage_y = (p->ny + sty - 1) / sty;
-    L.mag_big = (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0;
+    L.mag_big = !small_mag && (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0;
     L.mag_tx = L.mag_big ? MAG_BIG_TX : MAG_SMALL_TX;
     L.mag_ty = L.mag_big ? MAG_BIG_TY : MAG_SMALL_TY;
     L.tiles_mag_x = (p->nx + L.mag_tx - 1) / L.mag_tx;
@@ -123,6 +128,194 @@ Layout make_layout(const lbfs_params* p)
     return L;
 }
 
+// The launches of one time step over a set of tile lists (one instance for a solver,
+// the concatenated tiles of every live instance for a batch), with the potential
+// buffer parity and the captured graphs of one step per parity.
+struct Exec {
+    bool f64 = false;
+    int mag_big = 0;
+    int sweeps = 4;
+    double omega = 1.0;
+    hipStream_t stream = nullptr;
+    const DevInst* dinst = nullptr;
+    int ninst = 0;
+    const Tile* tiles_stage = nullptr;
+    int nstage = 0;
+    const Tile* tiles_mag = nullptr;
+    int nmag = 0;
+    int phase = 0;                       // potential buffer holding the current phi'
+    bool use_graph = false;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+};
+
+hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
+{
+    return E.f64 ? launch_mag<double>(E.mag_big, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                      E.stream)
+                 : launch_mag<float>(E.mag_big, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                     E.stream);
+}
+
+hipError_t exec_stage(Exec& E, int stage)
+{
+    return E.f64 ? launch_stage<double>(stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream)
+                 : launch_stage<float>(stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream);
+}
+
+hipError_t exec_state_partials(Exec& E)
+{
+    return E.f64 ? launch_state_partials<double>(E.dinst, E.tiles_stage, E.nstage, E.stream)
+                 : launch_state_partials<float>(E.dinst, E.tiles_stage, E.nstage, E.stream);
+}
+
+// one time step: magnetic phase and three Runge-Kutta stages (the observables of the
+// state are summed when they are read)
+hipError_t exec_enqueue_step(Exec& E)
+{
+    hipError_t e = exec_mag(E, E.sweeps, E.omega, 1);
+    for (int st = 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
+    return e;
+}
+
+void exec_drop_graphs(Exec& E)
+{
+    for (int k = 0; k < 2; k++) {
+        if (E.graph_exec[k]) (void)hipGraphExecDestroy(E.graph_exec[k]);
+        if (E.graph[k]) (void)hipGraphDestroy(E.graph[k]);
+        E.graph_exec[k] = nullptr;
+        E.graph[k] = nullptr;
+    }
+}
+
+// capture one time step starting from potential buffer `ph` into a HIP graph (once
+// per buffer); replays cost one launch per step
+hipError_t exec_ensure_graph(Exec& E, int ph)
+{
+    if (E.graph_exec[ph]) return hipSuccess;
+    const int saved = E.phase;
+    E.phase = ph;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(E.stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        E.phase = saved;
+        return e;
+    }
+    e = exec_enqueue_step(E);
+    const hipError_t ec = hipStreamEndCapture(E.stream, &g);
+    E.phase = saved;
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[ph], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        E.graph_exec[ph] = nullptr;
+        return e;
+    }
+    E.graph[ph] = g;
+    return hipSuccess;
+}
+
+// potential-buffer flips of one step (one per magnetic launch)
+int exec_step_flips(const Exec& E)
+{
+    const int launches = E.sweeps == 0 ? 1 : (E.sweeps + MAG_KMAX - 1) / MAG_KMAX;
+    return launches & 1;
+}
+
+// one step, as a graph replay when graphs are on
+hipError_t exec_run_step(Exec& E)
+{
+    if (!E.use_graph) return exec_enqueue_step(E);
+    const int ph = E.phase;
+    hipError_t e = exec_ensure_graph(E, ph);
+    if (e != hipSuccess) return e;
+    e = hipGraphLaunch(E.graph_exec[ph], E.stream);
+    E.phase = ph ^ exec_step_flips(E);
+    return e;
+}
+
+// nsteps steps with HIP events around the kernel phases of every sample_every-th step;
+// after_step() runs on the host after each enqueued step
+template <typename F>
+int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int32_t* launches, F&& after_step)
+{
+    const int nsample = (nsteps + sample_every - 1) / sample_every;
+    if (nsample > 4096) return LBFS_E_INVAL;
+    const int per_step = 4;
+    std::vector<hipEvent_t> ev((size_t)nsample * per_step * 2, nullptr);
+    std::vector<int> kind((size_t)nsample * per_step, 0);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return LBFS_E_DEVICE;
+        }
+    int rc = LBFS_OK;
+    size_t slot = 0;
+    auto timed = [&](int k, auto&& launch) -> hipError_t {
+        kind[slot] = k;
+        hipError_t e = hipEventRecord(ev[2 * slot], E.stream);
+        if (e != hipSuccess) return e;
+        e = launch();
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(ev[2 * slot + 1], E.stream);
+        slot++;
+        return e;
+    };
+    for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
+        hipError_t e;
+        if (n % sample_every == 0) {
+            e = timed(LBFS_K_MAG, [&] { return exec_mag(E, E.sweeps, E.omega, 1); });
+            for (int st = 1; st <= 3 && e == hipSuccess; st++)
+                e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
+        } else {
+            e = exec_run_step(E);
+        }
+        if (e != hipSuccess) rc = LBFS_E_DEVICE;
+        after_step();
+    }
+    if (rc == LBFS_OK && hipStreamSynchronize(E.stream) != hipSuccess) rc = LBFS_E_DEVICE;
+    for (int k = 0; k < LBFS_NKERNELS; k++) {
+        kernel_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (rc == LBFS_OK)
+        for (size_t q = 0; q < slot; q++) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess) {
+                rc = LBFS_E_DEVICE;
+                break;
+            }
+            kernel_ms[kind[q]] += ms;
+            launches[kind[q]] += 1;
+        }
+    for (int k = 0; k < LBFS_NKERNELS; k++)
+        if (launches[k] > 0) kernel_ms[k] /= launches[k];
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// observables of one instance from its FP64 reduction results
+int fill_observables(const lbfs_params& p, double t, int64_t step, double vol0, const double* r,
+                     lbfs_observables* o)
+{
+    const double dA = p.dx * p.dx;
+    std::memset(o, 0, sizeof *o);
+    o->t = t;
+    o->step = step;
+    o->volume = r[RES_CT] * dA;
+    o->volume0 = vol0;
+    o->liquid_fraction = r[RES_CT] > 0.0 ? r[RES_CTFL] / r[RES_CT] : 0.0;
+    o->solid_ratio = vol0 > 0.0 ? r[RES_FS] * dA / vol0 : 0.0;
+    o->mag_residual = std::sqrt(r[RES_MAGR2]);
+    o->umax = r[RES_UMAX];
+    o->umax_drop = r[RES_UDROP];
+    o->height = r[RES_HEIGHT] * p.dx;
+    o->wall_heat = r[RES_HEAT];
+    o->nonfinite = r[RES_NONFINITE] != 0.0 || !std::isfinite(r[RES_CT]) ? 1 : 0;
+    return o->nonfinite ? LBFS_E_NONFINITE : LBFS_OK;
+}
+
 }  // namespace
 
 struct lbfs_solver {
@@ -132,14 +325,10 @@ struct lbfs_solver {
     char* base = nullptr;
     DevInst hinst{};
     DevInst* dinst = nullptr;
-    Tile* dtiles_stage = nullptr;
-    Tile* dtiles_mag = nullptr;
     Tile* dtiles_pt = nullptr;
-    hipGraph_t graph[2] = {nullptr, nullptr};          // one captured step per potential buffer
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-    bool use_graph = true;
-    int phase = 0;                       // potential buffer holding the current phi'
-    int phi_field() const { return phase ? 17 : 15; }
+    Exec E;                              // launches over this instance's own tiles
+    bool batched = false;                // owned by a batch: stepped only by the batch
+    int phi_field() const { return E.phase ? 17 : 15; }
     double* hres = nullptr;      // pinned copy of the results
     void* staging = nullptr;     // pinned field staging (nx*ny elements of 8 bytes)
     double t = 0.0;
@@ -150,48 +339,29 @@ struct lbfs_solver {
     bool f64() const { return p.precision == LBFS_FP64; }
 };
 
-#define HIPCHK(x)                                   \
-    do {                                            \
-        if ((x) != hipSuccess) return LBFS_E_DEVICE; \
+// a failed HIP call: with LBFS_DEBUG=1 in the environment, name it on stderr
+static bool hip_failed(hipError_t e, const char* expr, int line)
+{
+    if (e == hipSuccess) return false;
+    static const int debug = [] {
+        const char* v = std::getenv("LBFS_DEBUG");
+        return v && v[0] == '1' ? 1 : 0;
+    }();
+    if (debug) std::fprintf(stderr, "lbfs: %s failed (lbfs_api.hip:%d): %s\n", expr, line, hipGetErrorString(e));
+    return true;
+}
+#define HIPFAIL(x) hip_failed((x), #x, __LINE__)
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if (HIPFAIL(x)) return LBFS_E_DEVICE;      \
     } while (0)
 
 namespace {
 
-hipError_t launch_mag_phase(lbfs_solver* s, int nsweeps, double omega, int residual)
-{
-    const int nm = s->L.ntile_mag();
-    return s->f64()
-        ? launch_mag<double>(s->L.mag_big, nsweeps, omega, residual, &s->phase, s->dinst, s->dtiles_mag, nm, s->stream)
-        : launch_mag<float>(s->L.mag_big, nsweeps, omega, residual, &s->phase, s->dinst, s->dtiles_mag, nm, s->stream);
-}
-
-hipError_t launch_stage_k(lbfs_solver* s, int stage)
-{
-    const int ns = s->L.ntile_stage();
-    return s->f64() ? launch_stage<double>(stage, s->phase, s->dinst, s->dtiles_stage, ns, s->stream)
-                    : launch_stage<float>(stage, s->phase, s->dinst, s->dtiles_stage, ns, s->stream);
-}
-
-hipError_t launch_state_part(lbfs_solver* s)
-{
-    const int ns = s->L.ntile_stage();
-    return s->f64() ? launch_state_partials<double>(s->dinst, s->dtiles_stage, ns, s->stream)
-                    : launch_state_partials<float>(s->dinst, s->dtiles_stage, ns, s->stream);
-}
-
-// one time step: magnetic phase and three Runge-Kutta stages (the observables of the
-// state are summed when they are read)
-hipError_t enqueue_step(lbfs_solver* s)
-{
-    hipError_t e = launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1);
-    for (int st = 1; st <= 3 && e == hipSuccess; st++) e = launch_stage_k(s, st);
-    return e;
-}
-
 // residual of the magnetic system of the current state, synchronously
 int mag_residual_now(lbfs_solver* s, double* out)
 {
-    HIPCHK(launch_mag_phase(s, 0, 1.0, 1));
+    HIPCHK(exec_mag(s->E, 0, 1.0, 1));
     HIPCHK(launch_reduce(s->dinst, 1, s->stream));
     HIPCHK(hipMemcpyAsync(s->hres, s->hinst.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -314,14 +484,18 @@ size_t lbfs_state_bytes(const lbfs_params* p)
     return make_layout(p).total;
 }
 
-int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, lbfs_solver** out)
+static void destroy_solver(lbfs_solver* s);
+
+// lbfs_init, with the option of the small magnetic tile shape (batch instances)
+static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, bool small_mag,
+                       lbfs_solver** out)
 {
     if (!out) return LBFS_E_INVAL;
     *out = nullptr;
     const int v = validate(p);
     if (v != LBFS_OK) return v;
     if (!dev_buf) return LBFS_E_INVAL;
-    const Layout L = make_layout(p);
+    const Layout L = make_layout(p, small_mag);
     if (bytes < L.total) return LBFS_E_NOMEM;
 
     lbfs_solver* s = new (std::nothrow) lbfs_solver();
@@ -333,11 +507,21 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
     s->stream = static_cast<hipStream_t>(stream);
     s->base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(dev_buf), ALIGN));
     s->dinst = reinterpret_cast<DevInst*>(s->base + L.off_inst);
-    s->dtiles_stage = reinterpret_cast<Tile*>(s->base + L.off_tstage);
-    s->dtiles_mag = reinterpret_cast<Tile*>(s->base + L.off_tmag);
     s->dtiles_pt = reinterpret_cast<Tile*>(s->base + L.off_tpt);
+    Exec& E = s->E;
+    E.f64 = p->precision == LBFS_FP64;
+    E.mag_big = L.mag_big;
+    E.sweeps = p->sweeps;
+    E.omega = p->sor_omega;
+    E.stream = s->stream;
+    E.dinst = s->dinst;
+    E.ninst = 1;
+    E.tiles_stage = reinterpret_cast<Tile*>(s->base + L.off_tstage);
+    E.nstage = L.ntile_stage();
+    E.tiles_mag = reinterpret_cast<Tile*>(s->base + L.off_tmag);
+    E.nmag = L.ntile_mag();
     auto fail = [&](int code) {
-        lbfs_destroy(s);
+        destroy_solver(s);
         return code;
     };
     if (hipHostMalloc(&s->hres, sizeof(double) * NRES, hipHostMallocDefault) != hipSuccess) return fail(LBFS_E_DEVICE);
@@ -409,8 +593,10 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
                 tp.push_back(Tile{0, tx * PT_TX, ty * PT_TY, (int)tp.size()});
     }
     if (hipMemcpyAsync(s->dinst, &I, sizeof I, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->dtiles_stage, ts.data(), sizeof(Tile) * ts.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->dtiles_mag, tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<Tile*>(E.tiles_stage), ts.data(), sizeof(Tile) * ts.size(), hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<Tile*>(E.tiles_mag), tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess ||
         hipMemcpyAsync(s->dtiles_pt, tp.data(), sizeof(Tile) * tp.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_part, 0, L.off_fields - L.off_part, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_fields, 0, L.field_bytes * NFIELDS, s->stream) != hipSuccess ||
@@ -437,7 +623,7 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
     while (r0 > 0.0 && used < p->init_max && r > p->init_tol * r0) {
         int k = s->p.init_check;
         if (used + k > p->init_max) k = p->init_max - used;
-        if (launch_mag_phase(s, k, om, 0) != hipSuccess) return fail(LBFS_E_DEVICE);
+        if (exec_mag(E, k, om, 0) != hipSuccess) return fail(LBFS_E_DEVICE);
         used += k;
         const double r_prev = r;
         if (mag_residual_now(s, &r) != LBFS_OK) return fail(LBFS_E_DEVICE);
@@ -445,72 +631,29 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, l
         if (r > 0.98 * r_prev) break;   // stagnated at the round-off floor of the precision
     }
     // observables of the initial state (also the reference volume A0)
-    if (launch_state_part(s) != hipSuccess || launch_reduce(s->dinst, 1, s->stream) != hipSuccess ||
+    if (exec_state_partials(E) != hipSuccess || launch_reduce(s->dinst, 1, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->hres, I.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
     s->vol0 = s->hres[RES_CT] * p->dx * p->dx;
     s->hres[RES_MAGR2] = r * r;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
-    s->use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
+    E.use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
     *out = s;
     return LBFS_OK;
 }
 
-// capture one time step starting from potential buffer `ph` into a HIP graph (once
-// per buffer); replays cost one launch per step
-static int ensure_graph(lbfs_solver* s, int ph)
+int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, lbfs_solver** out)
 {
-    if (!s->use_graph || s->graph_exec[ph]) return LBFS_OK;
-    const int saved = s->phase;
-    s->phase = ph;
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
-        s->phase = saved;
-        return LBFS_E_DEVICE;
-    }
-    const hipError_t e = enqueue_step(s);
-    const hipError_t ec = hipStreamEndCapture(s->stream, &g);
-    s->phase = saved;
-    if (e != hipSuccess || ec != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return LBFS_E_DEVICE;
-    }
-    if (hipGraphInstantiate(&s->graph_exec[ph], g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        s->graph_exec[ph] = nullptr;
-        return LBFS_E_DEVICE;
-    }
-    s->graph[ph] = g;
-    return LBFS_OK;
-}
-
-// potential-buffer flips of one step (one per magnetic launch)
-static int step_flips(const lbfs_solver* s)
-{
-    const int launches = s->p.sweeps == 0 ? 1 : (s->p.sweeps + MAG_KMAX - 1) / MAG_KMAX;
-    return launches & 1;
-}
-
-// one step, as a graph replay when graphs are on
-static hipError_t run_step(lbfs_solver* s)
-{
-    if (s->use_graph) {
-        const int ph = s->phase;
-        if (ensure_graph(s, ph) != LBFS_OK) return hipErrorUnknown;
-        const hipError_t e = hipGraphLaunch(s->graph_exec[ph], s->stream);
-        s->phase = ph ^ step_flips(s);
-        return e;
-    }
-    return enqueue_step(s);
+    return init_solver(p, dev_buf, bytes, stream, false, out);
 }
 
 int lbfs_step(lbfs_solver* s, int32_t nsteps)
 {
-    if (!s) return LBFS_E_STATE;
+    if (!s || s->batched) return LBFS_E_STATE;
     if (nsteps < 0) return LBFS_E_INVAL;
     for (int n = 0; n < nsteps; n++) {
-        if (run_step(s) != hipSuccess) return LBFS_E_DEVICE;
+        if (exec_run_step(s->E) != hipSuccess) return LBFS_E_DEVICE;
         s->t += s->p.dt;
         s->step += 1;
         s->stepped_since_observe = true;
@@ -521,105 +664,33 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps)
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches)
 {
-    if (!s) return LBFS_E_STATE;
+    if (!s || s->batched) return LBFS_E_STATE;
     if (nsteps < 0 || sample_every < 1 || !kernel_ms || !launches) return LBFS_E_INVAL;
-    const int nsample = (nsteps + sample_every - 1) / sample_every;
-    if (nsample > 4096) return LBFS_E_INVAL;
-
-    const int per_step = 4;
-    std::vector<hipEvent_t> ev((size_t)nsample * per_step * 2, nullptr);
-    std::vector<int> kind((size_t)nsample * per_step, 0);
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto& f : ev)
-                if (f) (void)hipEventDestroy(f);
-            return LBFS_E_DEVICE;
-        }
-    int rc = LBFS_OK;
-    size_t slot = 0;
-    auto timed = [&](int k, bool on, auto&& launch) -> hipError_t {
-        if (on) {
-            kind[slot] = k;
-            hipError_t e = hipEventRecord(ev[2 * slot], s->stream);
-            if (e != hipSuccess) return e;
-        }
-        hipError_t e = launch();
-        if (e != hipSuccess) return e;
-        if (on) {
-            e = hipEventRecord(ev[2 * slot + 1], s->stream);
-            slot++;
-        }
-        return e;
-    };
-    for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
-        const bool on = n % sample_every == 0;
-        hipError_t e;
-        if (on) {
-            e = timed(LBFS_K_MAG, on, [&] { return launch_mag_phase(s, s->p.sweeps, s->p.sor_omega, 1); });
-            for (int st = 1; st <= 3 && e == hipSuccess; st++)
-                e = timed(LBFS_K_STAGE1 + st - 1, on, [&] { return launch_stage_k(s, st); });
-        } else {
-            e = run_step(s);
-        }
-        if (e != hipSuccess) rc = LBFS_E_DEVICE;
+    return exec_profiled(s->E, nsteps, sample_every, kernel_ms, launches, [&] {
         s->t += s->p.dt;
         s->step += 1;
         s->stepped_since_observe = true;
-    }
-    if (rc == LBFS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LBFS_E_DEVICE;
-    for (int k = 0; k < LBFS_NKERNELS; k++) {
-        kernel_ms[k] = 0.0;
-        launches[k] = 0;
-    }
-    if (rc == LBFS_OK)
-        for (size_t q = 0; q < slot; q++) {
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess) {
-                rc = LBFS_E_DEVICE;
-                break;
-            }
-            kernel_ms[kind[q]] += ms;
-            launches[kind[q]] += 1;
-        }
-    for (int k = 0; k < LBFS_NKERNELS; k++)
-        if (launches[k] > 0) kernel_ms[k] /= launches[k];
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    return rc;
+    });
 }
 
 int lbfs_observe(lbfs_solver* s, lbfs_observables* o)
 {
     if (!s || !o) return s ? LBFS_E_INVAL : LBFS_E_STATE;
     if (s->stepped_since_observe) {
-        HIPCHK(launch_state_part(s));
+        HIPCHK(exec_state_partials(s->E));
         HIPCHK(launch_reduce(s->dinst, 1, s->stream));
         HIPCHK(hipMemcpyAsync(s->hres, s->hinst.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         s->stepped_since_observe = false;
     }
-    const double* r = s->hres;
-    const double dA = s->p.dx * s->p.dx;
-    std::memset(o, 0, sizeof *o);
-    o->t = s->t;
-    o->step = s->step;
-    o->volume = r[RES_CT] * dA;
-    o->volume0 = s->vol0;
-    o->liquid_fraction = r[RES_CT] > 0.0 ? r[RES_CTFL] / r[RES_CT] : 0.0;
-    o->solid_ratio = s->vol0 > 0.0 ? r[RES_FS] * dA / s->vol0 : 0.0;
-    o->mag_residual = std::sqrt(r[RES_MAGR2]);
-    o->umax = r[RES_UMAX];
-    o->umax_drop = r[RES_UDROP];
-    o->height = r[RES_HEIGHT] * s->p.dx;
-    o->wall_heat = r[RES_HEAT];
-    o->nonfinite = r[RES_NONFINITE] != 0.0 || !std::isfinite(r[RES_CT]) ? 1 : 0;
-    return o->nonfinite ? LBFS_E_NONFINITE : LBFS_OK;
+    return fill_observables(s->p, s->t, s->step, s->vol0, s->hres, o);
 }
 
 int lbfs_rhs(lbfs_solver* s, double* host_R)
 {
     if (!s) return LBFS_E_STATE;
     if (!host_R) return LBFS_E_INVAL;
-    HIPCHK(launch_stage_k(s, 0));
+    HIPCHK(exec_stage(s->E, 0));
     const size_t n = (size_t)s->p.nx * s->p.ny;
     for (int k = 0; k < 5; k++) {
         const int rc = copy_field_out(s, 5 + k, host_R + k * n);
@@ -631,8 +702,9 @@ int lbfs_rhs(lbfs_solver* s, double* host_R)
 int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* residual)
 {
     if (!s) return LBFS_E_STATE;
+    if (s->batched) return LBFS_E_STATE;   // would flip the potential parity of one batch member
     if (nsweeps < 0 || !(omega > 0.0 && omega < 2.0)) return LBFS_E_INVAL;
-    HIPCHK(launch_mag_phase(s, nsweeps, omega, 0));
+    HIPCHK(exec_mag(s->E, nsweeps, omega, 0));
     double r = 0.0;
     const int rc = mag_residual_now(s, &r);
     if (rc != LBFS_OK) return rc;
@@ -746,17 +818,20 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes)
     return LBFS_OK;
 }
 
-void lbfs_destroy(lbfs_solver* s)
+static void destroy_solver(lbfs_solver* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    for (int k = 0; k < 2; k++) {
-        if (s->graph_exec[k]) (void)hipGraphExecDestroy(s->graph_exec[k]);
-        if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
-    }
+    exec_drop_graphs(s->E);
     if (s->hres) (void)hipHostFree(s->hres);
     if (s->staging) (void)hipHostFree(s->staging);
     delete s;
+}
+
+void lbfs_destroy(lbfs_solver* s)
+{
+    if (!s || s->batched) return;   // batch members are released by lbfs_batch_retire
+    destroy_solver(s);
 }
 
 const char* lbfs_strerror(int status)
@@ -771,6 +846,412 @@ const char* lbfs_strerror(int status)
     case LBFS_E_ABI: return "ABI version mismatch";
     default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// first-fit allocator over [0, size) in ALIGN units, coalescing on free
+struct Arena {
+    std::map<size_t, size_t> free_;   // offset -> length
+    void reset(size_t size)
+    {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+    }
+    bool alloc(size_t len, size_t* off)
+    {
+        len = align_up(len, ALIGN);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= len) {
+                *off = it->first;
+                const size_t rest = it->second - len, at = it->first + len;
+                free_.erase(it);
+                if (rest > 0) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t len)
+    {
+        len = align_up(len, ALIGN);
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (const auto& kv : free_) m = kv.second > m ? kv.second : m;
+        return m;
+    }
+};
+
+struct Slot {
+    lbfs_solver* s = nullptr;
+    size_t off = 0, bytes = 0;
+};
+
+// tiles of one instance for the batch's stage and magnetic lists
+int stage_tiles(const Layout& L) { return L.ntile_stage(); }
+int mag_tiles(const Layout& L) { return L.ntile_mag(); }
+
+}  // namespace
+
+struct lbfs_batch {
+    int32_t max_slots = 0, precision = 0, sweeps = 0;
+    double omega = 1.0;
+    char* base = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    std::vector<Slot> slots;
+    // metadata block: DevInst[max_slots] | results[max_slots][NRES] | stage tiles | magnetic tiles
+    size_t meta_off = 0, meta_bytes = 0;
+    int cap_stage = 0, cap_mag = 0;
+    std::vector<int32_t> compact;   // compact instance index -> slot
+    double* hres = nullptr;         // pinned [max_slots][NRES]
+    bool dirty = true, stepped_since_observe = true;
+    Exec E;
+    DevInst* meta_inst() const { return reinterpret_cast<DevInst*>(base + meta_off); }
+    double* meta_res() const
+    {
+        return reinterpret_cast<double*>(base + meta_off + align_up(sizeof(DevInst) * max_slots, ALIGN));
+    }
+    Tile* meta_stage() const
+    {
+        return reinterpret_cast<Tile*>(reinterpret_cast<char*>(meta_res()) +
+                                       align_up(sizeof(double) * NRES * max_slots, ALIGN));
+    }
+    Tile* meta_mag() const
+    {
+        return reinterpret_cast<Tile*>(reinterpret_cast<char*>(meta_stage()) +
+                                       align_up(sizeof(Tile) * cap_stage, ALIGN));
+    }
+};
+
+namespace {
+
+size_t meta_size(int max_slots, int cap_stage, int cap_mag)
+{
+    return align_up(sizeof(DevInst) * max_slots, ALIGN) + align_up(sizeof(double) * NRES * max_slots, ALIGN) +
+           align_up(sizeof(Tile) * cap_stage, ALIGN) + align_up(sizeof(Tile) * cap_mag, ALIGN);
+}
+
+// make room in the metadata block for need_stage / need_mag tiles (grows by half
+// again, so admissions rarely move it); the old block is released after the stream
+// has drained (a captured graph may still read it)
+int batch_reserve(lbfs_batch* b, int need_stage, int need_mag)
+{
+    if (need_stage <= b->cap_stage && need_mag <= b->cap_mag && b->meta_bytes > 0) return LBFS_OK;
+    const int cs = need_stage > b->cap_stage ? need_stage + need_stage / 2 : b->cap_stage;
+    const int cm = need_mag > b->cap_mag ? need_mag + need_mag / 2 : b->cap_mag;
+    const size_t nb = meta_size(b->max_slots, cs, cm);
+    size_t off = 0;
+    if (!b->arena.alloc(nb, &off)) {
+        // retry at the exact size
+        const size_t nb2 = meta_size(b->max_slots, need_stage, need_mag);
+        if (!b->arena.alloc(nb2, &off)) return LBFS_E_NOMEM;
+        if (HIPFAIL(hipStreamSynchronize(b->stream))) {
+            b->arena.release(off, nb2);
+            return LBFS_E_DEVICE;
+        }
+        if (b->meta_bytes) b->arena.release(b->meta_off, b->meta_bytes);
+        b->meta_off = off;
+        b->meta_bytes = nb2;
+        b->cap_stage = need_stage;
+        b->cap_mag = need_mag;
+        b->dirty = true;
+        return LBFS_OK;
+    }
+    if (HIPFAIL(hipStreamSynchronize(b->stream))) {
+        b->arena.release(off, nb);
+        return LBFS_E_DEVICE;
+    }
+    if (b->meta_bytes) b->arena.release(b->meta_off, b->meta_bytes);
+    b->meta_off = off;
+    b->meta_bytes = nb;
+    b->cap_stage = cs;
+    b->cap_mag = cm;
+    b->dirty = true;
+    return LBFS_OK;
+}
+
+// rebuild the descriptors and tile lists of the live instances and drop the graphs
+int batch_rebuild(lbfs_batch* b)
+{
+    if (!b->dirty) return LBFS_OK;
+    if (HIPFAIL(hipStreamSynchronize(b->stream))) return LBFS_E_DEVICE;
+    exec_drop_graphs(b->E);
+    b->compact.clear();
+    std::vector<DevInst> insts;
+    std::vector<Tile> ts, tm;
+    const int stx = b->precision == LBFS_FP64 ? STAGE_TX_F64 : STAGE_TX_F32;
+    const int sty = b->precision == LBFS_FP64 ? STAGE_TY_F64 : STAGE_TY_F32;
+    for (int k = 0; k < b->max_slots; k++) {
+        lbfs_solver* s = b->slots[k].s;
+        if (!s) continue;
+        const int c = (int)b->compact.size();
+        b->compact.push_back(k);
+        DevInst I = s->hinst;
+        I.result = b->meta_res() + (size_t)NRES * c;
+        insts.push_back(I);
+        const Layout& L = s->L;
+        int idx = 0;
+        for (int ty = 0; ty < L.tiles_stage_y; ty++)
+            for (int tx = 0; tx < L.tiles_stage_x; tx++) ts.push_back(Tile{c, tx * stx, ty * sty, idx++});
+        idx = 0;
+        for (int ty = 0; ty < L.tiles_mag_y; ty++)
+            for (int tx = 0; tx < L.tiles_mag_x; tx++) tm.push_back(Tile{c, tx * L.mag_tx, ty * L.mag_ty, idx++});
+    }
+    if ((int)ts.size() > b->cap_stage || (int)tm.size() > b->cap_mag) return LBFS_E_STATE;
+    if (!insts.empty()) {
+        HIPCHK(hipMemcpyAsync(b->meta_inst(), insts.data(), sizeof(DevInst) * insts.size(), hipMemcpyHostToDevice,
+                              b->stream));
+        HIPCHK(hipMemcpyAsync(b->meta_stage(), ts.data(), sizeof(Tile) * ts.size(), hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->meta_mag(), tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    Exec& E = b->E;
+    E.dinst = b->meta_inst();
+    E.ninst = (int)insts.size();
+    E.tiles_stage = b->meta_stage();
+    E.nstage = (int)ts.size();
+    E.tiles_mag = b->meta_mag();
+    E.nmag = (int)tm.size();
+    b->dirty = false;
+    return LBFS_OK;
+}
+
+void batch_after_step(lbfs_batch* b)
+{
+    for (int k = 0; k < b->max_slots; k++) {
+        lbfs_solver* s = b->slots[k].s;
+        if (!s) continue;
+        s->t += s->p.dt;
+        s->step += 1;
+        s->E.phase = b->E.phase;
+        s->stepped_since_observe = true;
+    }
+    b->stepped_since_observe = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbfs_batch_instance_bytes(const lbfs_params* p)
+{
+    if (validate(p) != LBFS_OK) return 0;
+    return align_up(make_layout(p, true).total, ALIGN);
+}
+
+int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, double sor_omega, void* dev_buf,
+                      size_t bytes, void* stream, lbfs_batch** out)
+{
+    if (!out) return LBFS_E_INVAL;
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > (1 << 16) || !dev_buf) return LBFS_E_INVAL;
+    if (precision != LBFS_FP32 && precision != LBFS_FP64) return LBFS_E_INVAL;
+    if (sweeps < 0 || sweeps > 1000 || !(sor_omega > 0.0 && sor_omega < 2.0)) return LBFS_E_INVAL;
+    lbfs_batch* b = new (std::nothrow) lbfs_batch();
+    if (!b) return LBFS_E_NOMEM;
+    b->max_slots = max_slots;
+    b->precision = precision;
+    b->sweeps = sweeps;
+    b->omega = sor_omega;
+    char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(dev_buf), ALIGN));
+    const size_t lost = (size_t)(base - static_cast<char*>(dev_buf));
+    b->base = base;
+    b->bytes = bytes > lost ? (bytes - lost) / ALIGN * ALIGN : 0;
+    b->arena.reset(b->bytes);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->slots.assign(max_slots, Slot{});
+    Exec& E = b->E;
+    E.f64 = precision == LBFS_FP64;
+    E.mag_big = 0;
+    E.sweeps = sweeps;
+    E.omega = sor_omega;
+    E.stream = b->stream;
+    const char* ng = std::getenv("LBFS_NO_GRAPH");
+    E.use_graph = b->stream != nullptr && !(ng && ng[0] == '1');
+    if (HIPFAIL(hipHostMalloc(&b->hres, sizeof(double) * NRES * max_slots, hipHostMallocDefault))) {
+        delete b;
+        return LBFS_E_DEVICE;
+    }
+    const int rc = batch_reserve(b, 0, 0);
+    if (rc != LBFS_OK) {
+        lbfs_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBFS_OK;
+}
+
+int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
+{
+    if (!b) return LBFS_E_STATE;
+    if (!p || !slot_out) return LBFS_E_INVAL;
+    const int v = validate(p);
+    if (v != LBFS_OK) return v;
+    if (p->precision != b->precision || p->sweeps != b->sweeps || p->sor_omega != b->omega) return LBFS_E_INVAL;
+    int slot = -1;
+    for (int k = 0; k < b->max_slots && slot < 0; k++)
+        if (!b->slots[k].s) slot = k;
+    if (slot < 0) return LBFS_E_NOMEM;
+    const Layout L = make_layout(p, true);
+    int ns = stage_tiles(L), nm = mag_tiles(L);
+    for (const Slot& q : b->slots)
+        if (q.s) {
+            ns += stage_tiles(q.s->L);
+            nm += mag_tiles(q.s->L);
+        }
+    int rc = batch_reserve(b, ns, nm);
+    if (rc != LBFS_OK) return rc;
+    const size_t need = align_up(L.total, ALIGN);
+    size_t off = 0;
+    if (!b->arena.alloc(need, &off)) return LBFS_E_NOMEM;
+    lbfs_solver* s = nullptr;
+    rc = init_solver(p, b->base + off, need, b->stream, true, &s);
+    if (rc != LBFS_OK) {
+        b->arena.release(off, need);
+        return rc;
+    }
+    // bring the potential into the batch's current buffer
+    if (s->E.phase != b->E.phase) {
+        const int from = s->phi_field();
+        s->E.phase = b->E.phase;
+        if (HIPFAIL(hipMemcpyAsync(s->field(s->phi_field()), s->field(from), s->L.field_bytes,
+                                   hipMemcpyDeviceToDevice, b->stream)) ||
+            HIPFAIL(hipStreamSynchronize(b->stream))) {
+            destroy_solver(s);
+            b->arena.release(off, need);
+            return LBFS_E_DEVICE;
+        }
+    }
+    s->batched = true;
+    b->slots[slot] = Slot{s, off, need};
+    b->dirty = true;
+    b->stepped_since_observe = true;
+    *slot_out = slot;
+    return LBFS_OK;
+}
+
+int lbfs_batch_retire(lbfs_batch* b, int32_t slot)
+{
+    if (!b) return LBFS_E_STATE;
+    if (slot < 0 || slot >= b->max_slots) return LBFS_E_INVAL;
+    Slot& q = b->slots[slot];
+    if (!q.s) return LBFS_E_STATE;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    destroy_solver(q.s);
+    b->arena.release(q.off, q.bytes);
+    q = Slot{};
+    b->dirty = true;
+    b->stepped_since_observe = true;
+    return LBFS_OK;
+}
+
+int lbfs_batch_step(lbfs_batch* b, int32_t nsteps)
+{
+    if (!b) return LBFS_E_STATE;
+    if (nsteps < 0) return LBFS_E_INVAL;
+    const int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    if (b->E.ninst == 0) return LBFS_OK;
+    for (int n = 0; n < nsteps; n++) {
+        if (exec_run_step(b->E) != hipSuccess) return LBFS_E_DEVICE;
+        batch_after_step(b);
+    }
+    return LBFS_OK;
+}
+
+int lbfs_batch_step_profiled(lbfs_batch* b, int32_t nsteps, int32_t sample_every, double* kernel_ms,
+                             int32_t* launches)
+{
+    if (!b) return LBFS_E_STATE;
+    if (nsteps < 0 || sample_every < 1 || !kernel_ms || !launches) return LBFS_E_INVAL;
+    const int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    if (b->E.ninst == 0) nsteps = 0;
+    return exec_profiled(b->E, nsteps, sample_every, kernel_ms, launches, [&] { batch_after_step(b); });
+}
+
+int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live)
+{
+    if (!b) return LBFS_E_STATE;
+    if (!out || !live) return LBFS_E_INVAL;
+    int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    const int n = b->E.ninst;
+    if (b->stepped_since_observe && n > 0) {
+        HIPCHK(exec_state_partials(b->E));
+        HIPCHK(launch_reduce(b->E.dinst, n, b->stream));
+        HIPCHK(hipMemcpyAsync(b->hres, b->meta_res(), sizeof(double) * NRES * n, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->stepped_since_observe = false;
+    }
+    rc = LBFS_OK;
+    for (int k = 0; k < b->max_slots; k++) {
+        live[k] = 0;
+        std::memset(&out[k], 0, sizeof out[k]);
+    }
+    for (int c = 0; c < n; c++) {
+        const int k = b->compact[c];
+        lbfs_solver* s = b->slots[k].s;
+        live[k] = 1;
+        if (fill_observables(s->p, s->t, s->step, s->vol0, b->hres + (size_t)NRES * c, &out[k]) != LBFS_OK)
+            rc = LBFS_E_NONFINITE;
+    }
+    return rc;
+}
+
+int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out)
+{
+    if (!b) return LBFS_E_STATE;
+    if (!out || slot < 0 || slot >= b->max_slots) return LBFS_E_INVAL;
+    *out = b->slots[slot].s;
+    return *out ? LBFS_OK : LBFS_E_STATE;
+}
+
+int lbfs_batch_info(lbfs_batch* b, int32_t* live, int64_t* cells, size_t* largest_free)
+{
+    if (!b) return LBFS_E_STATE;
+    int32_t n = 0;
+    int64_t c = 0;
+    for (const Slot& q : b->slots)
+        if (q.s) {
+            n++;
+            c += (int64_t)q.s->p.nx * q.s->p.ny;
+        }
+    if (live) *live = n;
+    if (cells) *cells = c;
+    if (largest_free) *largest_free = b->arena.largest();
+    return LBFS_OK;
+}
+
+void lbfs_batch_destroy(lbfs_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    exec_drop_graphs(b->E);
+    for (Slot& q : b->slots)
+        if (q.s) destroy_solver(q.s);
+    if (b->hres) (void)hipHostFree(b->hres);
+    delete b;
 }
 
 }  // extern "C"

@@ -29,6 +29,9 @@ EXPORTS = (
     "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
+    "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
+    "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_observe", "lbfs_batch_slot",
+    "lbfs_batch_info", "lbfs_batch_destroy",
 )
 
 
@@ -75,6 +78,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime under the same soname as the system one that
+        # liblbfs.so links against; loading torch first makes both use that one runtime
+        # (two runtimes in one process do not share devices, streams or memory)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, dp, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int32
         sig = {
@@ -95,6 +102,16 @@ def lib():
             "lbfs_load_state": (C.c_int, [vp, vp, C.c_size_t]),
             "lbfs_destroy": (None, [vp]),
             "lbfs_strerror": (C.c_char_p, [C.c_int]),
+            "lbfs_batch_instance_bytes": (C.c_size_t, [C.POINTER(Params)]),
+            "lbfs_batch_create": (C.c_int, [i32, i32, i32, C.c_double, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "lbfs_batch_admit": (C.c_int, [vp, C.POINTER(Params), C.POINTER(C.c_int32)]),
+            "lbfs_batch_retire": (C.c_int, [vp, i32]),
+            "lbfs_batch_step": (C.c_int, [vp, i32]),
+            "lbfs_batch_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
+            "lbfs_batch_observe": (C.c_int, [vp, C.POINTER(Observables), C.POINTER(C.c_uint8)]),
+            "lbfs_batch_slot": (C.c_int, [vp, i32, C.POINTER(vp)]),
+            "lbfs_batch_info": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "lbfs_batch_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -179,70 +196,27 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-class Solver:
-    """One LBFS solve resident on a ROCm device; state lives in a torch uint8 buffer."""
+class _Instance:
+    """Calls on one instance handle (owned by a Solver, or borrowed from a Batch slot)."""
 
-    def __init__(self, prob, device: str = "cuda:0", stream=None):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("the LBFS solver needs a ROCm GPU (torch.cuda.is_available() is False)")
-        self.params = prob if isinstance(prob, Params) else make_params(prob)
-        self.nx, self.ny = self.params.nx, self.params.ny
-        nbytes = int(lib().lbfs_state_bytes(C.byref(self.params)))
-        if nbytes == 0:
-            raise LbfsError(LBFS_E_INVAL, "lbfs_state_bytes")
-        self.device = torch.device(device)
-        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        # a stream of its own (default priority) so that a step can be replayed as a graph
-        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-        h = C.c_void_p()
-        with torch.cuda.device(self.device):
-            _check(lib().lbfs_init(C.byref(self.params), C.c_void_p(self.buffer.data_ptr()), nbytes,
-                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfs_init")
-        self._h = h
+    _h = None
+    nx = ny = 0
 
     @property
     def n(self) -> int:
         return self.nx * self.ny
-
-    def close(self) -> None:
-        if getattr(self, "_h", None):
-            lib().lbfs_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    def step(self, n: int = 1) -> None:
-        _check(lib().lbfs_step(self._h, int(n)), "lbfs_step")
-
-    def step_profiled(self, n: int, sample_every: int = 10) -> dict:
-        """Steps with HIP events around the kernels of every sample_every-th step;
-        returns {kernel kind: (mean ms per launch, timed launches)}."""
-        ms = (C.c_double * NKERNELS)()
-        cnt = (C.c_int32 * NKERNELS)()
-        _check(lib().lbfs_step_profiled(self._h, int(n), int(sample_every), ms, cnt), "lbfs_step_profiled")
-        return {KERNELS[k]: (ms[k], cnt[k]) for k in range(NKERNELS)}
 
     def observe(self, allow_nonfinite: bool = False) -> dict:
         o = Observables()
         st = lib().lbfs_observe(self._h, C.byref(o))
         if not (st == LBFS_OK or (allow_nonfinite and st == LBFS_E_NONFINITE)):
             _check(st, "lbfs_observe")
-        return {n: getattr(o, n) for n, _ in Observables._fields_}
+        return _obs_dict(o)
 
     def rhs(self) -> np.ndarray:
         out = np.zeros(5 * self.n)
         _check(lib().lbfs_rhs(self._h, _dp(out)), "lbfs_rhs")
         return out.reshape(5, self.ny, self.nx)
-
-    def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
-        r = C.c_double()
-        _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
-        return r.value
 
     def get(self, name: str) -> np.ndarray:
         out = np.zeros(self.n)
@@ -270,3 +244,152 @@ class Solver:
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().lbfs_load_state(self._h, buf, len(blob)), "lbfs_load_state")
 
+
+def _obs_dict(o: Observables) -> dict:
+    return {n: getattr(o, n) for n, _ in Observables._fields_}
+
+
+def _kernel_times(ms, cnt) -> dict:
+    return {KERNELS[k]: (ms[k], cnt[k]) for k in range(NKERNELS)}
+
+
+class Solver(_Instance):
+    """One LBFS solve resident on a ROCm device; state lives in a torch uint8 buffer."""
+
+    def __init__(self, prob, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the LBFS solver needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.params = prob if isinstance(prob, Params) else make_params(prob)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = int(lib().lbfs_state_bytes(C.byref(self.params)))
+        if nbytes == 0:
+            raise LbfsError(LBFS_E_INVAL, "lbfs_state_bytes")
+        self.device = torch.device(device)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # a stream of its own (default priority) so that a step can be replayed as a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().lbfs_init(C.byref(self.params), C.c_void_p(self.buffer.data_ptr()), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfs_init")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lbfs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1) -> None:
+        _check(lib().lbfs_step(self._h, int(n)), "lbfs_step")
+
+    def step_profiled(self, n: int, sample_every: int = 10) -> dict:
+        """Steps with HIP events around the kernels of every sample_every-th step;
+        returns {kernel kind: (mean ms per launch, timed launches)}."""
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        _check(lib().lbfs_step_profiled(self._h, int(n), int(sample_every), ms, cnt), "lbfs_step_profiled")
+        return _kernel_times(ms, cnt)
+
+    def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
+        r = C.c_double()
+        _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
+        return r.value
+
+
+class _SlotView(_Instance):
+    """Borrowed handle of a batch slot (valid until the slot is retired)."""
+
+    def __init__(self, handle, nx: int, ny: int):
+        self._h, self.nx, self.ny = handle, nx, ny
+
+
+class Batch:
+    """Many independent solves advanced by the same launches (lbfs_batch_*); the state of
+    every instance is carved from one torch uint8 buffer of `nbytes` bytes."""
+
+    def __init__(self, max_slots: int, nbytes: int, precision: str = "fp32", sweeps: int = 4,
+                 omega: float = 1.0, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the LBFS batch needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.max_slots = int(max_slots)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.buffer = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._dims = {}
+        h = C.c_void_p()
+        prec = LBFS_FP64 if precision == "fp64" else LBFS_FP32
+        with torch.cuda.device(self.device):
+            _check(lib().lbfs_batch_create(self.max_slots, prec, int(sweeps), float(omega),
+                                           C.c_void_p(self.buffer.data_ptr()), int(nbytes),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfs_batch_create")
+        self._h = h
+
+    @staticmethod
+    def instance_bytes(prob) -> int:
+        p = prob if isinstance(prob, Params) else make_params(prob)
+        return int(lib().lbfs_batch_instance_bytes(C.byref(p)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lbfs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, prob):
+        """Admit a problem; returns its slot, or None when the batch has no room."""
+        p = prob if isinstance(prob, Params) else make_params(prob)
+        slot = C.c_int32(-1)
+        st = lib().lbfs_batch_admit(self._h, C.byref(p), C.byref(slot))
+        if st == LBFS_E_NOMEM:
+            return None
+        _check(st, "lbfs_batch_admit")
+        self._dims[slot.value] = (p.nx, p.ny)
+        return slot.value
+
+    def retire(self, slot: int) -> None:
+        _check(lib().lbfs_batch_retire(self._h, int(slot)), "lbfs_batch_retire")
+        self._dims.pop(int(slot), None)
+
+    def step(self, n: int = 1) -> None:
+        _check(lib().lbfs_batch_step(self._h, int(n)), "lbfs_batch_step")
+
+    def step_profiled(self, n: int, sample_every: int = 10) -> dict:
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        _check(lib().lbfs_batch_step_profiled(self._h, int(n), int(sample_every), ms, cnt),
+               "lbfs_batch_step_profiled")
+        return _kernel_times(ms, cnt)
+
+    def observe(self, allow_nonfinite: bool = False) -> dict:
+        """{slot: observables} of the live instances."""
+        out = (Observables * self.max_slots)()
+        live = (C.c_uint8 * self.max_slots)()
+        st = lib().lbfs_batch_observe(self._h, out, live)
+        if not (st == LBFS_OK or (allow_nonfinite and st == LBFS_E_NONFINITE)):
+            _check(st, "lbfs_batch_observe")
+        return {k: _obs_dict(out[k]) for k in range(self.max_slots) if live[k]}
+
+    def slot(self, k: int) -> _SlotView:
+        h = C.c_void_p()
+        _check(lib().lbfs_batch_slot(self._h, int(k), C.byref(h)), "lbfs_batch_slot")
+        nx, ny = self._dims[int(k)]
+        return _SlotView(h, nx, ny)
+
+    def info(self) -> dict:
+        n, c, f = C.c_int32(), C.c_int64(), C.c_size_t()
+        _check(lib().lbfs_batch_info(self._h, C.byref(n), C.byref(c), C.byref(f)), "lbfs_batch_info")
+        return {"live": n.value, "cells": c.value, "largest_free": f.value}

@@ -81,3 +81,28 @@ def test_oracle_and_product_read_the_same_problem():
         assert list(a.tbc) == list(b.thermal_bc) and list(a.mbc) == list(b.mag_bc)
         assert list(a.tval) == list(b.thermal_val) and list(a.periodic) == list(b.periodic)
         assert a.sweeps == b.sweeps and a.omega == b.sor_omega
+
+
+def test_batch_host_checks():
+    """Host-side checks of the batch calls (no device work is reached)."""
+    p = lbfs.make_params(wl.config1())
+    nb = lbfs.lib().lbfs_batch_instance_bytes(C.byref(p))
+    # the same fields as a solver; the magnetic tile lists of the small shape
+    assert lbfs.state_bytes(p) <= nb < lbfs.state_bytes(p) + 64 * 1024
+    big = lbfs.make_params(wl.config2("fp32"))
+    # 1024^2 uses the large magnetic tiles alone, the small ones in a batch (more tiles)
+    assert lbfs.lib().lbfs_batch_instance_bytes(C.byref(big)) > lbfs.state_bytes(big)
+    q = lbfs.make_params(wl.config0())
+    q.nx = 2
+    assert lbfs.lib().lbfs_batch_instance_bytes(C.byref(q)) == 0
+    out = C.c_void_p()
+    L = lbfs.lib()
+    assert L.lbfs_batch_create(0, 0, 4, 1.0, C.c_void_p(1), 1 << 20, None, C.byref(out)) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_batch_create(4, 3, 4, 1.0, C.c_void_p(1), 1 << 20, None, C.byref(out)) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_batch_create(4, 0, 4, 2.5, C.c_void_p(1), 1 << 20, None, C.byref(out)) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_batch_create(4, 0, 4, 1.0, None, 1 << 20, None, C.byref(out)) == lbfs.LBFS_E_INVAL
+    slot = C.c_int32()
+    assert L.lbfs_batch_admit(None, C.byref(p), C.byref(slot)) == lbfs.LBFS_E_STATE
+    assert L.lbfs_batch_step(None, 1) == lbfs.LBFS_E_STATE
+    assert L.lbfs_batch_retire(None, 0) == lbfs.LBFS_E_STATE
+    L.lbfs_batch_destroy(None)
