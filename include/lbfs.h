@@ -186,6 +186,35 @@ size_t lbfs_checkpoint_bytes(const lbfs_solver* s);
 int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes);
 int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
 
+/* ------------------------------------------------------------------ tile shapes
+ * Every kernel works on a list of rectangular tiles. The stage kernels and the magnetic
+ * kernel each have a small table of candidate tile shapes (cells per tile and threads
+ * per workgroup); the results do not depend on the shape (each cell and face is
+ * computed by the same arithmetic), only the time does. The first shape of each table
+ * is the default (the magnetic kernel takes its second shape above 512 x 512 cells). */
+
+#define LBFS_MAX_SHAPES 8
+
+/* kind 0: stage kernels, 1: magnetic kernel. With index < 0 returns the number of
+   shapes of that kind; otherwise writes the tile (tx x ty cells) and the workgroup
+   size (threads) of shape `index`. */
+int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads);
+
+/* Use the given shapes from the next launch on (a changed magnetic shape recomputes the
+   residual as lbfs_autotune does). Synchronous. */
+int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape);
+
+/* Autotuner: time every stage shape (reps launches of the right-hand-side kernel, which
+   leaves the state unchanged) and then every magnetic shape (reps magnetic phases of a
+   step, on the current potential, which is restored afterwards) on this solver's
+   current state, and keep the fastest of each. chosen[2] receives the indices,
+   ms[2*LBFS_MAX_SHAPES] the mean ms per launch (stage shapes first, magnetic shapes
+   from index LBFS_MAX_SHAPES; either may be NULL). The state is unchanged; until the
+   next step, mag_residual then reports the residual of the current potential with the
+   current permeability (a step reports it with the permeability of the step's start).
+   Synchronous. */
+int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms);
+
 /* Release the handle (the device buffer stays the caller's). NULL is allowed; a handle
    owned by a batch (lbfs_batch_slot) is left alone. */
 void lbfs_destroy(lbfs_solver* s);
@@ -240,6 +269,11 @@ int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live);
    lbfs_observe, lbfs_save_state and lbfs_load_state. lbfs_step, lbfs_step_profiled and
    lbfs_mag_sweeps on it return LBFS_E_STATE; it is valid until the slot is retired. */
 int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
+
+/* lbfs_set_tile_shapes and lbfs_autotune for a batch: one shape pair for all live
+   instances (and those admitted later), timed on the concatenated tiles. */
+int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape, int32_t mag_shape);
+int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms);
 
 /* Live instances, cells they hold and free bytes of the buffer (largest free block). */
 int lbfs_batch_info(lbfs_batch* b, int32_t* live, int64_t* cells, size_t* largest_free);

@@ -26,15 +26,26 @@ constexpr uint32_t CKPT_MAGIC = 0x5346424cu;   // "LBFS"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+int tiles_of(int n, int t) { return (n + t - 1) / t; }
+int count_tiles(int nx, int ny, TileShape S) { return tiles_of(nx, S.tx) * tiles_of(ny, S.ty); }
+
+// tiles of one instance (inst: its index in the descriptor array), row-major order;
+// idx numbers them inside the instance (the slot of its partial sums)
+void append_tiles(std::vector<Tile>& out, int inst, int nx, int ny, TileShape S)
+{
+    int idx = 0;
+    for (int ty = 0; ty < tiles_of(ny, S.ty); ty++)
+        for (int tx = 0; tx < tiles_of(nx, S.tx); tx++) out.push_back(Tile{inst, tx * S.tx, ty * S.ty, idx++});
+}
+
+// Segments of one instance's state. Tile lists and partial sums have room for the
+// largest tile count of any candidate shape, so the tile shapes can change at run time.
 struct Layout {
     int pitch = 0;
     size_t esize = 0, field_bytes = 0;
-    int tiles_stage_x = 0, tiles_stage_y = 0, tiles_mag_x = 0, tiles_mag_y = 0, tiles_pt_x = 0, tiles_pt_y = 0;
-    int mag_big = 0, mag_tx = 0, mag_ty = 0;
+    int cap_stage = 0, cap_mag = 0, tiles_pt_x = 0, tiles_pt_y = 0;
     size_t off_inst = 0, off_tstage = 0, off_tmag = 0, off_tpt = 0, off_part = 0, off_mpart = 0, off_res = 0,
            off_fields = 0, total = 0;
-    int ntile_stage() const { return tiles_stage_x * tiles_stage_y; }
-    int ntile_mag() const { return tiles_mag_x * tiles_mag_y; }
     int ntile_pt() const { return tiles_pt_x * tiles_pt_y; }
 };
 
@@ -96,32 +107,29 @@ int validate(const lbfs_params* p)
     return LBFS_OK;
 }
 
-// small_mag: use the small magnetic tile shape whatever the grid size (instances of a
-// batch share one magnetic launch, hence one tile shape)
-Layout make_layout(const lbfs_params* p, bool small_mag = false)
+Layout make_layout(const lbfs_params* p)
 {
     Layout L;
     L.esize = p->precision == LBFS_FP64 ? 8 : 4;
     L.pitch = (int)align_up((size_t)p->nx, 64);
     L.field_bytes = align_up((size_t)L.pitch * p->ny * L.esize, ALIGN);
-    const int stx = p->precision == LBFS_FP64 ? STAGE_TX_F64 : STAGE_TX_F32;
-    const int sty = p->precision == LBFS_FP64 ? STAGE_TY_F64 : STAGE_TY_F32;
-    L.tiles_stage_x = (p->nx + stx - 1) / stx;
-    L.tiles_stage_y = (p->ny + sty - 1) / sty;
-    L.mag_big = !small_mag && (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0;
-    L.mag_tx = L.mag_big ? MAG_BIG_TX : MAG_SMALL_TX;
-    L.mag_ty = L.mag_big ? MAG_BIG_TY : MAG_SMALL_TY;
-    L.tiles_mag_x = (p->nx + L.mag_tx - 1) / L.mag_tx;
-    L.tiles_mag_y = (p->ny + L.mag_ty - 1) / L.mag_ty;
-    L.tiles_pt_x = (p->nx + PT_TX - 1) / PT_TX;
-    L.tiles_pt_y = (p->ny + PT_TY - 1) / PT_TY;
+    for (int k = 0; k < NSTAGE_SHAPES; k++) {
+        const int n = count_tiles(p->nx, p->ny, stage_shape(p->precision == LBFS_FP64, k));
+        L.cap_stage = n > L.cap_stage ? n : L.cap_stage;
+    }
+    for (int k = 0; k < NMAG_SHAPES; k++) {
+        const int n = count_tiles(p->nx, p->ny, MAG_SHAPES[k]);
+        L.cap_mag = n > L.cap_mag ? n : L.cap_mag;
+    }
+    L.tiles_pt_x = tiles_of(p->nx, PT_TX);
+    L.tiles_pt_y = tiles_of(p->ny, PT_TY);
     size_t off = 0;
     L.off_inst = off; off = align_up(off + sizeof(DevInst), ALIGN);
-    L.off_tstage = off; off = align_up(off + sizeof(Tile) * L.ntile_stage(), ALIGN);
-    L.off_tmag = off; off = align_up(off + sizeof(Tile) * L.ntile_mag(), ALIGN);
+    L.off_tstage = off; off = align_up(off + sizeof(Tile) * L.cap_stage, ALIGN);
+    L.off_tmag = off; off = align_up(off + sizeof(Tile) * L.cap_mag, ALIGN);
     L.off_tpt = off; off = align_up(off + sizeof(Tile) * L.ntile_pt(), ALIGN);
-    L.off_part = off; off = align_up(off + sizeof(double) * NPART * L.ntile_stage(), ALIGN);
-    L.off_mpart = off; off = align_up(off + sizeof(double) * L.ntile_mag(), ALIGN);
+    L.off_part = off; off = align_up(off + sizeof(double) * NPART * L.cap_stage, ALIGN);
+    L.off_mpart = off; off = align_up(off + sizeof(double) * L.cap_mag, ALIGN);
     L.off_res = off; off = align_up(off + sizeof(double) * NRES, ALIGN);
     L.off_fields = off; off += L.field_bytes * NFIELDS;
     L.total = off + ALIGN;   // room to align the caller's base pointer
@@ -133,7 +141,7 @@ Layout make_layout(const lbfs_params* p, bool small_mag = false)
 // buffer parity and the captured graphs of one step per parity.
 struct Exec {
     bool f64 = false;
-    int mag_big = 0;
+    int stage_shape = 0, mag_shape = 0;   // indices into the tile-shape tables
     int sweeps = 4;
     double omega = 1.0;
     hipStream_t stream = nullptr;
@@ -151,22 +159,22 @@ struct Exec {
 
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 {
-    return E.f64 ? launch_mag<double>(E.mag_big, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
-                                      E.stream)
-                 : launch_mag<float>(E.mag_big, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+    return E.f64 ? launch_mag<double>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag,
+                                      E.nmag, E.stream)
+                 : launch_mag<float>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
                                      E.stream);
 }
 
 hipError_t exec_stage(Exec& E, int stage)
 {
-    return E.f64 ? launch_stage<double>(stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream)
-                 : launch_stage<float>(stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream);
+    return E.f64 ? launch_stage<double>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream)
+                 : launch_stage<float>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream);
 }
 
 hipError_t exec_state_partials(Exec& E)
 {
-    return E.f64 ? launch_state_partials<double>(E.dinst, E.tiles_stage, E.nstage, E.stream)
-                 : launch_state_partials<float>(E.dinst, E.tiles_stage, E.nstage, E.stream);
+    return E.f64 ? launch_state_partials<double>(E.stage_shape, E.dinst, E.tiles_stage, E.nstage, E.stream)
+                 : launch_state_partials<float>(E.stage_shape, E.dinst, E.tiles_stage, E.nstage, E.stream);
 }
 
 // one time step: magnetic phase and three Runge-Kutta stages (the observables of the
@@ -486,16 +494,40 @@ size_t lbfs_state_bytes(const lbfs_params* p)
 
 static void destroy_solver(lbfs_solver* s);
 
-// lbfs_init, with the option of the small magnetic tile shape (batch instances)
-static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, bool small_mag,
-                       lbfs_solver** out)
+// tile lists of the given shapes into the solver's own segments; drops the graphs
+static int apply_shapes(lbfs_solver* s, int si, int mi)
+{
+    if (si < 0 || si >= NSTAGE_SHAPES || mi < 0 || mi >= NMAG_SHAPES) return LBFS_E_INVAL;
+    std::vector<Tile> ts, tm;
+    append_tiles(ts, 0, s->p.nx, s->p.ny, stage_shape(s->f64(), si));
+    append_tiles(tm, 0, s->p.nx, s->p.ny, MAG_SHAPES[mi]);
+    HIPCHK(hipStreamSynchronize(s->stream));   // launches in flight read the old lists
+    exec_drop_graphs(s->E);
+    Exec& E = s->E;
+    s->hinst.ntile_stage = (int)ts.size();
+    s->hinst.ntile_mag = (int)tm.size();
+    HIPCHK(hipMemcpyAsync(const_cast<Tile*>(E.tiles_stage), ts.data(), sizeof(Tile) * ts.size(),
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(const_cast<Tile*>(E.tiles_mag), tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(s->dinst, &s->hinst, sizeof(DevInst), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    E.stage_shape = si;
+    E.mag_shape = mi;
+    E.nstage = (int)ts.size();
+    E.nmag = (int)tm.size();
+    s->stepped_since_observe = true;
+    return LBFS_OK;
+}
+
+static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, lbfs_solver** out)
 {
     if (!out) return LBFS_E_INVAL;
     *out = nullptr;
     const int v = validate(p);
     if (v != LBFS_OK) return v;
     if (!dev_buf) return LBFS_E_INVAL;
-    const Layout L = make_layout(p, small_mag);
+    const Layout L = make_layout(p);
     if (bytes < L.total) return LBFS_E_NOMEM;
 
     lbfs_solver* s = new (std::nothrow) lbfs_solver();
@@ -510,16 +542,13 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     s->dtiles_pt = reinterpret_cast<Tile*>(s->base + L.off_tpt);
     Exec& E = s->E;
     E.f64 = p->precision == LBFS_FP64;
-    E.mag_big = L.mag_big;
     E.sweeps = p->sweeps;
     E.omega = p->sor_omega;
     E.stream = s->stream;
     E.dinst = s->dinst;
     E.ninst = 1;
     E.tiles_stage = reinterpret_cast<Tile*>(s->base + L.off_tstage);
-    E.nstage = L.ntile_stage();
     E.tiles_mag = reinterpret_cast<Tile*>(s->base + L.off_tmag);
-    E.nmag = L.ntile_mag();
     auto fail = [&](int code) {
         destroy_solver(s);
         return code;
@@ -552,8 +581,6 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
         I.mbc[w] = p->mag_bc[w];
         I.tval[w] = p->thermal_val[w];
     }
-    I.ntile_stage = L.ntile_stage();
-    I.ntile_mag = L.ntile_mag();
     int col = (int)std::floor(p->drop_cx / p->dx);
     I.col_height = col < 0 ? 0 : (col > p->nx - 1 ? p->nx - 1 : col);
     I.heat_on = (!p->periodic[1] && p->thermal_bc[2] == LBFS_TBC_FIXED) ? 1 : 0;
@@ -579,28 +606,15 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     I.grav[1] = p->gravity[1];
     I.vc = 1.0 - p->rho[0] / p->rho[1];
 
-    std::vector<Tile> ts, tm, tp;
-    {
-        const int stx = s->f64() ? STAGE_TX_F64 : STAGE_TX_F32, sty = s->f64() ? STAGE_TY_F64 : STAGE_TY_F32;
-        for (int ty = 0; ty < L.tiles_stage_y; ty++)
-            for (int tx = 0; tx < L.tiles_stage_x; tx++)
-                ts.push_back(Tile{0, tx * stx, ty * sty, (int)ts.size()});
-        for (int ty = 0; ty < L.tiles_mag_y; ty++)
-            for (int tx = 0; tx < L.tiles_mag_x; tx++)
-                tm.push_back(Tile{0, tx * L.mag_tx, ty * L.mag_ty, (int)tm.size()});
-        for (int ty = 0; ty < L.tiles_pt_y; ty++)
-            for (int tx = 0; tx < L.tiles_pt_x; tx++)
-                tp.push_back(Tile{0, tx * PT_TX, ty * PT_TY, (int)tp.size()});
-    }
-    if (hipMemcpyAsync(s->dinst, &I, sizeof I, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(const_cast<Tile*>(E.tiles_stage), ts.data(), sizeof(Tile) * ts.size(), hipMemcpyHostToDevice,
-                       s->stream) != hipSuccess ||
-        hipMemcpyAsync(const_cast<Tile*>(E.tiles_mag), tm.data(), sizeof(Tile) * tm.size(), hipMemcpyHostToDevice,
-                       s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->dtiles_pt, tp.data(), sizeof(Tile) * tp.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+    std::vector<Tile> tp;
+    append_tiles(tp, 0, p->nx, p->ny, TileShape{PT_TX, PT_TY, PT_TX * PT_TY});
+    if (hipMemcpyAsync(s->dtiles_pt, tp.data(), sizeof(Tile) * tp.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_part, 0, L.off_fields - L.off_part, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_fields, 0, L.field_bytes * NFIELDS, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(LBFS_E_DEVICE);
+    // default shapes: the first of each table; the large magnetic tiles above 512 x 512
+    if (apply_shapes(s, 0, (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0) != LBFS_OK)
         return fail(LBFS_E_DEVICE);
 
     hipError_t e = s->f64()
@@ -645,7 +659,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
 
 int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, lbfs_solver** out)
 {
-    return init_solver(p, dev_buf, bytes, stream, false, out);
+    return init_solver(p, dev_buf, bytes, stream, out);
 }
 
 int lbfs_step(lbfs_solver* s, int32_t nsteps)
@@ -850,6 +864,121 @@ const char* lbfs_strerror(int status)
 
 }  // extern "C"
 
+
+// ------------------------------------------------------------------ tile shapes
+
+namespace {
+
+// mean duration (ms) of `reps` enqueues of f on the stream, after one untimed warm-up
+template <typename F>
+int time_launches(hipStream_t stream, int reps, F&& f, double* ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (HIPFAIL(hipEventCreate(&e0)) || HIPFAIL(hipEventCreate(&e1))) {
+        if (e0) (void)hipEventDestroy(e0);
+        return LBFS_E_DEVICE;
+    }
+    int rc = LBFS_OK;
+    float t = 0.0f;
+    if (HIPFAIL(f()) || HIPFAIL(hipEventRecord(e0, stream))) rc = LBFS_E_DEVICE;
+    for (int k = 0; k < reps && rc == LBFS_OK; k++)
+        if (HIPFAIL(f())) rc = LBFS_E_DEVICE;
+    if (rc == LBFS_OK && (HIPFAIL(hipEventRecord(e1, stream)) || HIPFAIL(hipEventSynchronize(e1)) ||
+                          HIPFAIL(hipEventElapsedTime(&t, e0, e1))))
+        rc = LBFS_E_DEVICE;
+    *ms = rc == LBFS_OK ? (double)t / reps : 0.0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// the potential of an instance: saved to / restored from the stage-2 field He (free
+// between steps)
+hipError_t copy_phi(lbfs_solver* s, bool save)
+{
+    void* phi = s->field(s->phi_field());
+    void* keep = s->field(10);
+    return hipMemcpyAsync(save ? keep : phi, save ? phi : keep, s->L.field_bytes, hipMemcpyDeviceToDevice,
+                          s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads)
+{
+    if (precision != LBFS_FP32 && precision != LBFS_FP64) return LBFS_E_INVAL;
+    const int n = kind == 0 ? NSTAGE_SHAPES : kind == 1 ? NMAG_SHAPES : -1;
+    if (n < 0) return LBFS_E_INVAL;
+    if (index < 0) return n;
+    if (index >= n) return LBFS_E_INVAL;
+    const TileShape S = kind == 0 ? stage_shape(precision == LBFS_FP64, index) : MAG_SHAPES[index];
+    if (tx) *tx = S.tx;
+    if (ty) *ty = S.ty;
+    if (threads) *threads = S.nt;
+    return LBFS_OK;
+}
+
+int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape_idx, int32_t mag_shape_idx)
+{
+    if (!s || s->batched) return LBFS_E_STATE;
+    if (stage_shape_idx < 0 || stage_shape_idx >= NSTAGE_SHAPES || mag_shape_idx < 0 || mag_shape_idx >= NMAG_SHAPES)
+        return LBFS_E_INVAL;
+    const bool mag_changed = mag_shape_idx != s->E.mag_shape;
+    int rc = apply_shapes(s, stage_shape_idx, mag_shape_idx);
+    if (rc != LBFS_OK) return rc;
+    // residual partials of the current potential on the new magnetic tiles
+    if (mag_changed) {
+        HIPCHK(exec_mag(s->E, 0, 1.0, 1));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return LBFS_OK;
+}
+
+int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
+{
+    if (!s || s->batched) return LBFS_E_STATE;
+    if (reps < 1 || reps > 10000) return LBFS_E_INVAL;
+    Exec& E = s->E;
+    double t[2 * LBFS_MAX_SHAPES] = {0};
+    const int phase0 = E.phase;
+    HIPCHK(copy_phi(s, true));
+    int rc = LBFS_OK;
+    // stage kernels: the right-hand-side kernel (writes only the stage-1 fields)
+    int best_s = 0;
+    for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
+        rc = apply_shapes(s, k, E.mag_shape);
+        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_stage(E, 0); }, &t[k]);
+        if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
+    }
+    // magnetic kernel: a step's worth of sweeps, on the potential restored afterwards
+    int best_m = 0;
+    for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
+        rc = apply_shapes(s, best_s, k);
+        double* tk = &t[LBFS_MAX_SHAPES + k];
+        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
+        if (rc == LBFS_OK && *tk < t[LBFS_MAX_SHAPES + best_m]) best_m = k;
+    }
+    // restore the potential, keep the fastest shapes and recompute the residual partials
+    // of the restored potential on them (a sweep-free launch: a copy of the potential)
+    E.phase = phase0;
+    if (HIPFAIL(copy_phi(s, false))) rc = LBFS_E_DEVICE;
+    if (rc == LBFS_OK) rc = apply_shapes(s, best_s, best_m);
+    if (rc == LBFS_OK && (HIPFAIL(exec_mag(E, 0, 1.0, 1)) || HIPFAIL(hipStreamSynchronize(E.stream))))
+        rc = LBFS_E_DEVICE;
+    if (rc != LBFS_OK) return rc;
+    if (chosen) {
+        chosen[0] = best_s;
+        chosen[1] = best_m;
+    }
+    if (ms)
+        for (int k = 0; k < 2 * LBFS_MAX_SHAPES; k++) ms[k] = t[k];
+    return LBFS_OK;
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------------ batches
 
 namespace {
@@ -905,14 +1034,11 @@ struct Slot {
     size_t off = 0, bytes = 0;
 };
 
-// tiles of one instance for the batch's stage and magnetic lists
-int stage_tiles(const Layout& L) { return L.ntile_stage(); }
-int mag_tiles(const Layout& L) { return L.ntile_mag(); }
-
 }  // namespace
 
 struct lbfs_batch {
     int32_t max_slots = 0, precision = 0, sweeps = 0;
+    int stage_shape = 0, mag_shape = 0;   // tile shapes of every instance
     double omega = 1.0;
     char* base = nullptr;
     size_t bytes = 0;
@@ -999,8 +1125,7 @@ int batch_rebuild(lbfs_batch* b)
     b->compact.clear();
     std::vector<DevInst> insts;
     std::vector<Tile> ts, tm;
-    const int stx = b->precision == LBFS_FP64 ? STAGE_TX_F64 : STAGE_TX_F32;
-    const int sty = b->precision == LBFS_FP64 ? STAGE_TY_F64 : STAGE_TY_F32;
+    const TileShape SS = stage_shape(b->precision == LBFS_FP64, b->stage_shape), MS = MAG_SHAPES[b->mag_shape];
     for (int k = 0; k < b->max_slots; k++) {
         lbfs_solver* s = b->slots[k].s;
         if (!s) continue;
@@ -1008,14 +1133,11 @@ int batch_rebuild(lbfs_batch* b)
         b->compact.push_back(k);
         DevInst I = s->hinst;
         I.result = b->meta_res() + (size_t)NRES * c;
+        I.ntile_stage = count_tiles(s->p.nx, s->p.ny, SS);
+        I.ntile_mag = count_tiles(s->p.nx, s->p.ny, MS);
         insts.push_back(I);
-        const Layout& L = s->L;
-        int idx = 0;
-        for (int ty = 0; ty < L.tiles_stage_y; ty++)
-            for (int tx = 0; tx < L.tiles_stage_x; tx++) ts.push_back(Tile{c, tx * stx, ty * sty, idx++});
-        idx = 0;
-        for (int ty = 0; ty < L.tiles_mag_y; ty++)
-            for (int tx = 0; tx < L.tiles_mag_x; tx++) tm.push_back(Tile{c, tx * L.mag_tx, ty * L.mag_ty, idx++});
+        append_tiles(ts, c, s->p.nx, s->p.ny, SS);
+        append_tiles(tm, c, s->p.nx, s->p.ny, MS);
     }
     if ((int)ts.size() > b->cap_stage || (int)tm.size() > b->cap_mag) return LBFS_E_STATE;
     if (!insts.empty()) {
@@ -1032,6 +1154,8 @@ int batch_rebuild(lbfs_batch* b)
     E.nstage = (int)ts.size();
     E.tiles_mag = b->meta_mag();
     E.nmag = (int)tm.size();
+    E.stage_shape = b->stage_shape;
+    E.mag_shape = b->mag_shape;
     b->dirty = false;
     return LBFS_OK;
 }
@@ -1056,7 +1180,7 @@ extern "C" {
 size_t lbfs_batch_instance_bytes(const lbfs_params* p)
 {
     if (validate(p) != LBFS_OK) return 0;
-    return align_up(make_layout(p, true).total, ALIGN);
+    return align_up(make_layout(p).total, ALIGN);
 }
 
 int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, double sor_omega, void* dev_buf,
@@ -1082,7 +1206,6 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
     b->slots.assign(max_slots, Slot{});
     Exec& E = b->E;
     E.f64 = precision == LBFS_FP64;
-    E.mag_big = 0;
     E.sweeps = sweeps;
     E.omega = sor_omega;
     E.stream = b->stream;
@@ -1112,12 +1235,13 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     for (int k = 0; k < b->max_slots && slot < 0; k++)
         if (!b->slots[k].s) slot = k;
     if (slot < 0) return LBFS_E_NOMEM;
-    const Layout L = make_layout(p, true);
-    int ns = stage_tiles(L), nm = mag_tiles(L);
+    // room for the tiles of every instance under any candidate shape
+    const Layout L = make_layout(p);
+    int ns = L.cap_stage, nm = L.cap_mag;
     for (const Slot& q : b->slots)
         if (q.s) {
-            ns += stage_tiles(q.s->L);
-            nm += mag_tiles(q.s->L);
+            ns += q.s->L.cap_stage;
+            nm += q.s->L.cap_mag;
         }
     int rc = batch_reserve(b, ns, nm);
     if (rc != LBFS_OK) return rc;
@@ -1125,10 +1249,19 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     size_t off = 0;
     if (!b->arena.alloc(need, &off)) return LBFS_E_NOMEM;
     lbfs_solver* s = nullptr;
-    rc = init_solver(p, b->base + off, need, b->stream, true, &s);
+    rc = init_solver(p, b->base + off, need, b->stream, &s);
     if (rc != LBFS_OK) {
         b->arena.release(off, need);
         return rc;
+    }
+    // the member's own tile lists take the batch's shapes, and its residual partials are
+    // recomputed on them (a sweep-free magnetic launch: a copy of the potential)
+    if (s->E.stage_shape != b->stage_shape || s->E.mag_shape != b->mag_shape) {
+        if (apply_shapes(s, b->stage_shape, b->mag_shape) != LBFS_OK || HIPFAIL(exec_mag(s->E, 0, 1.0, 1))) {
+            destroy_solver(s);
+            b->arena.release(off, need);
+            return LBFS_E_DEVICE;
+        }
     }
     // bring the potential into the batch's current buffer
     if (s->E.phase != b->E.phase) {
@@ -1240,6 +1373,89 @@ int lbfs_batch_info(lbfs_batch* b, int32_t* live, int64_t* cells, size_t* larges
     if (live) *live = n;
     if (cells) *cells = c;
     if (largest_free) *largest_free = b->arena.largest();
+    return LBFS_OK;
+}
+
+// residual partials of every member's current potential on the batch's magnetic tiles
+static int batch_refresh_residual(lbfs_batch* b)
+{
+    HIPCHK(exec_mag(b->E, 0, 1.0, 1));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (Slot& q : b->slots)
+        if (q.s) q.s->E.phase = b->E.phase;
+    b->stepped_since_observe = true;
+    return LBFS_OK;
+}
+
+int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape_idx, int32_t mag_shape_idx)
+{
+    if (!b) return LBFS_E_STATE;
+    if (stage_shape_idx < 0 || stage_shape_idx >= NSTAGE_SHAPES || mag_shape_idx < 0 || mag_shape_idx >= NMAG_SHAPES)
+        return LBFS_E_INVAL;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const bool mag_changed = mag_shape_idx != b->mag_shape;
+    b->stage_shape = stage_shape_idx;
+    b->mag_shape = mag_shape_idx;
+    for (Slot& q : b->slots)   // the members' own lists (used through borrowed handles)
+        if (q.s) {
+            const int rc = apply_shapes(q.s, stage_shape_idx, mag_shape_idx);
+            if (rc != LBFS_OK) return rc;
+        }
+    b->dirty = true;
+    b->stepped_since_observe = true;
+    int rc = batch_rebuild(b);
+    if (rc == LBFS_OK && mag_changed && b->E.ninst > 0) rc = batch_refresh_residual(b);
+    return rc;
+}
+
+int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms)
+{
+    if (!b) return LBFS_E_STATE;
+    if (reps < 1 || reps > 10000) return LBFS_E_INVAL;
+    int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    double t[2 * LBFS_MAX_SHAPES] = {0};
+    int best_s = b->stage_shape, best_m = b->mag_shape;
+    Exec& E = b->E;
+    if (E.ninst > 0) {
+        const int phase0 = E.phase;
+        for (Slot& q : b->slots)
+            if (q.s) HIPCHK(copy_phi(q.s, true));
+        best_s = 0;
+        for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
+            b->stage_shape = k;
+            b->dirty = true;
+            rc = batch_rebuild(b);
+            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_stage(E, 0); }, &t[k]);
+            if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
+        }
+        best_m = 0;
+        b->stage_shape = best_s;
+        for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
+            b->mag_shape = k;
+            b->dirty = true;
+            rc = batch_rebuild(b);
+            double* tk = &t[LBFS_MAX_SHAPES + k];
+            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
+            if (rc == LBFS_OK && *tk < t[LBFS_MAX_SHAPES + best_m]) best_m = k;
+        }
+        E.phase = phase0;
+        for (Slot& q : b->slots)
+            if (q.s) {
+                q.s->E.phase = phase0;
+                if (HIPFAIL(copy_phi(q.s, false))) rc = LBFS_E_DEVICE;
+            }
+        if (rc != LBFS_OK) return rc;
+        rc = lbfs_batch_set_tile_shapes(b, best_s, best_m);
+        if (rc == LBFS_OK) rc = batch_refresh_residual(b);
+        if (rc != LBFS_OK) return rc;
+    }
+    if (chosen) {
+        chosen[0] = best_s;
+        chosen[1] = best_m;
+    }
+    if (ms)
+        for (int k = 0; k < 2 * LBFS_MAX_SHAPES; k++) ms[k] = t[k];
     return LBFS_OK;
 }
 

@@ -11,18 +11,23 @@
 
 namespace lbfs {
 
-// stage tile shapes (cells) and workgroup sizes: enough threads for the tile plus its
-// 3-cell halo (38 x 14 = 532 / 22 x 14 = 308) and for all faces of the tile
-// (552 / 280) in one round. FP32 tiles are 32 wide so that each half-wave works on
-// one contiguous LDS row (no bank conflicts between rows).
-constexpr int STAGE_TX_F32 = 32, STAGE_TY_F32 = 8, STAGE_NT_F32 = 576;
-constexpr int STAGE_TX_F64 = 16, STAGE_TY_F64 = 8, STAGE_NT_F64 = 320;
-// fused magnetic kernel: interior tile shapes (256 threads) and the sweeps one launch
-// can do (LDS halo 2*MAG_KMAX+1)
+// Tile shapes (cells) and workgroup sizes. The kernels loop over their tile plus halo
+// and over its faces, so any shape works; these are the candidates the autotuner times
+// (index 0 is the default). Stage kernels stage the tile plus a 3-cell halo; FP32 tiles
+// 32 wide let each half-wave work on one contiguous LDS row.
+struct TileShape {
+    int tx, ty, nt;
+};
+constexpr int NSTAGE_SHAPES = 3;
+constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {{32, 8, 576}, {16, 16, 576}, {64, 4, 704}};
+constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {{16, 8, 320}, {8, 16, 320}, {32, 4, 384}};
+// fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
+// (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1.
 constexpr int MAG_KMAX = 4;
-// (workgroup sizes: one round per colour pass over the 50 x 26 / 82 x 34 region)
-constexpr int MAG_SMALL_TX = 32, MAG_SMALL_TY = 8, MAG_SMALL_NT = 704;
-constexpr int MAG_BIG_TX = 64, MAG_BIG_TY = 16, MAG_BIG_NT = 1024;
+constexpr int NMAG_SHAPES = 3;
+constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 16, 1024}, {64, 8, 1024}};
+
+constexpr TileShape stage_shape(bool f64, int k) { return f64 ? STAGE_SHAPES_F64[k] : STAGE_SHAPES_F32[k]; }
 // pointwise kernels (init, derived fields): one thread per cell
 constexpr int PT_TX = 64, PT_TY = 4;
 
@@ -65,17 +70,20 @@ struct DevInst {
 };
 
 // launchers (lbfs_kernels.hip); all enqueue on `stream`, return hipError_t
+// stage kernel of tile shape `shape` (index into the precision's table); stage 0 is
+// the plain right-hand side R(W) into W1
 template <typename T>
-hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
+hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                         hipStream_t stream);
 // magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
-// residual partials when residual != 0; big selects the large tile shape. Reads the
+// residual partials when residual != 0, on tiles of MAG_SHAPES[shape]. Reads the
 // potential buffer *pidx and flips *pidx once per launch.
 template <typename T>
-hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream);
+// per-tile FP64 partial sums of the observables over stage tiles of shape `shape`
 template <typename T>
-hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
+hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
 hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream);
 template <typename T>
 hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,

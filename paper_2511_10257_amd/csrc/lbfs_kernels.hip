@@ -629,15 +629,10 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     }
 }
 
-template <typename T>
-hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                        hipStream_t stream)
+template <typename T, int TX, int TY, int NT>
+hipError_t launch_stage_shape(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
+                              hipStream_t stream)
 {
-    constexpr bool f32 = sizeof(T) == 4;
-    constexpr int TX = f32 ? STAGE_TX_F32 : STAGE_TX_F64;
-    constexpr int TY = f32 ? STAGE_TY_F32 : STAGE_TY_F64;
-    constexpr int NT = f32 ? STAGE_NT_F32 : STAGE_NT_F64;
-    if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(NT);
     switch (stage) {
     case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 0>), grid, block, 0, stream, insts, tiles, pidx); break;
@@ -648,7 +643,22 @@ hipError_t launch_stage(int stage, int pidx, const DevInst* insts, const Tile* t
     return hipGetLastError();
 }
 
-// Observables of the current state (used at initialisation).
+template <typename T>
+hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
+                        hipStream_t stream)
+{
+    constexpr bool f64 = sizeof(T) == 8;
+    constexpr TileShape S0 = stage_shape(f64, 0), S1 = stage_shape(f64, 1), S2 = stage_shape(f64, 2);
+    static_assert(NSTAGE_SHAPES == 3, "one case per shape");
+    if (ntiles <= 0) return hipSuccess;
+    switch (shape) {
+    case 0: return launch_stage_shape<T, S0.tx, S0.ty, S0.nt>(stage, pidx, insts, tiles, ntiles, stream);
+    case 1: return launch_stage_shape<T, S1.tx, S1.ty, S1.nt>(stage, pidx, insts, tiles, ntiles, stream);
+    case 2: return launch_stage_shape<T, S2.tx, S2.ty, S2.nt>(stage, pidx, insts, tiles, ntiles, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_state_partials(const DevInst* __restrict__ insts,
                                                         const Tile* __restrict__ tiles, int TX, int TY)
@@ -673,12 +683,12 @@ __global__ __launch_bounds__(256) void k_state_partials(const DevInst* __restric
 }
 
 template <typename T>
-hipError_t launch_state_partials(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
+hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream)
 {
-    constexpr bool f32 = sizeof(T) == 4;
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_state_partials<T>), dim3(ntiles), dim3(256), 0, stream, insts, tiles,
-                       f32 ? STAGE_TX_F32 : STAGE_TX_F64, f32 ? STAGE_TY_F32 : STAGE_TY_F64);
+    if (shape < 0 || shape >= NSTAGE_SHAPES) return hipErrorInvalidValue;
+    const TileShape S = stage_shape(sizeof(T) == 8, shape);
+    hipLaunchKernelGGL((k_state_partials<T>), dim3(ntiles), dim3(256), 0, stream, insts, tiles, S.tx, S.ty);
     return hipGetLastError();
 }
 
@@ -736,12 +746,13 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
             const int gx = ox + r % L::RX, gy = oy + r / L::RX;
             int sx = gx, sy = gy;
             bool in = r < L::NR;
+            // a periodic axis may be shorter than the halo: wrap as often as needed
             if (gx < 0 || gx >= nx) {
-                if (I.per_x) sx = gx < 0 ? gx + nx : gx - nx;
+                if (I.per_x) sx = ((gx % nx) + nx) % nx;
                 else in = false;
             }
             if (gy < 0 || gy >= ny) {
-                if (I.per_y) sy = gy < 0 ? gy + ny : gy - ny;
+                if (I.per_y) sy = ((gy % ny) + ny) % ny;
                 else in = false;
             }
             in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
@@ -870,10 +881,13 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
 }
 
 template <typename T>
-hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream)
 {
+    constexpr TileShape M0 = MAG_SHAPES[0], M1 = MAG_SHAPES[1], M2 = MAG_SHAPES[2];
+    static_assert(NMAG_SHAPES == 3, "one case per shape");
     if (ntiles <= 0) return hipSuccess;
+    if (shape < 0 || shape >= NMAG_SHAPES) return hipErrorInvalidValue;
     // the potential is read from phi[*pidx] and written to the other buffer (halo cells
     // of a tile belong to other workgroups); sweeps beyond the LDS halo run as further
     // launches
@@ -881,12 +895,20 @@ hipError_t launch_mag(int big, int nsweeps, double omega, int residual, int* pid
         const int k = nsweeps > MAG_KMAX ? MAG_KMAX : nsweeps;
         nsweeps -= k;
         const int res = residual && nsweeps == 0;
-        if (big)
-            hipLaunchKernelGGL((k_mag_fused<T, MAG_BIG_TX, MAG_BIG_TY, MAG_BIG_NT>), dim3(ntiles), dim3(MAG_BIG_NT),
-                               0, stream, insts, tiles, k, omega, res, *pidx);
-        else
-            hipLaunchKernelGGL((k_mag_fused<T, MAG_SMALL_TX, MAG_SMALL_TY, MAG_SMALL_NT>), dim3(ntiles),
-                               dim3(MAG_SMALL_NT), 0, stream, insts, tiles, k, omega, res, *pidx);
+        switch (shape) {
+        case 0:
+            hipLaunchKernelGGL((k_mag_fused<T, M0.tx, M0.ty, M0.nt>), dim3(ntiles), dim3(M0.nt), 0, stream, insts,
+                               tiles, k, omega, res, *pidx);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_mag_fused<T, M1.tx, M1.ty, M1.nt>), dim3(ntiles), dim3(M1.nt), 0, stream, insts,
+                               tiles, k, omega, res, *pidx);
+            break;
+        default:
+            hipLaunchKernelGGL((k_mag_fused<T, M2.tx, M2.ty, M2.nt>), dim3(ntiles), dim3(M2.nt), 0, stream, insts,
+                               tiles, k, omega, res, *pidx);
+            break;
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         *pidx ^= 1;
@@ -981,9 +1003,9 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
 }
 
 #define LBFS_INSTANTIATE(T)                                                                          \
-    template hipError_t launch_stage<T>(int, int, const DevInst*, const Tile*, int, hipStream_t);   \
+    template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t); \
-    template hipError_t launch_state_partials<T>(const DevInst*, const Tile*, int, hipStream_t);    \
+    template hipError_t launch_state_partials<T>(int, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \
     template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);

@@ -29,10 +29,12 @@ EXPORTS = (
     "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
+    "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_autotune",
     "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
     "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_observe", "lbfs_batch_slot",
-    "lbfs_batch_info", "lbfs_batch_destroy",
+    "lbfs_batch_info", "lbfs_batch_destroy", "lbfs_batch_set_tile_shapes", "lbfs_batch_autotune",
 )
+MAX_SHAPES = 8
 
 
 class Params(C.Structure):
@@ -102,6 +104,12 @@ def lib():
             "lbfs_load_state": (C.c_int, [vp, vp, C.c_size_t]),
             "lbfs_destroy": (None, [vp]),
             "lbfs_strerror": (C.c_char_p, [C.c_int]),
+            "lbfs_tile_shape": (C.c_int, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]),
+            "lbfs_set_tile_shapes": (C.c_int, [vp, i32, i32]),
+            "lbfs_autotune": (C.c_int, [vp, i32, C.POINTER(C.c_int32), dp]),
+            "lbfs_batch_set_tile_shapes": (C.c_int, [vp, i32, i32]),
+            "lbfs_batch_autotune": (C.c_int, [vp, i32, C.POINTER(C.c_int32), dp]),
             "lbfs_batch_instance_bytes": (C.c_size_t, [C.POINTER(Params)]),
             "lbfs_batch_create": (C.c_int, [i32, i32, i32, C.c_double, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbfs_batch_admit": (C.c_int, [vp, C.POINTER(Params), C.POINTER(C.c_int32)]),
@@ -185,6 +193,25 @@ def make_params(prob: dict) -> Params:
         if "h0" in prob:
             p.h0 = float(prob["h0"])
     return p
+
+
+def tile_shapes(kind: str, precision: str = "fp32") -> list:
+    """Candidate tile shapes (tx, ty, threads) of the "stage" or "mag" kernels."""
+    k = 0 if kind == "stage" else 1
+    prec = LBFS_FP64 if precision == "fp64" else LBFS_FP32
+    n = lib().lbfs_tile_shape(k, prec, -1, None, None, None)
+    out = []
+    for i in range(n):
+        tx, ty, nt = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbfs_tile_shape(k, prec, i, C.byref(tx), C.byref(ty), C.byref(nt)), "lbfs_tile_shape")
+        out.append((tx.value, ty.value, nt.value))
+    return out
+
+
+def _tune_result(chosen, ms, precision: str) -> dict:
+    ns, nm = len(tile_shapes("stage", precision)), len(tile_shapes("mag", precision))
+    return {"stage_shape": chosen[0], "mag_shape": chosen[1],
+            "stage_ms": [ms[k] for k in range(ns)], "mag_ms": [ms[MAX_SHAPES + k] for k in range(nm)]}
 
 
 def state_bytes(prob_or_params) -> int:
@@ -302,6 +329,16 @@ class Solver(_Instance):
         _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
         return r.value
 
+    def set_tile_shapes(self, stage_shape: int, mag_shape: int) -> None:
+        _check(lib().lbfs_set_tile_shapes(self._h, int(stage_shape), int(mag_shape)), "lbfs_set_tile_shapes")
+
+    def autotune(self, reps: int = 20) -> dict:
+        """Time the candidate tile shapes on the current state and keep the fastest."""
+        chosen = (C.c_int32 * 2)()
+        ms = (C.c_double * (2 * MAX_SHAPES))()
+        _check(lib().lbfs_autotune(self._h, int(reps), chosen, ms), "lbfs_autotune")
+        return _tune_result(chosen, ms, "fp64" if self.params.precision == LBFS_FP64 else "fp32")
+
 
 class _SlotView(_Instance):
     """Borrowed handle of a batch slot (valid until the slot is retired)."""
@@ -388,6 +425,17 @@ class Batch:
         _check(lib().lbfs_batch_slot(self._h, int(k), C.byref(h)), "lbfs_batch_slot")
         nx, ny = self._dims[int(k)]
         return _SlotView(h, nx, ny)
+
+    def set_tile_shapes(self, stage_shape: int, mag_shape: int) -> None:
+        _check(lib().lbfs_batch_set_tile_shapes(self._h, int(stage_shape), int(mag_shape)),
+               "lbfs_batch_set_tile_shapes")
+
+    def autotune(self, reps: int = 20) -> dict:
+        """Time the candidate tile shapes over all live instances and keep the fastest."""
+        chosen = (C.c_int32 * 2)()
+        ms = (C.c_double * (2 * MAX_SHAPES))()
+        _check(lib().lbfs_batch_autotune(self._h, int(reps), chosen, ms), "lbfs_batch_autotune")
+        return _tune_result(chosen, ms, self.precision)
 
     def info(self) -> dict:
         n, c, f = C.c_int32(), C.c_int64(), C.c_size_t()

@@ -87,11 +87,8 @@ def test_batch_host_checks():
     """Host-side checks of the batch calls (no device work is reached)."""
     p = lbfs.make_params(wl.config1())
     nb = lbfs.lib().lbfs_batch_instance_bytes(C.byref(p))
-    # the same fields as a solver; the magnetic tile lists of the small shape
+    # the same segments as a solver (tile lists sized for every candidate shape)
     assert lbfs.state_bytes(p) <= nb < lbfs.state_bytes(p) + 64 * 1024
-    big = lbfs.make_params(wl.config2("fp32"))
-    # 1024^2 uses the large magnetic tiles alone, the small ones in a batch (more tiles)
-    assert lbfs.lib().lbfs_batch_instance_bytes(C.byref(big)) > lbfs.state_bytes(big)
     q = lbfs.make_params(wl.config0())
     q.nx = 2
     assert lbfs.lib().lbfs_batch_instance_bytes(C.byref(q)) == 0
@@ -106,3 +103,18 @@ def test_batch_host_checks():
     assert L.lbfs_batch_step(None, 1) == lbfs.LBFS_E_STATE
     assert L.lbfs_batch_retire(None, 0) == lbfs.LBFS_E_STATE
     L.lbfs_batch_destroy(None)
+
+
+def test_tile_shape_tables():
+    L = lbfs.lib()
+    for prec in ("fp32", "fp64"):
+        for kind in ("stage", "mag"):
+            shapes = lbfs.tile_shapes(kind, prec)
+            assert 1 <= len(shapes) <= lbfs.MAX_SHAPES
+            for tx, ty, nt in shapes:
+                assert nt % 64 == 0 and nt <= 1024 and tx * ty <= (nt if kind == "stage" else 4096)
+    assert L.lbfs_tile_shape(2, 0, 0, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_tile_shape(0, 5, 0, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_tile_shape(0, 0, 99, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_set_tile_shapes(None, 0, 0) == lbfs.LBFS_E_STATE
+    assert L.lbfs_autotune(None, 5, None, None) == lbfs.LBFS_E_STATE
