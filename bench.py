@@ -6,10 +6,16 @@ FP64 reductions, 4 red-black sweeps per step. One "step" is the whole hot path: 
 magnetic sweeps and residual, three fused Runge-Kutta stages with the Kelvin force,
 the end-of-step Eq. 8 update and the FP64 reductions.
 
-Prints one JSON line: throughput in MLUPS (cell updates per second / 1e6) with the
-state resident in HBM, the roofline of the dominant kernel (its mean launch duration
-from HIP events recorded on the solver's stream inside the timed region), and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host.
+Other workloads: config0 (64 x 64, FP64), config2 / config2-fp64 (1024 x 1024), config3
+(a batch of 64 uneven instances advanced by the same launches, tile shapes autotuned)
+and config4 (a Poisson stream of freezing requests served by continuous batching, FP32,
+beside the same stream served one solve at a time in FP64).
+
+Prints one JSON line: throughput in MLUPS (cell updates per second / 1e6; solves/s for
+config4) with the state resident in HBM, the roofline of the dominant kernel (its mean
+launch duration from HIP events recorded on the solver's stream inside the timed
+region), and the FP64 CPU oracle timed on a bounded sample of the same workload on the
+host.
 """
 from __future__ import annotations
 
@@ -51,19 +57,38 @@ ALG_FLOPS = {"mag": 152.7, "stage1": 4613.4, "stage2": 4613.4, "stage3": 4613.4,
 BOUND = {"mag": "hbm", "stage1": "alu", "stage2": "alu", "stage3": "alu", "reduce": "hbm"}
 
 
+DEFAULT_STEPS = {"config0": 2000, "config1": 20000, "config2": 1000, "config2-fp64": 1000, "config3": 1000}
+DEFAULT_WARMUP = {"config0": 100, "config1": 200, "config2": 100, "config2-fp64": 100, "config3": 100}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2", "config2-fp64"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default per workload)")
+    ap.add_argument("--workload", default="config1",
+                    choices=["config0", "config1", "config2", "config2-fp64", "config3", "config4"])
     ap.add_argument("--sample-every", type=int, default=20,
                     help="bracket the kernels of every n-th timed step with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
-    return ap.parse_args()
+    ap.add_argument("--autotune", action="store_true", help="autotune the tile shapes (always on for config3)")
+    # serving (config4)
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrivals are cut after this time")
+    ap.add_argument("--serve-drain", type=float, default=60.0, help="hard cap after the last arrival")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-chunk", type=int, default=200, help="steps between observations")
+    ap.add_argument("--no-serve-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS.get(args.workload, 0)
+    if args.warmup is None:
+        args.warmup = DEFAULT_WARMUP.get(args.workload, 0)
+    return args
 
 
 def kernel_sources_digest() -> str:
@@ -107,6 +132,142 @@ def cpu_baseline(prob: dict, budget_s: float) -> dict:
                       f"FP64, single thread, {secs:.1f} s (init excluded)"}
 
 
+def roofline(kern: dict, cells: int, precision: str, workload: str) -> dict:
+    """Roofline of the kernel kind with the largest mean duration per step."""
+    share = {k: kern[k][0] for k in kern}
+    dominant = max(share, key=share.get)
+    esize = 8 if precision == "fp64" else 4
+    alg_bytes = FIELD_ACCESSES[dominant] * esize * cells
+    alg_flops = ALG_FLOPS[dominant] * cells
+    dur_s = kern[dominant][0] * 1e-3
+    gbs = alg_bytes / dur_s / 1e9
+    tflops = alg_flops / dur_s / 1e12
+    traffic = measured_traffic(dominant, workload)
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes}
+    vpeak = VALU_PEAK_TFLOPS[precision]
+    alu = {"bound": "alu", "achieved": tflops, "peak": vpeak, "unit": "TFLOP/s", "frac": tflops / vpeak,
+           "traffic": traffic, "algorithmic_flops_per_launch": alg_flops,
+           "frac_of_nonpacked_peak": tflops / VALU_PEAK_NONPACKED_TFLOPS}
+    roof = dict(alu if BOUND[dominant] == "alu" else hbm)
+    roof.update({"kernel": dominant, "mean_launch_us": kern[dominant][0] * 1e3,
+                 "timed_launches": kern[dominant][1],
+                 "other_ceiling": hbm if BOUND[dominant] == "alu" else alu})
+    return roof
+
+
+def kernel_fields(kern: dict) -> dict:
+    share = {k: kern[k][0] for k in kern}
+    total = sum(share.values()) or 1.0
+    return {"kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kern.items()},
+            "step_share": {k: round(v / total, 4) for k, v in share.items()}}
+
+
+def line(args, value, unit, ms_per_step, dtype, config, higher=True) -> dict:
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def copy_calibration(torch, mib: int) -> None:
+    if mib <= 0:
+        return
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def run_single(args, torch, lbfs, wl) -> dict:
+    prob = {"config0": wl.config0, "config1": wl.config1, "config2": lambda: wl.config2("fp32"),
+            "config2-fp64": lambda: wl.config2("fp64")}[args.workload]()
+    cells = prob["nx"] * prob["ny"]
+    copy_calibration(torch, args.copy_calibration_mib)
+    solver = lbfs.Solver(prob, device="cuda:0")
+    tuned = solver.autotune() if args.autotune else None
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = solver.step_profiled(args.steps, args.sample_every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    obs = solver.observe()
+    secs = t1 - t0
+    out = line(args, cells * args.steps / secs / 1e6, "MLUPS", secs * 1e3 / args.steps,
+               "f64" if prob["precision"] == "fp64" else "f32",
+               {"workload": prob["name"], "nx": prob["nx"], "ny": prob["ny"], "precision": prob["precision"],
+                "angle_deg": prob["angle_deg"], "bo_m": prob["bo_m"], "ste": prob["ste"],
+                "sweeps_per_step": prob["sweeps"], "reductions": "f64",
+                "tile_shapes": "autotuned" if tuned else "default"})
+    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload)
+    out.update(kernel_fields(kern))
+    if tuned:
+        out["autotune"] = tuned
+    out["liquid_fraction_reached"] = obs["liquid_fraction"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return out
+
+
+def run_batch(args, torch, lbfs, wl) -> dict:
+    probs = wl.config3()
+    cells = sum(p["nx"] * p["ny"] for p in probs)
+    budget = sum(lbfs.Batch.instance_bytes(p) for p in probs) + (64 << 20)
+    copy_calibration(torch, args.copy_calibration_mib)
+    batch = lbfs.Batch(len(probs), budget, precision="fp32", sweeps=probs[0]["sweeps"], omega=probs[0]["omega"])
+    for p in probs:
+        if batch.admit(p) is None:
+            raise RuntimeError("the batch buffer is too small for the workload")
+    tuned = batch.autotune(reps=10)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = batch.step_profiled(args.steps, args.sample_every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    obs = batch.observe()
+    secs = t1 - t0
+    fl = [o["liquid_fraction"] for o in obs.values()]
+    out = line(args, cells * args.steps / secs / 1e6, "MLUPS", secs * 1e3 / args.steps, "f32",
+               {"workload": f"batch of {len(probs)} droplets, edges 64-256 (seed 1), FP32", "instances": len(probs),
+                "cells": cells, "edges": sorted({p["nx"] for p in probs}), "precision": "fp32",
+                "sweeps_per_step": probs[0]["sweeps"], "reductions": "f64", "tile_shapes": "autotuned",
+                "launches_per_step": "one graph replay"})
+    out["roofline"] = roofline(kern, cells, "fp32", args.workload)
+    out.update(kernel_fields(kern))
+    out["autotune"] = tuned
+    out["liquid_fraction_range"] = [min(fl), max(fl)]
+    if not args.no_cpu_baseline:
+        # the oracle on one instance of the mix (the largest edge), per-cell rate
+        big = max(probs, key=lambda p: p["nx"] * p["ny"])
+        out["cpu_baseline"] = cpu_baseline(big, args.cpu_seconds)
+    return out
+
+
+def run_serve(args, torch, lbfs, wl) -> dict:
+    from paper_2511_10257_amd import serve
+    stream = wl.config4(rate_hz=args.serve_rate, horizon_s=args.serve_seconds)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    cap = args.serve_seconds + args.serve_drain
+    srv = serve.Server(budget, max_slots=args.serve_slots, precision="fp32", chunk=args.serve_chunk)
+    rep = srv.run(stream, clock="wall", horizon=args.serve_seconds, cap=cap, progress_every=20.0)
+    srv.close()
+    out = line(args, rep["solves_per_unit"], "solves/s", None, "f32",
+               {"workload": f"Poisson stream {args.serve_rate:g}/s for {args.serve_seconds:g} s (seed 2), edges "
+                            f"96-512, run to liquid fraction < 1e-3, FP32 continuous batching",
+                "slots": args.serve_slots, "budget_gib": args.serve_budget_gib, "chunk_steps": args.serve_chunk,
+                "drain_cap_s": args.serve_drain})
+    out["serve"] = rep
+    if not args.no_serve_baseline:
+        base = serve.Server(budget, max_slots=1, precision="fp64", chunk=args.serve_chunk)
+        rb = base.run(stream, clock="wall", horizon=args.serve_seconds, cap=cap, progress_every=20.0)
+        base.close()
+        out["serve_fp64_one_at_a_time"] = rb
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -117,71 +278,13 @@ def main():
 
     from paper_2511_10257_amd import lbfs, workloads as wl
 
-    if args.workload == "config0":
-        prob = wl.config0()
-    elif args.workload == "config1":
-        prob = wl.config1()
-    elif args.workload == "config2":
-        prob = wl.config2("fp32")
+    if args.workload == "config3":
+        out = run_batch(args, torch, lbfs, wl)
+    elif args.workload == "config4":
+        out = run_serve(args, torch, lbfs, wl)
     else:
-        prob = wl.config2("fp64")
-    nx, ny = prob["nx"], prob["ny"]
-    cells = nx * ny
-    if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    solver = lbfs.Solver(prob, device="cuda:0")
-    solver.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kern = solver.step_profiled(args.steps, args.sample_every)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    obs = solver.observe()
-    secs = t1 - t0
-    mlups = cells * args.steps / secs / 1e6
-
-    share = {k: kern[k][0] for k in kern}
-    dominant = max(share, key=share.get)
-    esize = 8 if prob["precision"] == "fp64" else 4
-    alg_bytes = FIELD_ACCESSES[dominant] * esize * cells
-    alg_flops = ALG_FLOPS[dominant] * cells
-    dur_s = kern[dominant][0] * 1e-3
-    gbs = alg_bytes / dur_s / 1e9
-    tflops = alg_flops / dur_s / 1e12
-    traffic = measured_traffic(dominant, args.workload)
-    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes}
-    vpeak = VALU_PEAK_TFLOPS[prob["precision"]]
-    alu = {"bound": "alu", "achieved": tflops, "peak": vpeak, "unit": "TFLOP/s", "frac": tflops / vpeak,
-           "traffic": traffic, "algorithmic_flops_per_launch": alg_flops,
-           "frac_of_nonpacked_peak": tflops / VALU_PEAK_NONPACKED_TFLOPS}
-    roof = dict(alu if BOUND[dominant] == "alu" else hbm)
-    roof.update({"kernel": dominant, "mean_launch_us": kern[dominant][0] * 1e3,
-                 "timed_launches": kern[dominant][1],
-                 "other_ceiling": hbm if BOUND[dominant] == "alu" else alu})
-
-    line = {
-        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": secs * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prob["precision"] == "fp64" else "f32",
-        "data": "synthetic",
-        "config": {"workload": prob["name"], "nx": nx, "ny": ny, "precision": prob["precision"],
-                   "angle_deg": prob["angle_deg"], "bo_m": prob["bo_m"], "ste": prob["ste"],
-                   "sweeps_per_step": prob["sweeps"], "reductions": "f64"},
-        "roofline": roof,
-        "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kern.items()},
-        "step_share": {k: round(v / sum(share.values()), 4) for k, v in share.items()},
-        "liquid_fraction_reached": obs["liquid_fraction"],
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+        out = run_single(args, torch, lbfs, wl)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -16,6 +16,7 @@ steps; deterministic, used by the tests).
 from __future__ import annotations
 
 import dataclasses
+import sys
 import time
 from collections import deque
 
@@ -81,10 +82,12 @@ class Server:
             self.live[slot] = req
         waiting.extend(kept)
 
-    def run(self, arrivals, clock: str = "wall", horizon: float | None = None, cap: float | None = None) -> dict:
+    def run(self, arrivals, clock: str = "wall", horizon: float | None = None, cap: float | None = None,
+            progress_every: float | None = None) -> dict:
         """Serve (arrival time, problem) pairs in arrival order. Arrivals after `horizon`
         are dropped; the run ends when everything admitted has finished or at `cap`
-        (same unit as the clock), whichever is first."""
+        (same unit as the clock), whichever is first. With progress_every (seconds of
+        host time), a status line goes to stderr that often."""
         reqs = [Request(i, prob, float(t)) for i, (t, prob) in enumerate(arrivals)
                 if horizon is None or t < horizon]
         waiting: deque = deque()
@@ -94,6 +97,8 @@ class Server:
 
         def now() -> float:
             return time.perf_counter() - t0 if clock == "wall" else float(vsteps)
+
+        last_report = time.perf_counter()
 
         while True:
             t = now()
@@ -115,6 +120,11 @@ class Server:
                 else:
                     vsteps = max(vsteps, int(np.ceil(reqs[nxt].arrival)))
                 continue
+            if progress_every is not None and time.perf_counter() - last_report >= progress_every:
+                last_report = time.perf_counter()
+                done = sum(1 for r in reqs if r.finished is not None)
+                print(f"serve: t={t:.1f} arrived={nxt} live={len(self.live)} waiting={len(waiting)} "
+                      f"done={done} cell_steps={self.cell_steps:.3e}", file=sys.stderr, flush=True)
             n = self.chunk
             if self.max_steps is not None:
                 n = min(n, max(1, min(self.max_steps - r.steps for r in self.live.values())))
