@@ -153,11 +153,12 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps);
    reduction of those partials, runs in lbfs_observe and is not timed here. */
 enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUCE, LBFS_NKERNELS };
 
-/* lbfs_step with HIP events recorded on the solver's stream around every kernel
-   phase of every sample_every-th step (sample_every >= 1; at most 4096 sampled
-   steps; the other steps run as in lbfs_step). Synchronises at the end and writes,
-   per kind, the mean duration of one phase in ms (kernel_ms[LBFS_NKERNELS]) and the
-   number of timed phases (launches[LBFS_NKERNELS]). */
+/* lbfs_step with the kernel phases of every sample_every-th step timed: their launches
+   (hipExtLaunchKernelGGL on the solver's stream) record the start of the phase's first
+   kernel and the end of its last into HIP events (sample_every >= 1; at most 4096
+   sampled steps; the other steps run as in lbfs_step). Synchronises at the end and
+   writes, per kind, the mean duration of one phase in ms (kernel_ms[LBFS_NKERNELS]) and
+   the number of timed phases (launches[LBFS_NKERNELS]). */
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches);
 
@@ -204,11 +205,11 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
    residual as lbfs_autotune does). Synchronous. */
 int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape);
 
-/* Autotuner: time every stage shape (reps launches of the right-hand-side kernel, which
-   leaves the state unchanged) and then every magnetic shape (reps magnetic phases of a
+/* Autotuner: time every stage shape (reps runs of the first two Runge-Kutta stages,
+   which write only stage fields) and then every magnetic shape (reps magnetic phases of a
    step, on the current potential, which is restored afterwards) on this solver's
    current state, and keep the fastest of each. chosen[2] receives the indices,
-   ms[2*LBFS_MAX_SHAPES] the mean ms per launch (stage shapes first, magnetic shapes
+   ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes first, magnetic shapes
    from index LBFS_MAX_SHAPES; either may be NULL). The state is unchanged; until the
    next step, mag_residual then reports the residual of the current potential with the
    current permeability (a step reports it with the permeability of the step's start).

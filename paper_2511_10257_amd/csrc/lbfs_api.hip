@@ -153,6 +153,7 @@ struct Exec {
     int nmag = 0;
     int phase = 0;                       // potential buffer holding the current phi'
     bool use_graph = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing of the next launch (profiled steps)
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
 };
@@ -160,15 +161,17 @@ struct Exec {
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 {
     return E.f64 ? launch_mag<double>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag,
-                                      E.nmag, E.stream)
+                                      E.nmag, E.stream, E.ev0, E.ev1)
                  : launch_mag<float>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
-                                     E.stream);
+                                     E.stream, E.ev0, E.ev1);
 }
 
 hipError_t exec_stage(Exec& E, int stage)
 {
-    return E.f64 ? launch_stage<double>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream)
-                 : launch_stage<float>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream);
+    return E.f64 ? launch_stage<double>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream,
+                                        E.ev0, E.ev1)
+                 : launch_stage<float>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream,
+                                       E.ev0, E.ev1);
 }
 
 hipError_t exec_state_partials(Exec& E)
@@ -260,13 +263,13 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
         }
     int rc = LBFS_OK;
     size_t slot = 0;
+    // the launch itself timestamps the kernel's start and end into the events
     auto timed = [&](int k, auto&& launch) -> hipError_t {
         kind[slot] = k;
-        hipError_t e = hipEventRecord(ev[2 * slot], E.stream);
-        if (e != hipSuccess) return e;
-        e = launch();
-        if (e != hipSuccess) return e;
-        e = hipEventRecord(ev[2 * slot + 1], E.stream);
+        E.ev0 = ev[2 * slot];
+        E.ev1 = ev[2 * slot + 1];
+        const hipError_t e = launch();
+        E.ev0 = E.ev1 = nullptr;
         slot++;
         return e;
     };
@@ -892,8 +895,16 @@ int time_launches(hipStream_t stream, int reps, F&& f, double* ms)
     return rc;
 }
 
+// the first two Runge-Kutta stages of a step: they read the state and write only the
+// stage fields W1 and W2, so timing them leaves the state as it is
+hipError_t stage_pair(Exec& E)
+{
+    const hipError_t e = exec_stage(E, 1);
+    return e == hipSuccess ? exec_stage(E, 2) : e;
+}
+
 // the potential of an instance: saved to / restored from the stage-2 field He (free
-// between steps)
+// between steps; the stage timing that writes it comes first)
 hipError_t copy_phi(lbfs_solver* s, bool save)
 {
     void* phi = s->field(s->phi_field());
@@ -943,14 +954,18 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     Exec& E = s->E;
     double t[2 * LBFS_MAX_SHAPES] = {0};
     const int phase0 = E.phase;
-    HIPCHK(copy_phi(s, true));
     int rc = LBFS_OK;
-    // stage kernels: the right-hand-side kernel (writes only the stage-1 fields)
+    // stage kernels: the first two Runge-Kutta stages (they write only the stage fields)
     int best_s = 0;
     for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
         rc = apply_shapes(s, k, E.mag_shape);
-        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_stage(E, 0); }, &t[k]);
+        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
         if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
+    }
+    bool saved = false;
+    if (rc == LBFS_OK) {
+        if (HIPFAIL(copy_phi(s, true))) rc = LBFS_E_DEVICE;
+        else saved = true;
     }
     // magnetic kernel: a step's worth of sweeps, on the potential restored afterwards
     int best_m = 0;
@@ -963,7 +978,7 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     // restore the potential, keep the fastest shapes and recompute the residual partials
     // of the restored potential on them (a sweep-free launch: a copy of the potential)
     E.phase = phase0;
-    if (HIPFAIL(copy_phi(s, false))) rc = LBFS_E_DEVICE;
+    if (saved && HIPFAIL(copy_phi(s, false))) rc = LBFS_E_DEVICE;
     if (rc == LBFS_OK) rc = apply_shapes(s, best_s, best_m);
     if (rc == LBFS_OK && (HIPFAIL(exec_mag(E, 0, 1.0, 1)) || HIPFAIL(hipStreamSynchronize(E.stream))))
         rc = LBFS_E_DEVICE;
@@ -1419,16 +1434,19 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
     Exec& E = b->E;
     if (E.ninst > 0) {
         const int phase0 = E.phase;
-        for (Slot& q : b->slots)
-            if (q.s) HIPCHK(copy_phi(q.s, true));
         best_s = 0;
         for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
             b->stage_shape = k;
             b->dirty = true;
             rc = batch_rebuild(b);
-            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_stage(E, 0); }, &t[k]);
+            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
             if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
         }
+        // the potentials are stashed only once every stage timing is done (stage 2 writes
+        // the stash field)
+        const bool stash = rc == LBFS_OK;
+        for (Slot& q : b->slots)
+            if (q.s && stash && HIPFAIL(copy_phi(q.s, true))) rc = LBFS_E_DEVICE;
         best_m = 0;
         b->stage_shape = best_s;
         for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
@@ -1443,7 +1461,7 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
         for (Slot& q : b->slots)
             if (q.s) {
                 q.s->E.phase = phase0;
-                if (HIPFAIL(copy_phi(q.s, false))) rc = LBFS_E_DEVICE;
+                if (stash && HIPFAIL(copy_phi(q.s, false))) rc = LBFS_E_DEVICE;
             }
         if (rc != LBFS_OK) return rc;
         rc = lbfs_batch_set_tile_shapes(b, best_s, best_m);

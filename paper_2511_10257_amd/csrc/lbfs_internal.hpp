@@ -13,14 +13,20 @@ namespace lbfs {
 
 // Tile shapes (cells) and workgroup sizes. The kernels loop over their tile plus halo
 // and over its faces, so any shape works; these are the candidates the autotuner times
-// (index 0 is the default). Stage kernels stage the tile plus a 3-cell halo; FP32 tiles
-// 32 wide let each half-wave work on one contiguous LDS row.
+// (index 0, the default, was the fastest on 256^2 to 1024^2 grids and on batches).
+// Stage kernels stage the tile plus a 3-cell halo.
 struct TileShape {
     int tx, ty, nt;
 };
-constexpr int NSTAGE_SHAPES = 3;
-constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {{32, 8, 576}, {16, 16, 576}, {64, 4, 704}};
-constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {{16, 8, 320}, {8, 16, 320}, {32, 4, 384}};
+// Small workgroups: with the stage kernels' register use (about 90 VGPRs in FP32, 180 in
+// FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
+// other's barrier and LDS waits better than one large one, although small tiles
+// recompute more halo cells (3x for 8 x 8) and faces (2.25 per cell).
+constexpr int NSTAGE_SHAPES = 5;
+constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
+    {8, 8, 192}, {16, 4, 256}, {8, 8, 256}, {16, 8, 320}, {32, 4, 384}};
+constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
+    {8, 8, 256}, {8, 8, 192}, {16, 4, 256}, {16, 8, 320}, {8, 4, 128}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
 // (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1.
 constexpr int MAG_KMAX = 4;
@@ -72,15 +78,17 @@ struct DevInst {
 // launchers (lbfs_kernels.hip); all enqueue on `stream`, return hipError_t
 // stage kernel of tile shape `shape` (index into the precision's table); stage 0 is
 // the plain right-hand side R(W) into W1
+// (with e0 / e1 the launch records the kernel's start / end time into them)
 template <typename T>
 hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                        hipStream_t stream);
+                        hipStream_t stream, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
 // residual partials when residual != 0, on tiles of MAG_SHAPES[shape]. Reads the
 // potential buffer *pidx and flips *pidx once per launch.
 template <typename T>
 hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
-                      const Tile* tiles, int ntiles, hipStream_t stream);
+                      const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 // per-tile FP64 partial sums of the observables over stage tiles of shape `shape`
 template <typename T>
 hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);

@@ -20,7 +20,23 @@
 // the stage kernel reads each tile plus a 3-cell halo once into LDS.
 #include "lbfs_internal.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace lbfs {
+
+// Launch on `stream`; with timing events the launch timestamps the kernel's own start
+// and end into them (hipExtLaunchKernelGGL), so the measured duration holds no
+// dispatch gap.
+template <typename K, typename... A>
+hipError_t launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t e0, hipEvent_t e1,
+                        A... args)
+{
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------ helpers
 
@@ -631,30 +647,32 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
 
 template <typename T, int TX, int TY, int NT>
 hipError_t launch_stage_shape(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                              hipStream_t stream)
+                              hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
-    dim3 grid(ntiles), block(NT);
+    const dim3 grid(ntiles), block(NT);
     switch (stage) {
-    case 0: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 0>), grid, block, 0, stream, insts, tiles, pidx); break;
-    case 1: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 1>), grid, block, 0, stream, insts, tiles, pidx); break;
-    case 2: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 2>), grid, block, 0, stream, insts, tiles, pidx); break;
-    default: hipLaunchKernelGGL((k_stage<T, TX, TY, NT, 3>), grid, block, 0, stream, insts, tiles, pidx); break;
+    case 0: return launch_timed(k_stage<T, TX, TY, NT, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 1: return launch_timed(k_stage<T, TX, TY, NT, 1>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 2: return launch_timed(k_stage<T, TX, TY, NT, 2>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    default: return launch_timed(k_stage<T, TX, TY, NT, 3>, grid, block, stream, e0, e1, insts, tiles, pidx);
     }
-    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                        hipStream_t stream)
+                        hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     constexpr bool f64 = sizeof(T) == 8;
-    constexpr TileShape S0 = stage_shape(f64, 0), S1 = stage_shape(f64, 1), S2 = stage_shape(f64, 2);
-    static_assert(NSTAGE_SHAPES == 3, "one case per shape");
+    constexpr TileShape S0 = stage_shape(f64, 0), S1 = stage_shape(f64, 1), S2 = stage_shape(f64, 2),
+                        S3 = stage_shape(f64, 3), S4 = stage_shape(f64, 4);
+    static_assert(NSTAGE_SHAPES == 5, "one case per shape");
     if (ntiles <= 0) return hipSuccess;
     switch (shape) {
-    case 0: return launch_stage_shape<T, S0.tx, S0.ty, S0.nt>(stage, pidx, insts, tiles, ntiles, stream);
-    case 1: return launch_stage_shape<T, S1.tx, S1.ty, S1.nt>(stage, pidx, insts, tiles, ntiles, stream);
-    case 2: return launch_stage_shape<T, S2.tx, S2.ty, S2.nt>(stage, pidx, insts, tiles, ntiles, stream);
+    case 0: return launch_stage_shape<T, S0.tx, S0.ty, S0.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    case 1: return launch_stage_shape<T, S1.tx, S1.ty, S1.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    case 2: return launch_stage_shape<T, S2.tx, S2.ty, S2.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    case 3: return launch_stage_shape<T, S3.tx, S3.ty, S3.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    case 4: return launch_stage_shape<T, S4.tx, S4.ty, S4.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -882,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
 
 template <typename T>
 hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
-                      const Tile* tiles, int ntiles, hipStream_t stream)
+                      const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     constexpr TileShape M0 = MAG_SHAPES[0], M1 = MAG_SHAPES[1], M2 = MAG_SHAPES[2];
     static_assert(NMAG_SHAPES == 3, "one case per shape");
@@ -890,28 +908,31 @@ hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* p
     if (shape < 0 || shape >= NMAG_SHAPES) return hipErrorInvalidValue;
     // the potential is read from phi[*pidx] and written to the other buffer (halo cells
     // of a tile belong to other workgroups); sweeps beyond the LDS halo run as further
-    // launches
+    // launches (timing: start of the first, end of the last)
+    bool first = true;
     do {
         const int k = nsweeps > MAG_KMAX ? MAG_KMAX : nsweeps;
         nsweeps -= k;
         const int res = residual && nsweeps == 0;
+        const hipEvent_t a = first ? e0 : nullptr, b = nsweeps == 0 ? e1 : nullptr;
+        hipError_t e;
         switch (shape) {
         case 0:
-            hipLaunchKernelGGL((k_mag_fused<T, M0.tx, M0.ty, M0.nt>), dim3(ntiles), dim3(M0.nt), 0, stream, insts,
-                               tiles, k, omega, res, *pidx);
+            e = launch_timed(k_mag_fused<T, M0.tx, M0.ty, M0.nt>, dim3(ntiles), dim3(M0.nt), stream, a, b, insts,
+                             tiles, k, omega, res, *pidx);
             break;
         case 1:
-            hipLaunchKernelGGL((k_mag_fused<T, M1.tx, M1.ty, M1.nt>), dim3(ntiles), dim3(M1.nt), 0, stream, insts,
-                               tiles, k, omega, res, *pidx);
+            e = launch_timed(k_mag_fused<T, M1.tx, M1.ty, M1.nt>, dim3(ntiles), dim3(M1.nt), stream, a, b, insts,
+                             tiles, k, omega, res, *pidx);
             break;
         default:
-            hipLaunchKernelGGL((k_mag_fused<T, M2.tx, M2.ty, M2.nt>), dim3(ntiles), dim3(M2.nt), 0, stream, insts,
-                               tiles, k, omega, res, *pidx);
+            e = launch_timed(k_mag_fused<T, M2.tx, M2.ty, M2.nt>, dim3(ntiles), dim3(M2.nt), stream, a, b, insts,
+                             tiles, k, omega, res, *pidx);
             break;
         }
-        const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         *pidx ^= 1;
+        first = false;
     } while (nsweeps > 0);
     return hipSuccess;
 }
@@ -1003,8 +1024,10 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
 }
 
 #define LBFS_INSTANTIATE(T)                                                                          \
-    template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t); \
-    template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t); \
+    template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t, hipEvent_t, \
+                                        hipEvent_t);                                                   \
+    template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
+                                      hipEvent_t, hipEvent_t);                                         \
     template hipError_t launch_state_partials<T>(int, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \

@@ -76,7 +76,8 @@ def test_batch_autotune_keeps_every_member():
     slots = [batch.admit(p) for p in probs]
     batch.step(6)
     res = batch.autotune(reps=3)
-    assert 0 <= res["stage_shape"] < 3 and 0 <= res["mag_shape"] < 3
+    assert 0 <= res["stage_shape"] < len(lbfs.tile_shapes("stage"))
+    assert 0 <= res["mag_shape"] < len(lbfs.tile_shapes("mag"))
     batch.step(6)
     for p, k in zip(probs, slots):
         alone = lbfs.Solver(p)
