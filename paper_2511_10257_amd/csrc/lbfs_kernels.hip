@@ -21,6 +21,7 @@
 #include "lbfs_internal.hpp"
 
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 namespace lbfs {
 
@@ -713,26 +714,29 @@ hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* ti
 // ------------------------------------------------------------- magnetics
 
 // Fused magnetic phase on one tile of MTX x MTY cells: permeability (Eq. 2 with
-// Eq. 11) of the tile plus a halo of 2*MAG_KMAX+1 cells into LDS, up to MAG_KMAX
-// red-black sweeps of the compact system done in LDS (temporal blocking: the
-// region where the sweeps are exact shrinks by one cell per colour pass), the tile's
-// potential written back, and optionally the FP64 residual of the tile. Each cell
-// update is the same arithmetic as an untiled red-black pass, so the result does not
-// depend on the tiling.
+// Eq. 11) of the tile plus a halo of 2*MAG_KMAX+1 cells, up to MAG_KMAX red-black
+// sweeps of the compact system done in LDS (temporal blocking: the region where the
+// sweeps are exact shrinks by one cell per colour pass), the tile's potential written
+// back, and optionally the FP64 residual of the tile. Each cell update is the same
+// arithmetic as an untiled red-black pass, so the result does not depend on the tiling.
 //
 // Update of cell c: phi'_c <- (1-w) phi'_c + w sum_f a_f (phi'_nb + phi0_nb - phi0_c) / sum_f a_f,
 // a_f = mean(mu) on interior faces, 2 mu_c towards a fixed-potential wall half a cell
 // away (where phi' = 0), no term at an insulating wall; phi0 = -(h0x x + h0y y).
+//
+// LDS holds the potential split by colour: cell (lx, ly) of colour c lives at
+// ph[c][ly * RXH + lx / 2], so the cells a colour pass updates, and the neighbours it
+// reads (all of the other colour), are contiguous. Each thread owns fixed cells of
+// both colours and keeps their face weights, constant term and 1 / sum of weights in
+// registers; a pass costs four LDS reads and one write per cell.
 template <typename T, int MTX, int MTY>
 struct MagLds {
     static constexpr int H = 2 * MAG_KMAX + 1;
     static constexpr int RX = MTX + 2 * H, RY = MTY + 2 * H, NR = RX * RY;
+    static constexpr int RXH = RX / 2, HALF = NR / 2;
     static_assert(RX % 2 == 0, "region rows hold whole red-black pairs");
-    T phi[NR];
-    T we[NR];         // weight of the east face (0 unless both cells are in the domain)
-    T wn[NR];         // weight of the north face
-    T b[NR];          // sum_f a_f (phi0_nb - phi0_c): the applied-field part of the numerator
-    T rden[NR];       // 1 / sum_f a_f (0: cell not updated)
+    T ph[2][HALF];   // potential by colour
+    T mu[NR];        // permeability, natural layout (set-up only); 0 outside the domain
     double red[16];
 };
 
@@ -743,18 +747,20 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
 {
     using L = MagLds<T, MTX, MTY>;
     static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
-    constexpr int NIT = (L::NR + NT - 1) / NT;
+    constexpr int NIT = (L::NR + NT - 1) / NT;       // region cells per thread (load)
+    constexpr int NOWN = (L::HALF + NT - 1) / NT;    // owned cells per thread and colour
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
     const int tid = threadIdx.x;
     const int nx = I.nx, ny = I.ny;
     const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
+    const int par0 = (ox + oy) & 1;                  // colour of region cell (0, 0)
     const GLOBAL T* phin = gp<T>(I.phi[pin]);
     const GLOBAL T* He_ = gp<T>(I.W[0]);
     const GLOBAL T* C_ = gp<T>(I.W[4]);
-    // 1. load the region (all loads of this thread in flight together); mu = 0 outside
-    //    the domain. The permeability goes to rden temporarily.
+    // 1. load the region (all loads of this thread in flight together): permeability in
+    //    natural layout (0 outside the domain), potential by colour
     {
         T vHe[NIT], vC[NIT], vph[NIT];
         bool vin[NIT];
@@ -784,6 +790,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             if (r >= L::NR) break;
+            const int lx = r % L::RX, ly = r / L::RX;
             T mu = T(0);
             if (vin[it]) {
                 T Tt, Fl;
@@ -791,100 +798,111 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
                 const T ct = clamp01(vC[it]);
                 mu = T(I.mu0) * (T(1) + mix3<T>(I.chi, ct * (T(1) - Fl), ct));
             }
-            s.rden[r] = mu;
-            s.phi[r] = vin[it] ? vph[it] : T(0);
+            s.mu[r] = mu;
+            s.ph[(par0 + lx + ly) & 1][ly * L::RXH + (lx >> 1)] = vin[it] ? vph[it] : T(0);
         }
     }
     __syncthreads();
-    // 2. face weights (mean permeability of two domain cells), then the constant part of
-    //    the numerator and 1 / sum of the weights; a fixed-potential wall half a cell away
-    //    has weight 2 mu_c, an insulating wall none.
+    // 2. owned cells: item q = c * NOWN + j is the (tid + j * NT)-th cell of colour c.
+    //    Face weights (mean permeability of two domain cells; a fixed-potential wall half
+    //    a cell away has weight 2 mu_c, an insulating wall none), the constant part of the
+    //    numerator and 1 / sum of the weights; rd = 0 marks a cell that is not updated
+    //    (region ring 0 or outside the domain).
     const T hx = T(I.h0x) * T(I.dx), hy = T(I.h0y) * T(I.dx);
-    for (int r = tid; r < L::NR; r += NT) {
-        const int lx = r % L::RX, ly = r / L::RX;
-        const T muc = s.rden[r];
-        const T mue = lx + 1 < L::RX ? s.rden[r + 1] : T(0);
-        const T mun = ly + 1 < L::RY ? s.rden[r + L::RX] : T(0);
-        s.we[r] = (muc > T(0) && mue > T(0)) ? T(0.5) * (muc + mue) : T(0);
-        s.wn[r] = (muc > T(0) && mun > T(0)) ? T(0.5) * (muc + mun) : T(0);
-    }
-    __syncthreads();
-    T bb[NIT], dd[NIT];
+    T wq[2 * NOWN][4], bq[2 * NOWN], rq[2 * NOWN], pq[2 * NOWN];
+    int iq[2 * NOWN], sq[2 * NOWN];   // own index in ph[c], row start of the other colour + shift
 #pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const int r = tid + it * NT;
-        bb[it] = T(0);
-        dd[it] = T(0);
-        if (r >= L::NR) break;
-        const int lx = r % L::RX, ly = r / L::RX;
-        const T muc = s.rden[r];
-        if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1 || !(muc > T(0))) continue;
-        const T w[4] = {s.we[r - 1], s.we[r], s.wn[r - L::RX], s.wn[r]};   // W, E, S, N
+    for (int q = 0; q < 2 * NOWN; q++) {
+        const int c = q / NOWN, k = tid + (q % NOWN) * NT;
+        rq[q] = T(0);
+        bq[q] = T(0);
+        pq[q] = T(0);
+        iq[q] = 0;
+        sq[q] = 0;
+#pragma unroll
+        for (int d = 0; d < 4; d++) wq[q][d] = T(0);
+        if (k >= L::HALF) continue;
+        const int ly = k / L::RXH, kx = k % L::RXH;
+        const int sh = (par0 + ly + c) & 1;           // lx = 2 kx + sh
+        const int lx = 2 * kx + sh;
+        iq[q] = k;
+        sq[q] = ly * L::RXH + kx + sh;                 // east neighbour; west is one less
+        pq[q] = s.ph[c][k];
+        if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
+        const int r = ly * L::RX + lx;
+        const T muc = s.mu[r];
+        if (!(muc > T(0))) continue;
+        const T mnb[4] = {s.mu[r - 1], s.mu[r + 1], s.mu[r - L::RX], s.mu[r + L::RX]};   // W, E, S, N
         const T D0[4] = {hx, -hx, hy, -hy};   // phi0_nb - phi0_c across each face
         T bsum = T(0), den = T(0);
 #pragma unroll
         for (int d = 0; d < 4; d++) {
-            if (w[d] > T(0)) {
-                bsum += w[d] * D0[d];
-                den += w[d];
-            } else {
-                const int q = r + (d == 0 ? -1 : d == 1 ? 1 : d == 2 ? -L::RX : L::RX);
-                const bool nb_in = s.rden[q] > T(0);
-                if (!nb_in && I.mbc[d]) {   // a wall face
-                    const T ww = T(2) * muc;
-                    bsum += ww * (T(0.5) * D0[d]);
-                    den += ww;
-                }
+            const bool nb_in = mnb[d] > T(0);
+            // (same operand order as the mean over the face from its west / south cell)
+            const T w = nb_in ? (d == 0 || d == 2 ? T(0.5) * (mnb[d] + muc) : T(0.5) * (muc + mnb[d])) : T(0);
+            wq[q][d] = w;
+            if (w > T(0)) {
+                bsum += w * D0[d];
+                den += w;
+            } else if (!nb_in && I.mbc[d]) {   // a wall face
+                const T ww = T(2) * muc;
+                bsum += ww * (T(0.5) * D0[d]);
+                den += ww;
             }
         }
-        bb[it] = bsum;
-        dd[it] = den;
+        bq[q] = bsum;
+        rq[q] = den > T(0) ? T(1) / den : T(0);
     }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const int r = tid + it * NT;
-        if (r >= L::NR) break;
-        s.b[r] = bb[it];
-        s.rden[r] = dd[it] > T(0) ? T(1) / dd[it] : T(0);
-    }
-    __syncthreads();
-    // 3. red-black passes in LDS
+    // 3. red-black sweeps: a colour pass reads the other colour's array and writes its
+    //    own (the colour is a compile-time constant, so the owned-cell registers are
+    //    never indexed dynamically)
     const T om = T(omega);
-    constexpr int HALF = L::NR / 2, PAIRS = L::RX / 2;
-    constexpr int NITH = (HALF + NT - 1) / NT;
-    for (int pass = 0; pass < 2 * nsweeps; pass++) {
-        const int color = pass & 1;
+    auto colour_pass = [&](auto colour) {
+        constexpr int c = decltype(colour)::value;
+        const T* po = s.ph[c ^ 1];
 #pragma unroll
-        for (int it = 0; it < NITH; it++) {
-            const int k = tid + it * NT;
-            if (k >= HALF) break;
-            const int ly = k / PAIRS;
-            const int lx = 2 * (k % PAIRS) + ((ox + oy + ly + color) & 1);
-            const int r = ly * L::RX + lx;
-            const T rd = s.rden[r];
-            if (rd == T(0)) continue;   // ring 0, outside the domain
-            const T num = s.b[r] + s.we[r - 1] * s.phi[r - 1] + s.we[r] * s.phi[r + 1] +
-                          s.wn[r - L::RX] * s.phi[r - L::RX] + s.wn[r] * s.phi[r + L::RX];
-            s.phi[r] = (T(1) - om) * s.phi[r] + om * num * rd;
+        for (int j = 0; j < NOWN; j++) {
+            constexpr int q0 = c * NOWN;
+            const int q = q0 + j;
+            if (rq[q] == T(0)) continue;
+            const int e = sq[q], k = iq[q];
+            const T num = bq[q] + wq[q][0] * po[e - 1] + wq[q][1] * po[e] + wq[q][2] * po[k - L::RXH] +
+                          wq[q][3] * po[k + L::RXH];
+            pq[q] = (T(1) - om) * pq[q] + om * num * rq[q];
+            s.ph[c][k] = pq[q];
         }
         __syncthreads();
+    };
+    for (int sw = 0; sw < nsweeps; sw++) {
+        colour_pass(std::integral_constant<int, 0>{});
+        colour_pass(std::integral_constant<int, 1>{});
     }
-    // 4. write the tile; FP64 residual r_c = sum_f a_f (phi_nb - phi_c)
+    // 4. FP64 residual r_c = sum_f a_f (phi_nb - phi_c) over the owned cells of the tile
     double r2 = 0.0;
-    GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
-    for (int c = tid; c < MTX * MTY; c += NT) {
-        const int gx = tile.x0 + c % MTX, gy = tile.y0 + c / MTX;
-        if (gx >= nx || gy >= ny) continue;
-        const int r = (c / MTX + L::H) * L::RX + (c % MTX + L::H);
-        phout[(size_t)gy * I.pitch + gx] = s.phi[r];
-        if (residual && s.rden[r] != T(0)) {
-            const double res = double(s.b[r]) + double(s.we[r - 1]) * double(s.phi[r - 1]) +
-                               double(s.we[r]) * double(s.phi[r + 1]) +
-                               double(s.wn[r - L::RX]) * double(s.phi[r - L::RX]) +
-                               double(s.wn[r]) * double(s.phi[r + L::RX]) - double(s.phi[r]) / double(s.rden[r]);
+    if (residual) {
+#pragma unroll
+        for (int q = 0; q < 2 * NOWN; q++) {
+            if (rq[q] == T(0)) continue;
+            const int c = q / NOWN, k = iq[q];
+            const int ly = k / L::RXH, lx = 2 * (k % L::RXH) + ((par0 + ly + c) & 1);
+            const int tx = lx - L::H, ty = ly - L::H;
+            if (tx < 0 || tx >= MTX || ty < 0 || ty >= MTY || tile.x0 + tx >= nx || tile.y0 + ty >= ny) continue;
+            const T* po = s.ph[c ^ 1];
+            const int e = sq[q];
+            const double res = double(bq[q]) + double(wq[q][0]) * double(po[e - 1]) +
+                               double(wq[q][1]) * double(po[e]) + double(wq[q][2]) * double(po[k - L::RXH]) +
+                               double(wq[q][3]) * double(po[k + L::RXH]) - double(pq[q]) / double(rq[q]);
             r2 += res * res;
         }
+    }
+    // 5. write the tile in natural order (coalesced)
+    GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
+    for (int cidx = tid; cidx < MTX * MTY; cidx += NT) {
+        const int tx = cidx % MTX, ty = cidx / MTX;
+        const int gx = tile.x0 + tx, gy = tile.y0 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        const int lx = tx + L::H, ly = ty + L::H;
+        phout[(size_t)gy * I.pitch + gx] = s.ph[(par0 + lx + ly) & 1][ly * L::RXH + (lx >> 1)];
     }
     if (residual) {
         r2 = wave_sum(r2);
