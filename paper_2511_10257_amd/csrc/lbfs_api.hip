@@ -306,6 +306,42 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
     return rc;
 }
 
+// the descriptor's parameters in one precision, with the kernels' derived constants
+template <typename T>
+void fill_coef(Coef<T>& K, const DevInst& I)
+{
+    for (int k = 0; k < 3; k++) {
+        K.rho[k] = T(I.rho[k]);
+        K.mu[k] = T(I.mu_[k]);
+        K.lam[k] = T(I.lam[k]);
+        K.cp[k] = T(I.cp[k]);
+        K.chi[k] = T(I.chi[k]);
+    }
+    for (int w = 0; w < 4; w++) K.tval[w] = T(I.tval[w]);
+    K.latent = T(I.latent);
+    K.tm = T(I.tm);
+    K.dx = T(I.dx);
+    K.dt = T(I.dt);
+    K.cpref = T(I.cpref);
+    K.qg = T(I.qg);
+    K.tau_g = T(I.tau_g);
+    K.beta = T(I.beta);
+    K.kappa = T(I.kappa);
+    K.mu0 = T(I.mu0);
+    K.h0x = T(I.h0x);
+    K.h0y = T(I.h0y);
+    K.vc = T(I.vc);
+    K.grav[0] = T(I.grav[0]);
+    K.grav[1] = T(I.grav[1]);
+    K.idx = T(1.0 / I.dx);
+    K.inv2dx = T(1.0 / (2.0 * I.dx));
+    K.idx2 = T(1.0 / (I.dx * I.dx));
+    K.i_halfdx = T(2.0 / I.dx);
+    K.idt = T(1.0 / I.dt);
+    K.tauf_k = T(3.0 / I.dts);
+    K.tauh_k = T(3.0 / (I.cpref * I.dts));
+}
+
 // observables of one instance from its FP64 reduction results
 int fill_observables(const lbfs_params& p, double t, int64_t step, double vol0, const double* r,
                      lbfs_observables* o)
@@ -608,6 +644,8 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     I.grav[0] = p->gravity[0];
     I.grav[1] = p->gravity[1];
     I.vc = 1.0 - p->rho[0] / p->rho[1];
+    fill_coef(I.cf, I);
+    fill_coef(I.cd, I);
 
     std::vector<Tile> tp;
     append_tiles(tp, 0, p->nx, p->ny, TileShape{PT_TX, PT_TY, PT_TX * PT_TY});

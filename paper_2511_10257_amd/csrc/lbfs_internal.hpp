@@ -50,9 +50,27 @@ struct Tile {
     int32_t idx;     // tile index inside its instance (partials slot)
 };
 
+// Parameters of one instance in one precision, with the derived constants the kernels
+// need precomputed on the host: the kernels read them as uniform scalars (no per-thread
+// conversion from FP64, no per-thread division of constants).
+template <typename T>
+struct Coef {
+    T rho[3], mu[3], lam[3], cp[3], chi[3];   // [solid, liquid, gas] (Eq. 11)
+    T tval[4];                                // fixed wall temperatures
+    T latent, tm, dx, dt, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, vc;
+    T grav[2];
+    T idx;      // 1 / dx
+    T inv2dx;   // 1 / (2 dx)
+    T idx2;     // 1 / dx^2
+    T i_halfdx; // 2 / dx
+    T idt;      // 1 / dt
+    T tauf_k;   // 3 / delta_t:           tau_f = 1/2 + (mu / rho) tauf_k
+    T tauh_k;   // 3 / (Cp,ref delta_t):  tau_h = 1/2 + (lambda / rho) tauh_k
+};
+
 // Per-instance descriptor, resident in device memory. Field pointers are typed by
-// the instance precision (float or double); parameters are kept in FP64 and
-// converted once per workgroup.
+// the instance precision (float or double); parameters are kept in FP64 (host side
+// and FP64 reductions) and in the coefficient blocks of both precisions.
 struct DevInst {
     void* W[5];      // state at the start of the step: He, p, Mx, My, C
     void* W1[5];     // stage-1 output (also the R(W) output of the rhs call)
@@ -73,7 +91,16 @@ struct DevInst {
     double latent, tm, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;
     double grav[2];
     double vc;       // 1 - rho_s / rho_l
+    Coef<float> cf;  // the parameters above in FP32 (FP32 instances)
+    Coef<double> cd; // and in FP64 (FP64 instances)
 };
+
+template <typename T>
+__host__ __device__ inline const Coef<T>& coef(const DevInst& I);
+template <>
+__host__ __device__ inline const Coef<float>& coef<float>(const DevInst& I) { return I.cf; }
+template <>
+__host__ __device__ inline const Coef<double>& coef<double>(const DevInst& I) { return I.cd; }
 
 // launchers (lbfs_kernels.hip); all enqueue on `stream`, return hipError_t
 // stage kernel of tile shape `shape` (index into the precision's table); stage 0 is

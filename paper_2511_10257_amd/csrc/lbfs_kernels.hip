@@ -52,28 +52,37 @@ __device__ __forceinline__ T clamp01(T c) { return c < T(0) ? T(0) : (c > T(1) ?
 
 // Eq. 11: property of the solid / liquid / gas mixture
 template <typename T>
-__device__ __forceinline__ T mix3(const double* g, T fs, T ct)
+__device__ __forceinline__ T mix3(const T* g, T fs, T ct)
 {
-    return fs * T(g[0]) + (T(1) - fs) * ct * T(g[1]) + (T(1) - fs) * (T(1) - ct) * T(g[2]);
+    return fs * g[0] + (T(1) - fs) * ct * g[1] + (T(1) - fs) * (T(1) - ct) * g[2];
 }
+
+// 1 / x for x bounded away from 0 and infinity (densities): the hardware reciprocal
+// (1 ulp) in FP32, a correctly rounded division in FP64
+template <typename T>
+__device__ __forceinline__ T rcp_bounded(T x);
+template <>
+__device__ __forceinline__ float rcp_bounded<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp_bounded<double>(double x) { return 1.0 / x; }
 
 // Eq. 8 with Ts = Tl = Tm, local latent heat Ct L and branch heat capacities of the
 // solid-gas and liquid-gas mixtures
 template <typename T>
-__device__ __forceinline__ void enthalpy_state(const DevInst& I, T He, T C, T& Tt, T& Fl)
+__device__ __forceinline__ void enthalpy_state(const Coef<T>& K, T He, T C, T& Tt, T& Fl)
 {
     const T ct = clamp01(C);
-    const T cps = ct * T(I.cp[0]) + (T(1) - ct) * T(I.cp[2]);
-    const T cpl = ct * T(I.cp[1]) + (T(1) - ct) * T(I.cp[2]);
-    const T tm = T(I.tm);
+    const T cps = ct * K.cp[0] + (T(1) - ct) * K.cp[2];
+    const T cpl = ct * K.cp[1] + (T(1) - ct) * K.cp[2];
+    const T tm = K.tm;
     const T Hes = cps * tm;
-    const T Hel = cpl * tm + ct * T(I.latent);
+    const T Hel = cpl * tm + ct * K.latent;
     // branch of Eq. 8, then the one quotient that branch needs
     const bool liq = He > Hel;
     const bool mushy = !liq && He >= Hes && Hel > Hes;
     const T num = liq ? He - Hel : (mushy ? He - Hes : He);
     const T den = liq ? cpl : (mushy ? Hel - Hes : cps);
-    const T q = num / den;
+    const T q = num / den;   // exact: the mushy denominator Ct L can be tiny
     Fl = liq ? T(1) : (mushy ? q : T(0));
     Tt = liq ? tm + q : (mushy ? tm : q);
 }
@@ -84,18 +93,18 @@ struct Prim {
 };
 
 template <typename T>
-__device__ __forceinline__ Prim<T> primitives(const DevInst& I, T He, T p, T Mx, T My, T C)
+__device__ __forceinline__ Prim<T> primitives(const Coef<T>& K, T He, T p, T Mx, T My, T C)
 {
     Prim<T> q;
     T Fl;
-    enthalpy_state<T>(I, He, C, q.Tt, Fl);
+    enthalpy_state<T>(K, He, C, q.Tt, Fl);
     const T ct = clamp01(C);
     q.fs = ct * (T(1) - Fl);
-    q.rho = mix3<T>(I.rho, q.fs, ct);
-    q.mu = mix3<T>(I.mu_, q.fs, ct);
-    q.lam = mix3<T>(I.lam, q.fs, ct);
-    q.cp = mix3<T>(I.cp, q.fs, ct);
-    const T inv = T(3) / q.rho;   // 1 / (rho cs^2)
+    q.rho = mix3<T>(K.rho, q.fs, ct);
+    q.mu = mix3<T>(K.mu, q.fs, ct);
+    q.lam = mix3<T>(K.lam, q.fs, ct);
+    q.cp = mix3<T>(K.cp, q.fs, ct);
+    const T inv = T(3) * rcp_bounded(q.rho);   // 1 / (rho cs^2)
     q.u = Mx * inv;
     q.v = My * inv;
     q.p = p;
@@ -147,10 +156,10 @@ struct Side {
 // M_eq(face) are the closed-form moments of the face equilibria (D2Q9 identities).
 // Output: F[0] He, F[1] p, F[2] normal momentum, F[3] tangential momentum, F[4] C.
 template <typename T>
-__device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, const Side<T>& R,
+__device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, const Side<T>& R,
                                           T F[5])
 {
-    const T h = T(0.5) * T(I.dx);
+    const T h = T(0.5) * K.dx;
     // reconstructions at the nine points, per variable
     T rc[NV][9];
 #pragma unroll
@@ -168,16 +177,16 @@ __device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, co
         rc[k][8] = L.v[k] + h * L.gt[k];
     }
     const T rho_f = rc[V_RHO][0];
-    const T irho_f = T(1) / rho_f;
+    const T irho_f = rcp_bounded(rho_f);
     const T mu_f = T(0.5) * (L.mu + R.mu);
     const T lam_f = T(0.5) * (L.lam + R.lam);
     const T cp_f = T(0.5) * (L.cp + R.cp);
-    const T cpref = T(I.cpref);
-    const T Q = T(I.qg);
+    const T cpref = K.cpref;
+    const T Q = K.qg;
     // tau_f = 1/2 + mu / (rho cs^2 delta_t), tau_h = 1/2 + lambda / (rho Cp,ref cs^2 delta_t)
-    const T tau_f = T(0.5) + mu_f * irho_f * T(3.0 / I.dts);
-    const T tau_h = T(0.5) + lam_f * irho_f * T(3.0 / (I.cpref * I.dts));
-    const T tau_g = T(I.tau_g);
+    const T tau_f = T(0.5) + mu_f * irho_f * K.tauf_k;
+    const T tau_h = T(0.5) + lam_f * irho_f * K.tauh_k;
+    const T tau_g = K.tau_g;
 
     // (e_n, e_t) of the nine points in the face frame and their weights
     constexpr int EN[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -215,7 +224,7 @@ __device__ __forceinline__ void face_flux(const DevInst& I, const Side<T>& L, co
     const T C_f = rc[V_C][0] - T(3) * Q * T(5.0 / 9.0) * rc[V_MUC][0] + Cs;
     const T He_f = rc[V_HE][0] - cpref * rc[V_T][0] + Hs;
     T T_f, Fl_f;
-    enthalpy_state<T>(I, He_f, C_f, T_f, Fl_f);
+    enthalpy_state<T>(K, He_f, C_f, T_f, Fl_f);
     // Eqs. 40 and 43 through the star distributions
     F[1] = Sn;
     F[2] = (T(1.5) - tau_f) * (p_f + rho_f * un_f * un_f) * T(1.0 / 3.0) + (tau_f - T(0.5)) * Mnn;
@@ -297,10 +306,11 @@ template <typename T>
 __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int gx, int gy, double* pr)
 {
     T T1, Fl1;
-    enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
+    const Coef<T>& K = coef<T>(I);
+    enthalpy_state<T>(K, Wn[0], Wn[4], T1, Fl1);
     const T ct1 = clamp01(Wn[4]);
     const T fs1 = ct1 * (T(1) - Fl1);
-    const T rho1 = mix3<T>(I.rho, fs1, ct1);
+    const T rho1 = mix3<T>(K.rho, fs1, ct1);
     const double u1 = double(Wn[2]) * 3.0 / double(rho1), v1 = double(Wn[3]) * 3.0 / double(rho1);
     const double um = sqrt(u1 * u1 + v1 * v1);
     bool finite = true;
@@ -315,7 +325,7 @@ __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int
     pr[PART_HEIGHT] = gx == I.col_height ? double(ct1) : 0.0;
     pr[PART_HEAT] = 0.0;
     if (gy == 0 && I.heat_on) {
-        const double lam1 = double(mix3<T>(I.lam, fs1, ct1));
+        const double lam1 = double(mix3<T>(K.lam, fs1, ct1));
         pr[PART_HEAT] = -lam1 * (double(T1) - I.tval[2]) / (0.5 * I.dx) * I.dx;
     }
 }
@@ -396,8 +406,9 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     const int tid = threadIdx.x;
     const int x0 = tile.x0, y0 = tile.y0;
     const int nx = I.nx, ny = I.ny, pitch = I.pitch;
-    const T dx = T(I.dx);
-    const T inv2dx = T(1) / (T(2) * dx);
+    const Coef<T>& K = coef<T>(I);
+    const T dx = K.dx;
+    const T inv2dx = K.inv2dx;
 
     T* const* Wbase = reinterpret_cast<T* const*>(I.W);
     T* const* Win = STAGE == 2 ? reinterpret_cast<T* const*>(I.W1)
@@ -445,20 +456,20 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             if (r >= L::NR) break;
-            Prim<T> q = primitives<T>(I, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]);
+            Prim<T> q = primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]);
             T ph = vph[it];
             const int wx = vwx[it], wy = vwy[it];
             if (wx >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
-                if (I.tbc[wx]) q.Tt = T(2) * T(I.tval[wx]) - q.Tt;
-                ph = I.mbc[wx] ? -ph : ph - T(I.h0x) * T(vdx[it]) * dx;
+                if (I.tbc[wx]) q.Tt = T(2) * K.tval[wx] - q.Tt;
+                ph = I.mbc[wx] ? -ph : ph - K.h0x * T(vdx[it]) * dx;
             }
             if (wy >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
-                if (I.tbc[wy]) q.Tt = T(2) * T(I.tval[wy]) - q.Tt;
-                ph = I.mbc[wy] ? -ph : ph - T(I.h0y) * T(vdy[it]) * dx;
+                if (I.tbc[wy]) q.Tt = T(2) * K.tval[wy] - q.Tt;
+                ph = I.mbc[wy] ? -ph : ph - K.h0y * T(vdy[it]) * dx;
             }
             s.q[Q_P][r] = q.p;
             s.q[Q_U][r] = q.u;
@@ -477,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
 
     // ---- B: chemical potential on tile + 2 (mu_c = 2 beta C (C-1)(2C-1) - kappa lap C)
     {
-        const T beta = T(I.beta), kappa = T(I.kappa), idx2 = T(1) / (dx * dx);
+        const T beta = K.beta, kappa = K.kappa, idx2 = K.idx2;
         for (int r = tid; r < L::NR; r += NT) {
             const int lx = r % L::RX, ly = r / L::RX;
             if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
@@ -490,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     __syncthreads();
 
     // ---- C: central gradients and |H|^2 on tile + 1
-    const T h0x = T(I.h0x), h0y = T(I.h0y);
+    const T h0x = K.h0x, h0y = K.h0y;
     for (int gi = tid; gi < L::NG; gi += NT) {
         const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
         const int r = ly * L::RX + lx;
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         gather_side<T>(s, rL, gL, xf ? 0 : 1, SL);
         gather_side<T>(s, rR, gR, xf ? 0 : 1, SR);
         T F[5];
-        face_flux<T>(I, SL, SR, F);
+        face_flux<T>(K, SL, SR, F);
         // walls: no mass or order-parameter flux; heat through the half cell
         const int gface = xf ? x0 + cx : y0 + cy;
         const int nax = xf ? nx : ny;
@@ -560,9 +571,9 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             F[1] = T(0);
             F[4] = T(0);
             if (I.tbc[wall]) {
-                const T k = s.q[Q_LAM][rc] / s.q[Q_RHO][rc];
-                const T Tc = s.q[Q_T][rc], Tw = T(I.tval[wall]);
-                F[0] = lo ? -k * (Tc - Tw) / (T(0.5) * dx) : -k * (Tw - Tc) / (T(0.5) * dx);
+                const T k = s.q[Q_LAM][rc] * rcp_bounded(s.q[Q_RHO][rc]);
+                const T Tc = s.q[Q_T][rc], Tw = K.tval[wall];
+                F[0] = lo ? -k * (Tc - Tw) * K.i_halfdx : -k * (Tw - Tc) * K.i_halfdx;
             } else {
                 F[0] = T(0);
             }
@@ -579,18 +590,18 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     if (inside) {
         const int r = (ly + 3) * L::RX + (lx + 3);
         const int gi = (ly + 1) * L::GX + (lx + 1);
-        const T dt = T(I.dt);
-        const T idt = T(1.0 / I.dt), idx = T(1.0 / I.dx);
+        const T dt = K.dt;
+        const T idt = K.idt, idx = K.idx;
         const T cs2 = T(1.0 / 3.0);
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
         if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
         else { Cn = cWb[4]; Hen = cWb[0]; }
         T Tn, Fln;
-        enthalpy_state<T>(I, Hen, Cn, Tn, Fln);
+        enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
         const T ctn = clamp01(Cn);
-        const T chi = mix3<T>(I.chi, ctn * (T(1) - Fln), ctn);
-        const T kmg = T(0.5) * T(I.mu0) * chi;
+        const T chi = mix3<T>(K.chi, ctn * (T(1) - Fln), ctn);
+        const T kmg = T(0.5) * K.mu0 * chi;
         const T fmx = kmg * (s.h2[gi + 1] - s.h2[gi - 1]) * inv2dx;
         const T fmy = kmg * (s.h2[gi + L::GX] - s.h2[gi - L::GX]) * inv2dx;
         // stage-state cell fields
@@ -603,15 +614,15 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         const T dmy = (s.muc[r + L::RX] - s.muc[r - L::RX]) * inv2dx;
         const T c = s.q[Q_C][r], rho = RH[r], u = U[r], v = V[r];
         T Tc, Flc;
-        enthalpy_state<T>(I, s.q[Q_HE][r], c, Tc, Flc);
+        enthalpy_state<T>(K, s.q[Q_HE][r], c, Tc, Flc);
         const T fs = clamp01(c) * (T(1) - Flc);
         const T Sv = cS;
-        const T vc = T(I.vc);
+        const T vc = K.vc;
         T src[5];
         src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
         src[1] = cs2 * (u * drx + v * dry) + rho * cs2 * vc * Sv;
-        src[2] = cs2 * (-c * dmx + fmx + rho * T(I.grav[0]) - rho * u * fs * idt);
-        src[3] = cs2 * (-c * dmy + fmy + rho * T(I.grav[1]) - rho * v * fs * idt);
+        src[2] = cs2 * (-c * dmx + fmx + rho * K.grav[0] - rho * u * fs * idt);
+        src[3] = cs2 * (-c * dmy + fmy + rho * K.grav[1] - rho * v * fs * idt);
         src[4] = c * vc * Sv;
         const int fW = ly * (TX + 1) + lx, fS = ly * TX + lx;
         T Rk[5];
@@ -639,7 +650,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             }
             // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
             T T1, Fl1;
-            enthalpy_state<T>(I, Wn[0], Wn[4], T1, Fl1);
+            enthalpy_state<T>(K, Wn[0], Wn[4], T1, Fl1);
             const T ct1 = clamp01(Wn[4]);
             gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) * idt;
         }
@@ -752,6 +763,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
+    const Coef<T>& K = coef<T>(I);
     const int tid = threadIdx.x;
     const int nx = I.nx, ny = I.ny;
     const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
@@ -794,9 +806,9 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
             T mu = T(0);
             if (vin[it]) {
                 T Tt, Fl;
-                enthalpy_state<T>(I, vHe[it], vC[it], Tt, Fl);
+                enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
                 const T ct = clamp01(vC[it]);
-                mu = T(I.mu0) * (T(1) + mix3<T>(I.chi, ct * (T(1) - Fl), ct));
+                mu = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
             }
             s.mu[r] = mu;
             s.ph[(par0 + lx + ly) & 1][ly * L::RXH + (lx >> 1)] = vin[it] ? vph[it] : T(0);
@@ -808,7 +820,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
     //    a cell away has weight 2 mu_c, an insulating wall none), the constant part of the
     //    numerator and 1 / sum of the weights; rd = 0 marks a cell that is not updated
     //    (region ring 0 or outside the domain).
-    const T hx = T(I.h0x) * T(I.dx), hy = T(I.h0y) * T(I.dx);
+    const T hx = K.h0x * K.dx, hy = K.h0y * K.dx;
     T wq[2 * NOWN][4], bq[2 * NOWN], rq[2 * NOWN], pq[2 * NOWN];
     int iq[2 * NOWN], sq[2 * NOWN];   // own index in ph[c], row start of the other colour + shift
 #pragma unroll
@@ -1017,7 +1029,8 @@ __global__ __launch_bounds__(PT_TX* PT_TY) void k_derived(const DevInst* __restr
     if (gx >= I.nx || gy >= I.ny) return;
     const size_t o = (size_t)gy * I.pitch + gx;
     T Tt, Fl;
-    enthalpy_state<T>(I, reinterpret_cast<const T*>(I.W[0])[o], reinterpret_cast<const T*>(I.W[4])[o], Tt, Fl);
+    enthalpy_state<T>(coef<T>(I), reinterpret_cast<const T*>(I.W[0])[o], reinterpret_cast<const T*>(I.W[4])[o], Tt,
+                      Fl);
     reinterpret_cast<T*>(I.W1[0])[o] = Tt;
     reinterpret_cast<T*>(I.W1[1])[o] = Fl;
 }
