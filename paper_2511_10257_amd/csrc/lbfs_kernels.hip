@@ -188,35 +188,68 @@ __device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, co
     const T tau_h = T(0.5) + lam_f * irho_f * K.tauh_k;
     const T tau_g = K.tau_g;
 
-    // (e_n, e_t) of the nine points in the face frame and their weights
+    // (e_n, e_t) of the nine points in the face frame. The sums over the points are
+    // taken per weight class (centre 4/9, axis 1/9, diagonal 1/36) without the weight,
+    // which is applied once per class at the end.
     constexpr int EN[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ET[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    const T WA[9] = {T(4.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0), T(1.0 / 9.0),
-                     T(1.0 / 36.0), T(1.0 / 36.0), T(1.0 / 36.0), T(1.0 / 36.0)};
-    T S0 = 0, Sn = 0, St = 0, Mnn = 0, Mnt = 0, Cs = 0, Gn = 0, Hs = 0, Hn = 0;
+    const T c3 = T(3) * cp_f;
+    T S0c, Hsc;
+    T S0a = 0, Hsa = 0, Sna = 0, Mnna = 0, Hna = 0, Sta = 0, Csa = 0, Gna = 0;
+    T S0d = 0, Hsd = 0, Snd = 0, Mnnd = 0, Hnd = 0, Std = 0, Mntd = 0, Csd = 0, Gnd = 0;
+    {
+        // centre: e = 0, Gamma = -|u|^2 / 2 (no mass, momentum or C moment)
+        const T un = rc[V_UN][0], ut = rc[V_UT][0];
+        const T gam = T(-0.5) * (un * un + ut * ut);
+        S0c = rc[V_P][0] + rc[V_RHO][0] * gam;
+        Hsc = rc[V_T][0] * (cpref + c3 * gam);
+    }
 #pragma unroll
-    for (int a = 0; a < 9; a++) {
+    for (int a = 1; a < 9; a++) {
         const T un = rc[V_UN][a], ut = rc[V_UT][a];
         const T eu = T(EN[a]) * un + T(ET[a]) * ut;
-        const T gam = eu + T(1.5) * eu * eu - T(0.5) * (un * un + ut * ut);
-        const T A = WA[a] * (rc[V_P][a] + rc[V_RHO][a] * gam);
-        const T B = WA[a] * (rc[V_P][a] + rho_f * gam);
-        const T Hq = WA[a] * (cpref * rc[V_T][a] + T(3) * cp_f * rc[V_T][a] * gam);
-        S0 += A;
-        Hs += Hq;
-        if (EN[a] != 0) {
-            Sn += T(EN[a]) * A;
-            Mnn += B;                      // e_n^2 = 1
-            Hn += T(EN[a]) * Hq;
-        }
-        if (ET[a] != 0) St += T(ET[a]) * A;
-        if (EN[a] != 0 && ET[a] != 0) Mnt += T(EN[a] * ET[a]) * B;
-        if (a > 0) {
-            const T Gq = WA[a] * T(3) * (Q * rc[V_MUC][a] + rc[V_C][a] * eu);
-            Cs += Gq;
-            if (EN[a] != 0) Gn += T(EN[a]) * Gq;
+        // Gamma_a = e.u + 1.5 (e.u)^2 - 0.5 |u|^2
+        const T gam = (T(1.5) * eu) * eu + eu - T(0.5) * (un * un + ut * ut);
+        const T pa = rc[V_P][a];
+        const T A = pa + rc[V_RHO][a] * gam;                  // f_eq / w
+        const T Hq = rc[V_T][a] * (cpref + c3 * gam);         // h_eq / w (a > 0)
+        const T G = Q * rc[V_MUC][a] + rc[V_C][a] * eu;       // g_eq / (3 w)
+        if (a < 5) {
+            S0a += A;
+            Hsa += Hq;
+            Csa += G;
+            if (EN[a] != 0) {
+                const T B = pa + rho_f * gam;                 // f_eqm / w
+                Sna += T(EN[a]) * A;
+                Mnna += B;
+                Hna += T(EN[a]) * Hq;
+                Gna += T(EN[a]) * G;
+            } else {
+                Sta += T(ET[a]) * A;
+            }
+        } else {
+            const T B = pa + rho_f * gam;
+            S0d += A;
+            Hsd += Hq;
+            Csd += G;
+            Snd += T(EN[a]) * A;
+            Mnnd += B;
+            Hnd += T(EN[a]) * Hq;
+            Gnd += T(EN[a]) * G;
+            Std += T(ET[a]) * A;
+            Mntd += T(EN[a] * ET[a]) * B;
         }
     }
+    const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+    const T S0 = w0 * S0c + w1 * S0a + w2 * S0d;
+    const T Hs = w0 * Hsc + w1 * Hsa + w2 * Hsd;
+    const T Sn = w1 * Sna + w2 * Snd;
+    const T St = w1 * Sta + w2 * Std;
+    const T Mnn = w1 * Mnna + w2 * Mnnd;
+    const T Mnt = w2 * Mntd;
+    const T Hn = w1 * Hna + w2 * Hnd;
+    const T Cs = T(3) * (w1 * Csa + w2 * Csd);
+    const T Gn = T(3) * (w1 * Gna + w2 * Gnd);
     // Eq. 45: face state
     const T p_f = S0;
     const T un_f = T(3) * Sn * irho_f;
@@ -430,9 +463,41 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     cS = gp<T>(I.S)[o];
 
     // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image); every load of
-    //      this thread is issued before the first one is used
-    {
-        constexpr int NIT = (L::NR + NT - 1) / NT;
+    //      this thread is issued before the first one is used. A tile whose halo lies
+    //      inside the domain (most of them) takes a path without images or mirrors.
+    const bool interior = x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= nx && y0 + TY + 3 <= ny;
+    auto store_cell = [&](int r, const Prim<T>& q, T ph) {
+        s.q[Q_P][r] = q.p;
+        s.q[Q_U][r] = q.u;
+        s.q[Q_V][r] = q.v;
+        s.q[Q_RHO][r] = q.rho;
+        s.q[Q_C][r] = q.C;
+        s.q[Q_T][r] = q.Tt;
+        s.q[Q_HE][r] = q.He;
+        s.q[Q_MU][r] = q.mu;
+        s.q[Q_LAM][r] = q.lam;
+        s.q[Q_CP][r] = q.cp;
+        s.q[Q_PHI][r] = ph;
+    };
+    constexpr int NIT = (L::NR + NT - 1) / NT;
+    if (interior) {
+        T vW[NIT][5], vph[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            const int rr = r < L::NR ? r : L::NR - 1;
+            const size_t oh = (size_t)(y0 - 3 + rr / L::RX) * pitch + (x0 - 3 + rr % L::RX);
+#pragma unroll
+            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            vph[it] = phi[oh];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR) break;
+            store_cell(r, primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]), vph[it]);
+        }
+    } else {
         T vW[NIT][5], vph[NIT];
         int vwx[NIT], vwy[NIT], vdx[NIT], vdy[NIT];
 #pragma unroll
@@ -471,17 +536,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
                 if (I.tbc[wy]) q.Tt = T(2) * K.tval[wy] - q.Tt;
                 ph = I.mbc[wy] ? -ph : ph - K.h0y * T(vdy[it]) * dx;
             }
-            s.q[Q_P][r] = q.p;
-            s.q[Q_U][r] = q.u;
-            s.q[Q_V][r] = q.v;
-            s.q[Q_RHO][r] = q.rho;
-            s.q[Q_C][r] = q.C;
-            s.q[Q_T][r] = q.Tt;
-            s.q[Q_HE][r] = q.He;
-            s.q[Q_MU][r] = q.mu;
-            s.q[Q_LAM][r] = q.lam;
-            s.q[Q_CP][r] = q.cp;
-            s.q[Q_PHI][r] = ph;
+            store_cell(r, q, ph);
         }
     }
     __syncthreads();
@@ -512,8 +567,8 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             s.g[k][1][gi] = (src[k][r + L::RX] - src[k][r - L::RX]) * inv2dx;
         }
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
-        const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
-        const bool wally = !I.per_y && (gy < 0 || gy >= ny);
+        const bool wallx = !interior && !I.per_x && (gx < 0 || gx >= nx);
+        const bool wally = !interior && !I.per_y && (gy < 0 || gy >= ny);
         if (!wallx && !wally) {
             const T* P = s.q[Q_PHI];
             const T Hx = h0x - (P[r + 1] - P[r - 1]) * inv2dx;
@@ -522,8 +577,8 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         }
     }
     __syncthreads();
-    // |H|^2 of wall ghosts mirrors the interior cell
-    for (int gi = tid; gi < L::NG; gi += NT) {
+    // |H|^2 of wall ghosts mirrors the interior cell (no wall ghosts on interior tiles)
+    for (int gi = tid; gi < (interior ? 0 : L::NG); gi += NT) {
         const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
