@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
-    ap.add_argument("--autotune", action="store_true", help="autotune the tile shapes (always on for config3)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     # serving (config4)
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrivals are cut after this time")
     ap.add_argument("--serve-drain", type=float, default=60.0, help="hard cap after the last arrival")
@@ -186,7 +186,7 @@ def run_single(args, torch, lbfs, wl) -> dict:
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")
-    tuned = solver.autotune() if args.autotune else None
+    tuned = None if args.no_autotune else solver.autotune()
     solver.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -220,7 +220,7 @@ def run_batch(args, torch, lbfs, wl) -> dict:
     for p in probs:
         if batch.admit(p) is None:
             raise RuntimeError("the batch buffer is too small for the workload")
-    tuned = batch.autotune(reps=10)
+    tuned = None if args.no_autotune else batch.autotune(reps=10)
     batch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -233,11 +233,13 @@ def run_batch(args, torch, lbfs, wl) -> dict:
     out = line(args, cells * args.steps / secs / 1e6, "MLUPS", secs * 1e3 / args.steps, "f32",
                {"workload": f"batch of {len(probs)} droplets, edges 64-256 (seed 1), FP32", "instances": len(probs),
                 "cells": cells, "edges": sorted({p["nx"] for p in probs}), "precision": "fp32",
-                "sweeps_per_step": probs[0]["sweeps"], "reductions": "f64", "tile_shapes": "autotuned",
+                "sweeps_per_step": probs[0]["sweeps"], "reductions": "f64",
+                "tile_shapes": "autotuned" if tuned else "default",
                 "launches_per_step": "one graph replay"})
     out["roofline"] = roofline(kern, cells, "fp32", args.workload)
     out.update(kernel_fields(kern))
-    out["autotune"] = tuned
+    if tuned:
+        out["autotune"] = tuned
     out["liquid_fraction_range"] = [min(fl), max(fl)]
     if not args.no_cpu_baseline:
         # the oracle on one instance of the mix (the largest edge), per-cell rate

@@ -13,7 +13,7 @@ namespace lbfs {
 
 // Tile shapes (cells) and workgroup sizes. The kernels loop over their tile plus halo
 // and over its faces, so any shape works; these are the candidates the autotuner times
-// (index 0, the default, was the fastest on 256^2 to 1024^2 grids and on batches).
+// (index 0, the default, was among the fastest on 1024^2 grids and on batches).
 // Stage kernels stage the tile plus a 3-cell halo.
 struct TileShape {
     int tx, ty, nt;
@@ -22,11 +22,13 @@ struct TileShape {
 // FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
 // other's barrier and LDS waits better than one large one, although small tiles
 // recompute more halo cells (3x for 8 x 8) and faces (2.25 per cell).
-constexpr int NSTAGE_SHAPES = 5;
+// Tiles with a face count just under a multiple of 64 ((TX+1)TY + TX(TY+1)) and a halo
+// that fits the workgroup in one round keep every lane of the face phase busy.
+constexpr int NSTAGE_SHAPES = 6;
 constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
-    {8, 8, 192}, {16, 4, 256}, {8, 8, 256}, {16, 8, 320}, {32, 4, 384}};
+    {12, 7, 256}, {12, 8, 256}, {10, 8, 256}, {8, 7, 192}, {8, 8, 192}, {16, 8, 320}};
 constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
-    {8, 8, 256}, {8, 8, 192}, {16, 4, 256}, {16, 8, 320}, {8, 4, 128}};
+    {8, 8, 256}, {12, 7, 256}, {10, 8, 256}, {8, 7, 192}, {8, 8, 192}, {16, 4, 256}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
 // (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1.
 constexpr int MAG_KMAX = 4;

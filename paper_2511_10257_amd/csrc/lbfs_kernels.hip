@@ -725,23 +725,27 @@ hipError_t launch_stage_shape(int stage, int pidx, const DevInst* insts, const T
     }
 }
 
+// dispatch a run-time shape index to the kernel instantiated for that table entry
+template <typename T, int K>
+hipError_t launch_stage_idx(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
+                            hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
+{
+    if constexpr (K < NSTAGE_SHAPES) {
+        constexpr TileShape S = stage_shape(sizeof(T) == 8, K);
+        if (shape == K)
+            return launch_stage_shape<T, S.tx, S.ty, S.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+        return launch_stage_idx<T, K + 1>(shape, stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                         hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
-    constexpr bool f64 = sizeof(T) == 8;
-    constexpr TileShape S0 = stage_shape(f64, 0), S1 = stage_shape(f64, 1), S2 = stage_shape(f64, 2),
-                        S3 = stage_shape(f64, 3), S4 = stage_shape(f64, 4);
-    static_assert(NSTAGE_SHAPES == 5, "one case per shape");
     if (ntiles <= 0) return hipSuccess;
-    switch (shape) {
-    case 0: return launch_stage_shape<T, S0.tx, S0.ty, S0.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
-    case 1: return launch_stage_shape<T, S1.tx, S1.ty, S1.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
-    case 2: return launch_stage_shape<T, S2.tx, S2.ty, S2.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
-    case 3: return launch_stage_shape<T, S3.tx, S3.ty, S3.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
-    case 4: return launch_stage_shape<T, S4.tx, S4.ty, S4.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
-    default: return hipErrorInvalidValue;
-    }
+    return launch_stage_idx<T, 0>(shape, stage, pidx, insts, tiles, ntiles, stream, e0, e1);
 }
 
 template <typename T>
