@@ -205,8 +205,9 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
    residual as lbfs_autotune does). Synchronous. */
 int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape);
 
-/* Autotuner: time every stage shape (reps runs of the first two Runge-Kutta stages,
-   which write only stage fields) and then every magnetic shape (reps magnetic phases of a
+/* Autotuner: time every stage shape (reps runs of Runge-Kutta stage 1 and twice stage 2,
+   which write only stage fields; stage 3 costs what stage 2 does) and then every
+   magnetic shape (reps magnetic phases of a
    step, on the current potential, which is restored afterwards) on this solver's
    current state, and keep the fastest of each. chosen[2] receives the indices,
    ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes first, magnetic shapes

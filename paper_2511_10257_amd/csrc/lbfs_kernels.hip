@@ -66,6 +66,17 @@ __device__ __forceinline__ float rcp_bounded<float>(float x) { return __builtin_
 template <>
 __device__ __forceinline__ double rcp_bounded<double>(double x) { return 1.0 / x; }
 
+// num / den of the Eq. 8 branch. The denominators are heat capacities (>= the gas one)
+// or, on the mushy branch, Ct L, which is tiny in a trace of liquid; there the quotient
+// is a liquid fraction in [0, 1], clamped by the caller. FP32: the hardware reciprocal
+// of the denominator raised to the smallest normal float (1 ulp), FP64: a correctly
+// rounded division.
+__device__ __forceinline__ float branch_quotient(float num, float den)
+{
+    return num * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f));
+}
+__device__ __forceinline__ double branch_quotient(double num, double den) { return num / den; }
+
 // Eq. 8 with Ts = Tl = Tm, local latent heat Ct L and branch heat capacities of the
 // solid-gas and liquid-gas mixtures
 template <typename T>
@@ -82,8 +93,8 @@ __device__ __forceinline__ void enthalpy_state(const Coef<T>& K, T He, T C, T& T
     const bool mushy = !liq && He >= Hes && Hel > Hes;
     const T num = liq ? He - Hel : (mushy ? He - Hes : He);
     const T den = liq ? cpl : (mushy ? Hel - Hes : cps);
-    const T q = num / den;   // exact: the mushy denominator Ct L can be tiny
-    Fl = liq ? T(1) : (mushy ? q : T(0));
+    const T q = branch_quotient(num, den);
+    Fl = liq ? T(1) : (mushy ? clamp01(q) : T(0));
     Tt = liq ? tm + q : (mushy ? tm : q);
 }
 
