@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrivals are cut after this time")
     ap.add_argument("--serve-drain", type=float, default=60.0, help="hard cap after the last arrival")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-edges", default="96,128,256,512", help="grid edges the requests draw from")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-chunk", type=int, default=200, help="steps between observations")
@@ -250,7 +251,8 @@ def run_batch(args, torch, lbfs, wl) -> dict:
 
 def run_serve(args, torch, lbfs, wl) -> dict:
     from paper_2511_10257_amd import serve
-    stream = wl.config4(rate_hz=args.serve_rate, horizon_s=args.serve_seconds)
+    edges = tuple(int(e) for e in args.serve_edges.split(","))
+    stream = wl.config4(rate_hz=args.serve_rate, horizon_s=args.serve_seconds, edges=edges)
     budget = int(args.serve_budget_gib * (1 << 30))
     cap = args.serve_seconds + args.serve_drain
     srv = serve.Server(budget, max_slots=args.serve_slots, precision="fp32", chunk=args.serve_chunk)
@@ -258,7 +260,8 @@ def run_serve(args, torch, lbfs, wl) -> dict:
     srv.close()
     out = line(args, rep["solves_per_unit"], "solves/s", None, "f32",
                {"workload": f"Poisson stream {args.serve_rate:g}/s for {args.serve_seconds:g} s (seed 2), edges "
-                            f"96-512, run to liquid fraction < 1e-3, FP32 continuous batching",
+                            f"{args.serve_edges}, run to liquid fraction < 1e-3, FP32 continuous batching",
+                "edges": list(edges), "rate_per_s": args.serve_rate,
                 "slots": args.serve_slots, "budget_gib": args.serve_budget_gib, "chunk_steps": args.serve_chunk,
                 "drain_cap_s": args.serve_drain})
     out["serve"] = rep
