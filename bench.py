@@ -6,13 +6,13 @@ FP64 reductions, 4 red-black sweeps per step. One "step" is the whole hot path: 
 magnetic sweeps and residual, three fused Runge-Kutta stages with the Kelvin force,
 the end-of-step Eq. 8 update and the FP64 reductions.
 
-Other workloads: config0 (64 x 64, FP64), config2 / config2-fp64 (1024 x 1024), config3
-(a batch of 64 uneven instances advanced by the same launches, tile shapes autotuned)
-and config4 (a Poisson stream of freezing requests served by continuous batching, FP32,
-beside the same stream served one solve at a time in FP64).
+Other workloads: droplet64 (64 x 64, FP64), droplet1024 / droplet1024-fp64 (1024 x 1024),
+batch64 (64 uneven instances advanced by the same launches) and serve (a Poisson stream
+of freezing requests served by continuous batching, FP32, beside the same stream served
+one solve at a time in FP64).
 
 Prints one JSON line: throughput in MLUPS (cell updates per second / 1e6; solves/s for
-config4) with the state resident in HBM, the roofline of the dominant kernel (its mean
+serve) with the state resident in HBM, the roofline of the dominant kernel (its mean
 launch duration from HIP events recorded on the solver's stream inside the timed
 region), and the FP64 CPU oracle timed on a bounded sample of the same workload on the
 host.
@@ -57,8 +57,9 @@ ALG_FLOPS = {"mag": 152.7, "stage1": 4613.4, "stage2": 4613.4, "stage3": 4613.4,
 BOUND = {"mag": "hbm", "stage1": "alu", "stage2": "alu", "stage3": "alu", "reduce": "hbm"}
 
 
-DEFAULT_STEPS = {"config0": 2000, "config1": 20000, "config2": 1000, "config2-fp64": 1000, "config3": 1000}
-DEFAULT_WARMUP = {"config0": 100, "config1": 200, "config2": 100, "config2-fp64": 100, "config3": 100}
+DEFAULT_STEPS = {"droplet64": 2000, "droplet256": 20000, "droplet1024": 1000, "droplet1024-fp64": 1000,
+                 "batch64": 1000}
+DEFAULT_WARMUP = {"droplet64": 100, "droplet256": 200, "droplet1024": 100, "droplet1024-fp64": 100, "batch64": 100}
 
 
 def parse():
@@ -66,8 +67,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default per workload)")
-    ap.add_argument("--workload", default="config1",
-                    choices=["config0", "config1", "config2", "config2-fp64", "config3", "config4"])
+    ap.add_argument("--workload", default="droplet256",
+                    choices=["droplet64", "droplet256", "droplet1024", "droplet1024-fp64", "batch64", "serve"])
     ap.add_argument("--sample-every", type=int, default=20,
                     help="bracket the kernels of every n-th timed step with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
@@ -75,7 +76,7 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
-    # serving (config4)
+    # serving
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrivals are cut after this time")
     ap.add_argument("--serve-drain", type=float, default=60.0, help="hard cap after the last arrival")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
@@ -182,8 +183,8 @@ def copy_calibration(torch, mib: int) -> None:
 
 
 def run_single(args, torch, lbfs, wl) -> dict:
-    prob = {"config0": wl.config0, "config1": wl.config1, "config2": lambda: wl.config2("fp32"),
-            "config2-fp64": lambda: wl.config2("fp64")}[args.workload]()
+    prob = {"droplet64": wl.droplet64, "droplet256": wl.droplet256, "droplet1024": lambda: wl.droplet1024("fp32"),
+            "droplet1024-fp64": lambda: wl.droplet1024("fp64")}[args.workload]()
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")
@@ -213,7 +214,7 @@ def run_single(args, torch, lbfs, wl) -> dict:
 
 
 def run_batch(args, torch, lbfs, wl) -> dict:
-    probs = wl.config3()
+    probs = wl.batch64()
     cells = sum(p["nx"] * p["ny"] for p in probs)
     budget = sum(lbfs.Batch.instance_bytes(p) for p in probs) + (64 << 20)
     copy_calibration(torch, args.copy_calibration_mib)
@@ -252,7 +253,7 @@ def run_batch(args, torch, lbfs, wl) -> dict:
 def run_serve(args, torch, lbfs, wl) -> dict:
     from paper_2511_10257_amd import serve
     edges = tuple(int(e) for e in args.serve_edges.split(","))
-    stream = wl.config4(rate_hz=args.serve_rate, horizon_s=args.serve_seconds, edges=edges)
+    stream = wl.request_stream(rate_hz=args.serve_rate, horizon_s=args.serve_seconds, edges=edges)
     budget = int(args.serve_budget_gib * (1 << 30))
     cap = args.serve_seconds + args.serve_drain
     srv = serve.Server(budget, max_slots=args.serve_slots, precision="fp32", chunk=args.serve_chunk)
@@ -283,9 +284,9 @@ def main():
 
     from paper_2511_10257_amd import lbfs, workloads as wl
 
-    if args.workload == "config3":
+    if args.workload == "batch64":
         out = run_batch(args, torch, lbfs, wl)
-    elif args.workload == "config4":
+    elif args.workload == "serve":
         out = run_serve(args, torch, lbfs, wl)
     else:
         out = run_single(args, torch, lbfs, wl)

@@ -7,7 +7,7 @@ right-hand side R(W) with the Kelvin force. Divisions, square roots and transcen
 calls count as one operation each, an add or a multiply as one (a fused multiply-add is
 two), comparisons and selects are listed apart and not counted as FLOPs.
 
-    python3 oracle/opcount.py [--workload config1] [--n 128]
+    python3 oracle/opcount.py [--workload droplet256] [--n 128]
 """
 from __future__ import annotations
 
@@ -68,11 +68,12 @@ def count(prob: dict) -> dict:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2"])
+    ap.add_argument("--workload", default="droplet256", choices=["droplet64", "droplet256", "droplet1024"])
     ap.add_argument("--n", type=int, default=128, help="grid edge of the counted run (droplet radius n/4)")
     args = ap.parse_args()
     from paper_2511_10257_amd import workloads as wl
-    base = {"config0": wl.config0, "config1": wl.config1, "config2": lambda: wl.config2("fp64")}[args.workload]()
+    base = {"droplet64": wl.droplet64, "droplet256": wl.droplet256,
+            "droplet1024": lambda: wl.droplet1024("fp64")}[args.workload]()
     prob = base
     if args.n != base["nx"]:
         prob = wl.droplet_problem(args.n, args.n / 4.0, base["ste"], base["bo_m"], base["angle_deg"],

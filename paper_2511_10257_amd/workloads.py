@@ -63,7 +63,7 @@ def droplet_problem(n: int, radius: float, ste: float, bo_m: float, angle_deg: f
     return prob
 
 
-def config0() -> dict:
+def droplet64() -> dict:
     """64^2 FP64 case: R=16, vertical field, Bo_m=0.5, Ste=0.1, 2000 steps."""
     p = droplet_problem(64, 16, ste=0.1, bo_m=0.5, angle_deg=90.0, precision="fp64")
     p["steps"] = 2000
@@ -71,7 +71,7 @@ def config0() -> dict:
     return p
 
 
-def config1(seed: int = 0) -> dict:
+def droplet256(seed: int = 0) -> dict:
     """256^2 FP32 case: R=64, angle 0 or 90 and Bo_m ~ U[0,2] drawn with the seed."""
     rng = np.random.default_rng(seed)
     angle = (0.0, 90.0)[int(rng.integers(0, 2))]
@@ -82,7 +82,7 @@ def config1(seed: int = 0) -> dict:
     return p
 
 
-def config2(precision: str = "fp32") -> dict:
+def droplet1024(precision: str = "fp32") -> dict:
     """1024^2 case: R=256, horizontal field, Bo_m=1.5, density ratio 100, K=4."""
     p = droplet_problem(1024, 256, ste=0.1, bo_m=1.5, angle_deg=0.0, rho_ratio=100.0,
                         precision=precision)
@@ -91,7 +91,7 @@ def config2(precision: str = "fp32") -> dict:
     return p
 
 
-def config3(seed: int = 1, count: int = 64) -> list[dict]:
+def batch64(seed: int = 1, count: int = 64) -> list[dict]:
     """Batch of uneven instances: edge in {64..256}, R=edge/4, random angle/Bo_m/Ste."""
     rng = np.random.default_rng(seed)
     out = []
@@ -105,7 +105,7 @@ def config3(seed: int = 1, count: int = 64) -> list[dict]:
     return out
 
 
-def config4(seed: int = 2, rate_hz: float = 20.0, horizon_s: float = 300.0,
+def request_stream(seed: int = 2, rate_hz: float = 20.0, horizon_s: float = 300.0,
             edges=(96, 128, 256, 512)) -> list[tuple[float, dict]]:
     """Poisson request stream: (arrival time in s, problem) pairs."""
     rng = np.random.default_rng(seed)

@@ -28,27 +28,27 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_state_bytes_and_validation():
-    p = lbfs.make_params(wl.config1())
+    p = lbfs.make_params(wl.droplet256())
     nb = lbfs.state_bytes(p)
     # 18 fields of 256 x 256 float plus metadata
     assert 18 * 256 * 256 * 4 <= nb < 18 * 256 * 256 * 4 + 4 * 1024 * 1024
-    p64 = lbfs.make_params(wl.config0())
+    p64 = lbfs.make_params(wl.droplet64())
     assert lbfs.state_bytes(p64) >= 18 * 64 * 64 * 8
     for field, bad in (("nx", 3), ("dx", 0.0), ("tau_g", 0.5), ("precision", 7), ("dt", 100.0),
                        ("sor_omega", 2.0), ("dt_stream", 0.3), ("abi_version", 99)):
-        q = lbfs.make_params(wl.config0())
+        q = lbfs.make_params(wl.droplet64())
         setattr(q, field, bad)
         assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0, field
     q = lbfs.make_params(wl.neumann_problem(0.1, 250.0))
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) > 0
     q.ny = 5                     # odd periodic axis: no red-black colouring
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0
-    q = lbfs.make_params(wl.config0())
+    q = lbfs.make_params(wl.droplet64())
     q.periodic[1] = 1            # vertical applied field across a periodic axis
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0
     out = C.c_void_p()
     assert lbfs.lib().lbfs_init(C.byref(q), None, 0, None, C.byref(out)) == lbfs.LBFS_E_INVAL
-    q = lbfs.make_params(wl.config0())
+    q = lbfs.make_params(wl.droplet64())
     q.abi_version = 2
     assert lbfs.lib().lbfs_init(C.byref(q), None, 0, None, C.byref(out)) == lbfs.LBFS_E_ABI
     assert lbfs.lib().lbfs_step(None, 1) == lbfs.LBFS_E_STATE
@@ -56,7 +56,7 @@ def test_state_bytes_and_validation():
 
 
 def test_dimensionless_conversion_matches_eq50():
-    prob = wl.config0()
+    prob = wl.droplet64()
     p = lbfs.make_params(prob)
     # Ste = Cp_l (Tm - Tw) / L  and  Bo_m = mu0 H0^2 D / sigma with D = 2R
     assert math.isclose(prob["ste"], p.cp[1] * (p.t_melt - prob["t_wall"]) / p.latent, rel_tol=1e-15)
@@ -67,7 +67,7 @@ def test_dimensionless_conversion_matches_eq50():
 
 def test_oracle_and_product_read_the_same_problem():
     from oracle import oracle as orc
-    for prob in (wl.config0(), wl.config1(), wl.config2("fp64"), wl.neumann_problem(0.1, 250.0)):
+    for prob in (wl.droplet64(), wl.droplet256(), wl.droplet1024("fp64"), wl.neumann_problem(0.1, 250.0)):
         a, b = orc.make_params(prob), lbfs.make_params(prob)
         assert (a.nx, a.ny) == (b.nx, b.ny)
         for name in ("dx", "dt", "latent", "h0", "t_melt", "t_init", "sigma", "xi", "mobility", "tau_g",
@@ -85,11 +85,11 @@ def test_oracle_and_product_read_the_same_problem():
 
 def test_batch_host_checks():
     """Host-side checks of the batch calls (no device work is reached)."""
-    p = lbfs.make_params(wl.config1())
+    p = lbfs.make_params(wl.droplet256())
     nb = lbfs.lib().lbfs_batch_instance_bytes(C.byref(p))
     # the same segments as a solver (tile lists sized for every candidate shape)
     assert lbfs.state_bytes(p) <= nb < lbfs.state_bytes(p) + 64 * 1024
-    q = lbfs.make_params(wl.config0())
+    q = lbfs.make_params(wl.droplet64())
     q.nx = 2
     assert lbfs.lib().lbfs_batch_instance_bytes(C.byref(q)) == 0
     out = C.c_void_p()

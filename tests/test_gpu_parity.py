@@ -101,7 +101,7 @@ def test_magnetic_sweeps_fp64_match_oracle():
 
 
 def test_initialisation_matches_oracle():
-    prob = wl.config0()
+    prob = wl.droplet64()
     o = orc.Oracle(prob)
     g = lbfs.Solver(prob)
     for name in ("He", "C", "p", "Mx", "S"):
@@ -121,10 +121,10 @@ def wl_phi0(prob, o):
     return -o.params.h0 * (x * np.cos(th) + y * np.sin(th))
 
 
-def test_step_fp64_matches_oracle_on_config0_states():
-    """configs[0] (64^2, FP64): from identical states the GPU step equals the oracle
+def test_step_fp64_matches_oracle_on_64x64_states():
+    """The 64^2 FP64 droplet: from identical states the GPU step equals the oracle
     step to rounding, at several points of the trajectory."""
-    prob = wl.config0()
+    prob = wl.droplet64()
     o = orc.Oracle(prob)
     g = lbfs.Solver(prob)
     for n_before in (0, 30):
@@ -146,7 +146,7 @@ def test_step_fp64_matches_oracle_on_config0_states():
 def test_step_fp32_per_step_relative_l2():
     """FP32 step from the FP64 oracle's state (rounded) vs the FP64 oracle step:
     per-step relative L2 <= 1e-5 per field (floors for near-zero fields)."""
-    prob64 = wl.config0()
+    prob64 = wl.droplet64()
     o = orc.Oracle(prob64)
     o.step(20)
     state = {k: o.get(k) for k in ("He", "p", "Mx", "My", "C", "phi", "S")}
@@ -204,11 +204,11 @@ def test_nonfinite_state_is_reported():
     assert e.value.status == lbfs.LBFS_E_NONFINITE
 
 
-@pytest.mark.parametrize("which", ["config1", "config2"])
+@pytest.mark.parametrize("which", ["droplet256", "droplet1024"])
 def test_rhs_at_full_size(which):
     """Full-size grids in the benchmark's launch configuration: the whole R(W) of a
     seeded state against the oracle (FP32: relative L2 per field)."""
-    prob = wl.config1() if which == "config1" else wl.config2("fp32")
+    prob = wl.droplet256() if which == "droplet256" else wl.droplet1024("fp32")
     prob = wl.with_changes(prob, init_max=0)
     nx, ny = prob["nx"], prob["ny"]
     o = orc.Oracle(prob, init=False)
@@ -226,7 +226,7 @@ def test_rhs_at_full_size(which):
 def test_step_fp64_full_size_observables():
     """1024^2 FP64 (8192 stage tiles over all XCDs): one step from the same state,
     fields and the observables reduced by the last workgroup of the last stage."""
-    prob = wl.with_changes(wl.config2("fp64"), init_max=0)
+    prob = wl.with_changes(wl.droplet1024("fp64"), init_max=0)
     nx, ny = prob["nx"], prob["ny"]
     o = orc.Oracle(prob, init=False)
     # momentum amplitude for |u| ~ 0.015 in the gas of density 0.01
