@@ -58,8 +58,9 @@ BOUND = {"mag": "hbm", "stage1": "alu", "stage2": "alu", "stage3": "alu", "reduc
 
 
 DEFAULT_STEPS = {"droplet64": 2000, "droplet256": 20000, "droplet1024": 1000, "droplet1024-fp64": 1000,
-                 "batch64": 1000}
-DEFAULT_WARMUP = {"droplet64": 100, "droplet256": 200, "droplet1024": 100, "droplet1024-fp64": 100, "batch64": 100}
+                 "droplet4096": 200, "batch64": 1000}
+DEFAULT_WARMUP = {"droplet64": 100, "droplet256": 200, "droplet1024": 100, "droplet1024-fp64": 100,
+                  "droplet4096": 10, "batch64": 100}
 
 
 def parse():
@@ -68,7 +69,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default per workload)")
     ap.add_argument("--workload", default="droplet256",
-                    choices=["droplet64", "droplet256", "droplet1024", "droplet1024-fp64", "batch64", "serve"])
+                    choices=["droplet64", "droplet256", "droplet1024", "droplet1024-fp64", "droplet4096", "batch64",
+                             "serve"])
     ap.add_argument("--sample-every", type=int, default=20,
                     help="bracket the kernels of every n-th timed step with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
@@ -184,7 +186,7 @@ def copy_calibration(torch, mib: int) -> None:
 
 def run_single(args, torch, lbfs, wl) -> dict:
     prob = {"droplet64": wl.droplet64, "droplet256": wl.droplet256, "droplet1024": lambda: wl.droplet1024("fp32"),
-            "droplet1024-fp64": lambda: wl.droplet1024("fp64")}[args.workload]()
+            "droplet1024-fp64": lambda: wl.droplet1024("fp64"), "droplet4096": wl.droplet4096}[args.workload]()
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")

@@ -209,7 +209,8 @@ int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape)
    which write only stage fields; stage 3 costs what stage 2 does) and then every
    magnetic shape (reps magnetic phases of a
    step, on the current potential, which is restored afterwards) on this solver's
-   current state, and keep the fastest of each. chosen[2] receives the indices,
+   current state, and keep the fastest of each (the default, shape 0, unless another
+   is faster by more than 2 %, the spread of such timings). chosen[2] receives the indices,
    ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes first, magnetic shapes
    from index LBFS_MAX_SHAPES; either may be NULL). The state is unchanged; until the
    next step, mag_residual then reports the residual of the current potential with the

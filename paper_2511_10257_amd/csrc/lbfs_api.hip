@@ -933,6 +933,10 @@ int time_launches(hipStream_t stream, int reps, F&& f, double* ms)
     return rc;
 }
 
+// a candidate replaces the best so far (initially the default, index 0) only when it is
+// faster by more than the run-to-run spread of such timings (2 %)
+bool clearly_faster(double t, double best) { return t < 0.98 * best; }
+
 // stand-in for the three Runge-Kutta stages of a step: stage 1, then stage 2 twice
 // (stage 3 writes the state; its cost follows stage 2's, which reads as many fields).
 // Both write only the stage fields W1 and W2, so timing them leaves the state as it is.
@@ -1000,7 +1004,7 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
         rc = apply_shapes(s, k, E.mag_shape);
         if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
-        if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
+        if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
     }
     bool saved = false;
     if (rc == LBFS_OK) {
@@ -1013,7 +1017,7 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
         rc = apply_shapes(s, best_s, k);
         double* tk = &t[LBFS_MAX_SHAPES + k];
         if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
-        if (rc == LBFS_OK && *tk < t[LBFS_MAX_SHAPES + best_m]) best_m = k;
+        if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
     }
     // restore the potential, keep the fastest shapes and recompute the residual partials
     // of the restored potential on them (a sweep-free launch: a copy of the potential)
@@ -1480,7 +1484,7 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
             b->dirty = true;
             rc = batch_rebuild(b);
             if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
-            if (rc == LBFS_OK && t[k] < t[best_s]) best_s = k;
+            if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
         }
         // the potentials are stashed only once every stage timing is done (stage 2 writes
         // the stash field)
@@ -1495,7 +1499,7 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
             rc = batch_rebuild(b);
             double* tk = &t[LBFS_MAX_SHAPES + k];
             if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
-            if (rc == LBFS_OK && *tk < t[LBFS_MAX_SHAPES + best_m]) best_m = k;
+            if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
         }
         E.phase = phase0;
         for (Slot& q : b->slots)

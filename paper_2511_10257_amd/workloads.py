@@ -91,6 +91,16 @@ def droplet1024(precision: str = "fp32") -> dict:
     return p
 
 
+def droplet4096(precision: str = "fp32") -> dict:
+    """4096^2 case with the physics of the 1024^2 one (R=1024): its 1.2 GB of FP32 state
+    exceeds the 256 MB last-level cache, so every step streams from HBM."""
+    p = droplet_problem(4096, 1024, ste=0.1, bo_m=1.5, angle_deg=0.0, rho_ratio=100.0,
+                        precision=precision)
+    p["steps"] = 100
+    p["name"] = f"droplet-4096x4096-R1024-horizontal-Bo1.5-rho100-{precision}"
+    return p
+
+
 def batch64(seed: int = 1, count: int = 64) -> list[dict]:
     """Batch of uneven instances: edge in {64..256}, R=edge/4, random angle/Bo_m/Ste."""
     rng = np.random.default_rng(seed)
