@@ -77,7 +77,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="time the candidate tile shapes first (auto: for the batch only; single solves "
+                         "keep the default shapes, so that runs and profiles use the same kernels)")
     # serving
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrivals are cut after this time")
     ap.add_argument("--serve-drain", type=float, default=60.0, help="hard cap after the last arrival")
@@ -103,9 +105,9 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, shape: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources."""
+    taken on the current kernel sources with the same tile shape."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -113,8 +115,14 @@ def measured_traffic(kernel: str, workload: str):
     m = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_sources_digest():
         return None
-    m = re.search(rf"^\|\s*{kernel}\s*\|[^|]*\|[^|]*\|\s*([0-9.eE+]+)\s*\|", text, re.M)
-    return float(m.group(1)) if m else None
+    m = re.search(rf"^\|\s*{kernel}\s*\|\s*([^|]*?)\s*\|[^|]*\|[^|]*\|\s*([0-9.eE+]+)\s*\|", text, re.M)
+    return float(m.group(2)) if m and m.group(1) == shape else None
+
+
+def shape_names(lbfs, precision: str, in_use: tuple) -> dict:
+    st = lbfs.tile_shapes("stage", precision)[in_use[0]]
+    mg = lbfs.tile_shapes("mag", precision)[in_use[1]]
+    return {"stage": f"{st[0]}x{st[1]}/{st[2]}", "mag": f"{mg[0]}x{mg[1]}/{mg[2]}"}
 
 
 def cpu_baseline(prob: dict, budget_s: float) -> dict:
@@ -136,7 +144,7 @@ def cpu_baseline(prob: dict, budget_s: float) -> dict:
                       f"FP64, single thread, {secs:.1f} s (init excluded)"}
 
 
-def roofline(kern: dict, cells: int, precision: str, workload: str) -> dict:
+def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step."""
     share = {k: kern[k][0] for k in kern}
     dominant = max(share, key=share.get)
@@ -146,7 +154,7 @@ def roofline(kern: dict, cells: int, precision: str, workload: str) -> dict:
     dur_s = kern[dominant][0] * 1e-3
     gbs = alg_bytes / dur_s / 1e9
     tflops = alg_flops / dur_s / 1e12
-    traffic = measured_traffic(dominant, workload)
+    traffic = measured_traffic(dominant, workload, shapes["mag" if dominant == "mag" else "stage"])
     hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes}
     vpeak = VALU_PEAK_TFLOPS[precision]
@@ -154,7 +162,8 @@ def roofline(kern: dict, cells: int, precision: str, workload: str) -> dict:
            "traffic": traffic, "algorithmic_flops_per_launch": alg_flops,
            "frac_of_nonpacked_peak": tflops / VALU_PEAK_NONPACKED_TFLOPS}
     roof = dict(alu if BOUND[dominant] == "alu" else hbm)
-    roof.update({"kernel": dominant, "mean_launch_us": kern[dominant][0] * 1e3,
+    roof.update({"kernel": dominant, "tile_shape": shapes["mag" if dominant == "mag" else "stage"],
+                 "mean_launch_us": kern[dominant][0] * 1e3,
                  "timed_launches": kern[dominant][1],
                  "other_ceiling": hbm if BOUND[dominant] == "alu" else alu})
     return roof
@@ -190,7 +199,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")
-    tuned = None if args.no_autotune else solver.autotune()
+    tuned = solver.autotune() if args.autotune == "on" else None
+    shapes = shape_names(lbfs, prob["precision"], solver.tile_shapes_in_use())
     solver.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -204,8 +214,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
                {"workload": prob["name"], "nx": prob["nx"], "ny": prob["ny"], "precision": prob["precision"],
                 "angle_deg": prob["angle_deg"], "bo_m": prob["bo_m"], "ste": prob["ste"],
                 "sweeps_per_step": prob["sweeps"], "reductions": "f64",
-                "tile_shapes": "autotuned" if tuned else "default"})
-    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload)
+                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default")})
+    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload, shapes)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned
@@ -224,7 +234,8 @@ def run_batch(args, torch, lbfs, wl) -> dict:
     for p in probs:
         if batch.admit(p) is None:
             raise RuntimeError("the batch buffer is too small for the workload")
-    tuned = None if args.no_autotune else batch.autotune(reps=10)
+    tuned = batch.autotune(reps=10) if args.autotune in ("auto", "on") else None
+    shapes = shape_names(lbfs, "fp32", batch.tile_shapes_in_use())
     batch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,9 +249,9 @@ def run_batch(args, torch, lbfs, wl) -> dict:
                {"workload": f"batch of {len(probs)} droplets, edges 64-256 (seed 1), FP32", "instances": len(probs),
                 "cells": cells, "edges": sorted({p["nx"] for p in probs}), "precision": "fp32",
                 "sweeps_per_step": probs[0]["sweeps"], "reductions": "f64",
-                "tile_shapes": "autotuned" if tuned else "default",
+                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default"),
                 "launches_per_step": "one graph replay"})
-    out["roofline"] = roofline(kern, cells, "fp32", args.workload)
+    out["roofline"] = roofline(kern, cells, "fp32", args.workload, shapes)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned

@@ -205,6 +205,9 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
    residual as lbfs_autotune does). Synchronous. */
 int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape);
 
+/* The shapes the next launches use (indices into the tables of lbfs_tile_shape). */
+int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape, int32_t* mag_shape);
+
 /* Autotuner: time every stage shape (reps runs of Runge-Kutta stage 1 and twice stage 2,
    which write only stage fields; stage 3 costs what stage 2 does) and then every
    magnetic shape (reps magnetic phases of a
@@ -277,6 +280,7 @@ int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
    instances (and those admitted later), timed on the concatenated tiles. */
 int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape, int32_t mag_shape);
 int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms);
+int lbfs_batch_tile_shapes_in_use(const lbfs_batch* b, int32_t* stage_shape, int32_t* mag_shape);
 
 /* Live instances, cells they hold and free bytes of the buffer (largest free block). */
 int lbfs_batch_info(lbfs_batch* b, int32_t* live, int64_t* cells, size_t* largest_free);

@@ -991,6 +991,14 @@ int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape_idx, int32_t mag_sh
     return LBFS_OK;
 }
 
+int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape_idx, int32_t* mag_shape_idx)
+{
+    if (!s) return LBFS_E_STATE;
+    if (stage_shape_idx) *stage_shape_idx = s->E.stage_shape;
+    if (mag_shape_idx) *mag_shape_idx = s->E.mag_shape;
+    return LBFS_OK;
+}
+
 int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
 {
     if (!s || s->batched) return LBFS_E_STATE;
@@ -1518,6 +1526,14 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
     }
     if (ms)
         for (int k = 0; k < 2 * LBFS_MAX_SHAPES; k++) ms[k] = t[k];
+    return LBFS_OK;
+}
+
+int lbfs_batch_tile_shapes_in_use(const lbfs_batch* b, int32_t* stage_shape_idx, int32_t* mag_shape_idx)
+{
+    if (!b) return LBFS_E_STATE;
+    if (stage_shape_idx) *stage_shape_idx = b->stage_shape;
+    if (mag_shape_idx) *mag_shape_idx = b->mag_shape;
     return LBFS_OK;
 }
 

@@ -29,10 +29,11 @@ EXPORTS = (
     "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
-    "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_autotune",
+    "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
     "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
     "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_observe", "lbfs_batch_slot",
     "lbfs_batch_info", "lbfs_batch_destroy", "lbfs_batch_set_tile_shapes", "lbfs_batch_autotune",
+    "lbfs_batch_tile_shapes_in_use",
 )
 MAX_SHAPES = 8
 
@@ -107,6 +108,8 @@ def lib():
             "lbfs_tile_shape": (C.c_int, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]),
             "lbfs_set_tile_shapes": (C.c_int, [vp, i32, i32]),
+            "lbfs_tile_shapes_in_use": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+            "lbfs_batch_tile_shapes_in_use": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "lbfs_autotune": (C.c_int, [vp, i32, C.POINTER(C.c_int32), dp]),
             "lbfs_batch_set_tile_shapes": (C.c_int, [vp, i32, i32]),
             "lbfs_batch_autotune": (C.c_int, [vp, i32, C.POINTER(C.c_int32), dp]),
@@ -332,6 +335,12 @@ class Solver(_Instance):
     def set_tile_shapes(self, stage_shape: int, mag_shape: int) -> None:
         _check(lib().lbfs_set_tile_shapes(self._h, int(stage_shape), int(mag_shape)), "lbfs_set_tile_shapes")
 
+    def tile_shapes_in_use(self) -> tuple:
+        """(stage shape index, magnetic shape index) of the next launches."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().lbfs_tile_shapes_in_use(self._h, C.byref(a), C.byref(b)), "lbfs_tile_shapes_in_use")
+        return a.value, b.value
+
     def autotune(self, reps: int = 20) -> dict:
         """Time the candidate tile shapes on the current state and keep the fastest."""
         chosen = (C.c_int32 * 2)()
@@ -429,6 +438,12 @@ class Batch:
     def set_tile_shapes(self, stage_shape: int, mag_shape: int) -> None:
         _check(lib().lbfs_batch_set_tile_shapes(self._h, int(stage_shape), int(mag_shape)),
                "lbfs_batch_set_tile_shapes")
+
+    def tile_shapes_in_use(self) -> tuple:
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().lbfs_batch_tile_shapes_in_use(self._h, C.byref(a), C.byref(b)),
+               "lbfs_batch_tile_shapes_in_use")
+        return a.value, b.value
 
     def autotune(self, reps: int = 20) -> dict:
         """Time the candidate tile shapes over all live instances and keep the fastest."""
