@@ -120,9 +120,8 @@ def measured_traffic(kernel: str, workload: str, shape: str):
 
 
 def shape_names(lbfs, precision: str, in_use: tuple) -> dict:
-    st = lbfs.tile_shapes("stage", precision)[in_use[0]]
-    mg = lbfs.tile_shapes("mag", precision)[in_use[1]]
-    return {"stage": f"{st[0]}x{st[1]}/{st[2]}", "mag": f"{mg[0]}x{mg[1]}/{mg[2]}"}
+    return {"stage": lbfs.shape_name(lbfs.tile_shapes("stage", precision)[in_use[0]]),
+            "mag": lbfs.shape_name(lbfs.tile_shapes("mag", precision)[in_use[1]])}
 
 
 def cpu_baseline(prob: dict, budget_s: float) -> dict:

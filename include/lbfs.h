@@ -197,9 +197,11 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
 #define LBFS_MAX_SHAPES 8
 
 /* kind 0: stage kernels, 1: magnetic kernel. With index < 0 returns the number of
-   shapes of that kind; otherwise writes the tile (tx x ty cells) and the workgroup
-   size (threads) of shape `index`. */
-int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads);
+   shapes of that kind; otherwise writes the tile (tx x ty cells), the workgroup size
+   (threads) and flags of shape `index` (bit 0: the first two stages load the owned
+   cells' values before the halo rather than after the faces). Any pointer may be NULL. */
+int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads,
+                    int32_t* flags);
 
 /* Use the given shapes from the next launch on (a changed magnetic shape recomputes the
    residual as lbfs_autotune does). Synchronous. */

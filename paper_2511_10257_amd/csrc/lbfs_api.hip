@@ -961,7 +961,8 @@ hipError_t copy_phi(lbfs_solver* s, bool save)
 
 extern "C" {
 
-int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads)
+int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads,
+                    int32_t* flags)
 {
     if (precision != LBFS_FP32 && precision != LBFS_FP64) return LBFS_E_INVAL;
     const int n = kind == 0 ? NSTAGE_SHAPES : kind == 1 ? NMAG_SHAPES : -1;
@@ -972,6 +973,7 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
     if (tx) *tx = S.tx;
     if (ty) *ty = S.ty;
     if (threads) *threads = S.nt;
+    if (flags) *flags = S.early ? 1 : 0;
     return LBFS_OK;
 }
 

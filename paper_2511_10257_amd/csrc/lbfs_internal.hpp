@@ -17,18 +17,22 @@ namespace lbfs {
 // Stage kernels stage the tile plus a 3-cell halo.
 struct TileShape {
     int tx, ty, nt;
+    int early = 0;   // stage kernels: stage 0/1 load the owned cell's values before the halo
 };
 // Small workgroups: with the stage kernels' register use (about 90 VGPRs in FP32, 180 in
 // FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
 // other's barrier and LDS waits better than one large one, although small tiles
 // recompute more halo cells (3x for 8 x 8) and faces (2.25 per cell).
 // Tiles with a face count just under a multiple of 64 ((TX+1)TY + TX(TY+1)) and a halo
-// that fits the workgroup in one round keep every lane of the face phase busy.
+// that fits the workgroup in one round keep every lane of the face phase busy. Loading
+// the owned cell's values early hides their latency but holds registers through the
+// face phase; whether that costs a wave per SIMD depends on the shape, so both are
+// candidates.
 constexpr int NSTAGE_SHAPES = 6;
 constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
-    {12, 7, 256}, {12, 8, 256}, {10, 8, 256}, {8, 7, 192}, {8, 8, 192}, {16, 8, 320}};
+    {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {10, 8, 256, 0}, {8, 8, 192, 0}, {16, 8, 320, 0}};
 constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
-    {8, 8, 256}, {12, 7, 256}, {10, 8, 256}, {8, 7, 192}, {8, 8, 192}, {16, 4, 256}};
+    {8, 8, 256, 0}, {12, 7, 256, 0}, {10, 8, 256, 0}, {8, 7, 192, 0}, {8, 8, 192, 0}, {16, 4, 256, 0}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
 // (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1.
 constexpr int MAG_KMAX = 4;

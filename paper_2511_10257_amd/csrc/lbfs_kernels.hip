@@ -438,7 +438,7 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
 
 // NT >= every per-tile work count (halo cells, gradient cells, faces), so each phase
 // is one round; the first TX*TY threads own the tile's cells.
-template <typename T, int TX, int TY, int NT, int STAGE>
+template <typename T, int TX, int TY, int NT, int STAGE, int EARLY>
 __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
                                               const Tile* __restrict__ tiles, int pidx)
 {
@@ -459,19 +459,25 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
                   : STAGE == 3 ? reinterpret_cast<T* const*>(I.W2) : Wbase;
     const GLOBAL T* phi = gp<T>(I.phi[pidx]);
 
-    // cell owned by this thread (phase E); its point values are fetched now so that the
-    // loads overlap the halo phases
+    // cell owned by this thread (phase E). With EARLY, stages 0 and 1 fetch its point
+    // values now, overlapping the halo phases; otherwise they are loaded in phase E,
+    // which keeps the registers free for the faces (other workgroups on the CU hide the
+    // latency).
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool inside = tid < TX * TY && gx < nx && gy < ny;
     const size_t o = inside ? (size_t)gy * pitch + gx : 0;
+    constexpr bool early = EARLY && STAGE <= 1;
     T cWin[5], cWb[5], cS = T(0);
+    auto load_own = [&] {
 #pragma unroll
-    for (int k = 0; k < 5; k++) {
-        cWin[k] = STAGE >= 1 ? gp<T>(Win[k])[o] : T(0);
-        cWb[k] = STAGE >= 2 ? gp<T>(Wbase[k])[o] : T(0);
-    }
-    cS = gp<T>(I.S)[o];
+        for (int k = 0; k < 5; k++) {
+            cWin[k] = STAGE >= 1 ? gp<T>(Win[k])[o] : T(0);
+            cWb[k] = STAGE >= 2 ? gp<T>(Wbase[k])[o] : T(0);
+        }
+        cS = gp<T>(I.S)[o];
+    };
+    if constexpr (early) load_own();
 
     // ---- A: cell fields of tile + 3 (ghosts by mirror / periodic image); every load of
     //      this thread is issued before the first one is used. A tile whose halo lies
@@ -654,6 +660,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
 
     // ---- E: residual, sources, Runge-Kutta stage
     if (inside) {
+        if constexpr (!early) load_own();
         const int r = (ly + 3) * L::RX + (lx + 3);
         const int gi = (ly + 1) * L::GX + (lx + 1);
         const T dt = K.dt;
@@ -723,16 +730,16 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     }
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, int EARLY>
 hipError_t launch_stage_shape(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                               hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(ntiles), block(NT);
     switch (stage) {
-    case 0: return launch_timed(k_stage<T, TX, TY, NT, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    case 1: return launch_timed(k_stage<T, TX, TY, NT, 1>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    case 2: return launch_timed(k_stage<T, TX, TY, NT, 2>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    default: return launch_timed(k_stage<T, TX, TY, NT, 3>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 0: return launch_timed(k_stage<T, TX, TY, NT, 0, EARLY>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 1: return launch_timed(k_stage<T, TX, TY, NT, 1, EARLY>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 2: return launch_timed(k_stage<T, TX, TY, NT, 2, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    default: return launch_timed(k_stage<T, TX, TY, NT, 3, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
     }
 }
 
@@ -744,7 +751,8 @@ hipError_t launch_stage_idx(int shape, int stage, int pidx, const DevInst* insts
     if constexpr (K < NSTAGE_SHAPES) {
         constexpr TileShape S = stage_shape(sizeof(T) == 8, K);
         if (shape == K)
-            return launch_stage_shape<T, S.tx, S.ty, S.nt>(stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+            return launch_stage_shape<T, S.tx, S.ty, S.nt, S.early>(stage, pidx, insts, tiles, ntiles, stream, e0,
+                                                                    e1);
         return launch_stage_idx<T, K + 1>(shape, stage, pidx, insts, tiles, ntiles, stream, e0, e1);
     } else {
         return hipErrorInvalidValue;

@@ -106,7 +106,7 @@ def lib():
             "lbfs_destroy": (None, [vp]),
             "lbfs_strerror": (C.c_char_p, [C.c_int]),
             "lbfs_tile_shape": (C.c_int, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                          C.POINTER(C.c_int32)]),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "lbfs_set_tile_shapes": (C.c_int, [vp, i32, i32]),
             "lbfs_tile_shapes_in_use": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "lbfs_batch_tile_shapes_in_use": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -199,16 +199,22 @@ def make_params(prob: dict) -> Params:
 
 
 def tile_shapes(kind: str, precision: str = "fp32") -> list:
-    """Candidate tile shapes (tx, ty, threads) of the "stage" or "mag" kernels."""
+    """Candidate tile shapes (tx, ty, threads, flags) of the "stage" or "mag" kernels."""
     k = 0 if kind == "stage" else 1
     prec = LBFS_FP64 if precision == "fp64" else LBFS_FP32
-    n = lib().lbfs_tile_shape(k, prec, -1, None, None, None)
+    n = lib().lbfs_tile_shape(k, prec, -1, None, None, None, None)
     out = []
     for i in range(n):
-        tx, ty, nt = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().lbfs_tile_shape(k, prec, i, C.byref(tx), C.byref(ty), C.byref(nt)), "lbfs_tile_shape")
-        out.append((tx.value, ty.value, nt.value))
+        tx, ty, nt, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbfs_tile_shape(k, prec, i, C.byref(tx), C.byref(ty), C.byref(nt), C.byref(fl)),
+               "lbfs_tile_shape")
+        out.append((tx.value, ty.value, nt.value, fl.value))
     return out
+
+
+def shape_name(shape: tuple) -> str:
+    """'TXxTY/threads', with an 'e' for the early owned-cell loads of the first stages."""
+    return f"{shape[0]}x{shape[1]}/{shape[2]}" + ("e" if shape[3] & 1 else "")
 
 
 def _tune_result(chosen, ms, precision: str) -> dict:

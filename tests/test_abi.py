@@ -111,10 +111,10 @@ def test_tile_shape_tables():
         for kind in ("stage", "mag"):
             shapes = lbfs.tile_shapes(kind, prec)
             assert 1 <= len(shapes) <= lbfs.MAX_SHAPES
-            for tx, ty, nt in shapes:
+            for tx, ty, nt, flags in shapes:
                 assert nt % 64 == 0 and nt <= 1024 and tx * ty <= (nt if kind == "stage" else 4096)
-    assert L.lbfs_tile_shape(2, 0, 0, None, None, None) == lbfs.LBFS_E_INVAL
-    assert L.lbfs_tile_shape(0, 5, 0, None, None, None) == lbfs.LBFS_E_INVAL
-    assert L.lbfs_tile_shape(0, 0, 99, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_tile_shape(2, 0, 0, None, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_tile_shape(0, 5, 0, None, None, None, None) == lbfs.LBFS_E_INVAL
+    assert L.lbfs_tile_shape(0, 0, 99, None, None, None, None) == lbfs.LBFS_E_INVAL
     assert L.lbfs_set_tile_shapes(None, 0, 0) == lbfs.LBFS_E_STATE
     assert L.lbfs_autotune(None, 5, None, None) == lbfs.LBFS_E_STATE
