@@ -143,6 +143,14 @@ def cpu_baseline(prob: dict, budget_s: float) -> dict:
                       f"FP64, single thread, {secs:.1f} s (init excluded)"}
 
 
+def kernel_shape(kernel: str, shapes: dict) -> str:
+    """Shape of one kernel kind: stages 2 and 3 always load the owned cells late, so the
+    early-load mark of a stage shape applies to stages 0 and 1 only."""
+    if kernel == "mag":
+        return shapes["mag"]
+    return shapes["stage"] if kernel in ("stage0", "stage1") else shapes["stage"].rstrip("e")
+
+
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step."""
     share = {k: kern[k][0] for k in kern}
@@ -153,7 +161,7 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
     dur_s = kern[dominant][0] * 1e-3
     gbs = alg_bytes / dur_s / 1e9
     tflops = alg_flops / dur_s / 1e12
-    traffic = measured_traffic(dominant, workload, shapes["mag" if dominant == "mag" else "stage"])
+    traffic = measured_traffic(dominant, workload, kernel_shape(dominant, shapes))
     hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes}
     vpeak = VALU_PEAK_TFLOPS[precision]
@@ -161,7 +169,7 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
            "traffic": traffic, "algorithmic_flops_per_launch": alg_flops,
            "frac_of_nonpacked_peak": tflops / VALU_PEAK_NONPACKED_TFLOPS}
     roof = dict(alu if BOUND[dominant] == "alu" else hbm)
-    roof.update({"kernel": dominant, "tile_shape": shapes["mag" if dominant == "mag" else "stage"],
+    roof.update({"kernel": dominant, "tile_shape": kernel_shape(dominant, shapes),
                  "mean_launch_us": kern[dominant][0] * 1e3,
                  "timed_launches": kern[dominant][1],
                  "other_ceiling": hbm if BOUND[dominant] == "alu" else alu})
