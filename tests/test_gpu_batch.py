@@ -136,3 +136,30 @@ def test_batch_profiled_equals_plain():
         _same(b1.slot(x), b2.slot(y), "profiled batch")
     b1.close()
     b2.close()
+
+
+def test_full_size_batch_members_equal_alone():
+    """The 64-instance workload (1.78 M cells) in the benchmark's launch configuration
+    (autotuned tile shapes, graph replay): sampled members equal their solves alone,
+    with the same shapes, bit for bit."""
+    probs = wl.batch64()
+    batch = lbfs.Batch(len(probs), _budget(probs, extra=64 << 20))
+    slots = [batch.admit(p) for p in probs]
+    assert None not in slots
+    batch.autotune(reps=3)
+    si, mi = batch.tile_shapes_in_use()
+    batch.step(6)
+    obs = batch.observe()
+    assert len(obs) == 64 and not any(o["nonfinite"] for o in obs.values())
+    for k in (0, 7, 19, 23, 38, 41, 50, 63):
+        alone = lbfs.Solver(probs[k])
+        alone.set_tile_shapes(si, mi)
+        alone.step(6)
+        view = batch.slot(slots[k])
+        for f in STATE:
+            assert np.array_equal(view.get(f), alone.get(f)), (k, f)
+        ref = alone.observe()
+        for key in ("liquid_fraction", "volume", "umax", "step"):
+            assert obs[slots[k]][key] == ref[key], (k, key)
+        alone.close()
+    batch.close()
