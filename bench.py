@@ -99,8 +99,9 @@ def parse():
 
 def kernel_sources_digest() -> str:
     h = hashlib.sha256()
-    for name in ("lbfs_kernels.hip", "lbfs_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2511_10257_amd", "csrc", name), "rb") as f:
+    # the kernel sources and the build script (its compiler flags shape the kernels too)
+    for name in ("csrc/lbfs_kernels.hip", "csrc/lbfs_internal.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_2511_10257_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

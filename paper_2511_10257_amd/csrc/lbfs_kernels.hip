@@ -170,6 +170,9 @@ template <typename T>
 __device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, const Side<T>& R,
                                           T F[5])
 {
+    // the compiler may reorder these sums and products (rounding-level differences, no
+    // change of what is computed)
+#pragma clang fp reassociate(on)
     const T h = T(0.5) * K.dx;
     // reconstructions at the nine points, per variable
     T rc[NV][9];
