@@ -30,14 +30,16 @@ struct TileShape {
 // candidates.
 constexpr int NSTAGE_SHAPES = 6;
 constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
-    {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {10, 8, 256, 0}, {8, 8, 192, 0}, {16, 8, 320, 0}};
+    {10, 8, 256, 0}, {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {8, 8, 192, 0}, {16, 8, 320, 0}};
 constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
     {8, 8, 256, 0}, {12, 7, 256, 0}, {10, 8, 256, 0}, {8, 7, 192, 0}, {8, 8, 192, 0}, {16, 4, 256, 0}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
-// (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1.
+// (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1 (a
+// larger tile recomputes fewer halo cells: 2.0x for 64 x 32 against 2.7x for 64 x 16).
 constexpr int MAG_KMAX = 4;
-constexpr int NMAG_SHAPES = 3;
-constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 16, 1024}, {64, 8, 1024}};
+constexpr int NMAG_SHAPES = 5;
+constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 32, 1024}, {64, 16, 1024}, {64, 8, 1024},
+                                               {128, 16, 1024}};
 
 constexpr TileShape stage_shape(bool f64, int k) { return f64 ? STAGE_SHAPES_F64[k] : STAGE_SHAPES_F32[k]; }
 // pointwise kernels (init, derived fields): one thread per cell

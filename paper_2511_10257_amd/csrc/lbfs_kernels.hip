@@ -1009,12 +1009,26 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
     }
 }
 
+// one launch of the fused magnetic kernel on tiles of MAG_SHAPES[shape]
+template <typename T, int K>
+hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream,
+                          hipEvent_t e0, hipEvent_t e1, int nsweeps, double omega, int res, int pin)
+{
+    if constexpr (K < NMAG_SHAPES) {
+        constexpr TileShape M = MAG_SHAPES[K];
+        if (shape == K)
+            return launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt>, dim3(ntiles), dim3(M.nt), stream, e0, e1, insts,
+                                tiles, nsweeps, omega, res, pin);
+        return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, pin);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
-    constexpr TileShape M0 = MAG_SHAPES[0], M1 = MAG_SHAPES[1], M2 = MAG_SHAPES[2];
-    static_assert(NMAG_SHAPES == 3, "one case per shape");
     if (ntiles <= 0) return hipSuccess;
     if (shape < 0 || shape >= NMAG_SHAPES) return hipErrorInvalidValue;
     // the potential is read from phi[*pidx] and written to the other buffer (halo cells
@@ -1026,21 +1040,7 @@ hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* p
         nsweeps -= k;
         const int res = residual && nsweeps == 0;
         const hipEvent_t a = first ? e0 : nullptr, b = nsweeps == 0 ? e1 : nullptr;
-        hipError_t e;
-        switch (shape) {
-        case 0:
-            e = launch_timed(k_mag_fused<T, M0.tx, M0.ty, M0.nt>, dim3(ntiles), dim3(M0.nt), stream, a, b, insts,
-                             tiles, k, omega, res, *pidx);
-            break;
-        case 1:
-            e = launch_timed(k_mag_fused<T, M1.tx, M1.ty, M1.nt>, dim3(ntiles), dim3(M1.nt), stream, a, b, insts,
-                             tiles, k, omega, res, *pidx);
-            break;
-        default:
-            e = launch_timed(k_mag_fused<T, M2.tx, M2.ty, M2.nt>, dim3(ntiles), dim3(M2.nt), stream, a, b, insts,
-                             tiles, k, omega, res, *pidx);
-            break;
-        }
+        const hipError_t e = launch_mag_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, omega, res, *pidx);
         if (e != hipSuccess) return e;
         *pidx ^= 1;
         first = false;
