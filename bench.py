@@ -152,6 +152,33 @@ def kernel_shape(kernel: str, shapes: dict) -> str:
     return shapes["stage"] if kernel in ("stage0", "stage1") else shapes["stage"].rstrip("e")
 
 
+def error_vs_oracle(solver, prob: dict) -> dict:
+    """One step of the GPU path against one step of the FP64 oracle from the same state
+    (the solver's own current state, read back): relative L2 error per field, with the
+    floors of near-zero fields (He ~ L, C ~ 1, phi ~ H0 R, p ~ sigma/R, momentum ~
+    rho_l cs^2 sigma / mu_l)."""
+    import numpy as np
+    from oracle import oracle as orc
+    names = ("He", "p", "Mx", "My", "C", "phi", "S")
+    state = {k: solver.get(k) for k in names}
+    t0 = solver.observe()["t"]
+    o = orc.Oracle(dict(prob, precision="fp64", init_max=0), init=False)
+    o.set_state(state)
+    solver.set_state(state)          # the same values in the solver's own precision
+    o.step(1)
+    solver.step(1)
+    p = o.params
+    R = prob["drop"][2]
+    floor = dict(He=p.latent, p=p.sigma / R, Mx=p.rho[1] / 3.0 * p.sigma / p.mu[1],
+                 My=p.rho[1] / 3.0 * p.sigma / p.mu[1], C=1.0, phi=max(p.h0 * R, 1e-30))
+    err = {}
+    for k in ("He", "p", "Mx", "My", "C", "phi"):
+        a, b = solver.get(k), o.get(k)
+        err[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor[k] * np.sqrt(b.size)))
+    return {"per_step_rel_l2": err, "max": max(err.values()), "bound": 1e-5 if prob["precision"] == "fp32" else 1e-10,
+            "state": f"the solver's state at t = {t0:g} after the timed steps"}
+
+
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step."""
     share = {k: kern[k][0] for k in kern}
@@ -230,6 +257,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
     out["liquid_fraction_reached"] = obs["liquid_fraction"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        if cells <= 1024 * 1024:
+            out["error_vs_oracle"] = error_vs_oracle(solver, prob)
     return out
 
 
