@@ -238,8 +238,9 @@ void lbfs_destroy(lbfs_solver* s);
  * The batch's metadata (descriptors, tile lists, FP64 results) is carved from the same
  * buffer and grows on admission. A batch handle is not thread safe. */
 
-/* Device bytes one admission takes from the batch buffer for these parameters
-   (its state; the shared metadata grows by about 1 KB per instance); 0 if invalid. */
+/* Device bytes one admission takes from the batch buffer for these parameters (its
+   state; the shared metadata, descriptors and tile lists, grows with the instances'
+   tile counts, by about half a byte per cell); 0 if invalid. */
 size_t lbfs_batch_instance_bytes(const lbfs_params* p);
 
 /* Create an empty batch of at most max_slots instances over dev_buf (bytes, caller

@@ -1009,7 +1009,7 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     double t[2 * LBFS_MAX_SHAPES] = {0};
     const int phase0 = E.phase;
     int rc = LBFS_OK;
-    // stage kernels: the first two Runge-Kutta stages (they write only the stage fields)
+    // stage kernels: stage 1 and twice stage 2 (they write only the stage fields)
     int best_s = 0;
     for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
         rc = apply_shapes(s, k, E.mag_shape);
