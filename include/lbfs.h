@@ -105,6 +105,10 @@ typedef struct lbfs_observables {
     double umax_drop;         /* max |u| over cells with Ct >= 1/2                  */
     double height;            /* sum(Ct dx) along the column containing drop_cx     */
     double wall_heat;         /* sum over the south wall of -lambda dT/dy dx (fixed wall) */
+    double fourier;           /* Fo of Eq. 50: lambda_l t / (rho_l Cp_l R0^2), R0 = drop_radius */
+    double peclet;            /* Pe of Eq. 50 as umax_drop D / alpha_l, D = 2 R0,
+                                 alpha_l = lambda_l / (rho_l Cp_l) (printed with a square
+                                 that makes it dimensional; read as the usual u D / alpha) */
     int64_t step;
     int32_t nonfinite;        /* 1 if a conserved value was not finite              */
 } lbfs_observables;

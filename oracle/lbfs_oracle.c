@@ -753,4 +753,8 @@ void orc_observe(orc_sim* s, orc_obs* o)
     o->height = height;
     o->umax_drop = udrop;
     o->wall_heat = heat;
+    /* Eq. 50 with the liquid properties and the initial radius R0 */
+    double alpha_l = s->p.lam[1] / (s->p.rho[1] * s->p.cp[1]);
+    o->fourier = alpha_l * s->t / (s->p.drop_r * s->p.drop_r);
+    o->peclet = udrop * 2.0 * s->p.drop_r / alpha_l;
 }

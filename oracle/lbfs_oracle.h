@@ -68,9 +68,12 @@ typedef struct orc_obs {
     double mag_residual;     /* ||r||_2 of the magnetic system after the sweeps */
     double umax;             /* max |u| over all cells                     */
     double nonfinite;        /* 1 if any conserved value is not finite     */
-    double height;           /* max y of a cell with Ct >= 1/2, + dx/2     */
+    double height;           /* sum(Ct dx) along the column through drop_cx */
     double umax_drop;        /* max |u| over cells with Ct >= 1/2          */
     double wall_heat;        /* integrated heat flux into the south wall   */
+    double fourier;          /* Fo of Eq. 50: lambda_l t / (rho_l Cp_l R0^2) */
+    double peclet;           /* Pe of Eq. 50, read as umax_drop D / alpha_l,
+                                D = 2 R0, alpha_l = lambda_l / (rho_l Cp_l) */
 } orc_obs;
 
 typedef struct orc_sim orc_sim;

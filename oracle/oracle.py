@@ -42,7 +42,7 @@ class Params(C.Structure):
 class Obs(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "t", "step", "liquid_fraction", "solid_ratio", "volume", "volume0",
-        "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat")]
+        "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat", "fourier", "peclet")]
 
 
 def build(force: bool = False) -> str:

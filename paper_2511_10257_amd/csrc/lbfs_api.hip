@@ -359,6 +359,10 @@ int fill_observables(const lbfs_params& p, double t, int64_t step, double vol0, 
     o->umax_drop = r[RES_UDROP];
     o->height = r[RES_HEIGHT] * p.dx;
     o->wall_heat = r[RES_HEAT];
+    // Eq. 50 with the liquid properties and the initial radius R0
+    const double alpha_l = p.lambda[1] / (p.rho[1] * p.cp[1]);
+    o->fourier = alpha_l * t / (p.drop_radius * p.drop_radius);
+    o->peclet = o->umax_drop * 2.0 * p.drop_radius / alpha_l;
     o->nonfinite = r[RES_NONFINITE] != 0.0 || !std::isfinite(r[RES_CT]) ? 1 : 0;
     return o->nonfinite ? LBFS_E_NONFINITE : LBFS_OK;
 }

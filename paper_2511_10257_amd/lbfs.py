@@ -62,7 +62,8 @@ class Observables(C.Structure):
         ("t", C.c_double), ("liquid_fraction", C.c_double), ("solid_ratio", C.c_double),
         ("volume", C.c_double), ("volume0", C.c_double), ("mag_residual", C.c_double),
         ("umax", C.c_double), ("umax_drop", C.c_double), ("height", C.c_double),
-        ("wall_heat", C.c_double), ("step", C.c_int64), ("nonfinite", C.c_int32),
+        ("wall_heat", C.c_double), ("fourier", C.c_double), ("peclet", C.c_double),
+        ("step", C.c_int64), ("nonfinite", C.c_int32),
     ]
 
 

@@ -131,6 +131,8 @@ def test_step_fp64_matches_oracle_on_64x64_states():
         o.step(n_before)
         state = {k: o.get(k) for k in ("He", "p", "Mx", "My", "C", "phi", "S")}
         g.set_state(state)
+        clock = o.observe()
+        g.set_time(clock["t"], int(clock["step"]))
         o.step(1)
         g.step(1)
         fl = floors(prob)
@@ -139,7 +141,7 @@ def test_step_fp64_matches_oracle_on_64x64_states():
             assert rel_l2(a, b, fl[name]) < 1e-11, (n_before, name, rel_l2(a, b, fl[name]))
         ob, og = o.observe(), g.observe()
         for key in ("liquid_fraction", "solid_ratio", "volume", "mag_residual", "umax", "height",
-                    "wall_heat", "umax_drop"):
+                    "wall_heat", "umax_drop", "fourier", "peclet", "t"):
             assert og[key] == pytest.approx(ob[key], rel=1e-9, abs=1e-14), key
 
 

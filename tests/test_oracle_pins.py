@@ -470,3 +470,18 @@ def test_fluxes_converge_to_the_macroscopic_relations():
         r2 = errs[3][q] / errs[2][q]
         assert 0.3 < r1 < 0.6 and 0.3 < r2 < 0.6, (q, [e[q] for e in errs])
         assert errs[3][q] < 0.1, (q, errs[3][q])
+
+
+def test_dimensionless_groups_of_eq50():
+    """Fo and Pe of Eq. 50 from the oracle's observables (plain definitions on top of the
+    clock and the droplet's largest speed): Fo grows linearly in time with slope
+    alpha_l / R0^2 and Pe is that speed over alpha_l / D."""
+    prob = wl.droplet_problem(32, 8.0, ste=0.2, bo_m=1.5, angle_deg=0.0, precision="fp64")
+    o = orc.Oracle(prob)
+    o.step(10)
+    a = o.observe()
+    o.step(10)
+    b = o.observe()
+    alpha_l = prob["lam"][1] / (prob["rho"][1] * prob["cp"][1])
+    assert b["fourier"] - a["fourier"] == pytest.approx(alpha_l * 10 * prob["dt"] / 8.0 ** 2, rel=1e-12)
+    assert b["peclet"] == pytest.approx(b["umax_drop"] * 16.0 / alpha_l, rel=1e-12)
