@@ -10,7 +10,9 @@
  * Method, in the paper's order (Table 1, "computational procedure"):
  *   magnetic potential  : Eq. 4, discretised by the magnetic LBFS flux of Sec. 3.1 at
  *                         delta_t = dx/2 (a compact 5-point system) and relaxed by
- *                         red-black Gauss-Seidel/SOR sweeps;
+ *                         red-black Gauss-Seidel/SOR sweeps, or (mag_method 1) the
+ *                         LBFS pseudo-time solve itself: m* fluxes built literally
+ *                         (Eqs. 13, 16, 18, 44, 45) and Eq. 17 advanced by SSP-RK3;
  *   Kelvin force        : Eq. 6, last line;
  *   thermal/flow/phase  : Eq. 38-46 (cell-centred FVM, Eq. 44 reconstruction, Eq. 45
  *                         compatibility, star distributions Eqs. 16, 22, 32, 33,
@@ -34,6 +36,11 @@
  *   - Walls: zero mass and order-parameter flux; fixed-temperature walls conduct
  *     through the half cell; momentum flux from the same LBFS face formula with
  *     mirrored ghost cells (no-slip).
+ *   - Magnetic LBFS: the flux sum_a e_a m*_a that Eqs. 15-16 give is -D mu grad(phi),
+ *     so Eq. 17 is a diffusion towards Eq. 4 (Eq. 18 prints the opposite sign);
+ *     tau_m uses the mean permeability of the face's two cells; the pseudo-time step
+ *     is a parameter, by default the stable dx^2 / (4 D mu_max); the initial solve
+ *     uses the sweeps whatever the per-step method (same fixed point).
  */
 #include "lbfs_oracle.h"
 
@@ -69,6 +76,8 @@ struct orc_sim {
     double *val[NREC], *gx[NREC], *gy[NREC];
     double *mu, *lam, *cp, *fs;
     double *fx[5], *fy[5];
+    /* magnetic LBFS pseudo-time solve: RK3 stage values, rate, cell gradients, fluxes */
+    double *mph[2], *mL, *mgx, *mgy, *mfx, *mfy;
 };
 
 #define IX(s, i, j) (((j) + G) * (s)->px + ((i) + G))
@@ -158,6 +167,8 @@ orc_sim* orc_new(const orc_params* pin)
     const orc_params* p = pin;
     if (p->nx < 4 || p->ny < 4 || p->dx <= 0 || p->dt <= 0 || p->dt_stream <= 0) return NULL;
     if (p->tau_g <= 0.5 || p->xi <= 0) return NULL;
+    if (p->mag_method < 0 || p->mag_method > 1) return NULL;
+    if (p->mag_method == 1 && !(p->mag_lbfs_d > 0.0)) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     s->nx = p->nx; s->ny = p->ny;
@@ -176,6 +187,8 @@ orc_sim* orc_new(const orc_params* pin)
     s->fmg[0] = zalloc(n); s->fmg[1] = zalloc(n);
     for (int k = 0; k < NREC; k++) { s->val[k] = zalloc(n); s->gx[k] = zalloc(n); s->gy[k] = zalloc(n); }
     s->mu = zalloc(n); s->lam = zalloc(n); s->cp = zalloc(n); s->fs = zalloc(n);
+    s->mph[0] = zalloc(n); s->mph[1] = zalloc(n); s->mL = zalloc(n); s->mgx = zalloc(n); s->mgy = zalloc(n);
+    s->mfx = zalloc((size_t)(p->nx + 1) * p->ny); s->mfy = zalloc((size_t)p->nx * (p->ny + 1));
     return s;
 }
 
@@ -186,6 +199,7 @@ void orc_free(orc_sim* s)
     free(s->phi); free(s->S); free(s->mum); free(s->fmg[0]); free(s->fmg[1]);
     for (int k = 0; k < NREC; k++) { free(s->val[k]); free(s->gx[k]); free(s->gy[k]); }
     free(s->mu); free(s->lam); free(s->cp); free(s->fs);
+    free(s->mph[0]); free(s->mph[1]); free(s->mL); free(s->mgx); free(s->mgy); free(s->mfx); free(s->mfy);
     free(s);
 }
 
@@ -306,6 +320,168 @@ double orc_mag_sweeps(orc_sim* s, int nsweeps, double omega)
     compute_mum(s);
     for (int k = 0; k < nsweeps; k++) { rb_pass(s, 0, omega); rb_pass(s, 1, omega); }
     return orc_mag_residual(s);
+}
+
+/* ------------------------------------------------ magnetic LBFS (Sec. 3.1) */
+
+/* Ghost layers of a potential for the LBFS construction: a fixed-potential wall keeps
+   the applied potential at the wall (odd reflection about it), an insulating wall
+   mirrors the potential (zero normal derivative), a periodic axis wraps. The x
+   direction on the interior rows first, then y on all columns. */
+static void fill_phi_ghosts(const orc_sim* s, double* a)
+{
+    int nx = s->nx, ny = s->ny;
+    double dx = s->p.dx;
+    for (int j = 0; j < ny; j++) {
+        double y = (j + 0.5) * dx;
+        for (int k = 0; k < G; k++) {
+            if (s->p.periodic[0]) {
+                a[IX(s, -1 - k, j)] = a[IX(s, nx - 1 - k, j)];
+                a[IX(s, nx + k, j)] = a[IX(s, k, j)];
+            } else {
+                double vw = a[IX(s, k, j)], ve = a[IX(s, nx - 1 - k, j)];
+                a[IX(s, -1 - k, j)] = s->p.mbc[0] == 1 ? 2.0 * phi_applied(s, 0.0, y) - vw : vw;
+                a[IX(s, nx + k, j)] = s->p.mbc[1] == 1 ? 2.0 * phi_applied(s, nx * dx, y) - ve : ve;
+            }
+        }
+    }
+    for (int i = -G; i < nx + G; i++) {
+        double x = (i + 0.5) * dx;
+        for (int k = 0; k < G; k++) {
+            if (s->p.periodic[1]) {
+                a[IX(s, i, -1 - k)] = a[IX(s, i, ny - 1 - k)];
+                a[IX(s, i, ny + k)] = a[IX(s, i, k)];
+            } else {
+                double vs = a[IX(s, i, k)], vn = a[IX(s, i, ny - 1 - k)];
+                a[IX(s, i, -1 - k)] = s->p.mbc[2] == 1 ? 2.0 * phi_applied(s, x, 0.0) - vs : vs;
+                a[IX(s, i, ny + k)] = s->p.mbc[3] == 1 ? 2.0 * phi_applied(s, x, ny * dx) - vn : vn;
+            }
+        }
+    }
+}
+
+/* Normal flux sum_a e_a.n m*_a (Eq. 18) through the face between cell (iL, jL) and its
+   neighbour along `axis`. The potential at the nine points x_f - e_a delta_t comes
+   from Eq. 44 (the cell on the point's side and its gradient; the two one-sided values
+   averaged for points on the face line), the face potential from the compatibility
+   sum of Eq. 45, the equilibria at the face and at the points from Eq. 13, the
+   non-equilibrium part and m* from Eq. 16 with tau_m = 1/2 + mu_f D / (cs^2 delta_t),
+   mu_f the mean permeability of the two cells. */
+static double lbfs_mag_face(const orc_sim* s, const double* ph, int axis, int iL, int jL, double D)
+{
+    double dx = s->p.dx, dts = s->p.dt_stream;
+    int iR = iL + (axis == 0), jR = jL + (axis == 1);
+    int cL = IX(s, iL, jL), cR = IX(s, iR, jR);
+    double xL = (iL + 0.5) * dx, yL = (jL + 0.5) * dx, xR = (iR + 0.5) * dx, yR = (jR + 0.5) * dx;
+    double xf = 0.5 * (xL + xR), yf = 0.5 * (yL + yR);
+    double pv[9], phif = 0.0;
+    for (int a = 0; a < 9; a++) {
+        double px = xf - EX[a] * dts, py = yf - EY[a] * dts;
+        double en = axis == 0 ? EX[a] : EY[a];
+        double vL = ph[cL] + (px - xL) * s->mgx[cL] + (py - yL) * s->mgy[cL];
+        double vR = ph[cR] + (px - xR) * s->mgx[cR] + (py - yR) * s->mgy[cR];
+        pv[a] = en > 0.0 ? vL : (en < 0.0 ? vR : 0.5 * (vL + vR));
+        phif += WA[a] * pv[a];
+    }
+    double muf = 0.5 * (s->mum[cL] + s->mum[cR]);
+    double taum = 0.5 + muf * D / (CS2 * dts);
+    double F = 0.0;
+    for (int a = 0; a < 9; a++) {
+        double en = axis == 0 ? EX[a] : EY[a];
+        double meq_f = WA[a] * phif;
+        double meq_p = WA[a] * pv[a];
+        double mneq = -taum * (meq_f - meq_p);
+        double mstar = meq_f + (1.0 - 0.5 / taum) * mneq;
+        F += en * mstar;
+    }
+    return F;
+}
+
+/* all face fluxes of potential ph into s->mfx / s->mfy (permeability and its ghosts
+   already in s->mum) */
+static void lbfs_mag_fluxes(orc_sim* s, double* ph, double D)
+{
+    int nx = s->nx, ny = s->ny;
+    double dx = s->p.dx;
+    fill_phi_ghosts(s, ph);
+    for (int j = -G + 1; j < ny + G - 1; j++)
+        for (int i = -G + 1; i < nx + G - 1; i++) {
+            int c = IX(s, i, j);
+            s->mgx[c] = (ph[IX(s, i + 1, j)] - ph[IX(s, i - 1, j)]) / (2.0 * dx);
+            s->mgy[c] = (ph[IX(s, i, j + 1)] - ph[IX(s, i, j - 1)]) / (2.0 * dx);
+        }
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i <= nx; i++) s->mfx[j * (nx + 1) + i] = lbfs_mag_face(s, ph, 0, i - 1, j, D);
+    for (int j = 0; j <= ny; j++)
+        for (int i = 0; i < nx; i++) s->mfy[j * nx + i] = lbfs_mag_face(s, ph, 1, i, j - 1, D);
+}
+
+/* d(phi)/d(tau) of Eq. 17 by the finite-volume balance of Eq. 42 */
+static void lbfs_mag_rate(orc_sim* s, double* ph, double D, double* L)
+{
+    int nx = s->nx, ny = s->ny;
+    double dx = s->p.dx;
+    lbfs_mag_fluxes(s, ph, D);
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++)
+            L[IX(s, i, j)] = -(s->mfx[j * (nx + 1) + i + 1] - s->mfx[j * (nx + 1) + i] +
+                               s->mfy[(j + 1) * nx + i] - s->mfy[j * nx + i]) / dx;
+}
+
+static void mag_permeability_with_ghosts(orc_sim* s)
+{
+    compute_mum(s);
+    fill_ghosts(s, s->mum, K_EVEN);
+}
+
+double orc_mag_lbfs_dtau(const orc_params* p, double D)
+{
+    /* Every row of the discrete operator sums in absolute value to at most
+       8 D mu_max / dx^2 and SSP-RK3 is stable on the negative real axis up to about
+       -2.51, so this step (|z| <= 2) keeps every mode stable. The mixture permeability
+       (Eq. 11) never exceeds that of the most permeable phase. */
+    double m = 1.0 + p->chi[0];
+    for (int k = 1; k < 3; k++)
+        if (1.0 + p->chi[k] > m) m = 1.0 + p->chi[k];
+    return p->dx * p->dx / (4.0 * D * p->mu0 * m);
+}
+
+double orc_mag_lbfs(orc_sim* s, int nsteps, double D, double dtau)
+{
+    int nx = s->nx, ny = s->ny;
+    if (dtau <= 0.0) dtau = orc_mag_lbfs_dtau(&s->p, D);
+    mag_permeability_with_ghosts(s);
+    double *u0 = s->phi, *u1 = s->mph[0], *u2 = s->mph[1], *L = s->mL;
+    for (int n = 0; n < nsteps; n++) {
+        lbfs_mag_rate(s, u0, D, L);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                int c = IX(s, i, j);
+                u1[c] = u0[c] + dtau * L[c];
+            }
+        lbfs_mag_rate(s, u1, D, L);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                int c = IX(s, i, j);
+                u2[c] = 0.75 * u0[c] + 0.25 * (u1[c] + dtau * L[c]);
+            }
+        lbfs_mag_rate(s, u2, D, L);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                int c = IX(s, i, j);
+                u0[c] = u0[c] / 3.0 + 2.0 / 3.0 * (u2[c] + dtau * L[c]);
+            }
+    }
+    return orc_mag_residual(s);
+}
+
+void orc_mag_lbfs_fluxes(orc_sim* s, double D, double* fx, double* fy)
+{
+    int nx = s->nx, ny = s->ny;
+    mag_permeability_with_ghosts(s);
+    lbfs_mag_fluxes(s, s->phi, D);
+    memcpy(fx, s->mfx, (size_t)(nx + 1) * ny * sizeof(double));
+    memcpy(fy, s->mfy, (size_t)nx * (ny + 1) * sizeof(double));
 }
 
 /* Kelvin force (Eq. 6): H = -grad(phi) and F = (mu0 chi / 2) grad|H|^2, central
@@ -618,8 +794,12 @@ void orc_step(orc_sim* s, int nsteps)
     int nx = s->nx, ny = s->ny;
     double dt = s->p.dt;
     for (int n = 0; n < nsteps; n++) {
-        /* magnetic potential: red-black sweeps, then the Kelvin force (frozen over the stages) */
-        s->res = orc_mag_sweeps(s, s->p.sweeps, s->p.omega);
+        /* magnetic potential: red-black sweeps or LBFS pseudo-time steps, then the Kelvin
+           force (frozen over the stages) */
+        if (s->p.mag_method == 1)
+            s->res = orc_mag_lbfs(s, s->p.sweeps, s->p.mag_lbfs_d, s->p.mag_lbfs_dtau);
+        else
+            s->res = orc_mag_sweeps(s, s->p.sweeps, s->p.omega);
         kelvin(s);
         /* SSP-RK3 on (He, p, Mx, My, C) */
         rhs(s, s->W, s->R);

@@ -58,6 +58,11 @@ typedef struct orc_params {
     double init_tol;      /* relative residual target of the initial solve */
     int init_max;         /* sweep cap of the initial solve                */
     int init_check;       /* sweeps between residual checks                */
+    int mag_method;       /* per-step magnetic update: 0 red-black sweeps of the compact
+                             system, 1 LBFS pseudo-time solve of Eq. 17 (Sec. 3.1), both
+                             `sweeps` iterations per time step                          */
+    double mag_lbfs_d;    /* free parameter D of tau_m (Sec. 3.1), > 0                   */
+    double mag_lbfs_dtau; /* pseudo-time step (<= 0: dx^2 / (4 D mu_max))                */
 } orc_params;
 
 typedef struct orc_obs {
@@ -94,6 +99,16 @@ void orc_set_time(orc_sim* s, double t, double step);
 void orc_observe(orc_sim* s, orc_obs* o);
 double orc_mag_sweeps(orc_sim* s, int nsweeps, double omega);  /* returns ||r||_2 after */
 double orc_mag_residual(orc_sim* s);
+/* LBFS pseudo-time solve of the magnetic potential (Eqs. 12-18): permeability from
+   the current state, then nsteps SSP-RK3 steps of size dtau (<= 0: automatic) of
+   Eq. 17 with the face fluxes built from m* (Eq. 16); returns ||r||_2 after. */
+double orc_mag_lbfs(orc_sim* s, int nsteps, double D, double dtau);
+/* Normal face fluxes sum_a e_a.n m*_a of the current potential (Eq. 18): fx is
+   (nx+1)*ny (x-faces, row-major j*(nx+1)+i, face i between cells i-1 and i), fy is
+   nx*(ny+1); the permeability is taken from the current state. */
+void orc_mag_lbfs_fluxes(orc_sim* s, double D, double* fx, double* fy);
+/* the automatic pseudo-time step of orc_mag_lbfs */
+double orc_mag_lbfs_dtau(const orc_params* p, double D);
 
 /* pointwise pieces, exposed for the moment and branch pins */
 void orc_lattice(double* ex, double* ey, double* w);

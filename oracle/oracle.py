@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("sweeps", C.c_int), ("omega", C.c_double),
         ("init_omega", C.c_double), ("init_tol", C.c_double),
         ("init_max", C.c_int), ("init_check", C.c_int),
+        ("mag_method", C.c_int), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
     ]
 
 
@@ -86,6 +87,11 @@ def load(path: str):
     L.orc_mag_sweeps.restype = C.c_double
     L.orc_mag_residual.argtypes = [C.c_void_p]
     L.orc_mag_residual.restype = C.c_double
+    L.orc_mag_lbfs.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+    L.orc_mag_lbfs.restype = C.c_double
+    L.orc_mag_lbfs_fluxes.argtypes = [C.c_void_p, C.c_double, dp, dp]
+    L.orc_mag_lbfs_dtau.argtypes = [C.POINTER(Params), C.c_double]
+    L.orc_mag_lbfs_dtau.restype = C.c_double
     L.orc_lattice.argtypes = [dp, dp, dp]
     L.orc_enthalpy_state.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp, dp]
     L.orc_equilibria.argtypes = [C.POINTER(Params)] + [C.c_double] * 9 + [dp, dp, dp]
@@ -129,6 +135,9 @@ def make_params(prob: dict) -> Params:
     p.init_tol = float(prob.get("init_tol", 1e-12))
     p.init_max = int(prob.get("init_max", 200000))
     p.init_check = int(prob.get("init_check", 50))
+    p.mag_method = {"sweeps": 0, "lbfs": 1}[prob.get("mag_method", "sweeps")]
+    p.mag_lbfs_d = float(prob.get("mag_lbfs_d", 1.0))
+    p.mag_lbfs_dtau = float(prob.get("mag_lbfs_dtau", 0.0))
     if "latent" in prob and "h0" in prob:
         p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
     else:
@@ -209,6 +218,20 @@ class Oracle:
 
     def mag_residual(self) -> float:
         return self._L.orc_mag_residual(self._h)
+
+    def mag_lbfs(self, n: int, D: float = 1.0, dtau: float = 0.0) -> float:
+        """n pseudo-time RK3 steps of the magnetic LBFS (Eq. 17); returns ||r||_2."""
+        return self._L.orc_mag_lbfs(self._h, int(n), float(D), float(dtau))
+
+    def mag_lbfs_fluxes(self, D: float = 1.0):
+        """Normal m* fluxes (Eq. 18) of the current potential: (ny, nx+1), (ny+1, nx)."""
+        fx = np.zeros((self.nx + 1) * self.ny)
+        fy = np.zeros(self.nx * (self.ny + 1))
+        self._L.orc_mag_lbfs_fluxes(self._h, float(D), _dp(fx), _dp(fy))
+        return fx.reshape(self.ny, self.nx + 1), fy.reshape(self.ny + 1, self.nx)
+
+    def mag_lbfs_dtau(self, D: float = 1.0) -> float:
+        return self._L.orc_mag_lbfs_dtau(C.byref(self.params), float(D))
 
 
 def lattice():
