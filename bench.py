@@ -52,6 +52,15 @@ FIELD_ACCESSES = {
 # type (oracle/opcount.py) on the 256 x 256 droplet: 13993 per cell-step, of which the
 # magnetic phase (permeability, 4 sweeps, residual) takes 152.7 and each stage 4613.4
 ALG_FLOPS = {"mag": 152.7, "stage1": 4613.4, "stage2": 4613.4, "stage3": 4613.4, "reduce": 0.0}
+# the magnetic phase by the LBFS pseudo-time solve, counted the same way on the oracle's
+# literal m* construction (nine reconstructed points, compatibility sum, equilibria and
+# star distributions per face): 51.8 per cell for the permeability and residual plus
+# 1682.5 per cell and pseudo-step. The kernel evaluates the exact reduction of that
+# construction at delta_t = dx/2 (about 45 operations per cell and pseudo-step), so
+# this count measures the definitional algorithm, not the instructions issued.
+ALG_FLOPS_MAG_LBFS = (51.8, 1682.5)
+# and by the sweeps: 51.8 per cell for the permeability and residual, 25.2 per sweep
+ALG_FLOPS_MAG_SWEEPS = (51.8, 25.23)
 # the resource that bounds each kernel: the sweeps stream fields with little arithmetic,
 # the stages are far above the ridge point (68 FLOP/B against 19.7 FP32 / 9.8 FP64)
 BOUND = {"mag": "hbm", "stage1": "alu", "stage2": "alu", "stage3": "alu", "reduce": "hbm"}
@@ -89,6 +98,15 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-chunk", type=int, default=200, help="steps between observations")
     ap.add_argument("--no-serve-baseline", action="store_true")
+    ap.add_argument("--mag-method", choices=["sweeps", "lbfs"], default="sweeps",
+                    help="per-step magnetic update of the single-solve workloads: red-black sweeps or "
+                         "the LBFS pseudo-time solve (Eq. 17)")
+    ap.add_argument("--mag-steps", type=int, default=None,
+                    help="sweeps or pseudo-steps per time step (default: the workload's)")
+    ap.add_argument("--mag-max-iters", type=int, default=0,
+                    help="convergence control: repeat chunks of --mag-steps iterations per step until the "
+                         "magnetic residual is at most --mag-tol, at most this many iterations (0: off)")
+    ap.add_argument("--mag-tol", type=float, default=0.0, help="absolute ||r||_2 target of the convergence control")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = DEFAULT_STEPS.get(args.workload, 0)
@@ -179,13 +197,17 @@ def error_vs_oracle(solver, prob: dict) -> dict:
             "state": f"the solver's state at t = {t0:g} after the timed steps"}
 
 
-def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict) -> dict:
-    """Roofline of the kernel kind with the largest mean duration per step."""
+def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict, mag_flops=None,
+             mag_launches: int = 1) -> dict:
+    """Roofline of the kernel kind with the largest mean duration per step. The magnetic
+    phase streams its fields once per launch (mag_launches per step)."""
     share = {k: kern[k][0] for k in kern}
     dominant = max(share, key=share.get)
     esize = 8 if precision == "fp64" else 4
-    alg_bytes = FIELD_ACCESSES[dominant] * esize * cells
-    alg_flops = ALG_FLOPS[dominant] * cells
+    accesses = dict(FIELD_ACCESSES, mag=FIELD_ACCESSES["mag"] * mag_launches)
+    alg_bytes = accesses[dominant] * esize * cells
+    flops = dict(ALG_FLOPS, **({"mag": mag_flops} if mag_flops is not None else {}))
+    alg_flops = flops[dominant] * cells
     dur_s = kern[dominant][0] * 1e-3
     gbs = alg_bytes / dur_s / 1e9
     tflops = alg_flops / dur_s / 1e12
@@ -231,6 +253,22 @@ def copy_calibration(torch, mib: int) -> None:
 def run_single(args, torch, lbfs, wl) -> dict:
     prob = {"droplet64": wl.droplet64, "droplet256": wl.droplet256, "droplet1024": lambda: wl.droplet1024("fp32"),
             "droplet1024-fp64": lambda: wl.droplet1024("fp64"), "droplet4096": wl.droplet4096}[args.workload]()
+    if args.mag_method != "sweeps" or args.mag_steps is not None or args.mag_max_iters > 0:
+        prob = wl.with_changes(prob, mag_method=args.mag_method,
+                               sweeps=prob["sweeps"] if args.mag_steps is None else args.mag_steps,
+                               mag_max_iters=args.mag_max_iters, mag_tol=args.mag_tol)
+        prob["name"] += f"-mag-{args.mag_method}{prob['sweeps']}"
+        if args.mag_max_iters > 0:
+            prob["name"] += f"-upto{args.mag_max_iters}-tol{args.mag_tol:g}"
+    # per step, at the fixed count (with convergence control, at the most chunks)
+    iters = max(prob["sweeps"], args.mag_max_iters)
+    base, per = ALG_FLOPS_MAG_LBFS if args.mag_method == "lbfs" else ALG_FLOPS_MAG_SWEEPS
+    mag_flops = base + per * iters
+    # launches of the magnetic phase: up to 4 sweeps or 3 pseudo-steps each, times the
+    # chunks of the convergence control (an upper bound: converged chunks only copy)
+    kmax = 3 if args.mag_method == "lbfs" else 4
+    chunks = -(-args.mag_max_iters // max(1, prob["sweeps"])) if args.mag_max_iters > 0 else 1
+    mag_launches = max(1, -(-prob["sweeps"] // kmax)) * chunks
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")
@@ -248,13 +286,16 @@ def run_single(args, torch, lbfs, wl) -> dict:
                "f64" if prob["precision"] == "fp64" else "f32",
                {"workload": prob["name"], "nx": prob["nx"], "ny": prob["ny"], "precision": prob["precision"],
                 "angle_deg": prob["angle_deg"], "bo_m": prob["bo_m"], "ste": prob["ste"],
+                "mag_method": prob.get("mag_method", "sweeps"),
+                "mag_max_iters": prob.get("mag_max_iters", 0), "mag_tol": prob.get("mag_tol", 0.0),
                 "sweeps_per_step": prob["sweeps"], "reductions": "f64",
                 "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default")})
-    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload, shapes)
+    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload, shapes, mag_flops, mag_launches)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned
     out["liquid_fraction_reached"] = obs["liquid_fraction"]
+    out["mag_residual_after_last_step"] = obs["mag_residual"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
         if cells <= 1024 * 1024:

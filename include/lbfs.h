@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBFS_ABI_VERSION 1u
+#define LBFS_ABI_VERSION 2u
 
 enum {
     LBFS_OK = 0,
@@ -57,6 +57,7 @@ enum { LBFS_MBC_INSULATING = 0, LBFS_MBC_FIXED = 1 };    /* magnetic wall condit
                                                             fixed = potential of the
                                                             applied uniform field  */
 enum { LBFS_INIT_DROPLET = 0, LBFS_INIT_UNIFORM = 1 };
+enum { LBFS_MAG_SWEEPS = 0, LBFS_MAG_LBFS = 1 };          /* per-step magnetic update */
 
 /* Problem statement (plain data, copied at init). Phase-indexed arrays are
    [solid, liquid, gas]; Eq. 11 mixes them with the solid fraction Fs and the
@@ -86,12 +87,31 @@ typedef struct lbfs_params {
     int32_t thermal_bc[4];    /* LBFS_TBC_* per wall                                */
     double thermal_val[4];    /* wall temperatures of fixed walls                   */
     int32_t mag_bc[4];        /* LBFS_MBC_* per wall                                */
-    int32_t sweeps;           /* red-black sweeps per step                          */
+    int32_t sweeps;           /* magnetic iterations per step: red-black sweeps, or
+                                 pseudo-time steps with LBFS_MAG_LBFS                */
     double sor_omega;         /* relaxation factor of the per-step sweeps (0, 2)    */
     double init_omega;        /* SOR factor of the initial solve, <= 0: automatic   */
     double init_tol;          /* relative residual target of the initial solve      */
     int32_t init_max;         /* sweep cap of the initial solve                     */
     int32_t init_check;       /* sweeps between residual checks of the initial solve */
+    /* Per-step magnetic update (the initial solve always uses the sweeps; both methods
+       have the same fixed point): LBFS_MAG_SWEEPS relaxes the compact system of the
+       magnetic LBFS flux (Sec. 3.1 at delta_t = dx/2) by red-black SOR; LBFS_MAG_LBFS
+       advances Eq. 17 in pseudo-time by SSP-RK3, the paper's own procedure (Table 1
+       (b)-(c)), with the face flux -D mu_f (phi_R - phi_L) / dx that the m* moments of
+       Eqs. 13, 16 and 44 reduce to at delta_t = dx/2. Only D * dtau matters. */
+    int32_t mag_method;       /* LBFS_MAG_*                                         */
+    double mag_lbfs_d;        /* D of tau_m = 1/2 + mu D / (cs^2 delta_t), > 0 (also
+                                 checked when the sweeps are the per-step method)    */
+    double mag_lbfs_dtau;     /* pseudo-time step; 0: dx^2 / (4 D mu_max), mu_max =
+                                 mu0 max_k (1 + chi_k), stable for every mode        */
+    /* Convergence control of the per-step magnetic update (either method): with
+       mag_max_iters > 0 the step repeats chunks of `sweeps` iterations until
+       ||r||_2 <= mag_tol (checked on the device after each chunk) or mag_max_iters
+       iterations (rounded up to whole chunks); every chunk is launched, and a converged
+       instance's chunks only copy the potential, so the step stays one graph. */
+    int32_t mag_max_iters;    /* 0: exactly `sweeps` iterations per step; <= 100000 */
+    double mag_tol;           /* absolute target of ||r||_2 (>= 0)                  */
 } lbfs_params;
 
 typedef struct lbfs_observables {
@@ -179,6 +199,12 @@ int lbfs_rhs(lbfs_solver* s, double* host_R);
    current state; *residual receives ||r||_2 afterwards. Synchronous. */
 int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* residual);
 
+/* Advance the magnetic potential by nsteps SSP-RK3 pseudo-time steps of the LBFS
+   solve (Sec. 3.1, Eq. 17) with the instance's D and dtau, whatever its per-step
+   method, on the permeability of the current state; *residual receives ||r||_2
+   afterwards. LBFS_E_STATE on a borrowed batch handle. Synchronous. */
+int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual);
+
 /* Copy a field to / from a host FP64 array of n = nx*ny values. Synchronous. */
 int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n);
 int lbfs_write_field(lbfs_solver* s, int32_t field, const double* host, size_t n);
@@ -256,7 +282,8 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
 /* Admit one problem: validate, carve its state, initialise it as lbfs_init does
    (synchronous). *slot_out receives its slot. LBFS_E_NOMEM when no slot is free or the
    buffer has no room for it (the batch is unchanged); LBFS_E_INVAL when p does not
-   share the batch's precision, sweeps or sor_omega. */
+   share the batch's precision, sweeps or sor_omega, or asks for LBFS_MAG_LBFS or
+   convergence control (batches run a fixed number of sweeps). */
 int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out);
 
 /* Retire the instance in a slot (after the work already enqueued); its memory and slot
@@ -279,8 +306,9 @@ int lbfs_batch_step_profiled(lbfs_batch* b, int32_t nsteps, int32_t sample_every
 int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live);
 
 /* Borrow the handle of a live slot for lbfs_read_field, lbfs_write_field, lbfs_rhs,
-   lbfs_observe, lbfs_save_state and lbfs_load_state. lbfs_step, lbfs_step_profiled and
-   lbfs_mag_sweeps on it return LBFS_E_STATE; it is valid until the slot is retired. */
+   lbfs_observe, lbfs_save_state and lbfs_load_state. lbfs_step, lbfs_step_profiled,
+   lbfs_mag_sweeps and lbfs_mag_pseudo_steps on it return LBFS_E_STATE; it is valid
+   until the slot is retired. */
 int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
 
 /* lbfs_set_tile_shapes and lbfs_autotune for a batch: one shape pair for all live

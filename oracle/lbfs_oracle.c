@@ -169,6 +169,7 @@ orc_sim* orc_new(const orc_params* pin)
     if (p->tau_g <= 0.5 || p->xi <= 0) return NULL;
     if (p->mag_method < 0 || p->mag_method > 1) return NULL;
     if (p->mag_method == 1 && !(p->mag_lbfs_d > 0.0)) return NULL;
+    if (p->mag_max_iters < 0 || (p->mag_max_iters > 0 && (p->sweeps <= 0 || !(p->mag_tol >= 0.0)))) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     s->nx = p->nx; s->ny = p->ny;
@@ -789,6 +790,23 @@ int orc_init(orc_sim* s)
     return used;
 }
 
+/* The magnetic update of one time step: `sweeps` iterations of the chosen method, or,
+   with mag_max_iters > 0, chunks of `sweeps` iterations until the residual reaches
+   mag_tol (checked after every chunk) or mag_max_iters iterations are done. */
+static double mag_phase(orc_sim* s)
+{
+    const orc_params* p = &s->p;
+    int used = 0;
+    double r;
+    for (;;) {
+        r = p->mag_method == 1 ? orc_mag_lbfs(s, p->sweeps, p->mag_lbfs_d, p->mag_lbfs_dtau)
+                               : orc_mag_sweeps(s, p->sweeps, p->omega);
+        used += p->sweeps;
+        if (p->mag_max_iters <= 0 || p->sweeps <= 0 || r <= p->mag_tol || used >= p->mag_max_iters) break;
+    }
+    return r;
+}
+
 void orc_step(orc_sim* s, int nsteps)
 {
     int nx = s->nx, ny = s->ny;
@@ -796,10 +814,7 @@ void orc_step(orc_sim* s, int nsteps)
     for (int n = 0; n < nsteps; n++) {
         /* magnetic potential: red-black sweeps or LBFS pseudo-time steps, then the Kelvin
            force (frozen over the stages) */
-        if (s->p.mag_method == 1)
-            s->res = orc_mag_lbfs(s, s->p.sweeps, s->p.mag_lbfs_d, s->p.mag_lbfs_dtau);
-        else
-            s->res = orc_mag_sweeps(s, s->p.sweeps, s->p.omega);
+        s->res = mag_phase(s);
         kelvin(s);
         /* SSP-RK3 on (He, p, Mx, My, C) */
         rhs(s, s->W, s->R);

@@ -63,6 +63,10 @@ typedef struct orc_params {
                              `sweeps` iterations per time step                          */
     double mag_lbfs_d;    /* free parameter D of tau_m (Sec. 3.1), > 0                   */
     double mag_lbfs_dtau; /* pseudo-time step (<= 0: dx^2 / (4 D mu_max))                */
+    int mag_max_iters;    /* > 0: repeat chunks of `sweeps` iterations until ||r||_2 <=
+                             mag_tol, at most this many iterations per step; 0: exactly
+                             `sweeps` iterations per step                               */
+    double mag_tol;       /* absolute target of ||r||_2 for mag_max_iters > 0            */
 } orc_params;
 
 typedef struct orc_obs {

@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE. Compiles the oracle's C source as C++ with a counting number type
 in place of double (opcount.cpp), runs one step of a workload and prints the operations
 per cell: the whole step, the magnetic phase (permeability, sweeps, residual) and one
-right-hand side R(W) with the Kelvin force. Divisions, square roots and transcendental
+right-hand side R(W) with the Kelvin force, and the magnetic phase by the LBFS
+pseudo-time solve (the literal m* construction of every face, same number of steps). Divisions, square roots and transcendental
 calls count as one operation each, an add or a multiply as one (a fused multiply-add is
 two), comparisons and selects are listed apart and not counted as FLOPs.
 
@@ -53,8 +54,17 @@ def count(prob: dict) -> dict:
     o.step(1)
     res["step"] = _counts(L)
     L.opc_reset()
+    o.mag_sweeps(0, 1.0)
+    res["mag_setup"] = _counts(L)           # permeability and residual only
+    L.opc_reset()
     o.mag_sweeps(int(prob.get("sweeps", 4)), float(prob.get("omega", 1.0)))
     res["mag"] = _counts(L)
+    L.opc_reset()
+    o.mag_lbfs(0, 1.0, 0.0)
+    res["mag_lbfs_setup"] = _counts(L)      # permeability and residual only
+    L.opc_reset()
+    o.mag_lbfs(int(prob.get("sweeps", 4)), 1.0, 0.0)
+    res["mag_lbfs"] = _counts(L)
     L.opc_reset()
     o.rhs()
     res["rhs"] = _counts(L)
@@ -63,6 +73,9 @@ def count(prob: dict) -> dict:
         flops = c["add"] + c["mul"] + c["div"] + c["special"]
         per[k] = dict({n: c[n] / cells for n in KINDS}, flops=flops / cells)
     per["stage"] = {"flops": (per["step"]["flops"] - per["mag"]["flops"]) / 3.0}
+    per["mag_sweep"] = {"flops": (per["mag"]["flops"] - per["mag_setup"]["flops"]) / max(1, int(prob.get("sweeps", 4)))}
+    per["mag_lbfs_pseudo_step"] = {"flops": (per["mag_lbfs"]["flops"] - per["mag_lbfs_setup"]["flops"]) /
+                                   max(1, int(prob.get("sweeps", 4)))}
     return {"workload": prob.get("name", f"droplet {o.nx}x{o.ny}"), "cells": cells, "per_cell": per}
 
 

@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("init_omega", C.c_double), ("init_tol", C.c_double),
         ("init_max", C.c_int), ("init_check", C.c_int),
         ("mag_method", C.c_int), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
+        ("mag_max_iters", C.c_int), ("mag_tol", C.c_double),
     ]
 
 
@@ -138,6 +139,8 @@ def make_params(prob: dict) -> Params:
     p.mag_method = {"sweeps": 0, "lbfs": 1}[prob.get("mag_method", "sweeps")]
     p.mag_lbfs_d = float(prob.get("mag_lbfs_d", 1.0))
     p.mag_lbfs_dtau = float(prob.get("mag_lbfs_dtau", 0.0))
+    p.mag_max_iters = int(prob.get("mag_max_iters", 0))
+    p.mag_tol = float(prob.get("mag_tol", 0.0))
     if "latent" in prob and "h0" in prob:
         p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
     else:

@@ -7,6 +7,7 @@
 #include "lbfs.h"
 #include "lbfs_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -86,6 +87,12 @@ int validate(const lbfs_params* p)
     }
     if (p->sweeps < 0 || p->sweeps > 1000) return LBFS_E_INVAL;
     if (!(p->sor_omega > 0.0 && p->sor_omega < 2.0)) return LBFS_E_INVAL;
+    if (p->mag_method != LBFS_MAG_SWEEPS && p->mag_method != LBFS_MAG_LBFS) return LBFS_E_INVAL;
+    if (!finite_pos(p->mag_lbfs_d) || !std::isfinite(p->mag_lbfs_dtau) || p->mag_lbfs_dtau < 0.0)
+        return LBFS_E_INVAL;
+    if (p->mag_max_iters < 0 || p->mag_max_iters > 100000) return LBFS_E_INVAL;
+    if (p->mag_max_iters > 0 && (p->sweeps < 1 || !std::isfinite(p->mag_tol) || p->mag_tol < 0.0))
+        return LBFS_E_INVAL;
     if (!std::isfinite(p->init_omega) || p->init_omega >= 2.0) return LBFS_E_INVAL;
     if (!std::isfinite(p->init_tol) || p->init_tol < 0.0 || p->init_max < 0 || p->init_check < 0)
         return LBFS_E_INVAL;
@@ -129,7 +136,7 @@ Layout make_layout(const lbfs_params* p)
     L.off_tmag = off; off = align_up(off + sizeof(Tile) * L.cap_mag, ALIGN);
     L.off_tpt = off; off = align_up(off + sizeof(Tile) * L.ntile_pt(), ALIGN);
     L.off_part = off; off = align_up(off + sizeof(double) * NPART * L.cap_stage, ALIGN);
-    L.off_mpart = off; off = align_up(off + sizeof(double) * L.cap_mag, ALIGN);
+    L.off_mpart = off; off = align_up(off + sizeof(double) * (L.cap_mag + 1), ALIGN);   // + convergence flag
     L.off_res = off; off = align_up(off + sizeof(double) * NRES, ALIGN);
     L.off_fields = off; off += L.field_bytes * NFIELDS;
     L.total = off + ALIGN;   // room to align the caller's base pointer
@@ -142,8 +149,10 @@ Layout make_layout(const lbfs_params* p)
 struct Exec {
     bool f64 = false;
     int stage_shape = 0, mag_shape = 0;   // indices into the tile-shape tables
-    int sweeps = 4;
+    int sweeps = 4;                      // sweeps, or pseudo-steps of the LBFS solve, per step
     double omega = 1.0;
+    int mag_method = LBFS_MAG_SWEEPS;
+    int mag_chunks = 1;                  // chunks of `sweeps` per step (convergence control)
     hipStream_t stream = nullptr;
     const DevInst* dinst = nullptr;
     int ninst = 0;
@@ -166,6 +175,42 @@ hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
                                      E.stream, E.ev0, E.ev1);
 }
 
+hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual, hipEvent_t e0, hipEvent_t e1, int gate)
+{
+    return E.f64 ? launch_mag_lbfs<double>(E.mag_shape, nsteps, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                           E.stream, e0, e1, gate)
+                 : launch_mag_lbfs<float>(E.mag_shape, nsteps, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                          E.stream, e0, e1, gate);
+}
+
+hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual) { return exec_mag_lbfs(E, nsteps, residual, E.ev0, E.ev1, 0); }
+
+// The magnetic phase of a time step, by the instance's method, with the residual. With
+// convergence control it is mag_chunks chunks of `sweeps` iterations; after the first,
+// each chunk is gated by the convergence flag of the chunk before it, so a converged
+// instance only copies its potential (the launch count, and with it the buffer flips,
+// stays fixed and the step can be captured in a graph). The timing events bracket the
+// whole phase.
+hipError_t exec_mag_step(Exec& E)
+{
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < E.mag_chunks && e == hipSuccess; c++) {
+        const hipEvent_t a = c == 0 ? E.ev0 : nullptr, b = c == E.mag_chunks - 1 ? E.ev1 : nullptr;
+        const int gate = c > 0;
+        if (gate) e = launch_mag_gate(E.dinst, E.ninst, E.stream);
+        if (e != hipSuccess) break;
+        if (E.mag_method == LBFS_MAG_LBFS) {
+            e = exec_mag_lbfs(E, E.sweeps, 1, a, b, gate);
+        } else {
+            e = E.f64 ? launch_mag<double>(E.mag_shape, E.sweeps, E.omega, 1, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                           E.stream, a, b, gate)
+                      : launch_mag<float>(E.mag_shape, E.sweeps, E.omega, 1, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                                          E.stream, a, b, gate);
+        }
+    }
+    return e;
+}
+
 hipError_t exec_stage(Exec& E, int stage)
 {
     return E.f64 ? launch_stage<double>(E.stage_shape, stage, E.phase, E.dinst, E.tiles_stage, E.nstage, E.stream,
@@ -184,7 +229,7 @@ hipError_t exec_state_partials(Exec& E)
 // state are summed when they are read)
 hipError_t exec_enqueue_step(Exec& E)
 {
-    hipError_t e = exec_mag(E, E.sweeps, E.omega, 1);
+    hipError_t e = exec_mag_step(E);
     for (int st = 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
     return e;
 }
@@ -229,8 +274,9 @@ hipError_t exec_ensure_graph(Exec& E, int ph)
 // potential-buffer flips of one step (one per magnetic launch)
 int exec_step_flips(const Exec& E)
 {
-    const int launches = E.sweeps == 0 ? 1 : (E.sweeps + MAG_KMAX - 1) / MAG_KMAX;
-    return launches & 1;
+    const int kmax = E.mag_method == LBFS_MAG_LBFS ? RK_KMAX : MAG_KMAX;
+    const int launches = E.sweeps == 0 ? 1 : (E.sweeps + kmax - 1) / kmax;
+    return (launches * E.mag_chunks) & 1;
 }
 
 // one step, as a graph replay when graphs are on
@@ -276,7 +322,7 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
     for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
         hipError_t e;
         if (n % sample_every == 0) {
-            e = timed(LBFS_K_MAG, [&] { return exec_mag(E, E.sweeps, E.omega, 1); });
+            e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E); });
             for (int st = 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
         } else {
@@ -338,6 +384,7 @@ void fill_coef(Coef<T>& K, const DevInst& I)
     K.idx2 = T(1.0 / (I.dx * I.dx));
     K.i_halfdx = T(2.0 / I.dx);
     K.idt = T(1.0 / I.dt);
+    K.mag_kdt = T(I.mag_kdt);
     K.tauf_k = T(3.0 / I.dts);
     K.tauh_k = T(3.0 / (I.cpref * I.dts));
 }
@@ -509,6 +556,11 @@ int lbfs_params_default(lbfs_params* p, int32_t nx, int32_t ny, int32_t precisio
     for (int w = 0; w < 4; w++) p->mag_bc[w] = LBFS_MBC_FIXED;
     p->sweeps = 4;
     p->sor_omega = 1.0;
+    p->mag_method = LBFS_MAG_SWEEPS;
+    p->mag_lbfs_d = 1.0;
+    p->mag_lbfs_dtau = 0.0;
+    p->mag_max_iters = 0;
+    p->mag_tol = 0.0;
     p->init_omega = 0.0;
     p->init_tol = precision == LBFS_FP64 ? 1e-9 : 1e-4;
     p->init_max = 20 * (nx > ny ? nx : ny) + 1000;
@@ -587,6 +639,8 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     E.f64 = p->precision == LBFS_FP64;
     E.sweeps = p->sweeps;
     E.omega = p->sor_omega;
+    E.mag_method = p->mag_method;
+    E.mag_chunks = p->mag_max_iters > 0 ? (p->mag_max_iters + p->sweeps - 1) / p->sweeps : 1;
     E.stream = s->stream;
     E.dinst = s->dinst;
     E.ninst = 1;
@@ -648,6 +702,17 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     I.grav[0] = p->gravity[0];
     I.grav[1] = p->gravity[1];
     I.vc = 1.0 - p->rho[0] / p->rho[1];
+    {
+        // the automatic pseudo-time step dx^2 / (4 D mu_max): every row of the discrete
+        // operator sums in absolute value to at most 8 D mu_max / dx^2, and SSP-RK3 is
+        // stable on the negative real axis to about -2.51; the mixture permeability
+        // never exceeds that of the most permeable phase
+        double mmax = 1.0 + p->chi[0];
+        for (int k = 1; k < 3; k++) mmax = std::max(mmax, 1.0 + p->chi[k]);
+        I.mag_kdt = p->mag_lbfs_dtau > 0.0 ? p->mag_lbfs_d * p->mag_lbfs_dtau / (p->dx * p->dx)
+                                           : 1.0 / (4.0 * p->mu0 * mmax);
+    }
+    I.mag_tol = p->mag_tol;
     fill_coef(I.cf, I);
     fill_coef(I.cd, I);
 
@@ -764,6 +829,19 @@ int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* resid
     if (s->batched) return LBFS_E_STATE;   // would flip the potential parity of one batch member
     if (nsweeps < 0 || !(omega > 0.0 && omega < 2.0)) return LBFS_E_INVAL;
     HIPCHK(exec_mag(s->E, nsweeps, omega, 0));
+    double r = 0.0;
+    const int rc = mag_residual_now(s, &r);
+    if (rc != LBFS_OK) return rc;
+    if (residual) *residual = r;
+    return LBFS_OK;
+}
+
+int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual)
+{
+    if (!s) return LBFS_E_STATE;
+    if (s->batched) return LBFS_E_STATE;
+    if (nsteps < 0) return LBFS_E_INVAL;
+    HIPCHK(exec_mag_lbfs(s->E, nsteps, 0));
     double r = 0.0;
     const int rc = mag_residual_now(s, &r);
     if (rc != LBFS_OK) return rc;
@@ -1030,7 +1108,7 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
         rc = apply_shapes(s, best_s, k);
         double* tk = &t[LBFS_MAX_SHAPES + k];
-        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
+        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag_step(E); }, tk);
         if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
     }
     // restore the potential, keep the fastest shapes and recompute the residual partials
@@ -1303,7 +1381,9 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     if (!p || !slot_out) return LBFS_E_INVAL;
     const int v = validate(p);
     if (v != LBFS_OK) return v;
-    if (p->precision != b->precision || p->sweeps != b->sweeps || p->sor_omega != b->omega) return LBFS_E_INVAL;
+    if (p->precision != b->precision || p->sweeps != b->sweeps || p->sor_omega != b->omega ||
+        p->mag_method != LBFS_MAG_SWEEPS || p->mag_max_iters != 0)
+        return LBFS_E_INVAL;
     int slot = -1;
     for (int k = 0; k < b->max_slots && slot < 0; k++)
         if (!b->slots[k].s) slot = k;

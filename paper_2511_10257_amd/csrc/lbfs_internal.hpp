@@ -40,6 +40,9 @@ constexpr int MAG_KMAX = 4;
 constexpr int NMAG_SHAPES = 5;
 constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 32, 1024}, {64, 16, 1024}, {64, 8, 1024},
                                                {128, 16, 1024}};
+// The magnetic LBFS pseudo-time solve runs on the same tiles: one launch does up to
+// RK_KMAX pseudo-steps of three stages each (LDS halo 3*RK_KMAX+1).
+constexpr int RK_KMAX = 3;
 
 constexpr TileShape stage_shape(bool f64, int k) { return f64 ? STAGE_SHAPES_F64[k] : STAGE_SHAPES_F32[k]; }
 // pointwise kernels (init, derived fields): one thread per cell
@@ -74,6 +77,7 @@ struct Coef {
     T idt;      // 1 / dt
     T tauf_k;   // 3 / delta_t:           tau_f = 1/2 + (mu / rho) tauf_k
     T tauh_k;   // 3 / (Cp,ref delta_t):  tau_h = 1/2 + (lambda / rho) tauh_k
+    T mag_kdt;  // D dtau / dx^2 of the magnetic pseudo-time solve
 };
 
 // Per-instance descriptor, resident in device memory. Field pointers are typed by
@@ -86,7 +90,7 @@ struct DevInst {
     void* phi[2];    // potential minus the applied-field potential, double buffered
     void* S;         // lagged dFs/dt
     double* part;    // [ntile_stage][NPART]
-    double* mpart;   // [ntile_mag]
+    double* mpart;   // [ntile_mag] residual partials, then the convergence flag (see k_mag_gate)
     double* result;  // [NRES]
     int32_t nx, ny, pitch;
     int32_t per_x, per_y;
@@ -99,6 +103,8 @@ struct DevInst {
     double latent, tm, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;
     double grav[2];
     double vc;       // 1 - rho_s / rho_l
+    double mag_kdt;  // D dtau / dx^2 (magnetic pseudo-time solve)
+    double mag_tol;  // ||r||_2 target of the convergence-controlled magnetic phase
     Coef<float> cf;  // the parameters above in FP32 (FP32 instances)
     Coef<double> cd; // and in FP64 (FP64 instances)
 };
@@ -120,10 +126,22 @@ hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, co
 // magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
 // residual partials when residual != 0, on tiles of MAG_SHAPES[shape]. Reads the
 // potential buffer *pidx and flips *pidx once per launch.
+// With gate != 0 an instance whose convergence flag is set only copies its potential
+// to the other buffer (the flip stays uniform) and keeps its residual partials.
 template <typename T>
 hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr);
+                      hipEvent_t e1 = nullptr, int gate = 0);
+// magnetic phase by the LBFS pseudo-time solve: permeability, nsteps SSP-RK3 steps of
+// Eq. 17 (rate factor mag_kdt of each instance) and the residual partials when
+// residual != 0, on tiles of MAG_SHAPES[shape]; buffers as launch_mag.
+template <typename T>
+hipError_t launch_mag_lbfs(int shape, int nsteps, int residual, int* pidx, const DevInst* insts,
+                           const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr, int gate = 0);
+// convergence flag of each instance: 1 when the residual of its last magnetic launch
+// is at most mag_tol (one workgroup per instance)
+hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream);
 // per-tile FP64 partial sums of the observables over stage tiles of shape `shape`
 template <typename T>
 hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);

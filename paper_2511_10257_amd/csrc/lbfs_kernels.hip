@@ -11,6 +11,8 @@
 //   k_mag_fused             permeability (Eq. 2 with Eq. 11), red-black sweeps of the
 //                           compact magnetic system (temporally blocked in LDS) and
 //                           the FP64 residual.
+//   k_mag_lbfs              the same phase by the magnetic LBFS pseudo-time solve
+//                           (Eq. 17, SSP-RK3 steps temporally blocked in LDS).
 //   k_reduce                fixed-order FP64 reduction of the partials per instance
 //                           (the last stage does the same in its last workgroup).
 //   k_init_fields, k_derived
@@ -21,6 +23,7 @@
 #include "lbfs_internal.hpp"
 
 #include <hip/hip_ext.h>
+#include <ratio>
 #include <type_traits>
 
 namespace lbfs {
@@ -821,6 +824,47 @@ hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* ti
 // reads (all of the other colour), are contiguous. Each thread owns fixed cells of
 // both colours and keeps their face weights, constant term and 1 / sum of weights in
 // registers; a pass costs four LDS reads and one write per cell.
+// A converged instance's magnetic launch: the tile's potential copied unchanged from
+// buffer pin to the other one.
+template <typename T, int MTX, int MTY, int NT>
+__device__ __forceinline__ void copy_tile(const DevInst& I, const Tile& tile, int pin)
+{
+    const GLOBAL T* src = gp<T>(I.phi[pin]);
+    GLOBAL T* dst = gp<T>(I.phi[pin ^ 1]);
+    for (int c = threadIdx.x; c < MTX * MTY; c += NT) {
+        const int gx = tile.x0 + c % MTX, gy = tile.y0 + c / MTX;
+        if (gx >= I.nx || gy >= I.ny) continue;
+        const size_t o = (size_t)gy * I.pitch + gx;
+        dst[o] = src[o];
+    }
+}
+
+// Convergence flag of one instance for the convergence-controlled magnetic phase:
+// the fixed-order FP64 sum of its residual partials against mag_tol^2, stored after
+// the partials (mpart[ntile_mag]).
+__global__ __launch_bounds__(256) void k_mag_gate(const DevInst* __restrict__ insts)
+{
+    __shared__ double red[4];
+    const DevInst& I = insts[blockIdx.x];
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int t = tid; t < I.ntile_mag; t += 256) acc += I.mpart[t];
+    acc = wave_sum(acc);
+    if (tid % 64 == 0) red[tid / 64] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        const double r2 = red[0] + red[1] + red[2] + red[3];
+        I.mpart[I.ntile_mag] = r2 <= I.mag_tol * I.mag_tol ? 1.0 : 0.0;
+    }
+}
+
+hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mag_gate, dim3(ninst), dim3(256), 0, stream, insts);
+    return hipGetLastError();
+}
+
 template <typename T, int MTX, int MTY>
 struct MagLds {
     static constexpr int H = 2 * MAG_KMAX + 1;
@@ -835,7 +879,7 @@ struct MagLds {
 template <typename T, int MTX, int MTY, int NT>
 __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ insts,
                                                   const Tile* __restrict__ tiles, int nsweeps, double omega,
-                                                  int residual, int pin)
+                                                  int residual, int pin, int gate)
 {
     using L = MagLds<T, MTX, MTY>;
     static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
@@ -844,6 +888,10 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
+    if (gate && I.mpart[I.ntile_mag] != 0.0) {
+        copy_tile<T, MTX, MTY, NT>(I, tile, pin);
+        return;
+    }
     const Coef<T>& K = coef<T>(I);
     const int tid = threadIdx.x;
     const int nx = I.nx, ny = I.ny;
@@ -1009,17 +1057,253 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
     }
 }
 
+// Magnetic LBFS pseudo-time solve on one tile of MTX x MTY cells: permeability of the
+// tile plus a halo of 3*RK_KMAX+1 cells, up to RK_KMAX SSP-RK3 steps of Eq. 17 done in
+// LDS, the tile's potential written back, and optionally the FP64 residual. At
+// delta_t = dx/2 the m* moment of Eqs. 13, 16 and 44 through a face is
+// -D mu_f (phi_R - phi_L) / dx, so the rate of cell c is
+// kdt (b_c + sum_f a_f phi'_nb - sum_f a_f phi'_c), kdt = D dtau / dx^2, with the face
+// weights a_f and constant b_c of the sweeps (same fixed point). Each stage reads the
+// previous stage's values of a cell and its four neighbours, so the exact region
+// shrinks by one cell per stage; the halo keeps the tile and its neighbours (for the
+// residual) exact. Every cell update is the same arithmetic whatever the tiling.
+//
+// LDS holds the stage values in natural layout, ping-pong between two arrays (the
+// second holds the permeability during set-up). Each thread owns the region cells
+// tid + j * NT and keeps their weights, constant term, pseudo-step base and current
+// value in registers; a stage costs four LDS reads and one write per cell.
+template <typename T, int MTX, int MTY>
+struct RkLds {
+    static constexpr int H = 3 * RK_KMAX + 1;
+    static constexpr int RX = MTX + 2 * H, RY = MTY + 2 * H, NR = RX * RY;
+    T ph[2][NR];
+    double red[16];
+};
+
+template <typename T, int MTX, int MTY, int NT>
+__global__ __launch_bounds__(NT) void k_mag_lbfs(const DevInst* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                 int nsteps, int residual, int pin, int gate)
+{
+    using L = RkLds<T, MTX, MTY>;
+    static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
+    constexpr int NIT = (L::NR + NT - 1) / NT;   // owned region cells per thread
+    __shared__ L s;
+    const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const DevInst& I = insts[tile.inst];
+    if (gate && I.mpart[I.ntile_mag] != 0.0) {
+        copy_tile<T, MTX, MTY, NT>(I, tile, pin);
+        return;
+    }
+    const Coef<T>& K = coef<T>(I);
+    const int tid = threadIdx.x;
+    const int nx = I.nx, ny = I.ny;
+    const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
+    const GLOBAL T* phin = gp<T>(I.phi[pin]);
+    const GLOBAL T* He_ = gp<T>(I.W[0]);
+    const GLOBAL T* C_ = gp<T>(I.W[4]);
+    T cq[NIT];   // current value of each owned cell
+    // 1. load the region: potential into ph[0], permeability into ph[1] (0 outside the
+    //    domain, where the potential is 0 too)
+    {
+        T vHe[NIT], vC[NIT];
+        bool vin[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            const int gx = ox + r % L::RX, gy = oy + r / L::RX;
+            int sx = gx, sy = gy;
+            bool in = r < L::NR;
+            if (gx < 0 || gx >= nx) {
+                if (I.per_x) sx = ((gx % nx) + nx) % nx;
+                else in = false;
+            }
+            if (gy < 0 || gy >= ny) {
+                if (I.per_y) sy = ((gy % ny) + ny) % ny;
+                else in = false;
+            }
+            in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+            vin[it] = in;
+            const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
+            vHe[it] = He_[o];
+            vC[it] = C_[o];
+            cq[it] = phin[o];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR) break;
+            T mu = T(0);
+            if (vin[it]) {
+                T Tt, Fl;
+                enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
+                const T ct = clamp01(vC[it]);
+                mu = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+            } else {
+                cq[it] = T(0);
+            }
+            s.ph[0][r] = cq[it];
+            s.ph[1][r] = mu;
+        }
+    }
+    __syncthreads();
+    // 2. owned cells: face weights (W, E, S, N), constant part b and sum of weights d;
+    //    d = 0 marks a cell that is not updated (region ring 0 or outside the domain)
+    const T hx = K.h0x * K.dx, hy = K.h0y * K.dx;
+    T wq[NIT][4], bq[NIT], dq[NIT], uq[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int r = tid + it * NT;
+        bq[it] = T(0);
+        dq[it] = T(0);
+        uq[it] = cq[it];
+#pragma unroll
+        for (int d = 0; d < 4; d++) wq[it][d] = T(0);
+        if (r >= L::NR) continue;
+        const int lx = r % L::RX, ly = r / L::RX;
+        if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
+        const T* mu = s.ph[1];
+        const T muc = mu[r];
+        if (!(muc > T(0))) continue;
+        const T mnb[4] = {mu[r - 1], mu[r + 1], mu[r - L::RX], mu[r + L::RX]};
+        const T D0[4] = {hx, -hx, hy, -hy};   // phi0_nb - phi0_c across each face
+        T bsum = T(0), den = T(0);
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const bool nb_in = mnb[d] > T(0);
+            const T w = nb_in ? (d == 0 || d == 2 ? T(0.5) * (mnb[d] + muc) : T(0.5) * (muc + mnb[d])) : T(0);
+            wq[it][d] = w;
+            if (w > T(0)) {
+                bsum += w * D0[d];
+                den += w;
+            } else if (!nb_in && I.mbc[d]) {   // a wall face
+                const T ww = T(2) * muc;
+                bsum += ww * (T(0.5) * D0[d]);
+                den += ww;
+            }
+        }
+        bq[it] = bsum;
+        dq[it] = den;
+    }
+    __syncthreads();   // the permeability in ph[1] is read by now
+    // 3. SSP-RK3 in pseudo-time: stage k writes a0 u + a1 (v + kdt R(v)) into the other
+    //    array, v the previous stage's values and u those at the start of the pseudo-step
+    const T kdt = K.mag_kdt;
+    int cur = 0;
+    auto stage = [&](auto a0c, auto a1c) {
+        const T a0 = T(decltype(a0c)::num) / T(decltype(a0c)::den);
+        const T a1 = T(decltype(a1c)::num) / T(decltype(a1c)::den);
+        const T* p = s.ph[cur];
+        T* q = s.ph[cur ^ 1];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR) break;
+            if (dq[it] != T(0)) {
+                const T rate = bq[it] + wq[it][0] * p[r - 1] + wq[it][1] * p[r + 1] + wq[it][2] * p[r - L::RX] +
+                               wq[it][3] * p[r + L::RX] - dq[it] * cq[it];
+                const T v = cq[it] + kdt * rate;
+                cq[it] = a0 == T(0) ? v : a0 * uq[it] + a1 * v;
+            }
+            q[r] = cq[it];
+        }
+        __syncthreads();
+        cur ^= 1;
+    };
+    using Z = std::ratio<0, 1>;
+    using One = std::ratio<1, 1>;
+    for (int n = 0; n < nsteps; n++) {
+        stage(Z{}, One{});
+        stage(std::ratio<3, 4>{}, std::ratio<1, 4>{});
+        stage(std::ratio<1, 3>{}, std::ratio<2, 3>{});
+#pragma unroll
+        for (int it = 0; it < NIT; it++) uq[it] = cq[it];
+    }
+    // 4. FP64 residual r_c = b_c + sum_f a_f (phi'_nb - phi'_c) over the owned tile cells
+    const T* p = s.ph[cur];
+    double r2 = 0.0;
+    if (residual) {
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= L::NR || dq[it] == T(0)) continue;
+            const int tx = r % L::RX - L::H, ty = r / L::RX - L::H;
+            if (tx < 0 || tx >= MTX || ty < 0 || ty >= MTY || tile.x0 + tx >= nx || tile.y0 + ty >= ny) continue;
+            const double res = double(bq[it]) + double(wq[it][0]) * double(p[r - 1]) +
+                               double(wq[it][1]) * double(p[r + 1]) + double(wq[it][2]) * double(p[r - L::RX]) +
+                               double(wq[it][3]) * double(p[r + L::RX]) - double(dq[it]) * double(cq[it]);
+            r2 += res * res;
+        }
+    }
+    // 5. write the tile (coalesced rows)
+    GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
+    for (int cidx = tid; cidx < MTX * MTY; cidx += NT) {
+        const int tx = cidx % MTX, ty = cidx / MTX;
+        const int gx = tile.x0 + tx, gy = tile.y0 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        phout[(size_t)gy * I.pitch + gx] = p[(ty + L::H) * L::RX + tx + L::H];
+    }
+    if (residual) {
+        r2 = wave_sum(r2);
+        if (tid % 64 == 0) s.red[tid / 64] = r2;
+        __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int w = 0; w < NT / 64; w++) acc += s.red[w];
+            I.mpart[tile.idx] = acc;
+        }
+    }
+}
+
+template <typename T, int K>
+hipError_t launch_mag_lbfs_idx(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream,
+                               hipEvent_t e0, hipEvent_t e1, int nsteps, int res, int pin, int gate)
+{
+    if constexpr (K < NMAG_SHAPES) {
+        constexpr TileShape M = MAG_SHAPES[K];
+        if (shape == K)
+            return launch_timed(k_mag_lbfs<T, M.tx, M.ty, M.nt>, dim3(ntiles), dim3(M.nt), stream, e0, e1, insts,
+                                tiles, nsteps, res, pin, gate);
+        return launch_mag_lbfs_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsteps, res, pin, gate);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_mag_lbfs(int shape, int nsteps, int residual, int* pidx, const DevInst* insts, const Tile* tiles,
+                           int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, int gate)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (shape < 0 || shape >= NMAG_SHAPES || nsteps < 0) return hipErrorInvalidValue;
+    // pseudo-steps beyond the LDS halo run as further launches (timing: start of the
+    // first, end of the last); each launch flips the potential buffer
+    bool first = true;
+    do {
+        const int k = nsteps > RK_KMAX ? RK_KMAX : nsteps;
+        nsteps -= k;
+        const int res = residual && nsteps == 0;
+        const hipEvent_t a = first ? e0 : nullptr, b = nsteps == 0 ? e1 : nullptr;
+        const hipError_t e =
+            launch_mag_lbfs_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, res, *pidx, gate);
+        if (e != hipSuccess) return e;
+        *pidx ^= 1;
+        first = false;
+    } while (nsteps > 0);
+    return hipSuccess;
+}
+
 // one launch of the fused magnetic kernel on tiles of MAG_SHAPES[shape]
 template <typename T, int K>
 hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream,
-                          hipEvent_t e0, hipEvent_t e1, int nsweeps, double omega, int res, int pin)
+                          hipEvent_t e0, hipEvent_t e1, int nsweeps, double omega, int res, int pin, int gate)
 {
     if constexpr (K < NMAG_SHAPES) {
         constexpr TileShape M = MAG_SHAPES[K];
         if (shape == K)
             return launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt>, dim3(ntiles), dim3(M.nt), stream, e0, e1, insts,
-                                tiles, nsweeps, omega, res, pin);
-        return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, pin);
+                                tiles, nsweeps, omega, res, pin, gate);
+        return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, pin,
+                                        gate);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1027,7 +1311,7 @@ hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, in
 
 template <typename T>
 hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
-                      const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
+                      const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, int gate)
 {
     if (ntiles <= 0) return hipSuccess;
     if (shape < 0 || shape >= NMAG_SHAPES) return hipErrorInvalidValue;
@@ -1040,7 +1324,8 @@ hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* p
         nsweeps -= k;
         const int res = residual && nsweeps == 0;
         const hipEvent_t a = first ? e0 : nullptr, b = nsweeps == 0 ? e1 : nullptr;
-        const hipError_t e = launch_mag_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, omega, res, *pidx);
+        const hipError_t e =
+            launch_mag_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, omega, res, *pidx, gate);
         if (e != hipSuccess) return e;
         *pidx ^= 1;
         first = false;
@@ -1139,7 +1424,9 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
     template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t, hipEvent_t, \
                                         hipEvent_t);                                                   \
     template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
-                                      hipEvent_t, hipEvent_t);                                         \
+                                      hipEvent_t, hipEvent_t, int);                                    \
+    template hipError_t launch_mag_lbfs<T>(int, int, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
+                                           hipEvent_t, hipEvent_t, int);                               \
     template hipError_t launch_state_partials<T>(int, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \

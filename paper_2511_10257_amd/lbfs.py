@@ -15,7 +15,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblbfs.so")
 
-LBFS_ABI_VERSION = 1
+LBFS_ABI_VERSION = 2
 LBFS_OK, LBFS_E_INVAL, LBFS_E_NOMEM, LBFS_E_NONFINITE, LBFS_E_DEVICE, LBFS_E_STATE, LBFS_E_ABI = (
     0, -1, -2, -3, -4, -5, -6)
 LBFS_FP32, LBFS_FP64 = 0, 1
@@ -26,7 +26,8 @@ NKERNELS = len(KERNELS)
 # every symbol include/lbfs.h declares
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
-    "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps", "lbfs_read_field",
+    "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
+    "lbfs_mag_pseudo_steps", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
@@ -54,6 +55,8 @@ class Params(C.Structure):
         ("mag_bc", C.c_int32 * 4), ("sweeps", C.c_int32), ("sor_omega", C.c_double),
         ("init_omega", C.c_double), ("init_tol", C.c_double), ("init_max", C.c_int32),
         ("init_check", C.c_int32),
+        ("mag_method", C.c_int32), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
+        ("mag_max_iters", C.c_int32), ("mag_tol", C.c_double),
     ]
 
 
@@ -98,6 +101,7 @@ def lib():
             "lbfs_observe": (C.c_int, [vp, C.POINTER(Observables)]),
             "lbfs_rhs": (C.c_int, [vp, dp]),
             "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
+            "lbfs_mag_pseudo_steps": (C.c_int, [vp, i32, dp]),
             "lbfs_read_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
             "lbfs_write_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
             "lbfs_set_time": (C.c_int, [vp, C.c_double, C.c_int64]),
@@ -144,6 +148,7 @@ def _check(status: int, what: str) -> None:
 
 _TBC = {"adiabatic": 0, "fixed": 1}
 _MBC = {"insulating": 0, "fixed": 1}
+_MAG = {"sweeps": 0, "lbfs": 1}
 
 
 def make_params(prob: dict) -> Params:
@@ -179,6 +184,11 @@ def make_params(prob: dict) -> Params:
             p.mag_bc[k] = _MBC[prob["mag_bc"][k]]
     p.sweeps = int(prob.get("sweeps", 4))
     p.sor_omega = float(prob.get("omega", 1.0))
+    p.mag_method = _MAG[prob.get("mag_method", "sweeps")]
+    p.mag_lbfs_d = float(prob.get("mag_lbfs_d", 1.0))
+    p.mag_lbfs_dtau = float(prob.get("mag_lbfs_dtau", 0.0))
+    p.mag_max_iters = int(prob.get("mag_max_iters", 0))
+    p.mag_tol = float(prob.get("mag_tol", 0.0))
     for key in ("init_max", "init_check"):
         if key in prob:
             setattr(p, key, int(prob[key]))
@@ -337,6 +347,12 @@ class Solver(_Instance):
     def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
         r = C.c_double()
         _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
+        return r.value
+
+    def mag_pseudo_steps(self, n: int) -> float:
+        """n pseudo-time steps of the magnetic LBFS solve (Eq. 17); returns ||r||_2."""
+        r = C.c_double()
+        _check(lib().lbfs_mag_pseudo_steps(self._h, int(n), C.byref(r)), "lbfs_mag_pseudo_steps")
         return r.value
 
     def set_tile_shapes(self, stage_shape: int, mag_shape: int) -> None:

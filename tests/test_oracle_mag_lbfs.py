@@ -223,3 +223,42 @@ def test_invalid_pseudo_time_parameters_are_rejected():
     p = wl.droplet_problem(16, 4.0, ste=0.1, bo_m=1.0, angle_deg=0.0, precision="fp64")
     with pytest.raises(ValueError):
         orc.Oracle(wl.with_changes(p, mag_method="lbfs", mag_lbfs_d=0.0))
+
+
+@pytest.mark.parametrize("method", ["sweeps", "lbfs"])
+def test_convergence_controlled_step_is_a_whole_number_of_chunks(method):
+    """With a residual target the magnetic phase repeats chunks of `sweeps` iterations
+    until ||r||_2 <= mag_tol or mag_max_iters: with an unreachable target it is the
+    fixed count mag_max_iters, and otherwise the fixed count of the chunks it used."""
+    base = wl.droplet_problem(20, 5.0, ste=0.1, bo_m=1.5, angle_deg=90.0, precision="fp64")
+    base.update(mag_method=method, init_tol=1e-6)
+    a = orc.Oracle(wl.with_changes(base, sweeps=4, mag_max_iters=12, mag_tol=0.0))
+    b = orc.Oracle(wl.with_changes(base, sweeps=12))
+    a.step(2)
+    b.step(2)
+    for name in ("phi", "He", "Mx", "C"):
+        assert np.array_equal(a.get(name), b.get(name)), name
+    # a reachable target: count the chunks on a copy of the state, then compare with the
+    # fixed count
+    probe = orc.Oracle(base)
+    probe.step(1)
+    state = {k: probe.get(k) for k in ("He", "p", "Mx", "My", "C", "phi", "S")}
+    state["phi"] = state["phi"] * 1.01          # away from the fixed point
+    counter = orc.Oracle(base, init=False)
+    counter.set_state(state)
+    tol = 0.02 * counter.mag_sweeps(0, 1.0)
+    chunks = 0
+    while True:
+        r = counter.mag_sweeps(2, 1.0) if method == "sweeps" else counter.mag_lbfs(2, 1.0, 0.0)
+        chunks += 1
+        if r <= tol or chunks >= 500:
+            break
+    assert 1 < chunks < 500
+    c = orc.Oracle(wl.with_changes(base, sweeps=2, mag_max_iters=1000, mag_tol=tol), init=False)
+    d = orc.Oracle(wl.with_changes(base, sweeps=2 * chunks), init=False)
+    for o in (c, d):
+        o.set_state(state)
+        o.step(1)
+    assert c.observe()["mag_residual"] <= tol
+    for name in ("phi", "He", "Mx", "C"):
+        assert np.array_equal(c.get(name), d.get(name)), name
