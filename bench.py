@@ -264,9 +264,9 @@ def run_single(args, torch, lbfs, wl) -> dict:
     iters = max(prob["sweeps"], args.mag_max_iters)
     base, per = ALG_FLOPS_MAG_LBFS if args.mag_method == "lbfs" else ALG_FLOPS_MAG_SWEEPS
     mag_flops = base + per * iters
-    # launches of the magnetic phase: up to 4 sweeps or 3 pseudo-steps each, times the
+    # launches of the magnetic phase: up to 4 sweeps or 4 pseudo-steps each, times the
     # chunks of the convergence control (an upper bound: converged chunks only copy)
-    kmax = 3 if args.mag_method == "lbfs" else 4
+    kmax = 4
     chunks = -(-args.mag_max_iters // max(1, prob["sweeps"])) if args.mag_max_iters > 0 else 1
     mag_launches = max(1, -(-prob["sweeps"] // kmax)) * chunks
     cells = prob["nx"] * prob["ny"]
@@ -290,7 +290,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
                 "mag_max_iters": prob.get("mag_max_iters", 0), "mag_tol": prob.get("mag_tol", 0.0),
                 "sweeps_per_step": prob["sweeps"], "reductions": "f64",
                 "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default")})
-    out["roofline"] = roofline(kern, cells, prob["precision"], args.workload, shapes, mag_flops, mag_launches)
+    profile_key = args.workload + ("-mag-lbfs" if args.mag_method == "lbfs" else "")
+    out["roofline"] = roofline(kern, cells, prob["precision"], profile_key, shapes, mag_flops, mag_launches)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned

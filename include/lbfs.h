@@ -205,6 +205,13 @@ int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* resid
    afterwards. LBFS_E_STATE on a borrowed batch handle. Synchronous. */
 int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual);
 
+/* Local heat flux Q = -lambda (dT/dy) at the south wall (Sec. 5.2, Fig. 15) of the
+   current state, one value per column into host_q (n = nx): the second-order one-sided
+   difference through the wall temperature and the first two cell centres, lambda of
+   the wall cell (Eq. 11). All zero unless the south wall holds a fixed temperature.
+   Also valid on a borrowed batch handle. Synchronous. */
+int lbfs_wall_heat_profile(lbfs_solver* s, double* host_q, size_t n);
+
 /* Copy a field to / from a host FP64 array of n = nx*ny values. Synchronous. */
 int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n);
 int lbfs_write_field(lbfs_solver* s, int32_t field, const double* host, size_t n);

@@ -908,6 +908,25 @@ void orc_set(orc_sim* s, int field, const double* in)
 
 void orc_set_time(orc_sim* s, double t, double step) { s->t = t; s->step = step; }
 
+void orc_wall_heat_profile(orc_sim* s, double* q)
+{
+    int nx = s->nx;
+    double dx = s->p.dx, tw = s->p.tval[2];
+    int on = !s->p.periodic[1] && s->p.tbc[2] == 1;
+    for (int i = 0; i < nx; i++) {
+        q[i] = 0.0;
+        if (!on) continue;
+        int c0 = IX(s, i, 0), c1 = IX(s, i, 1);
+        double T0, T1, Fl0, Fl1;
+        orc_enthalpy_state(&s->p, s->W[ORC_HE][c0], s->W[ORC_C][c0], &T0, &Fl0);
+        orc_enthalpy_state(&s->p, s->W[ORC_HE][c1], s->W[ORC_C][c1], &T1, &Fl1);
+        double ct = clamp01(s->W[ORC_C][c0]);
+        double lam = mix3(s->p.lam, ct * (1.0 - Fl0), ct);
+        /* T(y) through (0, Tw), (dx/2, T0), (3dx/2, T1): T'(0) = (9 T0 - T1 - 8 Tw) / (3 dx) */
+        q[i] = -lam * (9.0 * T0 - T1 - 8.0 * tw) / (3.0 * dx);
+    }
+}
+
 void orc_observe(orc_sim* s, orc_obs* o)
 {
     int nx = s->nx, ny = s->ny;

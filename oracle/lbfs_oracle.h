@@ -114,6 +114,12 @@ void orc_mag_lbfs_fluxes(orc_sim* s, double D, double* fx, double* fy);
 /* the automatic pseudo-time step of orc_mag_lbfs */
 double orc_mag_lbfs_dtau(const orc_params* p, double D);
 
+/* Local heat flux Q = -lambda dT/dy on the south wall (Sec. 5.2, Fig. 15), one value
+   per column: the second-order one-sided difference through the wall temperature and
+   the first two cell centres, lambda of the wall cell (Eq. 11). Zero when the south
+   wall is not a fixed-temperature wall. q holds nx values. */
+void orc_wall_heat_profile(orc_sim* s, double* q);
+
 /* pointwise pieces, exposed for the moment and branch pins */
 void orc_lattice(double* ex, double* ey, double* w);
 void orc_enthalpy_state(const orc_params* p, double He, double C, double* T, double* Fl);

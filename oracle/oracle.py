@@ -93,6 +93,7 @@ def load(path: str):
     L.orc_mag_lbfs_fluxes.argtypes = [C.c_void_p, C.c_double, dp, dp]
     L.orc_mag_lbfs_dtau.argtypes = [C.POINTER(Params), C.c_double]
     L.orc_mag_lbfs_dtau.restype = C.c_double
+    L.orc_wall_heat_profile.argtypes = [C.c_void_p, dp]
     L.orc_lattice.argtypes = [dp, dp, dp]
     L.orc_enthalpy_state.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp, dp]
     L.orc_equilibria.argtypes = [C.POINTER(Params)] + [C.c_double] * 9 + [dp, dp, dp]
@@ -232,6 +233,12 @@ class Oracle:
         fy = np.zeros(self.nx * (self.ny + 1))
         self._L.orc_mag_lbfs_fluxes(self._h, float(D), _dp(fx), _dp(fy))
         return fx.reshape(self.ny, self.nx + 1), fy.reshape(self.ny + 1, self.nx)
+
+    def wall_heat_profile(self) -> np.ndarray:
+        """Local heat flux -lambda dT/dy on the south wall, one value per column."""
+        out = np.zeros(self.nx)
+        self._L.orc_wall_heat_profile(self._h, _dp(out))
+        return out
 
     def mag_lbfs_dtau(self, D: float = 1.0) -> float:
         return self._L.orc_mag_lbfs_dtau(C.byref(self.params), float(D))

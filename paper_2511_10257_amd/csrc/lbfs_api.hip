@@ -849,6 +849,20 @@ int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual)
     return LBFS_OK;
 }
 
+int lbfs_wall_heat_profile(lbfs_solver* s, double* host_q, size_t n)
+{
+    if (!s) return LBFS_E_STATE;
+    if (!host_q || n != (size_t)s->p.nx) return LBFS_E_INVAL;
+    // the stage-1 field is free between steps: FP64 scratch for the nx values
+    double* out = static_cast<double*>(s->field(5));
+    HIPCHK(s->f64() ? launch_wall_profile<double>(s->dinst, s->p.nx, out, s->stream)
+                    : launch_wall_profile<float>(s->dinst, s->p.nx, out, s->stream));
+    HIPCHK(hipMemcpyAsync(s->staging, out, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    std::memcpy(host_q, s->staging, n * sizeof(double));
+    return LBFS_OK;
+}
+
 int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n)
 {
     if (!s) return LBFS_E_STATE;

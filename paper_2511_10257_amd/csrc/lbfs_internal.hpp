@@ -42,7 +42,7 @@ constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 32, 1024}, {64
                                                {128, 16, 1024}};
 // The magnetic LBFS pseudo-time solve runs on the same tiles: one launch does up to
 // RK_KMAX pseudo-steps of three stages each (LDS halo 3*RK_KMAX+1).
-constexpr int RK_KMAX = 3;
+constexpr int RK_KMAX = 4;
 
 constexpr TileShape stage_shape(bool f64, int k) { return f64 ? STAGE_SHAPES_F64[k] : STAGE_SHAPES_F32[k]; }
 // pointwise kernels (init, derived fields): one thread per cell
@@ -152,5 +152,8 @@ hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntile
                               hipStream_t stream);
 template <typename T>
 hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
+// local wall heat flux of instance 0 (nx FP64 values into out)
+template <typename T>
+hipError_t launch_wall_profile(const DevInst* insts, int nx, double* out, hipStream_t stream);
 
 }  // namespace lbfs

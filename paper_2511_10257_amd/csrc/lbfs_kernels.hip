@@ -15,7 +15,7 @@
 //                           (Eq. 17, SSP-RK3 steps temporally blocked in LDS).
 //   k_reduce                fixed-order FP64 reduction of the partials per instance
 //                           (the last stage does the same in its last workgroup).
-//   k_init_fields, k_derived
+//   k_init_fields, k_derived, k_wall_profile (local wall heat flux, Sec. 5.2)
 //
 // The path is a stencil: a few hundred flops per face over ~70 bytes per cell and
 // stage, no dense contraction, so no MFMA. Fields are SoA with a padded row pitch;
@@ -1401,6 +1401,35 @@ __global__ __launch_bounds__(PT_TX* PT_TY) void k_derived(const DevInst* __restr
     reinterpret_cast<T*>(I.W1[1])[o] = Fl;
 }
 
+// Local heat flux Q = -lambda dT/dy on the south wall (Sec. 5.2, Fig. 15) of instance 0,
+// one FP64 value per column into `out`: the second-order one-sided difference through
+// the wall temperature and the first two cell centres, lambda of the wall cell (Eq. 11);
+// zero unless the south wall holds a fixed temperature.
+template <typename T>
+__global__ __launch_bounds__(256) void k_wall_profile(const DevInst* __restrict__ insts, double* __restrict__ out)
+{
+    const DevInst& I = insts[0];
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= I.nx) return;
+    const Coef<T>& K = coef<T>(I);
+    const GLOBAL T* He = gp<T>(I.W[0]);
+    const GLOBAL T* C = gp<T>(I.W[4]);
+    T T0, F0, T1, F1;
+    enthalpy_state<T>(K, He[i], C[i], T0, F0);
+    enthalpy_state<T>(K, He[I.pitch + i], C[I.pitch + i], T1, F1);
+    const T ct = clamp01(C[i]);
+    const double lam = double(mix3<T>(K.lam, ct * (T(1) - F0), ct));
+    out[i] = I.heat_on ? -lam * (9.0 * double(T0) - double(T1) - 8.0 * I.tval[2]) / (3.0 * I.dx) : 0.0;
+}
+
+template <typename T>
+hipError_t launch_wall_profile(const DevInst* insts, int nx, double* out, hipStream_t stream)
+{
+    if (nx <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_wall_profile<T>), dim3((nx + 255) / 256), dim3(256), 0, stream, insts, out);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,
                               double c_init, double t_init, double cx, double cy, double r,
@@ -1430,7 +1459,8 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
     template hipError_t launch_state_partials<T>(int, const DevInst*, const Tile*, int, hipStream_t); \
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \
-    template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);
+    template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);                 \
+    template hipError_t launch_wall_profile<T>(const DevInst*, int, double*, hipStream_t);
 
 LBFS_INSTANTIATE(float)
 LBFS_INSTANTIATE(double)

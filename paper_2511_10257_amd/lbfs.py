@@ -27,7 +27,7 @@ NKERNELS = len(KERNELS)
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
     "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
-    "lbfs_mag_pseudo_steps", "lbfs_read_field",
+    "lbfs_mag_pseudo_steps", "lbfs_wall_heat_profile", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
@@ -102,6 +102,7 @@ def lib():
             "lbfs_rhs": (C.c_int, [vp, dp]),
             "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
             "lbfs_mag_pseudo_steps": (C.c_int, [vp, i32, dp]),
+            "lbfs_wall_heat_profile": (C.c_int, [vp, dp, C.c_size_t]),
             "lbfs_read_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
             "lbfs_write_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
             "lbfs_set_time": (C.c_int, [vp, C.c_double, C.c_int64]),
@@ -277,6 +278,13 @@ class _Instance:
     def set_state(self, state: dict) -> None:
         for k, v in state.items():
             self.set(k, v)
+
+    def wall_heat_profile(self) -> np.ndarray:
+        """Local heat flux -lambda dT/dy on the south wall, one value per column."""
+        out = np.zeros(self.nx)
+        _check(lib().lbfs_wall_heat_profile(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), out.size),
+               "lbfs_wall_heat_profile")
+        return out
 
     def set_time(self, t: float, step: int) -> None:
         _check(lib().lbfs_set_time(self._h, float(t), int(step)), "lbfs_set_time")

@@ -28,21 +28,31 @@ LAM_S = LAM_L * 2.32 / 0.72
 GAS_DIFFUSIVITY = 0.4
 
 
-def _props(rho_ratio: float = 10.0, visc_ratio: float = 10.0) -> dict:
+def _props(rho_ratio: float = 10.0, visc_ratio: float = 10.0, gas_lambda_ratio: float | None = None) -> dict:
+    """Gas conductivity: by default that of a gas of diffusivity GAS_DIFFUSIVITY and
+    heat capacity 1 (lambda_g / lambda_l = 0.8); with gas_lambda_ratio the conductivity
+    is that fraction of the liquid's (air against a water-based ferrofluid: about
+    0.036) at the same diffusivity, through a lower gas heat capacity."""
     rho_g = 1.0 / rho_ratio
     mu_l = 0.02
+    if gas_lambda_ratio is None:
+        lam_g, cp_g = GAS_DIFFUSIVITY * rho_g * 1.0, 1.0
+    else:
+        lam_g = gas_lambda_ratio * LAM_L
+        cp_g = lam_g / (rho_g * GAS_DIFFUSIVITY)
     return dict(
         rho=[RHO_S, 1.0, rho_g],
         mu=[mu_l, mu_l, mu_l / visc_ratio],
-        cp=[CP_S, 1.0, 1.0],
-        lam=[LAM_S, LAM_L, GAS_DIFFUSIVITY * rho_g * 1.0],
+        cp=[CP_S, 1.0, cp_g],
+        lam=[LAM_S, LAM_L, lam_g],
         chi=[1.0, 1.0, 0.0],
     )
 
 
 def droplet_problem(n: int, radius: float, ste: float, bo_m: float, angle_deg: float,
                     rho_ratio: float = 10.0, visc_ratio: float = 10.0,
-                    precision: str = "fp32", ny: int | None = None) -> dict:
+                    precision: str = "fp32", ny: int | None = None,
+                    gas_lambda_ratio: float | None = None) -> dict:
     """Half droplet on the cold south wall of an n x ny box (Sec. 5, Fig. 8)."""
     ny = n if ny is None else ny
     prob = dict(
@@ -59,7 +69,7 @@ def droplet_problem(n: int, radius: float, ste: float, bo_m: float, angle_deg: f
         init_check=50,
         precision=precision,
     )
-    prob.update(_props(rho_ratio, visc_ratio))
+    prob.update(_props(rho_ratio, visc_ratio, gas_lambda_ratio))
     return prob
 
 

@@ -1,0 +1,35 @@
+"""Sec. 5 diagnostics on the GPU against the oracle: the local wall heat flux (Fig. 15)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2511_10257_amd import lbfs, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wall_heat_profile_matches_oracle(precision):
+    prob = wl.droplet_problem(72, 18.0, ste=0.15, bo_m=1.0, angle_deg=90.0, precision=precision, ny=40)
+    g = lbfs.Solver(prob)
+    g.step(50)                                    # a freezing state with a mushy layer
+    st = {k: g.get(k) for k in ("He", "p", "Mx", "My", "C", "phi", "S")}
+    o = orc.Oracle(wl.with_changes(prob, init_max=0), init=False)
+    o.set_state(st)
+    qo, qg = o.wall_heat_profile(), g.wall_heat_profile()
+    assert np.all(qo <= 0.0) and np.min(qo) < 0.0    # heat leaves through the cold wall
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(qg - qo)) <= tol * np.max(np.abs(qo))
+
+
+def test_wall_heat_profile_on_a_batch_member_and_without_cold_wall():
+    prob = wl.droplet_problem(64, 16.0, ste=0.1, bo_m=0.5, angle_deg=0.0, precision="fp32")
+    batch = lbfs.Batch(2, 2 * lbfs.Batch.instance_bytes(prob))
+    slot = batch.admit(prob)
+    batch.step(20)
+    alone = lbfs.Solver(prob)
+    alone.step(20)
+    assert np.array_equal(batch.slot(slot).wall_heat_profile(), alone.wall_heat_profile())
+    batch.close()
+    warm = lbfs.Solver(wl.with_changes(prob, thermal_bc=["adiabatic"] * 4))
+    assert np.all(warm.wall_heat_profile() == 0.0)

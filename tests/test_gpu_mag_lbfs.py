@@ -2,7 +2,7 @@
 GPU with the FP64 oracle, whose face fluxes are the literal m* moments.
 
 FP64 agrees to rounding, FP32 within the relative L2 bound 1e-5 of the other parity
-tests. The kernel blocks up to three pseudo-steps per launch in LDS, so step counts
+tests. The kernel blocks up to four pseudo-steps per launch in LDS, so step counts
 around that limit, every tile shape, ragged grids, periodic and insulating walls and
 the full 1024^2 grid are covered.
 """
@@ -46,7 +46,7 @@ def check_phi(prob, o, g, precision, what):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("nsteps", [0, 1, 3, 4, 7])
+@pytest.mark.parametrize("nsteps", [0, 1, 4, 5, 9])
 def test_pseudo_steps_match_oracle(precision, nsteps):
     prob, o, g, _ = case(150, 70, seed=31 + nsteps, precision=precision)
     D = prob.get("mag_lbfs_d", 1.0)
@@ -106,7 +106,7 @@ def test_step_fp32_with_pseudo_time_method():
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_full_size_pseudo_steps_match_oracle(precision):
     """The 1024^2 droplet in the launch configuration of the benchmark (64 x 32 magnetic
-    tiles): three pseudo-steps (one launch) over the whole grid."""
+    tiles): four pseudo-steps (one launch) over the whole grid."""
     prob = wl.with_changes(wl.droplet1024(precision), init_max=0, mag_method="lbfs")
     nx, ny = prob["nx"], prob["ny"]
     o = orc.Oracle(prob, init=False)
@@ -115,8 +115,8 @@ def test_full_size_pseudo_steps_match_oracle(precision):
     g = lbfs.Solver(prob)
     g.set_state(st)
     assert g.tile_shapes_in_use()[1] == 1
-    o.mag_lbfs(3, 1.0, 0.0)
-    g.mag_pseudo_steps(3)
+    o.mag_lbfs(4, 1.0, 0.0)
+    g.mag_pseudo_steps(4)
     check_phi(prob, o, g, precision, "1024")
 
 

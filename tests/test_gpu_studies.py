@@ -1,0 +1,47 @@
+"""Trend-level checks of the Sec. 5 studies (Figs. 11, 16, 18) on synthetic droplets.
+
+The paper's figures carry no numeric data, so these tests check directions only: the
+droplet grows taller while it freezes (the solid is less dense), a vertical field makes
+it taller and a horizontal one flatter (Fig. 11), and, with a gas that conducts heat
+poorly (air against a water-based ferrofluid: lambda_g / lambda_l ~ 0.036), the
+vertical field slows the latent-heat release and the horizontal one speeds it up
+(Figs. 16 and 18). Magnitudes are parity-unpinned.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_10257_amd import studies
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sweep():
+    cases = studies.sweep_cases(64, [0.0, 16.0], [0.1], gas_lambda_ratio=0.036)
+    res = studies.run(cases, chunk=100, max_steps=6800)
+    return {(r["case"]["bo_m"], r["case"]["orientation"]): r["series"] for r in res}
+
+
+def test_droplet_grows_while_freezing(sweep):
+    h = np.array(sweep[(0.0, "none")]["h_r0"])
+    assert h[-1] > 1.03 and h[-1] > h[len(h) // 4] > h[0] - 1e-3
+
+
+def test_field_orientation_orders_the_height(sweep):
+    v, n, hz = (np.array(sweep[k]["h_r0"]) for k in ((16.0, "vertical"), (0.0, "none"), (16.0, "horizontal")))
+    late = slice(5, None)
+    assert np.all(v[late] > n[late]) and np.all(n[late] > hz[late])
+    assert v[-1] - n[-1] > 0.01 and n[-1] - hz[-1] > 0.01
+
+
+def test_field_orientation_orders_the_freezing_rate(sweep):
+    fl = {k: np.array(sweep[k]["fl"]) for k in sweep}
+    ql = {k: np.array(sweep[k]["q_l"]) for k in sweep}
+    v, n, hz = (16.0, "vertical"), (0.0, "none"), (16.0, "horizontal")
+    # second half of the run: more liquid left under the vertical field, less under the
+    # horizontal one; the solid ratio of Eq. 51 the other way round
+    half = slice(len(fl[n]) // 2, None)
+    assert np.all(fl[v][half] > fl[n][half]) and np.all(fl[n][half] > fl[hz][half])
+    assert np.all(ql[v][half] < ql[n][half]) and np.all(ql[n][half] < ql[hz][half])
+    for k in sweep:
+        assert np.all(np.isfinite(fl[k]))

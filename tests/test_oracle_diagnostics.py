@@ -1,0 +1,65 @@
+"""Pins of the oracle's Sec. 5 diagnostics: the local wall heat flux of Fig. 15.
+
+Q = -lambda (dT/dy) at the cold wall, with the gradient from a second-order one-sided
+difference through the wall temperature and the first two cell centres. A liquid state
+(C = 1, T above the melting point) makes T an explicit function of He (Eq. 8:
+He = Cp_l T + L), so temperature profiles with a known wall gradient can be imposed.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2511_10257_amd import workloads as wl
+
+
+def liquid_wall_case(nx, ny, dx, t_wall):
+    p = wl.droplet_problem(nx, nx / 4.0, ste=0.1, bo_m=0.0, angle_deg=90.0, precision="fp64", ny=ny)
+    p.update(dx=dx, dt=0.1 * dx * dx, dt_stream=0.5 * dx, init_max=0, latent=10.0, h0=0.0,
+             thermal_bc=["adiabatic", "adiabatic", "fixed", "adiabatic"], thermal_val=[0.0, 0.0, t_wall, 0.0])
+    o = orc.Oracle(p, init=False)
+    return p, o
+
+
+def impose_T(o, p, T):
+    cp_l, L = p["cp"][1], p["latent"]
+    o.set("C", np.ones_like(T))
+    o.set("He", cp_l * T + L)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_wall_flux_is_exact_for_linear_and_quadratic_profiles(order):
+    nx, ny, dx, tw = 12, 9, 0.5, 0.5
+    p, o = liquid_wall_case(nx, ny, dx, tw)
+    y = (np.arange(ny) + 0.5) * dx
+    a = np.linspace(0.3, 1.7, nx)               # wall gradient varies along the wall
+    b = 0.2 if order == 2 else 0.0
+    T = tw + a[None, :] * y[:, None] + b * y[:, None] ** 2
+    impose_T(o, p, T)
+    q = o.wall_heat_profile()
+    lam_l = p["lam"][1]
+    assert np.max(np.abs(q - (-lam_l * a))) < 1e-12
+
+
+def test_wall_flux_converges_at_second_order():
+    tw = 0.5
+    errs = []
+    for n in (8, 16, 32):
+        dx = 1.0 / n
+        p, o = liquid_wall_case(6, n, dx, tw)
+        y = (np.arange(n) + 0.5) * dx
+        T = tw + 0.8 * y + 1.5 * y ** 3
+        impose_T(o, p, np.repeat(T[:, None], 6, 1))
+        q = o.wall_heat_profile()
+        errs.append(abs(q[0] - (-p["lam"][1] * 0.8)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+def test_wall_flux_needs_a_fixed_temperature_wall():
+    p, o = liquid_wall_case(10, 8, 1.0, 0.5)
+    p2 = wl.with_changes(p, thermal_bc=["adiabatic"] * 4)
+    o2 = orc.Oracle(p2, init=False)
+    impose_T(o2, p2, np.full((8, 10), 0.7))
+    assert np.all(o2.wall_heat_profile() == 0.0)

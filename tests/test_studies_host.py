@@ -1,0 +1,32 @@
+"""Host logic of the Sec. 5 study driver: case generation, t* and the Fig. 17 slope."""
+import math
+
+import pytest
+
+from paper_2511_10257_amd import studies
+
+
+def test_sweep_cases_one_field_free_case_per_stefan_number():
+    cases = studies.sweep_cases(48, [0.0, 4.0], [0.1, 0.3])
+    keys = [(c["case"]["ste"], c["case"]["bo_m"], c["case"]["orientation"]) for c in cases]
+    assert keys == [(0.1, 0.0, "none"), (0.1, 4.0, "vertical"), (0.1, 4.0, "horizontal"),
+                    (0.3, 0.0, "none"), (0.3, 4.0, "vertical"), (0.3, 4.0, "horizontal")]
+    vert = [c for c in cases if c["case"]["orientation"] == "vertical"][0]
+    assert vert["angle_deg"] == 90.0 and vert["nx"] == 48 and vert["drop"][2] == 12.0
+    air = studies.sweep_cases(48, [0.0], [0.1], gas_lambda_ratio=0.036)[0]
+    assert air["lam"][2] == pytest.approx(0.036 * air["lam"][1])
+    assert air["lam"][2] / (air["rho"][2] * air["cp"][2]) == pytest.approx(0.4)
+
+
+def _res(ste, bo, ori, t, fo, hm):
+    return dict(case=dict(ste=ste, bo_m=bo, orientation=ori), frozen=True, freeze_t=t, freeze_fo=fo, hm_r0=hm)
+
+
+def test_t_star_and_scaling_slope():
+    res = [_res(0.1, 0.0, "none", 100.0, 1.0, 1.0), _res(0.1, 8.0, "vertical", 110.0, 1.1, 1.05),
+           _res(0.1, 8.0, "horizontal", 95.0, 0.95, 0.97), _res(0.3, 8.0, "vertical", 40.0, 0.4, 1.0)]
+    ts = {(t["ste"], t["orientation"]): t["t_star"] for t in studies.t_star(res)}
+    assert ts == {(0.1, "vertical"): pytest.approx(0.1), (0.1, "horizontal"): pytest.approx(-0.05)}
+    # points on H = (Ste Fo)^0.5 give the slope 0.5 exactly
+    pts = [_res(s, 0.0, "none", 1.0, fo, math.sqrt(s * fo)) for s, fo in ((0.1, 2.0), (0.2, 3.0), (0.3, 0.7))]
+    assert studies.scaling_slope(pts) == pytest.approx(0.5, abs=1e-12)
