@@ -112,6 +112,11 @@ typedef struct lbfs_params {
        instance's chunks only copy the potential, so the step stays one graph. */
     int32_t mag_max_iters;    /* 0: exactly `sweeps` iterations per step; <= 100000 */
     double mag_tol;           /* absolute target of ||r||_2 (>= 0)                  */
+    /* Contact angle of each wall through the liquid, degrees in (0, 180) (Sec. 4.2
+       wetting; the paper gives no condition): the order parameter's ghost cells carry
+       n.grad C = -(4/xi) cos(theta) C (1 - C), n into the fluid, the gradient of the
+       equilibrium profile meeting the wall at theta; 90 is the plain mirror. */
+    double contact_angle_deg[4];
 } lbfs_params;
 
 typedef struct lbfs_observables {
@@ -129,6 +134,13 @@ typedef struct lbfs_observables {
     double peclet;            /* Pe of Eq. 50 as umax_drop D / alpha_l, D = 2 R0,
                                  alpha_l = lambda_l / (rho_l Cp_l) (printed with a square
                                  that makes it dimensional; read as the usual u D / alpha) */
+    /* Droplet shape from the moments of Ct (Sec. 4.3 deformation ratio b/a): centroid;
+       2 sqrt of the Ct-weighted variance along x and along y; the same along the
+       principal axes of the covariance, and the major axis direction (degrees from +x,
+       in (-90, 90]). An ellipse of semi-axes a, b gives a and b exactly. */
+    double centroid_x, centroid_y;
+    double semi_axis_x, semi_axis_y;
+    double semi_axis_major, semi_axis_minor, major_axis_deg;
     int64_t step;
     int32_t nonfinite;        /* 1 if a conserved value was not finite              */
 } lbfs_observables;

@@ -35,7 +35,9 @@
  *   - dFs/dt is lagged by one step; F_IBM = -rho u Fs / Dt (direct forcing).
  *   - Walls: zero mass and order-parameter flux; fixed-temperature walls conduct
  *     through the half cell; momentum flux from the same LBFS face formula with
- *     mirrored ghost cells (no-slip).
+ *     mirrored ghost cells (no-slip). A wall with a contact angle other than 90 degrees
+ *     gives the order parameter's ghost cells the wall-normal gradient of that angle
+ *     (wetting; the paper does not give its condition).
  *   - Magnetic LBFS: the flux sum_a e_a m*_a that Eqs. 15-16 give is -D mu grad(phi),
  *     so Eq. 17 is a diffusion towards Eq. 4 (Eq. 18 prints the opposite sign);
  *     tau_m uses the mean permeability of the face's two cells; the pseudo-time step
@@ -63,7 +65,7 @@ static const double WA[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 static const double CS2 = 1.0 / 3.0;
 
-enum { K_EVEN, K_ODD, K_TEMP };
+enum { K_EVEN, K_ODD, K_TEMP, K_WET };
 
 struct orc_sim {
     orc_params p;
@@ -170,6 +172,8 @@ orc_sim* orc_new(const orc_params* pin)
     if (p->mag_method < 0 || p->mag_method > 1) return NULL;
     if (p->mag_method == 1 && !(p->mag_lbfs_d > 0.0)) return NULL;
     if (p->mag_max_iters < 0 || (p->mag_max_iters > 0 && (p->sweeps <= 0 || !(p->mag_tol >= 0.0)))) return NULL;
+    for (int w = 0; w < 4; w++)
+        if (!(p->contact_angle[w] > 0.0 && p->contact_angle[w] < 180.0)) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     s->nx = p->nx; s->ny = p->ny;
@@ -207,10 +211,20 @@ void orc_free(orc_sim* s)
 /* ------------------------------------------------------------------ ghosts */
 
 /* value of a ghost cell mirroring interior value v across wall w */
-static double reflect(const orc_sim* s, double v, int kind, int w)
+/* value of the ghost cell k layers beyond wall w (k = 0 nearest) that mirrors interior
+   value v; K_WET (the order parameter) adds the wall-normal gradient of the contact
+   angle: n.grad C = -(4/xi) cos(theta) C (1 - C) (n into the fluid, the equilibrium
+   tanh profile's |grad C| = (4/xi) C (1 - C)), over the 2k+1 cells between ghost and
+   mirror cell, with C of the mirror cell */
+static double reflect(const orc_sim* s, double v, int kind, int w, int k)
 {
     if (kind == K_ODD) return -v;
     if (kind == K_TEMP && s->p.tbc[w] == 1) return 2.0 * s->p.tval[w] - v;
+    if (kind == K_WET && s->p.contact_angle[w] != 90.0) {
+        double c = clamp01(v);
+        double g = 4.0 / s->p.xi * cos(s->p.contact_angle[w] * M_PI / 180.0) * c * (1.0 - c);
+        return v + (2 * k + 1) * s->p.dx * g;
+    }
     return v;
 }
 
@@ -225,8 +239,8 @@ static void fill_ghosts(const orc_sim* s, double* a, int kind)
                 a[IX(s, -1 - k, j)] = a[IX(s, nx - 1 - k, j)];
                 a[IX(s, nx + k, j)] = a[IX(s, k, j)];
             } else {
-                a[IX(s, -1 - k, j)] = reflect(s, a[IX(s, k, j)], kind, 0);
-                a[IX(s, nx + k, j)] = reflect(s, a[IX(s, nx - 1 - k, j)], kind, 1);
+                a[IX(s, -1 - k, j)] = reflect(s, a[IX(s, k, j)], kind, 0, k);
+                a[IX(s, nx + k, j)] = reflect(s, a[IX(s, nx - 1 - k, j)], kind, 1, k);
             }
         }
     for (int i = -G; i < nx + G; i++)
@@ -235,8 +249,8 @@ static void fill_ghosts(const orc_sim* s, double* a, int kind)
                 a[IX(s, i, -1 - k)] = a[IX(s, i, ny - 1 - k)];
                 a[IX(s, i, ny + k)] = a[IX(s, i, k)];
             } else {
-                a[IX(s, i, -1 - k)] = reflect(s, a[IX(s, i, k)], kind, 2);
-                a[IX(s, i, ny + k)] = reflect(s, a[IX(s, i, ny - 1 - k)], kind, 3);
+                a[IX(s, i, -1 - k)] = reflect(s, a[IX(s, i, k)], kind, 2, k);
+                a[IX(s, i, ny + k)] = reflect(s, a[IX(s, i, ny - 1 - k)], kind, 3, k);
             }
         }
 }
@@ -562,7 +576,7 @@ static void primitives(orc_sim* s, double* const Win[5])
     fill_ghosts(s, s->val[R_U], K_ODD);
     fill_ghosts(s, s->val[R_V], K_ODD);
     fill_ghosts(s, s->val[R_RHO], K_EVEN);
-    fill_ghosts(s, s->val[R_C], K_EVEN);
+    fill_ghosts(s, s->val[R_C], K_WET);
     fill_ghosts(s, s->val[R_T], K_TEMP);
     fill_ghosts(s, s->val[R_HE], K_EVEN);
     fill_ghosts(s, s->mu, K_EVEN);
@@ -936,12 +950,15 @@ void orc_observe(orc_sim* s, orc_obs* o)
     if (ic < 0) ic = 0;
     if (ic > nx - 1) ic = nx - 1;
     double height = 0.0;
+    double mx = 0, my = 0, mxx = 0, myy = 0, mxy = 0;
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             int c = IX(s, i, j);
             for (int k = 0; k < 5; k++)
                 if (!isfinite(s->W[k][c])) nonfinite = 1;
             double C = s->W[ORC_C][c], ct = clamp01(C), T, Fl;
+            double x = (i + 0.5) * dx, y = (j + 0.5) * dx;
+            mx += ct * x; my += ct * y; mxx += ct * x * x; myy += ct * y * y; mxy += ct * x * y;
             orc_enthalpy_state(&s->p, s->W[ORC_HE][c], C, &T, &Fl);
             double fs = ct * (1.0 - Fl);
             double rho = mix3(s->p.rho, fs, ct);
@@ -971,4 +988,22 @@ void orc_observe(orc_sim* s, orc_obs* o)
     double alpha_l = s->p.lam[1] / (s->p.rho[1] * s->p.cp[1]);
     o->fourier = alpha_l * s->t / (s->p.drop_r * s->p.drop_r);
     o->peclet = udrop * 2.0 * s->p.drop_r / alpha_l;
+    /* shape: covariance of the Ct distribution; an ellipse of semi-axes a, b has the
+       variance a^2/4 along its axis a */
+    o->centroid_x = o->centroid_y = o->semi_axis_x = o->semi_axis_y = 0.0;
+    o->semi_axis_major = o->semi_axis_minor = o->major_axis_deg = 0.0;
+    if (sc > 0.0) {
+        double cx = mx / sc, cy = my / sc;
+        double vxx = mxx / sc - cx * cx, vyy = myy / sc - cy * cy, vxy = mxy / sc - cx * cy;
+        if (vxx < 0.0) vxx = 0.0;
+        if (vyy < 0.0) vyy = 0.0;
+        double mean = 0.5 * (vxx + vyy), dev = sqrt(0.25 * (vxx - vyy) * (vxx - vyy) + vxy * vxy);
+        double lmin = mean - dev > 0.0 ? mean - dev : 0.0;
+        o->centroid_x = cx; o->centroid_y = cy;
+        o->semi_axis_x = 2.0 * sqrt(vxx); o->semi_axis_y = 2.0 * sqrt(vyy);
+        o->semi_axis_major = 2.0 * sqrt(mean + dev); o->semi_axis_minor = 2.0 * sqrt(lmin);
+        double ang = 0.5 * atan2(2.0 * vxy, vxx - vyy) * 180.0 / M_PI;
+        if (ang <= -90.0) ang += 180.0;
+        o->major_axis_deg = ang;
+    }
 }

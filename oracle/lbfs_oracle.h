@@ -67,6 +67,8 @@ typedef struct orc_params {
                              mag_tol, at most this many iterations per step; 0: exactly
                              `sweeps` iterations per step                               */
     double mag_tol;       /* absolute target of ||r||_2 for mag_max_iters > 0            */
+    double contact_angle[4]; /* wetting walls: contact angle through the liquid (degrees,
+                                0 < theta < 180; 90 is the mirror condition)             */
 } orc_params;
 
 typedef struct orc_obs {
@@ -83,6 +85,9 @@ typedef struct orc_obs {
     double fourier;          /* Fo of Eq. 50: lambda_l t / (rho_l Cp_l R0^2) */
     double peclet;           /* Pe of Eq. 50, read as umax_drop D / alpha_l,
                                 D = 2 R0, alpha_l = lambda_l / (rho_l Cp_l) */
+    double centroid_x, centroid_y;        /* Ct-weighted centroid                   */
+    double semi_axis_x, semi_axis_y;      /* 2 sqrt(Ct-weighted variance) along x, y */
+    double semi_axis_major, semi_axis_minor, major_axis_deg;  /* principal axes   */
 } orc_obs;
 
 typedef struct orc_sim orc_sim;

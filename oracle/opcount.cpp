@@ -53,6 +53,7 @@ inline Cnt tanh(Cnt a) { ++opc::n_special; return Cnt(::tanh(a.v)); }
 inline Cnt cos(Cnt a) { ++opc::n_special; return Cnt(::cos(a.v)); }
 inline Cnt sin(Cnt a) { ++opc::n_special; return Cnt(::sin(a.v)); }
 inline Cnt exp(Cnt a) { ++opc::n_special; return Cnt(::exp(a.v)); }
+inline Cnt atan2(Cnt a, Cnt b) { ++opc::n_special; return Cnt(::atan2(a.v, b.v)); }
 inline Cnt floor(Cnt a) { ++opc::n_cmp; return Cnt(::floor(a.v)); }
 inline Cnt fabs(Cnt a) { ++opc::n_cmp; return Cnt(::fabs(a.v)); }
 inline Cnt fmin(Cnt a, Cnt b) { ++opc::n_cmp; return Cnt(::fmin(a.v, b.v)); }

@@ -38,18 +38,22 @@ class Params(C.Structure):
         ("init_max", C.c_int), ("init_check", C.c_int),
         ("mag_method", C.c_int), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
         ("mag_max_iters", C.c_int), ("mag_tol", C.c_double),
+        ("contact_angle", C.c_double * 4),
     ]
 
 
 class Obs(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "t", "step", "liquid_fraction", "solid_ratio", "volume", "volume0",
-        "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat", "fourier", "peclet")]
+        "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat", "fourier", "peclet",
+        "centroid_x", "centroid_y", "semi_axis_x", "semi_axis_y", "semi_axis_major", "semi_axis_minor",
+        "major_axis_deg")]
 
 
 def build(force: bool = False) -> str:
     src = os.path.join(HERE, "lbfs_oracle.c")
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src):
+    newest = max(os.path.getmtime(src), os.path.getmtime(os.path.join(HERE, "lbfs_oracle.h")))
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
                                "-o", LIB, src, "-lm"])
     return LIB
@@ -61,8 +65,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
+        build()                   # rebuilds only when the source is newer than the library
         _lib = load(LIB)
     return _lib
 
@@ -142,6 +145,8 @@ def make_params(prob: dict) -> Params:
     p.mag_lbfs_dtau = float(prob.get("mag_lbfs_dtau", 0.0))
     p.mag_max_iters = int(prob.get("mag_max_iters", 0))
     p.mag_tol = float(prob.get("mag_tol", 0.0))
+    for k, a in enumerate(prob.get("contact_angle", [90.0] * 4)):
+        p.contact_angle[k] = float(a)
     if "latent" in prob and "h0" in prob:
         p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
     else:

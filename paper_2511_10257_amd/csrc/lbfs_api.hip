@@ -84,6 +84,7 @@ int validate(const lbfs_params* p)
         if (p->thermal_bc[w] != LBFS_TBC_ADIABATIC && p->thermal_bc[w] != LBFS_TBC_FIXED) return LBFS_E_INVAL;
         if (p->mag_bc[w] != LBFS_MBC_INSULATING && p->mag_bc[w] != LBFS_MBC_FIXED) return LBFS_E_INVAL;
         if (!std::isfinite(p->thermal_val[w])) return LBFS_E_INVAL;
+        if (!(p->contact_angle_deg[w] > 0.0 && p->contact_angle_deg[w] < 180.0)) return LBFS_E_INVAL;
     }
     if (p->sweeps < 0 || p->sweeps > 1000) return LBFS_E_INVAL;
     if (!(p->sor_omega > 0.0 && p->sor_omega < 2.0)) return LBFS_E_INVAL;
@@ -363,7 +364,10 @@ void fill_coef(Coef<T>& K, const DevInst& I)
         K.cp[k] = T(I.cp[k]);
         K.chi[k] = T(I.chi[k]);
     }
-    for (int w = 0; w < 4; w++) K.tval[w] = T(I.tval[w]);
+    for (int w = 0; w < 4; w++) {
+        K.tval[w] = T(I.tval[w]);
+        K.wet[w] = T(I.wet[w]);
+    }
     K.latent = T(I.latent);
     K.tm = T(I.tm);
     K.dx = T(I.dx);
@@ -410,6 +414,21 @@ int fill_observables(const lbfs_params& p, double t, int64_t step, double vol0, 
     const double alpha_l = p.lambda[1] / (p.rho[1] * p.cp[1]);
     o->fourier = alpha_l * t / (p.drop_radius * p.drop_radius);
     o->peclet = o->umax_drop * 2.0 * p.drop_radius / alpha_l;
+    if (r[RES_CT] > 0.0) {
+        const double S = r[RES_CT], cx = r[RES_MX] / S, cy = r[RES_MY] / S;
+        const double vxx = std::max(r[RES_MXX] / S - cx * cx, 0.0), vyy = std::max(r[RES_MYY] / S - cy * cy, 0.0);
+        const double vxy = r[RES_MXY] / S - cx * cy;
+        const double mean = 0.5 * (vxx + vyy), dev = std::sqrt(0.25 * (vxx - vyy) * (vxx - vyy) + vxy * vxy);
+        o->centroid_x = cx;
+        o->centroid_y = cy;
+        o->semi_axis_x = 2.0 * std::sqrt(vxx);
+        o->semi_axis_y = 2.0 * std::sqrt(vyy);
+        o->semi_axis_major = 2.0 * std::sqrt(mean + dev);
+        o->semi_axis_minor = 2.0 * std::sqrt(std::max(mean - dev, 0.0));
+        double ang = 0.5 * std::atan2(2.0 * vxy, vxx - vyy) * 180.0 / M_PI;
+        if (ang <= -90.0) ang += 180.0;
+        o->major_axis_deg = ang;
+    }
     o->nonfinite = r[RES_NONFINITE] != 0.0 || !std::isfinite(r[RES_CT]) ? 1 : 0;
     return o->nonfinite ? LBFS_E_NONFINITE : LBFS_OK;
 }
@@ -553,7 +572,10 @@ int lbfs_params_default(lbfs_params* p, int32_t nx, int32_t ny, int32_t precisio
     p->c_init = 1.0;
     p->thermal_bc[2] = LBFS_TBC_FIXED;
     p->thermal_val[2] = -1.0;
-    for (int w = 0; w < 4; w++) p->mag_bc[w] = LBFS_MBC_FIXED;
+    for (int w = 0; w < 4; w++) {
+        p->mag_bc[w] = LBFS_MBC_FIXED;
+        p->contact_angle_deg[w] = 90.0;
+    }
     p->sweeps = 4;
     p->sor_omega = 1.0;
     p->mag_method = LBFS_MAG_SWEEPS;
@@ -677,6 +699,9 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
         I.tbc[w] = p->thermal_bc[w];
         I.mbc[w] = p->mag_bc[w];
         I.tval[w] = p->thermal_val[w];
+        // wetting: n.grad C = -(4/xi) cos(theta) C (1 - C) at the wall (exactly the
+        // mirror at 90 degrees)
+        I.wet[w] = p->contact_angle_deg[w] == 90.0 ? 0.0 : 4.0 / p->xi * std::cos(p->contact_angle_deg[w] * M_PI / 180.0);
     }
     int col = (int)std::floor(p->drop_cx / p->dx);
     I.col_height = col < 0 ? 0 : (col > p->nx - 1 ? p->nx - 1 : col);

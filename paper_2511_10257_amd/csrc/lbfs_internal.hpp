@@ -50,10 +50,10 @@ constexpr int PT_TX = 64, PT_TY = 4;
 
 // per-tile partial sums of the observables of a state (FP64)
 enum { PART_CT = 0, PART_CTFL, PART_FS, PART_UMAX, PART_NONFINITE, PART_UDROP, PART_HEIGHT,
-       PART_HEAT, NPART };
+       PART_HEAT, PART_MX, PART_MY, PART_MXX, PART_MYY, PART_MXY, NPART };
 // per-instance results written by the reduction (FP64)
 enum { RES_CT = 0, RES_CTFL, RES_FS, RES_UMAX, RES_NONFINITE, RES_UDROP, RES_HEIGHT, RES_HEAT,
-       RES_MAGR2, NRES };
+       RES_MX, RES_MY, RES_MXX, RES_MYY, RES_MXY, RES_MAGR2, NRES };
 
 struct Tile {
     int32_t inst;    // instance index
@@ -68,6 +68,7 @@ template <typename T>
 struct Coef {
     T rho[3], mu[3], lam[3], cp[3], chi[3];   // [solid, liquid, gas] (Eq. 11)
     T tval[4];                                // fixed wall temperatures
+    T wet[4];                                 // (4 / xi) cos(contact angle) per wall, 0 at 90 degrees
     T latent, tm, dx, dt, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, vc;
     T grav[2];
     T idx;      // 1 / dx
@@ -99,6 +100,7 @@ struct DevInst {
     int32_t col_height;  // column of the height observable
     int32_t heat_on;     // south wall is a fixed-temperature wall
     double tval[4];
+    double wet[4];   // (4 / xi) cos(contact angle) per wall (0: mirror)
     double rho[3], mu_[3], lam[3], cp[3], chi[3];
     double latent, tm, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;
     double grav[2];

@@ -13,8 +13,7 @@
 //                           the FP64 residual.
 //   k_mag_lbfs              the same phase by the magnetic LBFS pseudo-time solve
 //                           (Eq. 17, SSP-RK3 steps temporally blocked in LDS).
-//   k_reduce                fixed-order FP64 reduction of the partials per instance
-//                           (the last stage does the same in its last workgroup).
+//   k_reduce                fixed-order FP64 reduction of the partials per instance.
 //   k_init_fields, k_derived, k_wall_profile (local wall heat flux, Sec. 5.2)
 //
 // The path is a stencil: a few hundred flops per face over ~70 bytes per cell and
@@ -350,8 +349,9 @@ __device__ __forceinline__ double wave_max(double x)
 }
 
 // FP64 observables of one cell of the state Wn (He, p, Mx, My, C): clamped order
-// parameter, Ct Fl, Fs, |u|, non-finite flag, |u| inside the drop, height column and
-// heat into a fixed south wall (-lambda dT/dy over the half cell, times dx).
+// parameter, Ct Fl, Fs, |u|, non-finite flag, |u| inside the drop, height column, heat
+// into a fixed south wall (-lambda dT/dy over the half cell, times dx), and the first and
+// second moments of Ct about the origin (droplet centroid and axes).
 template <typename T>
 __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int gx, int gy, double* pr)
 {
@@ -373,6 +373,12 @@ __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int
     pr[PART_NONFINITE] = finite ? 0.0 : 1.0;
     pr[PART_UDROP] = ct1 >= T(0.5) ? um : 0.0;
     pr[PART_HEIGHT] = gx == I.col_height ? double(ct1) : 0.0;
+    const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx, c = double(ct1);
+    pr[PART_MX] = c * x;
+    pr[PART_MY] = c * y;
+    pr[PART_MXX] = c * x * x;
+    pr[PART_MYY] = c * y * y;
+    pr[PART_MXY] = c * x * y;
     pr[PART_HEAT] = 0.0;
     if (gy == 0 && I.heat_on) {
         const double lam1 = double(mix3<T>(K.lam, fs1, ct1));
@@ -414,7 +420,7 @@ __device__ __forceinline__ bool res_is_max(int k)
 template <int NT>
 __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, double (*red)[NT / 64])
 {
-    double acc[NRES] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[NRES] = {};
     for (int t = tid; t < I.ntile_stage; t += NT) {
         const double* p = I.part + (size_t)t * NPART;
         acc[RES_CT] += p[PART_CT];
@@ -425,6 +431,11 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
         acc[RES_UDROP] = fmax(acc[RES_UDROP], p[PART_UDROP]);
         acc[RES_HEIGHT] += p[PART_HEIGHT];
         acc[RES_HEAT] += p[PART_HEAT];
+        acc[RES_MX] += p[PART_MX];
+        acc[RES_MY] += p[PART_MY];
+        acc[RES_MXX] += p[PART_MXX];
+        acc[RES_MYY] += p[PART_MYY];
+        acc[RES_MXY] += p[PART_MXY];
     }
     for (int t = tid; t < I.ntile_mag; t += NT) acc[RES_MAGR2] += I.mpart[t];
     __syncthreads();
@@ -547,17 +558,25 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             Prim<T> q = primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]);
             T ph = vph[it];
             const int wx = vwx[it], wy = vwy[it];
+            // a wetting wall adds the contact-angle gradient to the mirrored order
+            // parameter over the |vd| cells between ghost and mirror cell
+            auto wet = [&](T c, T wk, int vd) {
+                const T cc = clamp01(c);
+                return c + T(vd < 0 ? -vd : vd) * dx * wk * cc * (T(1) - cc);
+            };
             if (wx >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
                 if (I.tbc[wx]) q.Tt = T(2) * K.tval[wx] - q.Tt;
                 ph = I.mbc[wx] ? -ph : ph - K.h0x * T(vdx[it]) * dx;
+                if (K.wet[wx] != T(0)) q.C = wet(q.C, K.wet[wx], vdx[it]);
             }
             if (wy >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
                 if (I.tbc[wy]) q.Tt = T(2) * K.tval[wy] - q.Tt;
                 ph = I.mbc[wy] ? -ph : ph - K.h0y * T(vdy[it]) * dx;
+                if (K.wet[wy] != T(0)) q.C = wet(q.C, K.wet[wy], vdy[it]);
             }
             store_cell(r, q, ph);
         }
@@ -577,6 +596,30 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         }
     }
     __syncthreads();
+    // wall ghosts take the chemical potential of their mirror cell (no flux of C through
+    // a wall: d(mu_c)/dn = 0), whatever the order parameter's ghosts hold (a wetting
+    // wall's ghosts are not mirrors). A mirror cell is never a wall ghost, so one pass
+    // reads only cells it does not write.
+    if (!interior) {
+        for (int r = tid; r < L::NR; r += NT) {
+            const int lx = r % L::RX, ly = r / L::RX;
+            if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
+            const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+            const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
+            const bool wally = !I.per_y && (gy < 0 || gy >= ny);
+            if (!wallx && !wally) continue;
+            const int mx = wallx ? (gx < 0 ? -1 - gx : 2 * nx - 1 - gx) : gx;
+            const int my = wally ? (gy < 0 ? -1 - gy : 2 * ny - 1 - gy) : gy;
+            const int mlx = mx - (x0 - 3), mly = my - (y0 - 3);
+            // (cells further than the halo from a tiny domain mirror out of the domain or
+            // the region; their values never reach an output)
+            if (mx < 0 || mx >= nx || my < 0 || my >= ny || mlx < 1 || mlx > L::RX - 2 || mly < 1 ||
+                mly > L::RY - 2)
+                continue;
+            s.muc[r] = s.muc[mly * L::RX + mlx];
+        }
+        __syncthreads();
+    }
 
     // ---- C: central gradients and |H|^2 on tile + 1
     const T h0x = K.h0x, h0y = K.h0y;

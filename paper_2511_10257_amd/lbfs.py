@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("init_check", C.c_int32),
         ("mag_method", C.c_int32), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
         ("mag_max_iters", C.c_int32), ("mag_tol", C.c_double),
+        ("contact_angle_deg", C.c_double * 4),
     ]
 
 
@@ -66,6 +67,9 @@ class Observables(C.Structure):
         ("volume", C.c_double), ("volume0", C.c_double), ("mag_residual", C.c_double),
         ("umax", C.c_double), ("umax_drop", C.c_double), ("height", C.c_double),
         ("wall_heat", C.c_double), ("fourier", C.c_double), ("peclet", C.c_double),
+        ("centroid_x", C.c_double), ("centroid_y", C.c_double), ("semi_axis_x", C.c_double),
+        ("semi_axis_y", C.c_double), ("semi_axis_major", C.c_double), ("semi_axis_minor", C.c_double),
+        ("major_axis_deg", C.c_double),
         ("step", C.c_int64), ("nonfinite", C.c_int32),
     ]
 
@@ -190,6 +194,8 @@ def make_params(prob: dict) -> Params:
     p.mag_lbfs_dtau = float(prob.get("mag_lbfs_dtau", 0.0))
     p.mag_max_iters = int(prob.get("mag_max_iters", 0))
     p.mag_tol = float(prob.get("mag_tol", 0.0))
+    for k, a in enumerate(prob.get("contact_angle", [90.0] * 4)):
+        p.contact_angle_deg[k] = float(a)
     for key in ("init_max", "init_check"):
         if key in prob:
             setattr(p, key, int(prob[key]))

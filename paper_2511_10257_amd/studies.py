@@ -13,7 +13,11 @@ paper's figures:
 - the scaling of the final height with the freezing time, H_m/R0 against Ste Fo
   (Fig. 17), as the slope of a least-squares line in log-log axes;
 - the dimensionless freezing time t* = (t(Bo_m) - t(0)) / t(0) per Ste and
-  orientation (Fig. 18).
+  orientation (Fig. 18);
+- without freezing, the deformation ratio b/a of a suspended ferrofluid droplet in a
+  vertical field against Bo_m (Sec. 4.3, Fig. 7): b and a from the moments of the order
+  parameter along and across the field;
+- and water droplets at different contact angles freezing on the cold wall (Sec. 4.2).
 
 Inputs are the synthetic half droplets of workloads.droplet_problem; nothing here
 reads a dataset.
@@ -95,6 +99,75 @@ def run(cases: list[dict], chunk: int = 50, max_steps: int = 200000, done_fl: fl
     return results
 
 
+def deformation(n: int, bo_list, steps: int, chunk: int = 500, precision: str = "fp32") -> list[dict]:
+    """Suspended droplets (workloads.deformation_problem) for each Bo_m in one batch:
+    the series of b/a = semi_axis_y / semi_axis_x every chunk, and its mean over the last
+    third of the run (the shape oscillates about its equilibrium while viscosity damps
+    it)."""
+    cases = [wl.deformation_problem(n, float(bo), precision=precision) for bo in bo_list]
+    budget = sum(lbfs.Batch.instance_bytes(p) for p in cases) + (16 << 20)
+    batch = lbfs.Batch(len(cases), budget, precision=precision)
+    slots = [batch.admit(p) for p in cases]
+    if None in slots:
+        raise RuntimeError("the batch buffer does not hold every case")
+    series = {s: dict(step=[], b_over_a=[], umax=[]) for s in slots}
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        batch.step(k)
+        done += k
+        obs = batch.observe(allow_nonfinite=True)
+        for s, o in obs.items():
+            series[s]["step"].append(int(o["step"]))
+            series[s]["b_over_a"].append(o["semi_axis_y"] / o["semi_axis_x"] if o["semi_axis_x"] > 0 else float("nan"))
+            series[s]["umax"].append(o["umax"])
+    batch.close()
+    out = []
+    for p, s in zip(cases, slots):
+        ba = np.array(series[s]["b_over_a"])
+        tail = ba[len(ba) - max(1, len(ba) // 3):]
+        out.append(dict(bo_m=p["bo_m"], radius=p["drop"][2], b_over_a=float(np.mean(tail)),
+                        b_over_a_spread=float(np.max(tail) - np.min(tail)), series=series[s]))
+    return out
+
+
+def static_freezing(thetas, nx: int = 400, ny: int = 200, R0: float | None = None, chunk: int = 100,
+                    max_steps: int = 400000, done_fl: float = 1e-3, precision: str = "fp32") -> list[dict]:
+    """Sec. 4.2: water droplets at the given contact angles freezing on the cold wall
+    (workloads.static_droplet_problem), one batch to freezing; per angle the freezing
+    step, the final height and x semi-axis over R0, and the series of the liquid
+    fraction and height."""
+    cases = [wl.static_droplet_problem(float(t), nx, ny, R0, precision) for t in thetas]
+    budget = sum(lbfs.Batch.instance_bytes(p) for p in cases) + (16 << 20)
+    batch = lbfs.Batch(len(cases), budget, precision=precision)
+    slots = [batch.admit(p) for p in cases]
+    if None in slots:
+        raise RuntimeError("the batch buffer does not hold every case")
+    recs = {s: dict(theta=p["contact_angle"][2], r0=p["r0"], frozen=False,
+                    series=dict(step=[], fl=[], h_r0=[], a_r0=[])) for s, p in zip(slots, cases)}
+    live = set(slots)
+    steps = 0
+    while live and steps < max_steps:
+        batch.step(chunk)
+        steps += chunk
+        obs = batch.observe(allow_nonfinite=True)
+        for s, o in obs.items():
+            if s not in live:
+                continue
+            r = recs[s]
+            r["series"]["step"].append(int(o["step"]))
+            r["series"]["fl"].append(o["liquid_fraction"])
+            r["series"]["h_r0"].append(o["height"] / r["r0"])
+            r["series"]["a_r0"].append(o["semi_axis_x"] / r["r0"])
+            if o["liquid_fraction"] < done_fl or o["nonfinite"]:
+                r.update(frozen=not o["nonfinite"], freeze_step=int(o["step"]), hm_r0=o["height"] / r["r0"],
+                         am_r0=o["semi_axis_x"] / r["r0"])
+                batch.retire(s)
+                live.discard(s)
+    batch.close()
+    return [recs[s] for s in slots]
+
+
 def t_star(results: list[dict]) -> list[dict]:
     """(t(Bo_m) - t(0)) / t(0) for every frozen case with a frozen field-free case of the
     same Ste (Fig. 18)."""
@@ -119,6 +192,11 @@ def scaling_slope(results: list[dict]) -> float:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--deformation", action="store_true",
+                    help="the Sec. 4.3 deformation sweep (suspended droplets, no freezing) instead")
+    ap.add_argument("--steps", type=int, default=40000, help="steps of the deformation sweep")
+    ap.add_argument("--static", default=None,
+                    help="contact angles (e.g. 64,98) of the Sec. 4.2 static-droplet freezing instead")
     ap.add_argument("--edge", type=int, default=64)
     ap.add_argument("--bo", default="0,4,8,16", help="Bo_m values")
     ap.add_argument("--ste", default="0.1,0.2,0.3", help="Stefan numbers")
@@ -129,6 +207,21 @@ def main(argv=None):
                     help="gas conductivity over the liquid's at the default gas diffusivity (air: 0.036)")
     ap.add_argument("--out", default=None, help="write the results as JSON here")
     args = ap.parse_args(argv)
+    if args.static:
+        res = static_freezing([float(t) for t in args.static.split(",")], nx=2 * args.edge, ny=args.edge,
+                              precision=args.precision)
+        print(json.dumps([{k: v for k, v in r.items() if k != "series"} for r in res]))
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f)
+        return
+    if args.deformation:
+        res = deformation(args.edge, [float(b) for b in args.bo.split(",")], args.steps, precision=args.precision)
+        print(json.dumps([{k: v for k, v in r.items() if k != "series"} for r in res]))
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f)
+        return
     cases = sweep_cases(args.edge, [float(b) for b in args.bo.split(",")],
                         [float(s) for s in args.ste.split(",")], precision=args.precision,
                         gas_lambda_ratio=args.gas_lambda_ratio)
@@ -138,12 +231,12 @@ def main(argv=None):
             print(f"studies: step {steps}, {nlive} cases still freezing", file=sys.stderr, flush=True)
 
     res = run(cases, chunk=args.chunk, max_steps=args.max_steps, progress=progress)
-    summary = dict(edge=args.edge, gas_lambda_ratio=args.gas_lambda_ratio, cases=[dict(r["case"], frozen=r.get("frozen", False),
-                                               freeze_step=r.get("freeze_step"), freeze_fo=r.get("freeze_fo"),
-                                               hm_r0=r.get("hm_r0"),
-                                               h_r0_max=max(r["series"]["h_r0"]) if r["series"]["h_r0"] else None,
-                                               pe_max=max(r["series"]["pe"]) if r["series"]["pe"] else None)
-                                          for r in res],
+    per_case = [dict(r["case"], frozen=r.get("frozen", False), freeze_step=r.get("freeze_step"),
+                     freeze_fo=r.get("freeze_fo"), hm_r0=r.get("hm_r0"),
+                     h_r0_max=max(r["series"]["h_r0"]) if r["series"]["h_r0"] else None,
+                     pe_max=max(r["series"]["pe"]) if r["series"]["pe"] else None)
+                for r in res]
+    summary = dict(edge=args.edge, gas_lambda_ratio=args.gas_lambda_ratio, cases=per_case,
                    t_star=t_star(res), scaling_slope=scaling_slope(res))
     print(json.dumps(summary))
     if args.out:

@@ -111,6 +111,74 @@ def droplet4096(precision: str = "fp32") -> dict:
     return p
 
 
+def deformation_problem(n: int, bo_m: float, precision: str = "fp32", radius: float | None = None) -> dict:
+    """Suspended ferrofluid droplet in a carrier liquid, no freezing (Sec. 4.3, Table 2):
+    an n x n box, droplet of radius n/5 at the centre, relative permeability 2.2 inside
+    (chi = 1.2) and 1 outside, density ratio 1580/800 and viscosity ratio 0.016/0.0008
+    of Table 2. The field is vertical, imposed through the potential on the top and
+    bottom walls, with magnetically insulating side walls; every wall is no-slip and
+    adiabatic and the whole box stays liquid (T above the melting point), so only the
+    magnetic, capillary and viscous forces act. H0 follows Bo_m = mu0 H0^2 D / sigma
+    (Eq. 50) with D the droplet diameter."""
+    R = n / 5.0 if radius is None else float(radius)
+    sigma, mu0 = 0.005, 1.0
+    mu_l = 0.02
+    prob = dict(
+        nx=n, ny=n, dx=1.0, dt=0.5, dt_stream=0.5,
+        t_melt=0.0, t_init=1.0, latent=1.0, h0=float(np.sqrt(bo_m * sigma / (mu0 * 2.0 * R))),
+        ste=None, bo_m=float(bo_m), angle_deg=90.0,
+        mu0=mu0, grav=[0.0, 0.0], sigma=sigma, xi=4.0, mobility=0.05, tau_g=1.0,
+        drop=[n / 2.0, n / 2.0, R], init_kind="droplet", c_init=1.0,
+        periodic=[0, 0],
+        thermal_bc=["adiabatic"] * 4, thermal_val=[0.0] * 4,
+        mag_bc=["insulating", "insulating", "fixed", "fixed"],
+        sweeps=4, omega=1.0, init_omega=0.0,
+        init_tol=1e-9 if precision == "fp64" else 1e-4, init_max=20 * n + 1000, init_check=50,
+        precision=precision,
+        rho=[RHO_S, 1.0, 800.0 / 1580.0],
+        mu=[mu_l, mu_l, mu_l * 0.0008 / 0.016],
+        cp=[CP_S, 1.0, 1.0],
+        lam=[LAM_S, LAM_L, LAM_L],
+        chi=[1.2, 1.2, 0.0],
+        name=f"deformation-{n}x{n}-R{R:g}-Bo{bo_m:g}-{precision}",
+    )
+    return prob
+
+
+def sessile_radius(R0: float, theta_deg: float) -> float:
+    """Radius of the circular cap of contact angle theta whose area equals the half disc
+    of radius R0 (the 90 degree droplet): R^2 (theta - sin theta cos theta) = pi R0^2 / 2."""
+    th = np.deg2rad(theta_deg)
+    return float(R0 * np.sqrt((np.pi / 2.0) / (th - np.sin(th) * np.cos(th))))
+
+
+def static_droplet_problem(theta_deg: float, nx: int = 400, ny: int = 200, R0: float | None = None,
+                           precision: str = "fp32") -> dict:
+    """Water droplet freezing on a cold wall at contact angle theta (Sec. 4.2): Ste 0.19,
+    Bond number g R0 (rho_l - rho_g) / sigma = 0.22 with gravity towards the wall,
+    solid / liquid / gas densities 0.9 / 1 / 0.05, no magnetic field, a 400 x 200 box;
+    the droplet starts at the melting point as the circular cap of that contact angle
+    with the area of a half disc of radius R0 (nx / 8 by default). The Prandtl number of
+    the paper (13.47) is not matched (explicit stability), as for the other workloads."""
+    R0 = nx / 8.0 if R0 is None else float(R0)
+    R = sessile_radius(R0, theta_deg)
+    p = droplet_problem(nx, R0, ste=0.19, bo_m=0.0, angle_deg=90.0, precision=precision, ny=ny)
+    rho_g = 0.05
+    sigma = p["sigma"]
+    g = 0.22 * sigma / (R0 * (1.0 - rho_g))
+    p.update(
+        rho=[0.9, 1.0, rho_g],
+        lam=[LAM_S, LAM_L, GAS_DIFFUSIVITY * rho_g * 1.0],
+        chi=[0.0, 0.0, 0.0], h0=0.0,
+        grav=[0.0, -g],
+        drop=[nx / 2.0, -R * float(np.cos(np.deg2rad(theta_deg))), R],
+        contact_angle=[90.0, 90.0, float(theta_deg), 90.0],
+        name=f"static-droplet-{nx}x{ny}-R0{R0:g}-theta{theta_deg:g}-Ste0.19-Bo0.22-{precision}",
+    )
+    p["r0"] = R0
+    return p
+
+
 def batch64(seed: int = 1, count: int = 64) -> list[dict]:
     """Batch of uneven instances: edge in {64..256}, R=edge/4, random angle/Bo_m/Ste."""
     rng = np.random.default_rng(seed)

@@ -33,3 +33,28 @@ def test_wall_heat_profile_on_a_batch_member_and_without_cold_wall():
     batch.close()
     warm = lbfs.Solver(wl.with_changes(prob, thermal_bc=["adiabatic"] * 4))
     assert np.all(warm.wall_heat_profile() == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_shape_observables_match_oracle(precision):
+    """Centroid and axes of the order parameter (Sec. 4.3 deformation ratio) from the
+    device FP64 reduction against the oracle's, on a stretched, tilted droplet."""
+    n = 90
+    prob = wl.deformation_problem(n, 2.0, precision=precision)
+    prob.update(init_max=0)
+    o = orc.Oracle(prob, init=False)
+    y, x = np.mgrid[0:n, 0:n] + 0.5
+    th = np.deg2rad(25.0)
+    u = (x - 47.0) * np.cos(th) + (y - 41.0) * np.sin(th)
+    v = -(x - 47.0) * np.sin(th) + (y - 41.0) * np.cos(th)
+    r = np.sqrt((u / 22.0) ** 2 + (v / 15.0) ** 2)
+    st = dict(C=0.5 * (1 + np.tanh(2 * (1.0 - r) * 15.0 / 4.0)), He=np.full((n, n), 2.0))
+    o.set_state(st)
+    g = lbfs.Solver(prob)
+    g.set_state(st)
+    ob, og = o.observe(), g.observe()
+    rel = 1e-12 if precision == "fp64" else 1e-6
+    for k in ("centroid_x", "centroid_y", "semi_axis_x", "semi_axis_y", "semi_axis_major", "semi_axis_minor"):
+        assert og[k] == pytest.approx(ob[k], rel=rel), k
+    assert og["major_axis_deg"] == pytest.approx(ob["major_axis_deg"], abs=1e-4)
+    assert 20.0 < ob["major_axis_deg"] < 30.0

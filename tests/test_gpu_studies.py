@@ -45,3 +45,12 @@ def test_field_orientation_orders_the_freezing_rate(sweep):
     assert np.all(ql[v][half] < ql[n][half]) and np.all(ql[n][half] < ql[hz][half])
     for k in sweep:
         assert np.all(np.isfinite(fl[k]))
+
+
+def test_deformation_ratio_grows_with_the_magnetic_bond_number():
+    """Sec. 4.3 (Fig. 7): a suspended ferrofluid droplet (mu_r 2.2) stretches along a
+    vertical field, more for a stronger field; without a field it stays round. The
+    experimental ratios are not available, so only the trend is checked."""
+    res = {r["bo_m"]: r["b_over_a"] for r in studies.deformation(100, [0.0, 2.0, 4.0], steps=40000, chunk=1000)}
+    assert abs(res[0.0] - 1.0) < 1e-3
+    assert res[2.0] > 1.05 and res[4.0] > res[2.0] + 0.05

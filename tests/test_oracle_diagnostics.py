@@ -63,3 +63,31 @@ def test_wall_flux_needs_a_fixed_temperature_wall():
     o2 = orc.Oracle(p2, init=False)
     impose_T(o2, p2, np.full((8, 10), 0.7))
     assert np.all(o2.wall_heat_profile() == 0.0)
+
+
+@pytest.mark.parametrize("theta_deg", [0.0, 30.0, 90.0, -60.0])
+def test_shape_moments_recover_an_ellipse(theta_deg):
+    """The shape observables (centroid, semi-axes from the Ct covariance, major-axis
+    direction) of a sharp ellipse of semi-axes 30 and 18 on a fine grid: the discrete
+    moments match the continuous ones (a^2/4 along an axis) to the pixelation error (1%)."""
+    n = 160
+    p = wl.droplet_problem(n, 20.0, ste=0.1, bo_m=0.0, angle_deg=90.0, precision="fp64")
+    p.update(init_max=0)
+    o = orc.Oracle(p, init=False)
+    a, b, cx, cy = 30.0, 18.0, 83.0, 71.5
+    th = np.deg2rad(theta_deg)
+    y, x = np.mgrid[0:n, 0:n] + 0.5
+    u = (x - cx) * np.cos(th) + (y - cy) * np.sin(th)
+    v = -(x - cx) * np.sin(th) + (y - cy) * np.cos(th)
+    C = ((u / a) ** 2 + (v / b) ** 2 <= 1.0).astype(float)
+    o.set("C", C)
+    o.set("He", np.full((n, n), 20.0))
+    ob = o.observe()
+    assert abs(ob["centroid_x"] - cx) < 0.05 and abs(ob["centroid_y"] - cy) < 0.05
+    assert abs(ob["semi_axis_major"] - a) < 0.3 and abs(ob["semi_axis_minor"] - b) < 0.3
+    ang = ob["major_axis_deg"]
+    d = (ang - theta_deg + 90.0) % 180.0 - 90.0
+    assert abs(d) < 0.2, ang
+    # the axis-aligned variances: a^2 cos^2 + b^2 sin^2 along x
+    ex = np.sqrt(a * a * np.cos(th) ** 2 + b * b * np.sin(th) ** 2)
+    assert abs(ob["semi_axis_x"] - ex) < 0.3
