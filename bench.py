@@ -103,6 +103,9 @@ def parse():
                          "the LBFS pseudo-time solve (Eq. 17)")
     ap.add_argument("--mag-steps", type=int, default=None,
                     help="sweeps or pseudo-steps per time step (default: the workload's)")
+    ap.add_argument("--mag-in-stage1", choices=["auto", "on", "off"], default="auto",
+                    help="run the step's sweeps inside Runge-Kutta stage 1 (no magnetic launch): on, off, "
+                         "or the library's default for the grid")
     ap.add_argument("--mag-max-iters", type=int, default=0,
                     help="convergence control: repeat chunks of --mag-steps iterations per step until the "
                          "magnetic residual is at most --mag-tol, at most this many iterations (0: off)")
@@ -140,7 +143,7 @@ def measured_traffic(kernel: str, workload: str, shape: str):
 
 def shape_names(lbfs, precision: str, in_use: tuple) -> dict:
     return {"stage": lbfs.shape_name(lbfs.tile_shapes("stage", precision)[in_use[0]]),
-            "mag": lbfs.shape_name(lbfs.tile_shapes("mag", precision)[in_use[1]])}
+            "mag": lbfs.shape_name(lbfs.mag_shape(in_use[1], precision))}
 
 
 def cpu_baseline(prob: dict, budget_s: float) -> dict:
@@ -272,6 +275,10 @@ def run_single(args, torch, lbfs, wl) -> dict:
     cells = prob["nx"] * prob["ny"]
     copy_calibration(torch, args.copy_calibration_mib)
     solver = lbfs.Solver(prob, device="cuda:0")
+    if args.mag_in_stage1 != "auto":
+        si, mi = solver.tile_shapes_in_use()
+        fused = lbfs.mag_fused_index(prob["precision"])
+        solver.set_tile_shapes(si, fused if args.mag_in_stage1 == "on" else (mi if mi != fused else 0))
     tuned = solver.autotune() if args.autotune == "on" else None
     shapes = shape_names(lbfs, prob["precision"], solver.tile_shapes_in_use())
     solver.step(args.warmup)

@@ -248,12 +248,19 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
 /* kind 0: stage kernels, 1: magnetic kernel. With index < 0 returns the number of
    shapes of that kind; otherwise writes the tile (tx x ty cells), the workgroup size
    (threads) and flags of shape `index` (bit 0: the first two stages load the owned
-   cells' values before the halo rather than after the faces). Any pointer may be NULL. */
+   cells' values before the halo rather than after the faces). Any pointer may be NULL.
+   Kind 1 has one more index, equal to the count: no magnetic launch, the step's
+   red-black sweeps run inside Runge-Kutta stage 1 on its tiles (a halo of
+   2 MAG_KMAX + 3 = 11 cells in LDS, the same arithmetic, so the same results bit for
+   bit); flags bit 1 marks it, tx = ty = threads = 0. It needs the sweeps as the
+   per-step method, no convergence control and at most 4 sweeps per step. */
 int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* threads,
                     int32_t* flags);
 
 /* Use the given shapes from the next launch on (a changed magnetic shape recomputes the
-   residual as lbfs_autotune does). Synchronous. */
+   residual as lbfs_autotune does); mag_shape equal to the magnetic shape count selects
+   the sweeps inside stage 1 (LBFS_E_INVAL where that is not possible) and keeps the
+   current magnetic tiles for the initial solve and lbfs_mag_sweeps. Synchronous. */
 int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape);
 
 /* The shapes the next launches use (indices into the tables of lbfs_tile_shape). */
@@ -264,9 +271,13 @@ int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape, int32_t*
    magnetic shape (reps magnetic phases of a
    step, on the current potential, which is restored afterwards) on this solver's
    current state, and keep the fastest of each (the default, shape 0, unless another
-   is faster by more than 2 %, the spread of such timings). chosen[2] receives the indices,
-   ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes first, magnetic shapes
-   from index LBFS_MAX_SHAPES; either may be NULL). The state is unchanged; until the
+   is faster by more than 2 %, the spread of such timings). Where the sweeps can run
+   inside stage 1, that variant (stage 1 with the sweeps and stage 2 twice) is timed
+   too and chosen when it beats the best stage pair plus the best magnetic launch by
+   2 %. chosen[2] receives the indices (chosen[1] the count of magnetic shapes for
+   the fused variant), ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes
+   first, magnetic shapes from index LBFS_MAX_SHAPES, then the time the fused sweeps
+   add to the stage pair; either may be NULL). The state is unchanged; until the
    next step, mag_residual then reports the residual of the current potential with the
    current permeability (a step reports it with the permeability of the step's start).
    Synchronous. */

@@ -137,7 +137,9 @@ Layout make_layout(const lbfs_params* p)
     L.off_tmag = off; off = align_up(off + sizeof(Tile) * L.cap_mag, ALIGN);
     L.off_tpt = off; off = align_up(off + sizeof(Tile) * L.ntile_pt(), ALIGN);
     L.off_part = off; off = align_up(off + sizeof(double) * NPART * L.cap_stage, ALIGN);
-    L.off_mpart = off; off = align_up(off + sizeof(double) * (L.cap_mag + 1), ALIGN);   // + convergence flag
+    // residual partials (per magnetic tile, or per stage tile when stage 1 runs the
+    // sweeps) and the convergence flag
+    L.off_mpart = off; off = align_up(off + sizeof(double) * (std::max(L.cap_mag, L.cap_stage) + 1), ALIGN);
     L.off_res = off; off = align_up(off + sizeof(double) * NRES, ALIGN);
     L.off_fields = off; off += L.field_bytes * NFIELDS;
     L.total = off + ALIGN;   // room to align the caller's base pointer
@@ -154,6 +156,8 @@ struct Exec {
     double omega = 1.0;
     int mag_method = LBFS_MAG_SWEEPS;
     int mag_chunks = 1;                  // chunks of `sweeps` per step (convergence control)
+    bool fused = false;                  // the sweeps run inside stage 1 (no magnetic launch)
+    bool mres_stage = false;             // the last residual partials are per stage tile
     hipStream_t stream = nullptr;
     const DevInst* dinst = nullptr;
     int ninst = 0;
@@ -170,6 +174,7 @@ struct Exec {
 
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 {
+    E.mres_stage = false;
     return E.f64 ? launch_mag<double>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag,
                                       E.nmag, E.stream, E.ev0, E.ev1)
                  : launch_mag<float>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
@@ -178,6 +183,7 @@ hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 
 hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual, hipEvent_t e0, hipEvent_t e1, int gate)
 {
+    E.mres_stage = false;
     return E.f64 ? launch_mag_lbfs<double>(E.mag_shape, nsteps, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
                                            E.stream, e0, e1, gate)
                  : launch_mag_lbfs<float>(E.mag_shape, nsteps, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
@@ -195,6 +201,7 @@ hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual) { return exec_mag_lb
 hipError_t exec_mag_step(Exec& E)
 {
     hipError_t e = hipSuccess;
+    E.mres_stage = false;
     for (int c = 0; c < E.mag_chunks && e == hipSuccess; c++) {
         const hipEvent_t a = c == 0 ? E.ev0 : nullptr, b = c == E.mag_chunks - 1 ? E.ev1 : nullptr;
         const int gate = c > 0;
@@ -226,12 +233,25 @@ hipError_t exec_state_partials(Exec& E)
                  : launch_state_partials<float>(E.stage_shape, E.dinst, E.tiles_stage, E.nstage, E.stream);
 }
 
-// one time step: magnetic phase and three Runge-Kutta stages (the observables of the
-// state are summed when they are read)
+// stage 1 with the step's sweeps in front of it; flips the potential buffer
+hipError_t exec_stage_fused(Exec& E)
+{
+    const hipError_t e =
+        E.f64 ? launch_stage_fused<double>(E.stage_shape, E.phase, E.sweeps, E.omega, E.dinst, E.tiles_stage, E.nstage,
+                                           E.stream, E.ev0, E.ev1)
+              : launch_stage_fused<float>(E.stage_shape, E.phase, E.sweeps, E.omega, E.dinst, E.tiles_stage, E.nstage,
+                                          E.stream, E.ev0, E.ev1);
+    if (e == hipSuccess && E.nstage > 0) E.phase ^= 1;
+    E.mres_stage = true;
+    return e;
+}
+
+// one time step: magnetic phase and three Runge-Kutta stages, or the fused stage 1
+// and stages 2 and 3 (the observables of the state are summed when they are read)
 hipError_t exec_enqueue_step(Exec& E)
 {
-    hipError_t e = exec_mag_step(E);
-    for (int st = 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
+    hipError_t e = E.fused ? exec_stage_fused(E) : exec_mag_step(E);
+    for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
     return e;
 }
 
@@ -275,6 +295,7 @@ hipError_t exec_ensure_graph(Exec& E, int ph)
 // potential-buffer flips of one step (one per magnetic launch)
 int exec_step_flips(const Exec& E)
 {
+    if (E.fused) return 1;
     const int kmax = E.mag_method == LBFS_MAG_LBFS ? RK_KMAX : MAG_KMAX;
     const int launches = E.sweeps == 0 ? 1 : (E.sweeps + kmax - 1) / kmax;
     return (launches * E.mag_chunks) & 1;
@@ -289,6 +310,7 @@ hipError_t exec_run_step(Exec& E)
     if (e != hipSuccess) return e;
     e = hipGraphLaunch(E.graph_exec[ph], E.stream);
     E.phase = ph ^ exec_step_flips(E);
+    E.mres_stage = E.fused;
     return e;
 }
 
@@ -323,8 +345,9 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
     for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
         hipError_t e;
         if (n % sample_every == 0) {
-            e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E); });
-            for (int st = 1; st <= 3 && e == hipSuccess; st++)
+            if (E.fused) e = timed(LBFS_K_STAGE1, [&] { return exec_stage_fused(E); });
+            else e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E); });
+            for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
         } else {
             e = exec_run_step(E);
@@ -612,9 +635,20 @@ size_t lbfs_state_bytes(const lbfs_params* p)
 static void destroy_solver(lbfs_solver* s);
 
 // tile lists of the given shapes into the solver's own segments; drops the graphs
+// the sweeps can run inside stage 1: a fixed count within one launch's halo
+static bool fusable(const lbfs_params& p)
+{
+    return p.mag_method == LBFS_MAG_SWEEPS && p.mag_max_iters == 0 && p.sweeps <= MAG_KMAX;
+}
+
+// stage and magnetic tile shapes; mi == NMAG_SHAPES runs the sweeps inside stage 1 and
+// keeps the magnetic tiles (still used by the initial solve and lbfs_mag_sweeps)
 static int apply_shapes(lbfs_solver* s, int si, int mi)
 {
-    if (si < 0 || si >= NSTAGE_SHAPES || mi < 0 || mi >= NMAG_SHAPES) return LBFS_E_INVAL;
+    if (si < 0 || si >= NSTAGE_SHAPES || mi < 0 || mi > NMAG_SHAPES) return LBFS_E_INVAL;
+    if (mi == NMAG_SHAPES && !fusable(s->p)) return LBFS_E_INVAL;
+    const bool fuse = mi == NMAG_SHAPES;
+    if (fuse) mi = s->E.mag_shape;
     std::vector<Tile> ts, tm;
     append_tiles(ts, 0, s->p.nx, s->p.ny, stage_shape(s->f64(), si));
     append_tiles(tm, 0, s->p.nx, s->p.ny, MAG_SHAPES[mi]);
@@ -631,6 +665,7 @@ static int apply_shapes(lbfs_solver* s, int si, int mi)
     HIPCHK(hipStreamSynchronize(s->stream));
     E.stage_shape = si;
     E.mag_shape = mi;
+    E.fused = fuse;
     E.nstage = (int)ts.size();
     E.nmag = (int)tm.size();
     s->stepped_since_observe = true;
@@ -827,7 +862,7 @@ int lbfs_observe(lbfs_solver* s, lbfs_observables* o)
     if (!s || !o) return s ? LBFS_E_INVAL : LBFS_E_STATE;
     if (s->stepped_since_observe) {
         HIPCHK(exec_state_partials(s->E));
-        HIPCHK(launch_reduce(s->dinst, 1, s->stream));
+        HIPCHK(launch_reduce(s->dinst, 1, s->stream, s->E.mres_stage));
         HIPCHK(hipMemcpyAsync(s->hres, s->hinst.result, sizeof(double) * NRES, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         s->stepped_since_observe = false;
@@ -1089,6 +1124,13 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
     const int n = kind == 0 ? NSTAGE_SHAPES : kind == 1 ? NMAG_SHAPES : -1;
     if (n < 0) return LBFS_E_INVAL;
     if (index < 0) return n;
+    if (kind == 1 && index == n) {   // the sweeps inside stage 1, on its tiles
+        if (tx) *tx = 0;
+        if (ty) *ty = 0;
+        if (threads) *threads = 0;
+        if (flags) *flags = 2;
+        return LBFS_OK;
+    }
     if (index >= n) return LBFS_E_INVAL;
     const TileShape S = kind == 0 ? stage_shape(precision == LBFS_FP64, index) : MAG_SHAPES[index];
     if (tx) *tx = S.tx;
@@ -1101,9 +1143,9 @@ int lbfs_tile_shape(int32_t kind, int32_t precision, int32_t index, int32_t* tx,
 int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape_idx, int32_t mag_shape_idx)
 {
     if (!s || s->batched) return LBFS_E_STATE;
-    if (stage_shape_idx < 0 || stage_shape_idx >= NSTAGE_SHAPES || mag_shape_idx < 0 || mag_shape_idx >= NMAG_SHAPES)
+    if (stage_shape_idx < 0 || stage_shape_idx >= NSTAGE_SHAPES || mag_shape_idx < 0 || mag_shape_idx > NMAG_SHAPES)
         return LBFS_E_INVAL;
-    const bool mag_changed = mag_shape_idx != s->E.mag_shape;
+    const bool mag_changed = mag_shape_idx != NMAG_SHAPES && mag_shape_idx != s->E.mag_shape;
     int rc = apply_shapes(s, stage_shape_idx, mag_shape_idx);
     if (rc != LBFS_OK) return rc;
     // residual partials of the current potential on the new magnetic tiles
@@ -1118,7 +1160,7 @@ int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape_idx, int3
 {
     if (!s) return LBFS_E_STATE;
     if (stage_shape_idx) *stage_shape_idx = s->E.stage_shape;
-    if (mag_shape_idx) *mag_shape_idx = s->E.mag_shape;
+    if (mag_shape_idx) *mag_shape_idx = s->E.fused ? NMAG_SHAPES : s->E.mag_shape;
     return LBFS_OK;
 }
 
@@ -1137,6 +1179,23 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
         if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
         if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
     }
+    // the sweeps inside stage 1 (its tiles plus a wider halo, one launch less per step):
+    // the fused stage 1 and stage 2 twice, timed before the potential is saved (stage 2
+    // writes the field that holds the copy) with the buffer parity kept, so the fused
+    // launches read the current potential and write only the other buffer; compared
+    // below with the best stage pair plus the best magnetic launch
+    double t_fused = 0.0;
+    if (rc == LBFS_OK && fusable(s->p)) {
+        rc = apply_shapes(s, best_s, NMAG_SHAPES);
+        if (rc == LBFS_OK)
+            rc = time_launches(E.stream, reps, [&] {
+                const int ph = E.phase;
+                hipError_t e = exec_stage_fused(E);
+                E.phase = ph;
+                if (e == hipSuccess) e = exec_stage(E, 2);
+                return e == hipSuccess ? exec_stage(E, 2) : e;
+            }, &t_fused);
+    }
     bool saved = false;
     if (rc == LBFS_OK) {
         if (HIPFAIL(copy_phi(s, true))) rc = LBFS_E_DEVICE;
@@ -1150,17 +1209,23 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
         if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag_step(E); }, tk);
         if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
     }
+    bool fuse = false;
+    if (rc == LBFS_OK && t_fused > 0.0) {
+        t[LBFS_MAX_SHAPES + NMAG_SHAPES] = t_fused - t[best_s];
+        fuse = clearly_faster(t_fused, t[best_s] + t[LBFS_MAX_SHAPES + best_m]);
+    }
     // restore the potential, keep the fastest shapes and recompute the residual partials
     // of the restored potential on them (a sweep-free launch: a copy of the potential)
     E.phase = phase0;
     if (saved && HIPFAIL(copy_phi(s, false))) rc = LBFS_E_DEVICE;
     if (rc == LBFS_OK) rc = apply_shapes(s, best_s, best_m);
+    if (rc == LBFS_OK && fuse) rc = apply_shapes(s, best_s, NMAG_SHAPES);
     if (rc == LBFS_OK && (HIPFAIL(exec_mag(E, 0, 1.0, 1)) || HIPFAIL(hipStreamSynchronize(E.stream))))
         rc = LBFS_E_DEVICE;
     if (rc != LBFS_OK) return rc;
     if (chosen) {
         chosen[0] = best_s;
-        chosen[1] = best_m;
+        chosen[1] = fuse ? NMAG_SHAPES : best_m;
     }
     if (ms)
         for (int k = 0; k < 2 * LBFS_MAX_SHAPES; k++) ms[k] = t[k];

@@ -91,7 +91,8 @@ struct DevInst {
     void* phi[2];    // potential minus the applied-field potential, double buffered
     void* S;         // lagged dFs/dt
     double* part;    // [ntile_stage][NPART]
-    double* mpart;   // [ntile_mag] residual partials, then the convergence flag (see k_mag_gate)
+    double* mpart;   // residual partials of the magnetic phase (one per magnetic tile, or one
+                     // per stage tile when stage 1 runs the phase), then the convergence flag
     double* result;  // [NRES]
     int32_t nx, ny, pitch;
     int32_t per_x, per_y;
@@ -125,6 +126,13 @@ __host__ __device__ inline const Coef<double>& coef<double>(const DevInst& I) { 
 template <typename T>
 hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
                         hipStream_t stream, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// stage 1 with the step's magnetic phase fused in front of it (red-black sweeps of
+// each stage tile plus a halo of 2*MAG_KMAX+3 in LDS, nsweeps <= MAG_KMAX): reads the
+// potential buffer pidx, writes the other one and one residual partial per stage tile
+template <typename T>
+hipError_t launch_stage_fused(int shape, int pidx, int nsweeps, double omega, const DevInst* insts,
+                              const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0 = nullptr,
+                              hipEvent_t e1 = nullptr);
 // magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
 // residual partials when residual != 0, on tiles of MAG_SHAPES[shape]. Reads the
 // potential buffer *pidx and flips *pidx once per launch.
@@ -147,7 +155,9 @@ hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream);
 // per-tile FP64 partial sums of the observables over stage tiles of shape `shape`
 template <typename T>
 hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);
-hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream);
+// mres_stage != 0: the last magnetic residual partials came from stage 1 (one per stage
+// tile), else from a magnetic launch (one per magnetic tile)
+hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream, int mres_stage = 0);
 template <typename T>
 hipError_t launch_init_fields(const DevInst* insts, const Tile* tiles, int ntiles, int kind,
                               double c_init, double t_init, double cx, double cy, double r,

@@ -295,6 +295,188 @@ __device__ __forceinline__ int xcd_tile(int bid, int n)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// ------------------------------------------------------------- magnetics
+
+// Region of a temporally blocked red-black block: an MTX x MTY tile plus a halo of H
+// cells, the potential split by colour (cell (lx, ly) of colour c at
+// ph[c][ly * RXH + lx / 2]).
+template <int MTX, int MTY, int H_>
+struct MagGeom {
+    static constexpr int H = H_;
+    static constexpr int RX = MTX + 2 * H, RY = MTY + 2 * H, NR = RX * RY;
+    static constexpr int RXH = RX / 2, HALF = NR / 2;
+    static_assert(RX % 2 == 0, "region rows hold whole red-black pairs");
+};
+
+// Permeability (Eq. 2 with Eq. 11) of the tile at (x0, y0) plus a halo of H cells, then
+// nsweeps red-black sweeps of the compact magnetic system done in LDS (temporal
+// blocking: the region where the sweeps are exact shrinks by one cell per colour pass,
+// so cells at least 2 nsweeps from the region edge are exact), and optionally the FP64
+// residual of the tile's cells (returned as this thread's share). The final potential
+// stays in ph. Each cell update is the same arithmetic as an untiled red-black pass, so
+// the result does not depend on the tiling or on which kernel runs the block.
+//
+// Update of cell c: phi'_c <- (1-w) phi'_c + w sum_f a_f (phi'_nb + phi0_nb - phi0_c) / sum_f a_f,
+// a_f = mean(mu) on interior faces, 2 mu_c towards a fixed-potential wall half a cell
+// away (where phi' = 0), no term at an insulating wall; phi0 = -(h0x x + h0y y).
+//
+// Each thread owns fixed cells of both colours and keeps their face weights, constant
+// term and 1 / sum of weights in registers; a pass costs four LDS reads and one write
+// per cell, and reads only the other colour's array (contiguous, conflict free).
+template <typename T, int MTX, int MTY, int NT, int H>
+__device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, int pin, int nsweeps, double omega,
+                                            int residual, T (*ph)[MagGeom<MTX, MTY, H>::HALF], T* mu)
+{
+    using G = MagGeom<MTX, MTY, H>;
+    constexpr int NIT = (G::NR + NT - 1) / NT;       // region cells per thread (load)
+    constexpr int NOWN = (G::HALF + NT - 1) / NT;    // owned cells per thread and colour
+    const Coef<T>& K = coef<T>(I);
+    const int tid = threadIdx.x;
+    const int nx = I.nx, ny = I.ny;
+    const int ox = x0 - G::H, oy = y0 - G::H;
+    const int par0 = (ox + oy) & 1;                  // colour of region cell (0, 0)
+    const GLOBAL T* phin = gp<T>(I.phi[pin]);
+    const GLOBAL T* He_ = gp<T>(I.W[0]);
+    const GLOBAL T* C_ = gp<T>(I.W[4]);
+    // 1. load the region (all loads of this thread in flight together): permeability in
+    //    natural layout (0 outside the domain), potential by colour
+    {
+        T vHe[NIT], vC[NIT], vph[NIT];
+        bool vin[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            const int gx = ox + r % G::RX, gy = oy + r / G::RX;
+            int sx = gx, sy = gy;
+            bool in = r < G::NR;
+            // a periodic axis may be shorter than the halo: wrap as often as needed
+            if (gx < 0 || gx >= nx) {
+                if (I.per_x) sx = ((gx % nx) + nx) % nx;
+                else in = false;
+            }
+            if (gy < 0 || gy >= ny) {
+                if (I.per_y) sy = ((gy % ny) + ny) % ny;
+                else in = false;
+            }
+            in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+            vin[it] = in;
+            const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
+            vHe[it] = He_[o];
+            vC[it] = C_[o];
+            vph[it] = phin[o];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int r = tid + it * NT;
+            if (r >= G::NR) break;
+            const int lx = r % G::RX, ly = r / G::RX;
+            T m = T(0);
+            if (vin[it]) {
+                T Tt, Fl;
+                enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
+                const T ct = clamp01(vC[it]);
+                m = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+            }
+            mu[r] = m;
+            ph[(par0 + lx + ly) & 1][ly * G::RXH + (lx >> 1)] = vin[it] ? vph[it] : T(0);
+        }
+    }
+    __syncthreads();
+    // 2. owned cells: item q = c * NOWN + j is the (tid + j * NT)-th cell of colour c.
+    //    Face weights (mean permeability of two domain cells; a fixed-potential wall half
+    //    a cell away has weight 2 mu_c, an insulating wall none), the constant part of the
+    //    numerator and 1 / sum of the weights; rd = 0 marks a cell that is not updated
+    //    (region ring 0 or outside the domain).
+    const T hx = K.h0x * K.dx, hy = K.h0y * K.dx;
+    T wq[2 * NOWN][4], bq[2 * NOWN], rq[2 * NOWN], pq[2 * NOWN];
+    int iq[2 * NOWN], sq[2 * NOWN];   // own index in ph[c], row start of the other colour + shift
+#pragma unroll
+    for (int q = 0; q < 2 * NOWN; q++) {
+        const int c = q / NOWN, k = tid + (q % NOWN) * NT;
+        rq[q] = T(0);
+        bq[q] = T(0);
+        pq[q] = T(0);
+        iq[q] = 0;
+        sq[q] = 0;
+#pragma unroll
+        for (int d = 0; d < 4; d++) wq[q][d] = T(0);
+        if (k >= G::HALF) continue;
+        const int ly = k / G::RXH, kx = k % G::RXH;
+        const int sh = (par0 + ly + c) & 1;           // lx = 2 kx + sh
+        const int lx = 2 * kx + sh;
+        iq[q] = k;
+        sq[q] = ly * G::RXH + kx + sh;                 // east neighbour; west is one less
+        pq[q] = ph[c][k];
+        if (lx < 1 || lx >= G::RX - 1 || ly < 1 || ly >= G::RY - 1) continue;
+        const int r = ly * G::RX + lx;
+        const T muc = mu[r];
+        if (!(muc > T(0))) continue;
+        const T mnb[4] = {mu[r - 1], mu[r + 1], mu[r - G::RX], mu[r + G::RX]};   // W, E, S, N
+        const T D0[4] = {hx, -hx, hy, -hy};   // phi0_nb - phi0_c across each face
+        T bsum = T(0), den = T(0);
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const bool nb_in = mnb[d] > T(0);
+            // (same operand order as the mean over the face from its west / south cell)
+            const T w = nb_in ? (d == 0 || d == 2 ? T(0.5) * (mnb[d] + muc) : T(0.5) * (muc + mnb[d])) : T(0);
+            wq[q][d] = w;
+            if (w > T(0)) {
+                bsum += w * D0[d];
+                den += w;
+            } else if (!nb_in && I.mbc[d]) {   // a wall face
+                const T ww = T(2) * muc;
+                bsum += ww * (T(0.5) * D0[d]);
+                den += ww;
+            }
+        }
+        bq[q] = bsum;
+        rq[q] = den > T(0) ? T(1) / den : T(0);
+    }
+    // 3. red-black sweeps: a colour pass reads the other colour's array and writes its
+    //    own (the colour is a compile-time constant, so the owned-cell registers are
+    //    never indexed dynamically)
+    const T om = T(omega);
+    auto colour_pass = [&](auto colour) {
+        constexpr int c = decltype(colour)::value;
+        const T* po = ph[c ^ 1];
+#pragma unroll
+        for (int j = 0; j < NOWN; j++) {
+            constexpr int q0 = c * NOWN;
+            const int q = q0 + j;
+            if (rq[q] == T(0)) continue;
+            const int e = sq[q], k = iq[q];
+            const T num = bq[q] + wq[q][0] * po[e - 1] + wq[q][1] * po[e] + wq[q][2] * po[k - G::RXH] +
+                          wq[q][3] * po[k + G::RXH];
+            pq[q] = (T(1) - om) * pq[q] + om * num * rq[q];
+            ph[c][k] = pq[q];
+        }
+        __syncthreads();
+    };
+    for (int sw = 0; sw < nsweeps; sw++) {
+        colour_pass(std::integral_constant<int, 0>{});
+        colour_pass(std::integral_constant<int, 1>{});
+    }
+    // 4. FP64 residual r_c = sum_f a_f (phi_nb - phi_c) over the owned cells of the tile
+    double r2 = 0.0;
+    if (residual) {
+#pragma unroll
+        for (int q = 0; q < 2 * NOWN; q++) {
+            if (rq[q] == T(0)) continue;
+            const int c = q / NOWN, k = iq[q];
+            const int ly = k / G::RXH, lx = 2 * (k % G::RXH) + ((par0 + ly + c) & 1);
+            const int tx = lx - G::H, ty = ly - G::H;
+            if (tx < 0 || tx >= MTX || ty < 0 || ty >= MTY || x0 + tx >= nx || y0 + ty >= ny) continue;
+            const T* po = ph[c ^ 1];
+            const int e = sq[q];
+            const double res = double(bq[q]) + double(wq[q][0]) * double(po[e - 1]) +
+                               double(wq[q][1]) * double(po[e]) + double(wq[q][2]) * double(po[k - G::RXH]) +
+                               double(wq[q][3]) * double(po[k + G::RXH]) - double(pq[q]) / double(rq[q]);
+            r2 += res * res;
+        }
+    }
+    return r2;
+}
+
 // ------------------------------------------------------------- stage kernel
 
 enum { Q_P = 0, Q_U, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_MU, Q_LAM, Q_CP, Q_PHI, NQ };
@@ -418,7 +600,7 @@ __device__ __forceinline__ bool res_is_max(int k)
 // Fixed-order FP64 reduction of an instance's tile partials (and the magnetic
 // residual partials) into I.result; NT threads of one workgroup.
 template <int NT>
-__device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, double (*red)[NT / 64])
+__device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, double (*red)[NT / 64], int mres_stage)
 {
     double acc[NRES] = {};
     for (int t = tid; t < I.ntile_stage; t += NT) {
@@ -437,7 +619,8 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
         acc[RES_MYY] += p[PART_MYY];
         acc[RES_MXY] += p[PART_MXY];
     }
-    for (int t = tid; t < I.ntile_mag; t += NT) acc[RES_MAGR2] += I.mpart[t];
+    const int nm = mres_stage ? I.ntile_stage : I.ntile_mag;
+    for (int t = tid; t < nm; t += NT) acc[RES_MAGR2] += I.mpart[t];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NRES; k++) {
@@ -455,12 +638,13 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
 
 // NT >= every per-tile work count (halo cells, gradient cells, faces), so each phase
 // is one round; the first TX*TY threads own the tile's cells.
-template <typename T, int TX, int TY, int NT, int STAGE, int EARLY>
+template <typename T, int TX, int TY, int NT, int STAGE, int EARLY, int FUSE>
 __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
-                                              const Tile* __restrict__ tiles, int pidx)
+                                              const Tile* __restrict__ tiles, int pidx, int nsweeps, double omega)
 {
     using L = StageLds<T, TX, TY, NT>;
     static_assert(NT % 64 == 0 && NT >= TX * TY, "whole waves, one thread per cell at least");
+    static_assert(!FUSE || STAGE == 1, "the magnetic phase fuses into stage 1");
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
@@ -485,6 +669,45 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     const bool inside = tid < TX * TY && gx < nx && gy < ny;
     const size_t o = inside ? (size_t)gy * pitch + gx : 0;
     constexpr bool early = EARLY && STAGE <= 1;
+
+    // ---- M (FUSE): the step's magnetic phase for this tile: red-black sweeps of the tile
+    //      plus a halo of 2*MAG_KMAX+3 cells in LDS (the arithmetic of k_mag_fused, so
+    //      the potential is the same bit for bit, and exact on tile + 3), written to the
+    //      other potential buffer with this tile's FP64 residual partial; phase A takes
+    //      the potential from LDS. The block lives in the storage of the face-phase
+    //      arrays, which phases C and D fill only after A.
+    constexpr int HM = 2 * MAG_KMAX + 3;
+    using GM = MagGeom<TX, TY, HM>;
+    T (*const mph)[GM::HALF] = reinterpret_cast<T (*)[GM::HALF]>(&s.g[0][0][0]);
+    const int mpar0 = (x0 - HM + y0 - HM) & 1;
+    auto mphi = [&](int px, int py) {   // potential of grid cell (px, py) from the block
+        int lxm = px - x0 + HM, lym = py - y0 + HM;
+        lxm = lxm < 0 ? 0 : (lxm >= GM::RX ? GM::RX - 1 : lxm);
+        lym = lym < 0 ? 0 : (lym >= GM::RY ? GM::RY - 1 : lym);
+        return mph[(mpar0 + lxm + lym) & 1][lym * GM::RXH + (lxm >> 1)];
+    };
+    if constexpr (FUSE) {
+        static_assert(sizeof(T) * (2 * GM::HALF + GM::NR) <=
+                          sizeof(s.g) + sizeof(s.h2) + sizeof(s.fx) + sizeof(s.fy),
+                      "the magnetic block fits in the face-phase arrays");
+        __shared__ double mred[NT / 64];
+        T* const mmu = &mph[0][0] + 2 * GM::HALF;
+        const double r2 = mag_block<T, TX, TY, NT, HM>(I, x0, y0, pidx, nsweeps, omega, 1, mph, mmu);
+        GLOBAL T* phout = gp<T>(I.phi[pidx ^ 1]);
+        for (int c = tid; c < TX * TY; c += NT) {
+            const int tx = c % TX, ty = c / TX;
+            if (x0 + tx >= nx || y0 + ty >= ny) continue;
+            phout[(size_t)(y0 + ty) * pitch + (x0 + tx)] = mphi(x0 + tx, y0 + ty);
+        }
+        const double w = wave_sum(r2);
+        if (tid % 64 == 0) mred[tid / 64] = w;
+        __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int k = 0; k < NT / 64; k++) acc += mred[k];
+            I.mpart[tile.idx] = acc;
+        }
+    }
     T cWin[5], cWb[5], cS = T(0);
     auto load_own = [&] {
 #pragma unroll
@@ -523,7 +746,8 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             const size_t oh = (size_t)(y0 - 3 + rr / L::RX) * pitch + (x0 - 3 + rr % L::RX);
 #pragma unroll
             for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
-            vph[it] = phi[oh];
+            if constexpr (FUSE) vph[it] = mphi(x0 - 3 + rr % L::RX, y0 - 3 + rr / L::RX);
+            else vph[it] = phi[oh];
         }
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
@@ -549,7 +773,10 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             const size_t oh = (size_t)sy * pitch + sx;
 #pragma unroll
             for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
-            vph[it] = phi[oh];
+            // (the block holds periodic images in place and zeros beyond walls: a wall
+            // ghost reads its mirror cell)
+            if constexpr (FUSE) vph[it] = mphi(wx >= 0 ? sx : hx, wy >= 0 ? sy : hy);
+            else vph[it] = phi[oh];
         }
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
@@ -779,30 +1006,37 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     }
 }
 
+// stage 4 is stage 1 with the magnetic phase fused in front of it
 template <typename T, int TX, int TY, int NT, int EARLY>
-hipError_t launch_stage_shape(int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                              hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_stage_shape(int stage, int pidx, int nsw, double om, const DevInst* insts, const Tile* tiles,
+                              int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(ntiles), block(NT);
     switch (stage) {
-    case 0: return launch_timed(k_stage<T, TX, TY, NT, 0, EARLY>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    case 1: return launch_timed(k_stage<T, TX, TY, NT, 1, EARLY>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    case 2: return launch_timed(k_stage<T, TX, TY, NT, 2, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
-    default: return launch_timed(k_stage<T, TX, TY, NT, 3, 0>, grid, block, stream, e0, e1, insts, tiles, pidx);
+    case 0:
+        return launch_timed(k_stage<T, TX, TY, NT, 0, EARLY, 0>, grid, block, stream, e0, e1, insts, tiles, pidx, nsw, om);
+    case 1:
+        return launch_timed(k_stage<T, TX, TY, NT, 1, EARLY, 0>, grid, block, stream, e0, e1, insts, tiles, pidx, nsw, om);
+    case 2:
+        return launch_timed(k_stage<T, TX, TY, NT, 2, 0, 0>, grid, block, stream, e0, e1, insts, tiles, pidx, nsw, om);
+    case 3:
+        return launch_timed(k_stage<T, TX, TY, NT, 3, 0, 0>, grid, block, stream, e0, e1, insts, tiles, pidx, nsw, om);
+    default:
+        return launch_timed(k_stage<T, TX, TY, NT, 1, EARLY, 1>, grid, block, stream, e0, e1, insts, tiles, pidx, nsw, om);
     }
 }
 
 // dispatch a run-time shape index to the kernel instantiated for that table entry
 template <typename T, int K>
-hipError_t launch_stage_idx(int shape, int stage, int pidx, const DevInst* insts, const Tile* tiles, int ntiles,
-                            hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_stage_idx(int shape, int stage, int pidx, int nsw, double om, const DevInst* insts,
+                            const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     if constexpr (K < NSTAGE_SHAPES) {
         constexpr TileShape S = stage_shape(sizeof(T) == 8, K);
         if (shape == K)
-            return launch_stage_shape<T, S.tx, S.ty, S.nt, S.early>(stage, pidx, insts, tiles, ntiles, stream, e0,
-                                                                    e1);
-        return launch_stage_idx<T, K + 1>(shape, stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+            return launch_stage_shape<T, S.tx, S.ty, S.nt, S.early>(stage, pidx, nsw, om, insts, tiles, ntiles,
+                                                                    stream, e0, e1);
+        return launch_stage_idx<T, K + 1>(shape, stage, pidx, nsw, om, insts, tiles, ntiles, stream, e0, e1);
     } else {
         return hipErrorInvalidValue;
     }
@@ -813,7 +1047,17 @@ hipError_t launch_stage(int shape, int stage, int pidx, const DevInst* insts, co
                         hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
 {
     if (ntiles <= 0) return hipSuccess;
-    return launch_stage_idx<T, 0>(shape, stage, pidx, insts, tiles, ntiles, stream, e0, e1);
+    if (stage < 0 || stage > 3) return hipErrorInvalidValue;
+    return launch_stage_idx<T, 0>(shape, stage, pidx, 0, 1.0, insts, tiles, ntiles, stream, e0, e1);
+}
+
+template <typename T>
+hipError_t launch_stage_fused(int shape, int pidx, int nsweeps, double omega, const DevInst* insts,
+                              const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (nsweeps < 0 || nsweeps > MAG_KMAX) return hipErrorInvalidValue;
+    return launch_stage_idx<T, 0>(shape, 4, pidx, nsweeps, omega, insts, tiles, ntiles, stream, e0, e1);
 }
 
 template <typename T>
@@ -849,7 +1093,7 @@ hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* ti
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------- magnetics
+// ------------------------------------------------------------- magnetic kernels
 
 // Fused magnetic phase on one tile of MTX x MTY cells: permeability (Eq. 2 with
 // Eq. 11) of the tile plus a halo of 2*MAG_KMAX+1 cells, up to MAG_KMAX red-black
@@ -910,12 +1154,9 @@ hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream)
 
 template <typename T, int MTX, int MTY>
 struct MagLds {
-    static constexpr int H = 2 * MAG_KMAX + 1;
-    static constexpr int RX = MTX + 2 * H, RY = MTY + 2 * H, NR = RX * RY;
-    static constexpr int RXH = RX / 2, HALF = NR / 2;
-    static_assert(RX % 2 == 0, "region rows hold whole red-black pairs");
-    T ph[2][HALF];   // potential by colour
-    T mu[NR];        // permeability, natural layout (set-up only); 0 outside the domain
+    using G = MagGeom<MTX, MTY, 2 * MAG_KMAX + 1>;
+    T ph[2][G::HALF];   // potential by colour
+    T mu[G::NR];        // permeability, natural layout (set-up only); 0 outside the domain
     double red[16];
 };
 
@@ -925,9 +1166,8 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
                                                   int residual, int pin, int gate)
 {
     using L = MagLds<T, MTX, MTY>;
+    using G = typename L::G;
     static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
-    constexpr int NIT = (L::NR + NT - 1) / NT;       // region cells per thread (load)
-    constexpr int NOWN = (L::HALF + NT - 1) / NT;    // owned cells per thread and colour
     __shared__ L s;
     const Tile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const DevInst& I = insts[tile.inst];
@@ -935,166 +1175,24 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
         copy_tile<T, MTX, MTY, NT>(I, tile, pin);
         return;
     }
-    const Coef<T>& K = coef<T>(I);
-    const int tid = threadIdx.x;
-    const int nx = I.nx, ny = I.ny;
-    const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
-    const int par0 = (ox + oy) & 1;                  // colour of region cell (0, 0)
-    const GLOBAL T* phin = gp<T>(I.phi[pin]);
-    const GLOBAL T* He_ = gp<T>(I.W[0]);
-    const GLOBAL T* C_ = gp<T>(I.W[4]);
-    // 1. load the region (all loads of this thread in flight together): permeability in
-    //    natural layout (0 outside the domain), potential by colour
-    {
-        T vHe[NIT], vC[NIT], vph[NIT];
-        bool vin[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            const int r = tid + it * NT;
-            const int gx = ox + r % L::RX, gy = oy + r / L::RX;
-            int sx = gx, sy = gy;
-            bool in = r < L::NR;
-            // a periodic axis may be shorter than the halo: wrap as often as needed
-            if (gx < 0 || gx >= nx) {
-                if (I.per_x) sx = ((gx % nx) + nx) % nx;
-                else in = false;
-            }
-            if (gy < 0 || gy >= ny) {
-                if (I.per_y) sy = ((gy % ny) + ny) % ny;
-                else in = false;
-            }
-            in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
-            vin[it] = in;
-            const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
-            vHe[it] = He_[o];
-            vC[it] = C_[o];
-            vph[it] = phin[o];
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            const int r = tid + it * NT;
-            if (r >= L::NR) break;
-            const int lx = r % L::RX, ly = r / L::RX;
-            T mu = T(0);
-            if (vin[it]) {
-                T Tt, Fl;
-                enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
-                const T ct = clamp01(vC[it]);
-                mu = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
-            }
-            s.mu[r] = mu;
-            s.ph[(par0 + lx + ly) & 1][ly * L::RXH + (lx >> 1)] = vin[it] ? vph[it] : T(0);
-        }
-    }
-    __syncthreads();
-    // 2. owned cells: item q = c * NOWN + j is the (tid + j * NT)-th cell of colour c.
-    //    Face weights (mean permeability of two domain cells; a fixed-potential wall half
-    //    a cell away has weight 2 mu_c, an insulating wall none), the constant part of the
-    //    numerator and 1 / sum of the weights; rd = 0 marks a cell that is not updated
-    //    (region ring 0 or outside the domain).
-    const T hx = K.h0x * K.dx, hy = K.h0y * K.dx;
-    T wq[2 * NOWN][4], bq[2 * NOWN], rq[2 * NOWN], pq[2 * NOWN];
-    int iq[2 * NOWN], sq[2 * NOWN];   // own index in ph[c], row start of the other colour + shift
-#pragma unroll
-    for (int q = 0; q < 2 * NOWN; q++) {
-        const int c = q / NOWN, k = tid + (q % NOWN) * NT;
-        rq[q] = T(0);
-        bq[q] = T(0);
-        pq[q] = T(0);
-        iq[q] = 0;
-        sq[q] = 0;
-#pragma unroll
-        for (int d = 0; d < 4; d++) wq[q][d] = T(0);
-        if (k >= L::HALF) continue;
-        const int ly = k / L::RXH, kx = k % L::RXH;
-        const int sh = (par0 + ly + c) & 1;           // lx = 2 kx + sh
-        const int lx = 2 * kx + sh;
-        iq[q] = k;
-        sq[q] = ly * L::RXH + kx + sh;                 // east neighbour; west is one less
-        pq[q] = s.ph[c][k];
-        if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
-        const int r = ly * L::RX + lx;
-        const T muc = s.mu[r];
-        if (!(muc > T(0))) continue;
-        const T mnb[4] = {s.mu[r - 1], s.mu[r + 1], s.mu[r - L::RX], s.mu[r + L::RX]};   // W, E, S, N
-        const T D0[4] = {hx, -hx, hy, -hy};   // phi0_nb - phi0_c across each face
-        T bsum = T(0), den = T(0);
-#pragma unroll
-        for (int d = 0; d < 4; d++) {
-            const bool nb_in = mnb[d] > T(0);
-            // (same operand order as the mean over the face from its west / south cell)
-            const T w = nb_in ? (d == 0 || d == 2 ? T(0.5) * (mnb[d] + muc) : T(0.5) * (muc + mnb[d])) : T(0);
-            wq[q][d] = w;
-            if (w > T(0)) {
-                bsum += w * D0[d];
-                den += w;
-            } else if (!nb_in && I.mbc[d]) {   // a wall face
-                const T ww = T(2) * muc;
-                bsum += ww * (T(0.5) * D0[d]);
-                den += ww;
-            }
-        }
-        bq[q] = bsum;
-        rq[q] = den > T(0) ? T(1) / den : T(0);
-    }
-    // 3. red-black sweeps: a colour pass reads the other colour's array and writes its
-    //    own (the colour is a compile-time constant, so the owned-cell registers are
-    //    never indexed dynamically)
-    const T om = T(omega);
-    auto colour_pass = [&](auto colour) {
-        constexpr int c = decltype(colour)::value;
-        const T* po = s.ph[c ^ 1];
-#pragma unroll
-        for (int j = 0; j < NOWN; j++) {
-            constexpr int q0 = c * NOWN;
-            const int q = q0 + j;
-            if (rq[q] == T(0)) continue;
-            const int e = sq[q], k = iq[q];
-            const T num = bq[q] + wq[q][0] * po[e - 1] + wq[q][1] * po[e] + wq[q][2] * po[k - L::RXH] +
-                          wq[q][3] * po[k + L::RXH];
-            pq[q] = (T(1) - om) * pq[q] + om * num * rq[q];
-            s.ph[c][k] = pq[q];
-        }
-        __syncthreads();
-    };
-    for (int sw = 0; sw < nsweeps; sw++) {
-        colour_pass(std::integral_constant<int, 0>{});
-        colour_pass(std::integral_constant<int, 1>{});
-    }
-    // 4. FP64 residual r_c = sum_f a_f (phi_nb - phi_c) over the owned cells of the tile
-    double r2 = 0.0;
-    if (residual) {
-#pragma unroll
-        for (int q = 0; q < 2 * NOWN; q++) {
-            if (rq[q] == T(0)) continue;
-            const int c = q / NOWN, k = iq[q];
-            const int ly = k / L::RXH, lx = 2 * (k % L::RXH) + ((par0 + ly + c) & 1);
-            const int tx = lx - L::H, ty = ly - L::H;
-            if (tx < 0 || tx >= MTX || ty < 0 || ty >= MTY || tile.x0 + tx >= nx || tile.y0 + ty >= ny) continue;
-            const T* po = s.ph[c ^ 1];
-            const int e = sq[q];
-            const double res = double(bq[q]) + double(wq[q][0]) * double(po[e - 1]) +
-                               double(wq[q][1]) * double(po[e]) + double(wq[q][2]) * double(po[k - L::RXH]) +
-                               double(wq[q][3]) * double(po[k + L::RXH]) - double(pq[q]) / double(rq[q]);
-            r2 += res * res;
-        }
-    }
-    // 5. write the tile in natural order (coalesced)
+    const double r2 = mag_block<T, MTX, MTY, NT, G::H>(I, tile.x0, tile.y0, pin, nsweeps, omega, residual, s.ph, s.mu);
+    // write the tile in natural order (coalesced)
     GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
-    for (int cidx = tid; cidx < MTX * MTY; cidx += NT) {
+    const int par0 = (tile.x0 - G::H + tile.y0 - G::H) & 1;
+    for (int cidx = threadIdx.x; cidx < MTX * MTY; cidx += NT) {
         const int tx = cidx % MTX, ty = cidx / MTX;
         const int gx = tile.x0 + tx, gy = tile.y0 + ty;
-        if (gx >= nx || gy >= ny) continue;
-        const int lx = tx + L::H, ly = ty + L::H;
-        phout[(size_t)gy * I.pitch + gx] = s.ph[(par0 + lx + ly) & 1][ly * L::RXH + (lx >> 1)];
+        if (gx >= I.nx || gy >= I.ny) continue;
+        const int lx = tx + G::H, ly = ty + G::H;
+        phout[(size_t)gy * I.pitch + gx] = s.ph[(par0 + lx + ly) & 1][ly * G::RXH + (lx >> 1)];
     }
     if (residual) {
-        r2 = wave_sum(r2);
-        if (tid % 64 == 0) s.red[tid / 64] = r2;
+        const double w = wave_sum(r2);
+        if (threadIdx.x % 64 == 0) s.red[threadIdx.x / 64] = w;
         __syncthreads();
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             double acc = 0.0;
-            for (int w = 0; w < NT / 64; w++) acc += s.red[w];
+            for (int k = 0; k < NT / 64; k++) acc += s.red[k];
             I.mpart[tile.idx] = acc;
         }
     }
@@ -1378,16 +1476,16 @@ hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* p
 
 // ------------------------------------------------------------- reduction
 
-__global__ __launch_bounds__(256) void k_reduce(const DevInst* __restrict__ insts)
+__global__ __launch_bounds__(256) void k_reduce(const DevInst* __restrict__ insts, int mres_stage)
 {
     __shared__ double red[NRES][4];
-    instance_reduce<256>(insts[blockIdx.x], threadIdx.x, red);
+    instance_reduce<256>(insts[blockIdx.x], threadIdx.x, red, mres_stage);
 }
 
-hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream)
+hipError_t launch_reduce(const DevInst* insts, int ninst, hipStream_t stream, int mres_stage)
 {
     if (ninst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(ninst), dim3(256), 0, stream, insts);
+    hipLaunchKernelGGL(k_reduce, dim3(ninst), dim3(256), 0, stream, insts, mres_stage);
     return hipGetLastError();
 }
 
@@ -1495,6 +1593,8 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
 #define LBFS_INSTANTIATE(T)                                                                          \
     template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t, hipEvent_t, \
                                         hipEvent_t);                                                   \
+    template hipError_t launch_stage_fused<T>(int, int, int, double, const DevInst*, const Tile*, int, hipStream_t, \
+                                              hipEvent_t, hipEvent_t);                                 \
     template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
                                       hipEvent_t, hipEvent_t, int);                                    \
     template hipError_t launch_mag_lbfs<T>(int, int, int, int*, const DevInst*, const Tile*, int, hipStream_t, \

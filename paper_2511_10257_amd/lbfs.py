@@ -230,15 +230,36 @@ def tile_shapes(kind: str, precision: str = "fp32") -> list:
     return out
 
 
+def mag_fused_index(precision: str = "fp32") -> int:
+    """The magnetic "shape" index that runs the step's sweeps inside stage 1."""
+    return len(tile_shapes("mag", precision))
+
+
 def shape_name(shape: tuple) -> str:
-    """'TXxTY/threads', with an 'e' for the early owned-cell loads of the first stages."""
+    """'TXxTY/threads', with an 'e' for the early owned-cell loads of the first stages;
+    'in-stage-1' for the sweeps run inside stage 1."""
+    if shape[3] & 2:
+        return "in-stage-1"
     return f"{shape[0]}x{shape[1]}/{shape[2]}" + ("e" if shape[3] & 1 else "")
+
+
+def mag_shape(index: int, precision: str = "fp32") -> tuple:
+    """(tx, ty, threads, flags) of a magnetic shape index, the fused index included."""
+    k = 1
+    prec = LBFS_FP64 if precision == "fp64" else LBFS_FP32
+    tx, ty, nt, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().lbfs_tile_shape(k, prec, int(index), C.byref(tx), C.byref(ty), C.byref(nt), C.byref(fl)),
+           "lbfs_tile_shape")
+    return (tx.value, ty.value, nt.value, fl.value)
 
 
 def _tune_result(chosen, ms, precision: str) -> dict:
     ns, nm = len(tile_shapes("stage", precision)), len(tile_shapes("mag", precision))
-    return {"stage_shape": chosen[0], "mag_shape": chosen[1],
-            "stage_ms": [ms[k] for k in range(ns)], "mag_ms": [ms[MAX_SHAPES + k] for k in range(nm)]}
+    out = {"stage_shape": chosen[0], "mag_shape": chosen[1],
+           "stage_ms": [ms[k] for k in range(ns)], "mag_ms": [ms[MAX_SHAPES + k] for k in range(nm)]}
+    if ms[MAX_SHAPES + nm] != 0.0:
+        out["fused_sweeps_added_ms"] = ms[MAX_SHAPES + nm]
+    return out
 
 
 def state_bytes(prob_or_params) -> int:

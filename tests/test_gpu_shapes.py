@@ -104,3 +104,52 @@ def test_magnetic_sweeps_on_a_periodic_axis_shorter_than_the_halo(axis):
     ro, rg = o.mag_sweeps(4, 1.0), g.mag_sweeps(4, 1.0)
     assert abs(rg - ro) <= 1e-9 * ro
     assert np.max(np.abs(g.get("phi") - o.get("phi"))) <= 1e-12 * np.max(np.abs(o.get("phi")))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant", ["droplet", "periodic_x", "insulating_wetting", "tiny_periodic"])
+def test_sweeps_inside_stage_one_give_the_same_fields(precision, variant):
+    """The magnetic "shape" that runs the step's sweeps inside stage 1 (no magnetic
+    launch) computes every field bit for bit as the separate magnetic kernel does, with
+    graphs and without, for every stage shape; the residual observable is the same sum in
+    another order."""
+    prob = _prob(precision)
+    if variant == "periodic_x":
+        prob.update(periodic=[1, 0], angle_deg=90.0, nx=78)
+    elif variant == "insulating_wetting":
+        prob.update(mag_bc=["insulating", "insulating", "fixed", "fixed"], angle_deg=90.0,
+                    contact_angle=[70.0, 110.0, 60.0, 90.0])
+    elif variant == "tiny_periodic":
+        prob = wl.droplet_problem(6, 2.0, ste=0.1, bo_m=1.0, angle_deg=90.0, precision=precision, ny=30)
+        prob.update(periodic=[1, 0])
+    fused = lbfs.mag_fused_index(precision)
+    ref = lbfs.Solver(prob)
+    ref.step(9)
+    want, want_obs = _fields(ref), ref.observe()
+    for si in range(len(lbfs.tile_shapes("stage", precision))):
+        s = lbfs.Solver(prob)
+        s.set_tile_shapes(si, fused)
+        assert s.tile_shapes_in_use() == (si, fused)
+        s.step(9)
+        got = _fields(s)
+        for f in FIELDS:
+            assert np.array_equal(got[f], want[f]), (variant, si, f)
+        obs = s.observe()
+        for k in ("liquid_fraction", "volume", "umax", "solid_ratio"):
+            assert obs[k] == pytest.approx(want_obs[k], rel=1e-12, abs=1e-300), (si, k)
+        assert obs["mag_residual"] == pytest.approx(want_obs["mag_residual"], rel=1e-9)
+        kern = s.step_profiled(4, 2)
+        assert kern["mag"][1] == 0 and kern["stage1"][1] == 2
+        s.close()
+
+
+def test_sweeps_inside_stage_one_need_a_fixed_small_count():
+    base = _prob("fp32")
+    fused = lbfs.mag_fused_index()
+    for kw in (dict(mag_method="lbfs"), dict(sweeps=5), dict(mag_max_iters=40, mag_tol=1e-6)):
+        s = lbfs.Solver(wl.with_changes(base, **kw))
+        with pytest.raises(lbfs.LbfsError) as ei:
+            s.set_tile_shapes(0, fused)
+        assert ei.value.status == lbfs.LBFS_E_INVAL
+        s.close()
+    assert lbfs.shape_name(lbfs.mag_shape(fused)) == "in-stage-1"
