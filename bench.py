@@ -98,9 +98,9 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-chunk", type=int, default=200, help="steps between observations")
     ap.add_argument("--no-serve-baseline", action="store_true")
-    ap.add_argument("--mag-method", choices=["sweeps", "lbfs"], default="sweeps",
-                    help="per-step magnetic update of the single-solve workloads: red-black sweeps or "
-                         "the LBFS pseudo-time solve (Eq. 17)")
+    ap.add_argument("--mag-method", choices=["sweeps", "lbfs", "multigrid"], default="sweeps",
+                    help="per-step magnetic update of the single-solve workloads: red-black sweeps, "
+                         "the LBFS pseudo-time solve (Eq. 17) or multigrid V-cycles (--mag-steps of them)")
     ap.add_argument("--mag-steps", type=int, default=None,
                     help="sweeps or pseudo-steps per time step (default: the workload's)")
     ap.add_argument("--mag-in-stage1", choices=["auto", "on", "off"], default="auto",
@@ -201,10 +201,12 @@ def error_vs_oracle(solver, prob: dict) -> dict:
 
 
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict, mag_flops=None,
-             mag_launches: int = 1) -> dict:
+             mag_launches: int = 1, exclude=()) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step. The magnetic
-    phase streams its fields once per launch (mag_launches per step)."""
-    share = {k: kern[k][0] for k in kern}
+    phase streams its fields once per launch (mag_launches per step). Kinds in `exclude`
+    (a multigrid magnetic phase, many small launches with no algorithmic count) are not
+    candidates."""
+    share = {k: kern[k][0] for k in kern if k not in exclude}
     dominant = max(share, key=share.get)
     esize = 8 if precision == "fp64" else 4
     accesses = dict(FIELD_ACCESSES, mag=FIELD_ACCESSES["mag"] * mag_launches)
@@ -298,7 +300,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
                 "sweeps_per_step": prob["sweeps"], "reductions": "f64",
                 "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default")})
     profile_key = args.workload + ("-mag-lbfs" if args.mag_method == "lbfs" else "")
-    out["roofline"] = roofline(kern, cells, prob["precision"], profile_key, shapes, mag_flops, mag_launches)
+    out["roofline"] = roofline(kern, cells, prob["precision"], profile_key, shapes, mag_flops, mag_launches,
+                               exclude=("mag",) if args.mag_method == "multigrid" else ())
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned

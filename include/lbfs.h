@@ -57,7 +57,7 @@ enum { LBFS_MBC_INSULATING = 0, LBFS_MBC_FIXED = 1 };    /* magnetic wall condit
                                                             fixed = potential of the
                                                             applied uniform field  */
 enum { LBFS_INIT_DROPLET = 0, LBFS_INIT_UNIFORM = 1 };
-enum { LBFS_MAG_SWEEPS = 0, LBFS_MAG_LBFS = 1 };          /* per-step magnetic update */
+enum { LBFS_MAG_SWEEPS = 0, LBFS_MAG_LBFS = 1, LBFS_MAG_MULTIGRID = 2 };   /* per-step magnetic update */
 
 /* Problem statement (plain data, copied at init). Phase-indexed arrays are
    [solid, liquid, gas]; Eq. 11 mixes them with the solid fraction Fs and the
@@ -100,7 +100,10 @@ typedef struct lbfs_params {
        advances Eq. 17 in pseudo-time by SSP-RK3, the paper's own procedure (Table 1
        (b)-(c)), with the face flux -D mu_f (phi_R - phi_L) / dx that the m* moments of
        Eqs. 13, 16 and 44 reduce to at delta_t = dx/2. Only D * dtau matters. */
-    int32_t mag_method;       /* LBFS_MAG_*                                         */
+    int32_t mag_method;       /* LBFS_MAG_*; LBFS_MAG_MULTIGRID (not in the paper) runs
+                                 `sweeps` geometric multigrid V(2,2) cycles of the same
+                                 compact system per step (walls on every side, no
+                                 convergence control; the initial solve uses cycles too) */
     double mag_lbfs_d;        /* D of tau_m = 1/2 + mu D / (cs^2 delta_t), > 0 (also
                                  checked when the sweeps are the per-step method)    */
     double mag_lbfs_dtau;     /* pseudo-time step; 0: dx^2 / (4 D mu_max), mu_max =
@@ -216,6 +219,15 @@ int lbfs_mag_sweeps(lbfs_solver* s, int32_t nsweeps, double omega, double* resid
    method, on the permeability of the current state; *residual receives ||r||_2
    afterwards. LBFS_E_STATE on a borrowed batch handle. Synchronous. */
 int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual);
+
+/* Run ncycles geometric multigrid V(2,2) cycles of the compact magnetic system (the
+   fixed point of the sweeps and of the LBFS pseudo-time solve; not in the paper) on the
+   current state: 2 x 2 cell coarsening down to 32 cells a side, mean face weights,
+   the sum of the children's residuals, the correction interpolated bilinearly, the
+   coarsest level by red-black SOR in one workgroup. *residual receives ||r||_2
+   afterwards. Needs walls on every side (LBFS_E_INVAL on a periodic axis);
+   LBFS_E_STATE on a borrowed batch handle. Synchronous. */
+int lbfs_mag_multigrid(lbfs_solver* s, int32_t ncycles, double* residual);
 
 /* Local heat flux Q = -lambda (dT/dy) at the south wall (Sec. 5.2, Fig. 15) of the
    current state, one value per column into host_q (n = nx): the second-order one-sided

@@ -88,7 +88,11 @@ int validate(const lbfs_params* p)
     }
     if (p->sweeps < 0 || p->sweeps > 1000) return LBFS_E_INVAL;
     if (!(p->sor_omega > 0.0 && p->sor_omega < 2.0)) return LBFS_E_INVAL;
-    if (p->mag_method != LBFS_MAG_SWEEPS && p->mag_method != LBFS_MAG_LBFS) return LBFS_E_INVAL;
+    if (p->mag_method != LBFS_MAG_SWEEPS && p->mag_method != LBFS_MAG_LBFS && p->mag_method != LBFS_MAG_MULTIGRID)
+        return LBFS_E_INVAL;
+    // multigrid: walls on every side, a fixed number of cycles per step
+    if (p->mag_method == LBFS_MAG_MULTIGRID && (p->periodic[0] || p->periodic[1] || p->mag_max_iters != 0))
+        return LBFS_E_INVAL;
     if (!finite_pos(p->mag_lbfs_d) || !std::isfinite(p->mag_lbfs_dtau) || p->mag_lbfs_dtau < 0.0)
         return LBFS_E_INVAL;
     if (p->mag_max_iters < 0 || p->mag_max_iters > 100000) return LBFS_E_INVAL;
@@ -146,6 +150,22 @@ Layout make_layout(const lbfs_params* p)
     return L;
 }
 
+// Geometric multigrid of one instance's magnetic system: level sizes and the element
+// offsets of each level's arrays in a scratch region (the stage fields, free between
+// steps). Level 0 solves for the potential itself (in its double buffer); its permeability
+// is staged in its right-hand-side array while the face weights are formed.
+struct MgCtx {
+    int L = 0;                                   // levels; L - 1 is the coarsest
+    int nx[24] = {}, ny[24] = {};
+    size_t u[24] = {}, f[24] = {}, wx[24] = {}, wy[24] = {};
+    char* scratch = nullptr;                     // base of the offsets
+    void* phi[2] = {nullptr, nullptr};           // level-0 unknown, by potential parity
+    int pitch = 0;                               // of the level-0 unknown
+};
+
+// V(2,2) cycles with the coarsest level by red-black SOR in one workgroup
+constexpr int MG_PRE = 2, MG_POST = 2, MG_COARSE_SWEEPS = 40;
+
 // The launches of one time step over a set of tile lists (one instance for a solver,
 // the concatenated tiles of every live instance for a batch), with the potential
 // buffer parity and the captured graphs of one step per parity.
@@ -157,6 +177,7 @@ struct Exec {
     int mag_method = LBFS_MAG_SWEEPS;
     int mag_chunks = 1;                  // chunks of `sweeps` per step (convergence control)
     bool fused = false;                  // the sweeps run inside stage 1 (no magnetic launch)
+    const MgCtx* mg = nullptr;           // multigrid plan (solvers whose method is multigrid)
     bool mres_stage = false;             // the last residual partials are per stage tile
     hipStream_t stream = nullptr;
     const DevInst* dinst = nullptr;
@@ -192,6 +213,58 @@ hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual, hipEvent_t e0, hipEv
 
 hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual) { return exec_mag_lbfs(E, nsteps, residual, E.ev0, E.ev1, 0); }
 
+template <typename T>
+hipError_t mg_run(const Exec& E, const MgCtx& M, int ncycles, hipEvent_t e0)
+{
+    T* B = reinterpret_cast<T*>(M.scratch);
+    T* u0 = static_cast<T*>(M.phi[E.phase]);
+    auto U = [&](int l) { return l == 0 ? u0 : B + M.u[l]; };
+    auto P = [&](int l) { return l == 0 ? M.pitch : M.nx[l]; };
+    hipError_t e = launch_mg_setup0<T>(E.dinst, M.nx[0], M.ny[0], B + M.f[0], B + M.wx[0], B + M.wy[0], B + M.f[0],
+                                       E.stream, e0);
+    for (int l = 0; l + 1 < M.L && e == hipSuccess; l++)
+        e = launch_mg_coarsen<T>(M.nx[l], M.ny[l], B + M.wx[l], B + M.wy[l], M.nx[l + 1], M.ny[l + 1],
+                                 B + M.wx[l + 1], B + M.wy[l + 1], E.stream);
+    const int c = M.L - 1;
+    const int nmax = std::max(M.nx[c], M.ny[c]);
+    const double om = 2.0 / (1.0 + std::sin(M_PI / std::max(nmax, 2)));
+    for (int k = 0; k < ncycles && e == hipSuccess; k++) {
+        for (int l = 0; l < c && e == hipSuccess; l++) {
+            e = launch_mg_smooth<T>(M.nx[l], M.ny[l], P(l), U(l), B + M.f[l], B + M.wx[l], B + M.wy[l], MG_PRE,
+                                    E.stream);
+            if (e == hipSuccess)
+                e = launch_mg_restrict<T>(M.nx[l], M.ny[l], P(l), U(l), B + M.f[l], B + M.wx[l], B + M.wy[l],
+                                          M.nx[l + 1], M.ny[l + 1], B + M.f[l + 1], B + M.u[l + 1], E.stream);
+        }
+        if (e == hipSuccess)
+            e = launch_mg_coarsest<T>(M.nx[c], M.ny[c], P(c), U(c), B + M.f[c], B + M.wx[c], B + M.wy[c],
+                                      MG_COARSE_SWEEPS, om, E.stream);
+        for (int l = c - 1; l >= 0 && e == hipSuccess; l--) {
+            e = launch_mg_prolong<T>(M.nx[l], M.ny[l], P(l), U(l), M.nx[l + 1], M.ny[l + 1], U(l + 1), E.stream);
+            if (e == hipSuccess)
+                e = launch_mg_smooth<T>(M.nx[l], M.ny[l], P(l), U(l), B + M.f[l], B + M.wx[l], B + M.wy[l], MG_POST,
+                                        E.stream);
+        }
+    }
+    return e;
+}
+
+// ncycles multigrid cycles on the current potential (in place), then the residual
+// partials by a sweep-free magnetic launch (which flips the potential buffer); the
+// timing events bracket the first and the last launch
+hipError_t exec_mg(Exec& E, int ncycles, int residual)
+{
+    if (!E.mg) return hipErrorInvalidValue;
+    const hipEvent_t e0 = E.ev0;
+    hipError_t e = E.f64 ? mg_run<double>(E, *E.mg, ncycles, e0) : mg_run<float>(E, *E.mg, ncycles, e0);
+    if (e == hipSuccess && residual) {
+        E.ev0 = nullptr;
+        e = exec_mag(E, 0, 1.0, 1);
+        E.ev0 = e0;
+    }
+    return e;
+}
+
 // The magnetic phase of a time step, by the instance's method, with the residual. With
 // convergence control it is mag_chunks chunks of `sweeps` iterations; after the first,
 // each chunk is gated by the convergence flag of the chunk before it, so a converged
@@ -202,6 +275,7 @@ hipError_t exec_mag_step(Exec& E)
 {
     hipError_t e = hipSuccess;
     E.mres_stage = false;
+    if (E.mag_method == LBFS_MAG_MULTIGRID) return exec_mg(E, E.sweeps, 1);
     for (int c = 0; c < E.mag_chunks && e == hipSuccess; c++) {
         const hipEvent_t a = c == 0 ? E.ev0 : nullptr, b = c == E.mag_chunks - 1 ? E.ev1 : nullptr;
         const int gate = c > 0;
@@ -295,7 +369,7 @@ hipError_t exec_ensure_graph(Exec& E, int ph)
 // potential-buffer flips of one step (one per magnetic launch)
 int exec_step_flips(const Exec& E)
 {
-    if (E.fused) return 1;
+    if (E.fused || E.mag_method == LBFS_MAG_MULTIGRID) return 1;   // (the residual launch)
     const int kmax = E.mag_method == LBFS_MAG_LBFS ? RK_KMAX : MAG_KMAX;
     const int launches = E.sweeps == 0 ? 1 : (E.sweeps + kmax - 1) / kmax;
     return (launches * E.mag_chunks) & 1;
@@ -475,6 +549,7 @@ struct lbfs_solver {
     int64_t step = 0;
     double vol0 = 0.0;
     bool stepped_since_observe = false;
+    MgCtx mg;                            // multigrid plan (built on first use)
     void* field(int k) const { return base + L.off_fields + L.field_bytes * (size_t)k; }
     bool f64() const { return p.precision == LBFS_FP64; }
 };
@@ -497,6 +572,45 @@ static bool hip_failed(hipError_t e, const char* expr, int line)
     } while (0)
 
 namespace {
+
+// Multigrid plan of a solver: levels halve each side (rounding up) down to at most
+// MG_COARSE cells a side; the arrays of every level live in the ten stage fields.
+int mg_plan(lbfs_solver* s)
+{
+    if (s->mg.L > 0) return LBFS_OK;
+    if (s->p.periodic[0] || s->p.periodic[1]) return LBFS_E_INVAL;
+    MgCtx& M = s->mg;
+    const size_t es = s->L.esize;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t o = off;
+        off += (n + 63) / 64 * 64;   // 256-byte aligned in FP32
+        return o;
+    };
+    int nx = s->p.nx, ny = s->p.ny;
+    int L = 0;
+    while (true) {
+        if (L >= 24) return LBFS_E_INVAL;
+        M.nx[L] = nx;
+        M.ny[L] = ny;
+        M.wx[L] = take((size_t)(nx + 1) * ny);
+        M.wy[L] = take((size_t)nx * (ny + 1));
+        M.f[L] = take((size_t)nx * ny);
+        M.u[L] = L == 0 ? 0 : take((size_t)nx * ny);
+        L++;
+        if (std::max(nx, ny) <= MG_COARSE) break;
+        nx = (nx + 1) / 2;
+        ny = (ny + 1) / 2;
+    }
+    if (off * es > 10 * s->L.field_bytes) return LBFS_E_NOMEM;   // (never for grids of 4 x 4 and up)
+    M.L = L;
+    M.scratch = static_cast<char*>(s->field(5));
+    M.phi[0] = s->field(15);
+    M.phi[1] = s->field(17);
+    M.pitch = s->L.pitch;
+    s->E.mg = &s->mg;
+    return LBFS_OK;
+}
 
 // residual of the magnetic system of the current state, synchronously
 int mag_residual_now(lbfs_solver* s, double* out)
@@ -794,6 +908,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
                                     p->drop_cx, p->drop_cy, p->drop_radius, s->stream);
     if (e != hipSuccess) return fail(LBFS_E_DEVICE);
 
+    if (p->mag_method == LBFS_MAG_MULTIGRID && mg_plan(s) != LBFS_OK) return fail(LBFS_E_INVAL);
     // converge the magnetic potential (Table 1, before the main loop)
     double r0 = 0.0;
     if (mag_residual_now(s, &r0) != LBFS_OK) return fail(LBFS_E_DEVICE);
@@ -807,7 +922,12 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     while (r0 > 0.0 && used < p->init_max && r > p->init_tol * r0) {
         int k = s->p.init_check;
         if (used + k > p->init_max) k = p->init_max - used;
-        if (exec_mag(E, k, om, 0) != hipSuccess) return fail(LBFS_E_DEVICE);
+        if (p->mag_method == LBFS_MAG_MULTIGRID) {
+            // one cycle per check (init_max still counts sweeps: a cycle counts as init_check)
+            if (exec_mg(E, 1, 0) != hipSuccess) return fail(LBFS_E_DEVICE);
+        } else if (exec_mag(E, k, om, 0) != hipSuccess) {
+            return fail(LBFS_E_DEVICE);
+        }
         used += k;
         const double r_prev = r;
         if (mag_residual_now(s, &r) != LBFS_OK) return fail(LBFS_E_DEVICE);
@@ -905,6 +1025,22 @@ int lbfs_mag_pseudo_steps(lbfs_solver* s, int32_t nsteps, double* residual)
     double r = 0.0;
     const int rc = mag_residual_now(s, &r);
     if (rc != LBFS_OK) return rc;
+    if (residual) *residual = r;
+    return LBFS_OK;
+}
+
+int lbfs_mag_multigrid(lbfs_solver* s, int32_t ncycles, double* residual)
+{
+    if (!s) return LBFS_E_STATE;
+    if (s->batched) return LBFS_E_STATE;
+    if (ncycles < 0 || ncycles > 10000) return LBFS_E_INVAL;
+    const int rc = mg_plan(s);
+    if (rc != LBFS_OK) return rc;
+    exec_drop_graphs(s->E);   // (a plan built now changes no captured step; kept simple)
+    HIPCHK(exec_mg(s->E, ncycles, 0));
+    double r = 0.0;
+    const int rr = mag_residual_now(s, &r);
+    if (rr != LBFS_OK) return rr;
     if (residual) *residual = r;
     return LBFS_OK;
 }

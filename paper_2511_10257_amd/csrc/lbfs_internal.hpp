@@ -152,6 +152,27 @@ hipError_t launch_mag_lbfs(int shape, int nsteps, int residual, int* pidx, const
 // convergence flag of each instance: 1 when the residual of its last magnetic launch
 // is at most mag_tol (one workgroup per instance)
 hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream);
+// geometric multigrid for the compact magnetic system (lbfs_kernels.hip, one instance):
+// the coarsest level has at most MG_COARSE x MG_COARSE cells and is solved in the LDS of
+// one workgroup
+constexpr int MG_COARSE = 32;
+template <typename T>
+hipError_t launch_mg_setup0(const DevInst* insts, int nx, int ny, T* mu_tmp, T* wx, T* wy, T* f, hipStream_t stream,
+                            hipEvent_t e0 = nullptr);
+template <typename T>
+hipError_t launch_mg_coarsen(int nxf, int nyf, const T* wxf, const T* wyf, int nxc, int nyc, T* wxc, T* wyc,
+                             hipStream_t stream);
+template <typename T>
+hipError_t launch_mg_smooth(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
+                            hipStream_t stream);
+template <typename T>
+hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T* ff, const T* wxf, const T* wyf,
+                              int nxc, int nyc, T* fc, T* uc, hipStream_t stream);
+template <typename T>
+hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, hipStream_t stream);
+template <typename T>
+hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
+                              double omega, hipStream_t stream);
 // per-tile FP64 partial sums of the observables over stage tiles of shape `shape`
 template <typename T>
 hipError_t launch_state_partials(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream);

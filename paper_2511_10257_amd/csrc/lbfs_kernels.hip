@@ -14,6 +14,7 @@
 //   k_mag_lbfs              the same phase by the magnetic LBFS pseudo-time solve
 //                           (Eq. 17, SSP-RK3 steps temporally blocked in LDS).
 //   k_reduce                fixed-order FP64 reduction of the partials per instance.
+//   k_mg_*                  geometric multigrid for the compact magnetic system.
 //   k_init_fields, k_derived, k_wall_profile (local wall heat flux, Sec. 5.2)
 //
 // The path is a stencil: a few hundred flops per face over ~70 bytes per cell and
@@ -824,10 +825,10 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     }
     __syncthreads();
     // wall ghosts take the chemical potential of their mirror cell (no flux of C through
-    // a wall: d(mu_c)/dn = 0), whatever the order parameter's ghosts hold (a wetting
-    // wall's ghosts are not mirrors). A mirror cell is never a wall ghost, so one pass
-    // reads only cells it does not write.
-    if (!interior) {
+    // a wall: d(mu_c)/dn = 0) when a wetting wall's ghosts are not mirrors of the order
+    // parameter (otherwise the ghost values computed above are that mirror already). A
+    // mirror cell is never a wall ghost, so one pass reads only cells it does not write.
+    if (!interior && (K.wet[0] != T(0) || K.wet[1] != T(0) || K.wet[2] != T(0) || K.wet[3] != T(0))) {
         for (int r = tid; r < L::NR; r += NT) {
             const int lx = r % L::RX, ly = r / L::RX;
             if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
@@ -1590,6 +1591,283 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------- multigrid
+
+// Geometric multigrid for the compact magnetic system A u = f of one instance (not in
+// the paper; the same fixed point as the sweeps, reached in fewer launches when the
+// residual has to fall far). (A u)_c = sum over the cell's faces of w_f (u_c - u_nb),
+// a wall face with its weight (2 mu_c at a fixed-potential wall, 0 at an insulating
+// one) and u = 0 beyond it. Level 0 is the potential phi' itself with
+// f = sum_f w_f (phi0_nb - phi0_c) (the constant term of the sweeps); a coarse level
+// merges 2 x 2 cells (a last odd row or column maps to one cell), its face weight is
+// the mean of the fine faces it covers, its right-hand side the sum of the children's
+// residuals, and its correction is interpolated back to the children. Arrays: cells row-major
+// with a pitch, x-face weights wx[j (nx+1) + i] (face i between cells i-1 and i),
+// y-face weights wy[j nx + i] (face j between rows j-1 and j). One thread per cell or
+// face; non-periodic domains.
+
+// permeability of the level-0 cells (Eq. 2 with Eq. 11)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_mu0(const DevInst* __restrict__ insts, T* __restrict__ mu)
+{
+    const DevInst& I = insts[0];
+    const int c = blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= I.nx * I.ny) return;
+    const int i = c % I.nx, j = c / I.nx;
+    const size_t o = (size_t)j * I.pitch + i;
+    const Coef<T>& K = coef<T>(I);
+    const T C = gp<T>(I.W[4])[o];
+    T Tt, Fl;
+    enthalpy_state<T>(K, gp<T>(I.W[0])[o], C, Tt, Fl);
+    const T ct = clamp01(C);
+    mu[c] = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+}
+
+// level-0 face weights from the permeability: the mean of two cells, 2 mu_c towards a
+// fixed-potential wall, 0 at an insulating one
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_faces0(const DevInst* __restrict__ insts, const T* __restrict__ mu,
+                                                   T* __restrict__ wx, T* __restrict__ wy)
+{
+    const DevInst& I = insts[0];
+    const int nx = I.nx, ny = I.ny;
+    const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+    const int f = blockIdx.x * 256 + (int)threadIdx.x;
+    if (f < nfx) {
+        const int i = f % (nx + 1), j = f / (nx + 1);
+        T w;
+        if (i == 0) w = I.mbc[0] ? T(2) * mu[j * nx] : T(0);
+        else if (i == nx) w = I.mbc[1] ? T(2) * mu[j * nx + nx - 1] : T(0);
+        else w = T(0.5) * (mu[j * nx + i - 1] + mu[j * nx + i]);
+        wx[f] = w;
+    } else if (f < nfx + nfy) {
+        const int g = f - nfx;
+        const int i = g % nx, j = g / nx;
+        T w;
+        if (j == 0) w = I.mbc[2] ? T(2) * mu[i] : T(0);
+        else if (j == ny) w = I.mbc[3] ? T(2) * mu[(ny - 1) * nx + i] : T(0);
+        else w = T(0.5) * (mu[(j - 1) * nx + i] + mu[j * nx + i]);
+        wy[g] = w;
+    }
+}
+
+// level-0 right-hand side: the applied-field potential differences across each face
+// (half of them across a wall face)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_rhs0(const DevInst* __restrict__ insts, const T* __restrict__ wx,
+                                                 const T* __restrict__ wy, T* __restrict__ f)
+{
+    const DevInst& I = insts[0];
+    const int nx = I.nx, ny = I.ny;
+    const int c = blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= nx * ny) return;
+    const int i = c % nx, j = c / nx;
+    const Coef<T>& K = coef<T>(I);
+    const T hx = K.h0x * K.dx, hy = K.h0y * K.dx;
+    const T ww = wx[j * (nx + 1) + i], we = wx[j * (nx + 1) + i + 1];
+    const T ws = wy[j * nx + i], wn = wy[(j + 1) * nx + i];
+    f[c] = ww * (i == 0 ? T(0.5) * hx : hx) - we * (i == nx - 1 ? T(0.5) * hx : hx) +
+           ws * (j == 0 ? T(0.5) * hy : hy) - wn * (j == ny - 1 ? T(0.5) * hy : hy);
+}
+
+// coarse face weights: the mean of the one or two fine faces a coarse face covers
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_coarsen(int nxf, int nyf, const T* __restrict__ wxf,
+                                                    const T* __restrict__ wyf, int nxc, int nyc, T* __restrict__ wxc,
+                                                    T* __restrict__ wyc)
+{
+    const int nfx = (nxc + 1) * nyc, nfy = nxc * (nyc + 1);
+    const int f = blockIdx.x * 256 + (int)threadIdx.x;
+    if (f < nfx) {
+        const int I = f % (nxc + 1), J = f / (nxc + 1);
+        const int fi = min(2 * I, nxf);
+        T w = wxf[(2 * J) * (nxf + 1) + fi];
+        if (2 * J + 1 < nyf) w = T(0.5) * (w + wxf[(2 * J + 1) * (nxf + 1) + fi]);
+        wxc[f] = w;
+    } else if (f < nfx + nfy) {
+        const int g = f - nfx;
+        const int I = g % nxc, J = g / nxc;
+        const int fj = min(2 * J, nyf);
+        T w = wyf[fj * nxf + 2 * I];
+        if (2 * I + 1 < nxf) w = T(0.5) * (w + wyf[fj * nxf + 2 * I + 1]);
+        wyc[g] = w;
+    }
+}
+
+// (A u)_c and the sum of the cell's face weights
+template <typename T>
+__device__ __forceinline__ void mg_apply(int nx, int ny, int pitch, const T* u, const T* wx, const T* wy, int i,
+                                         int j, T& au, T& den, T& nbsum)
+{
+    const T ww = wx[j * (nx + 1) + i], we = wx[j * (nx + 1) + i + 1];
+    const T ws = wy[j * nx + i], wn = wy[(j + 1) * nx + i];
+    const T uw = i > 0 ? u[(size_t)j * pitch + i - 1] : T(0);
+    const T ue = i < nx - 1 ? u[(size_t)j * pitch + i + 1] : T(0);
+    const T us = j > 0 ? u[(size_t)(j - 1) * pitch + i] : T(0);
+    const T un = j < ny - 1 ? u[(size_t)(j + 1) * pitch + i] : T(0);
+    den = ww + we + ws + wn;
+    nbsum = ww * uw + we * ue + ws * us + wn * un;
+    au = den * u[(size_t)j * pitch + i] - nbsum;
+}
+
+// one red-black Gauss-Seidel colour pass, in place
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_smooth(int nx, int ny, int pitch, T* __restrict__ u,
+                                                   const T* __restrict__ f, const T* __restrict__ wx,
+                                                   const T* __restrict__ wy, int colour)
+{
+    // thread k takes the k-th cell of the colour in row-major order
+    const int k = blockIdx.x * 256 + (int)threadIdx.x;
+    const int half = (nx + 1) / 2;
+    const int j = k / half;
+    if (j >= ny) return;
+    const int i = 2 * (k % half) + ((j + colour) & 1);
+    if (i >= nx) return;
+    T au, den, nbsum;
+    mg_apply<T>(nx, ny, pitch, u, wx, wy, i, j, au, den, nbsum);
+    if (den > T(0)) u[(size_t)j * pitch + i] = (f[j * nx + i] + nbsum) / den;
+}
+
+// coarse right-hand side (sum of the children's residuals) and a zero coarse correction
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_restrict(int nxf, int nyf, int pitchf, const T* __restrict__ uf,
+                                                     const T* __restrict__ ff, const T* __restrict__ wxf,
+                                                     const T* __restrict__ wyf, int nxc, int nyc, T* __restrict__ fc,
+                                                     T* __restrict__ uc)
+{
+    const int c = blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= nxc * nyc) return;
+    const int I = c % nxc, J = c / nxc;
+    T r = T(0);
+    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 2; a++) {
+            const int i = 2 * I + a, j = 2 * J + b;
+            if (i >= nxf || j >= nyf) continue;
+            T au, den, nbsum;
+            mg_apply<T>(nxf, nyf, pitchf, uf, wxf, wyf, i, j, au, den, nbsum);
+            r += ff[j * nxf + i] - au;
+        }
+    fc[c] = r;
+    uc[c] = T(0);
+}
+
+// add the coarse correction to every child, interpolated bilinearly from the four
+// nearest coarse cells (9/16 its own, 3/16 each side neighbour, 1/16 the diagonal; a
+// neighbour beyond the domain repeats the cell)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_prolong(int nxf, int nyf, int pitchf, T* __restrict__ uf, int nxc,
+                                                    int nyc, const T* __restrict__ uc)
+{
+    const int c = blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= nxf * nyf) return;
+    const int i = c % nxf, j = c / nxf;
+    const int I = i / 2, J = j / 2;
+    int In = I + ((i & 1) ? 1 : -1), Jn = J + ((j & 1) ? 1 : -1);
+    In = In < 0 || In >= nxc ? I : In;
+    Jn = Jn < 0 || Jn >= nyc ? J : Jn;
+    const T v = T(9.0 / 16.0) * uc[J * nxc + I] + T(3.0 / 16.0) * (uc[J * nxc + In] + uc[Jn * nxc + I]) +
+                T(1.0 / 16.0) * uc[Jn * nxc + In];
+    uf[(size_t)j * pitchf + i] += v;
+}
+
+// the coarsest level (at most MG_COARSE x MG_COARSE cells) solved by red-black SOR in
+// the LDS of one workgroup
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mg_coarsest(int nx, int ny, int pitch, T* __restrict__ u,
+                                                      const T* __restrict__ f, const T* __restrict__ wx,
+                                                      const T* __restrict__ wy, int sweeps, double omega)
+{
+    constexpr int N = MG_COARSE * MG_COARSE;
+    __shared__ T su[N];
+    const int c = threadIdx.x;
+    const bool mine = c < nx * ny;
+    const int i = mine ? c % nx : 0, j = mine ? c / nx : 0;
+    T ww = T(0), we = T(0), ws = T(0), wn = T(0), fc = T(0), rd = T(0);
+    if (mine) {
+        ww = wx[j * (nx + 1) + i];
+        we = wx[j * (nx + 1) + i + 1];
+        ws = wy[j * nx + i];
+        wn = wy[(j + 1) * nx + i];
+        fc = f[j * nx + i];
+        const T den = ww + we + ws + wn;
+        rd = den > T(0) ? T(1) / den : T(0);
+        su[c] = u[(size_t)j * pitch + i];
+    }
+    __syncthreads();
+    const T om = T(omega);
+    for (int sw = 0; sw < 2 * sweeps; sw++) {
+        if (mine && ((i + j) & 1) == (sw & 1) && rd > T(0)) {
+            const T nb = (i > 0 ? ww * su[c - 1] : T(0)) + (i < nx - 1 ? we * su[c + 1] : T(0)) +
+                         (j > 0 ? ws * su[c - nx] : T(0)) + (j < ny - 1 ? wn * su[c + nx] : T(0));
+            su[c] = (T(1) - om) * su[c] + om * (fc + nb) * rd;
+        }
+        __syncthreads();
+    }
+    if (mine) u[(size_t)j * pitch + i] = su[c];
+}
+
+template <typename T>
+hipError_t launch_mg_setup0(const DevInst* insts, int nx, int ny, T* mu_tmp, T* wx, T* wy, T* f, hipStream_t stream,
+                            hipEvent_t e0)
+{
+    const int n = nx * ny, nf = (nx + 1) * ny + nx * (ny + 1);
+    const hipError_t e = launch_timed(k_mg_mu0<T>, dim3((n + 255) / 256), dim3(256), stream, e0, nullptr, insts, mu_tmp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mg_faces0<T>), dim3((nf + 255) / 256), dim3(256), 0, stream, insts, mu_tmp, wx, wy);
+    hipLaunchKernelGGL((k_mg_rhs0<T>), dim3((n + 255) / 256), dim3(256), 0, stream, insts, wx, wy, f);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_coarsen(int nxf, int nyf, const T* wxf, const T* wyf, int nxc, int nyc, T* wxc, T* wyc,
+                             hipStream_t stream)
+{
+    const int nf = (nxc + 1) * nyc + nxc * (nyc + 1);
+    hipLaunchKernelGGL((k_mg_coarsen<T>), dim3((nf + 255) / 256), dim3(256), 0, stream, nxf, nyf, wxf, wyf, nxc, nyc,
+                       wxc, wyc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_smooth(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
+                            hipStream_t stream)
+{
+    const int per_colour = ((nx + 1) / 2) * ny;
+    for (int k = 0; k < 2 * sweeps; k++)
+        hipLaunchKernelGGL((k_mg_smooth<T>), dim3((per_colour + 255) / 256), dim3(256), 0, stream, nx, ny, pitch, u,
+                           f, wx, wy, k & 1);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T* ff, const T* wxf, const T* wyf,
+                              int nxc, int nyc, T* fc, T* uc, hipStream_t stream)
+{
+    const int n = nxc * nyc;
+    hipLaunchKernelGGL((k_mg_restrict<T>), dim3((n + 255) / 256), dim3(256), 0, stream, nxf, nyf, pitchf, uf, ff, wxf,
+                       wyf, nxc, nyc, fc, uc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, hipStream_t stream)
+{
+    const int n = nxf * nyf;
+    hipLaunchKernelGGL((k_mg_prolong<T>), dim3((n + 255) / 256), dim3(256), 0, stream, nxf, nyf, pitchf, uf, nxc, nyc,
+                       uc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
+                              double omega, hipStream_t stream)
+{
+    if (nx * ny > MG_COARSE * MG_COARSE) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mg_coarsest<T>), dim3(1), dim3(1024), 0, stream, nx, ny, pitch, u, f, wx, wy, sweeps, omega);
+    return hipGetLastError();
+}
+
 #define LBFS_INSTANTIATE(T)                                                                          \
     template hipError_t launch_stage<T>(int, int, int, const DevInst*, const Tile*, int, hipStream_t, hipEvent_t, \
                                         hipEvent_t);                                                   \
@@ -1603,7 +1881,15 @@ hipError_t launch_derived(const DevInst* insts, const Tile* tiles, int ntiles, h
     template hipError_t launch_init_fields<T>(const DevInst*, const Tile*, int, int, double, double, \
                                               double, double, double, hipStream_t);                 \
     template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);                 \
-    template hipError_t launch_wall_profile<T>(const DevInst*, int, double*, hipStream_t);
+    template hipError_t launch_wall_profile<T>(const DevInst*, int, double*, hipStream_t);                \
+    template hipError_t launch_mg_setup0<T>(const DevInst*, int, int, T*, T*, T*, T*, hipStream_t, hipEvent_t); \
+    template hipError_t launch_mg_coarsen<T>(int, int, const T*, const T*, int, int, T*, T*, hipStream_t); \
+    template hipError_t launch_mg_smooth<T>(int, int, int, T*, const T*, const T*, const T*, int, hipStream_t); \
+    template hipError_t launch_mg_restrict<T>(int, int, int, const T*, const T*, const T*, const T*, int, int, T*, T*, \
+                                              hipStream_t);                                            \
+    template hipError_t launch_mg_prolong<T>(int, int, int, T*, int, int, const T*, hipStream_t);       \
+    template hipError_t launch_mg_coarsest<T>(int, int, int, T*, const T*, const T*, const T*, int, double, \
+                                              hipStream_t);
 
 LBFS_INSTANTIATE(float)
 LBFS_INSTANTIATE(double)

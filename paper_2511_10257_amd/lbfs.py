@@ -27,7 +27,7 @@ NKERNELS = len(KERNELS)
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
     "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
-    "lbfs_mag_pseudo_steps", "lbfs_wall_heat_profile", "lbfs_read_field",
+    "lbfs_mag_pseudo_steps", "lbfs_mag_multigrid", "lbfs_wall_heat_profile", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
@@ -106,6 +106,7 @@ def lib():
             "lbfs_rhs": (C.c_int, [vp, dp]),
             "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
             "lbfs_mag_pseudo_steps": (C.c_int, [vp, i32, dp]),
+            "lbfs_mag_multigrid": (C.c_int, [vp, i32, dp]),
             "lbfs_wall_heat_profile": (C.c_int, [vp, dp, C.c_size_t]),
             "lbfs_read_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
             "lbfs_write_field": (C.c_int, [vp, i32, dp, C.c_size_t]),
@@ -153,7 +154,7 @@ def _check(status: int, what: str) -> None:
 
 _TBC = {"adiabatic": 0, "fixed": 1}
 _MBC = {"insulating": 0, "fixed": 1}
-_MAG = {"sweeps": 0, "lbfs": 1}
+_MAG = {"sweeps": 0, "lbfs": 1, "multigrid": 2}
 
 
 def make_params(prob: dict) -> Params:
@@ -382,6 +383,12 @@ class Solver(_Instance):
     def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
         r = C.c_double()
         _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
+        return r.value
+
+    def mag_multigrid(self, n: int) -> float:
+        """n multigrid V(2,2) cycles of the compact magnetic system; returns ||r||_2."""
+        r = C.c_double()
+        _check(lib().lbfs_mag_multigrid(self._h, int(n), C.byref(r)), "lbfs_mag_multigrid")
         return r.value
 
     def mag_pseudo_steps(self, n: int) -> float:

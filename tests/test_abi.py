@@ -52,7 +52,7 @@ def test_state_bytes_and_validation():
     q.abi_version = lbfs.LBFS_ABI_VERSION - 1
     assert lbfs.lib().lbfs_init(C.byref(q), None, 0, None, C.byref(out)) == lbfs.LBFS_E_ABI
     # the magnetic method and its pseudo-time parameters
-    for kw in (dict(mag_method=2), dict(mag_method=1, mag_lbfs_d=0.0), dict(mag_method=1, mag_lbfs_dtau=-1.0),
+    for kw in (dict(mag_method=3), dict(mag_method=1, mag_lbfs_d=0.0), dict(mag_method=1, mag_lbfs_dtau=-1.0),
                dict(mag_method=1, mag_lbfs_d=float("nan")), dict(mag_lbfs_d=-1.0)):
         q = lbfs.make_params(wl.droplet64())
         for k, v in kw.items():
@@ -61,6 +61,15 @@ def test_state_bytes_and_validation():
     q = lbfs.make_params(wl.with_changes(wl.droplet64(), mag_method="lbfs", mag_lbfs_d=2.0, mag_lbfs_dtau=0.05))
     assert (q.mag_method, q.mag_lbfs_d, q.mag_lbfs_dtau) == (1, 2.0, 0.05)
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) > 0
+    # multigrid needs walls on every side and a fixed cycle count
+    for kw in (dict(periodic=[1, 0], field_angle_deg=90.0), dict(mag_max_iters=10, mag_tol=1e-3)):
+        q = lbfs.make_params(wl.with_changes(wl.droplet64(), mag_method="multigrid"))
+        for k, v in kw.items():
+            if k == "periodic":
+                q.periodic[0], q.periodic[1] = v
+            else:
+                setattr(q, k, v)
+        assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0, kw
     q = lbfs.Params()
     assert lbfs.lib().lbfs_params_default(C.byref(q), 64, 64, 0) == 0
     assert (q.mag_method, q.mag_lbfs_d, q.mag_lbfs_dtau) == (0, 1.0, 0.0)

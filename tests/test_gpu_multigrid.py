@@ -1,0 +1,78 @@
+"""Geometric multigrid for the compact magnetic system (not in the paper): the same
+fixed point as the red-black sweeps, reached in a few cycles; against the oracle's
+sweeps iterated to convergence."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2511_10257_amd import lbfs, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def case(nx, ny, seed, precision="fp64", **kw):
+    angle = kw.pop("angle", 60.0)
+    prob = wl.droplet_problem(nx, ny / 4.0, ste=0.1, bo_m=1.5, angle_deg=angle, precision=precision, ny=ny)
+    prob.update(init_max=0, **kw)
+    o = orc.Oracle(prob, init=False)
+    st = wl.smooth_state(nx, ny, seed, latent=o.params.latent, h0=o.params.h0, angle_deg=angle)
+    o.set_state(st)
+    g = lbfs.Solver(prob)
+    g.set_state(st)
+    return prob, o, g
+
+
+def converge_oracle(o):
+    r0 = o.mag_residual()
+    for _ in range(400):
+        if o.mag_sweeps(200, 1.9) < 1e-13 * r0:
+            break
+    return r0
+
+
+@pytest.mark.parametrize("shape", [(150, 70), (64, 64), (33, 17), (20, 24)])
+def test_cycles_converge_to_the_sweeps_fixed_point(shape):
+    prob, o, g = case(*shape, seed=3)
+    r0 = g.mag_sweeps(0)
+    res = [g.mag_multigrid(1) for _ in range(25)]
+    # V(2,2) with mean-weight coarse operators: about a quarter per cycle here
+    assert res[11] < 1e-6 * r0 and res[-1] < 1e-12 * r0, res
+    assert all(b <= a * 1.0001 or b < 1e-13 * r0 for a, b in zip(res, res[1:]))
+    converge_oracle(o)
+    po, pg = o.get("phi"), g.get("phi")
+    assert np.max(np.abs(pg - po)) <= 1e-8 * np.max(np.abs(po))
+
+
+def test_one_cycle_reduces_the_residual_tenfold_on_a_large_grid():
+    prob, _, g = case(512, 512, seed=4, precision="fp32", angle=0.0)
+    r0 = g.mag_sweeps(0)
+    r1 = g.mag_multigrid(1)
+    r2 = g.mag_multigrid(1)
+    assert r1 < 0.1 * r0 and r2 < 0.3 * r1, (r0, r1, r2)
+
+
+@pytest.mark.parametrize("walls", [["fixed"] * 4, ["insulating", "insulating", "fixed", "fixed"]])
+def test_steps_with_the_multigrid_method_match_the_oracle(walls):
+    """Six cycles a step against the oracle's sweeps converged every step."""
+    prob, o, g = case(48, 36, seed=21, mag_bc=walls, angle=90.0)
+    g = lbfs.Solver(wl.with_changes(prob, mag_method="multigrid", sweeps=6))
+    o = orc.Oracle(wl.with_changes(prob, sweeps=200, omega=1.8, mag_max_iters=20000, mag_tol=1e-14), init=False)
+    st = wl.smooth_state(48, 36, 21, latent=o.params.latent, h0=o.params.h0, angle_deg=90.0)
+    o.set_state(st)
+    g.set_state(st)
+    o.step(3)
+    g.step(3)
+    for name in ("phi", "He", "Mx", "C"):
+        x, y = g.get(name), o.get(name)
+        assert np.max(np.abs(x - y)) <= 1e-7 * max(1.0, np.max(np.abs(y))), name
+
+
+def test_multigrid_needs_walls_everywhere():
+    prob = wl.droplet_problem(64, 16.0, ste=0.1, bo_m=0.0, angle_deg=90.0, precision="fp32")
+    with pytest.raises(lbfs.LbfsError) as ei:
+        lbfs.Solver(wl.with_changes(prob, mag_method="multigrid", periodic=[1, 0]))
+    assert ei.value.status == lbfs.LBFS_E_INVAL
+    s = lbfs.Solver(wl.with_changes(prob, periodic=[1, 0]))
+    with pytest.raises(lbfs.LbfsError) as ei:
+        s.mag_multigrid(1)
+    assert ei.value.status == lbfs.LBFS_E_INVAL
