@@ -67,11 +67,13 @@ typedef struct lbfs_params {
     int32_t nx, ny;           /* cells, each >= 4                                   */
     int32_t precision;        /* lbfs_precision                                     */
     double dx;                /* cell size                                          */
-    double dt;                /* Runge-Kutta time step                              */
+    double dt;                /* Runge-Kutta time step; 0: min(dx/2, 0.4 dx^2 / D_max)
+                                 with D_max the largest kinematic viscosity or thermal
+                                 diffusivity of the three phases                     */
     double dt_stream;         /* streaming step delta_t; 0 or dx/2 (only dx/2 is supported) */
     double rho[3], mu[3], cp[3], lambda[3], chi[3];
     double latent;            /* latent heat L (Eq. 7)                              */
-    double t_melt;            /* Ts = Tl = Tm (Eq. 8)                               */
+    double t_melt;            /* solidus Ts (Eq. 8); the melting point Tm of Eq. 50 */
     double t_init;            /* initial temperature                                */
     double mu0;               /* vacuum permeability (Eq. 2)                        */
     double h0;                /* applied field strength                             */
@@ -120,6 +122,7 @@ typedef struct lbfs_params {
        n.grad C = -(4/xi) cos(theta) C (1 - C), n into the fluid, the gradient of the
        equilibrium profile meeting the wall at theta; 90 is the plain mirror. */
     double contact_angle_deg[4];
+    double t_liquidus;        /* liquidus Tl >= t_melt (Eq. 8); Ts = Tl = Tm by default */
 } lbfs_params;
 
 typedef struct lbfs_observables {

@@ -103,14 +103,15 @@ void orc_enthalpy_state(const orc_params* p, double He, double C, double* T, dou
     double ct = clamp01(C);
     double cp_sol = ct * p->cp[0] + (1.0 - ct) * p->cp[2];
     double cp_liq = ct * p->cp[1] + (1.0 - ct) * p->cp[2];
-    double Hes = cp_sol * p->t_melt;                    /* H_es = Cp,s Ts      */
-    double Hel = cp_liq * p->t_melt + ct * p->latent;   /* H_el = Cp,l Tl + L  */
+    double Ts = p->t_melt, Tl = p->t_liquidus;
+    double Hes = cp_sol * Ts;                    /* H_es = Cp,s Ts      */
+    double Hel = cp_liq * Tl + ct * p->latent;   /* H_el = Cp,l Tl + L  */
     if (He > Hel) {
         *Fl = 1.0;
-        *T = p->t_melt + (He - Hel) / cp_liq;
+        *T = Tl + (He - Hel) / cp_liq;
     } else if (He >= Hes && Hel > Hes) {
         *Fl = (He - Hes) / (Hel - Hes);
-        *T = p->t_melt;   /* Ts + Fl (Tl - Ts) with Ts = Tl */
+        *T = Ts + *Fl * (Tl - Ts);
     } else {
         *Fl = 0.0;
         *T = He / cp_sol;
@@ -167,8 +168,9 @@ static double* zalloc(size_t n) { return (double*)calloc(n, sizeof(double)); }
 orc_sim* orc_new(const orc_params* pin)
 {
     const orc_params* p = pin;
-    if (p->nx < 4 || p->ny < 4 || p->dx <= 0 || p->dt <= 0 || p->dt_stream <= 0) return NULL;
+    if (p->nx < 4 || p->ny < 4 || p->dx <= 0 || p->dt < 0 || p->dt_stream <= 0) return NULL;
     if (p->tau_g <= 0.5 || p->xi <= 0) return NULL;
+    if (!(p->t_liquidus >= p->t_melt)) return NULL;
     if (p->mag_method < 0 || p->mag_method > 1) return NULL;
     if (p->mag_method == 1 && !(p->mag_lbfs_d > 0.0)) return NULL;
     if (p->mag_max_iters < 0 || (p->mag_max_iters > 0 && (p->sweeps <= 0 || !(p->mag_tol >= 0.0)))) return NULL;
@@ -176,6 +178,18 @@ orc_sim* orc_new(const orc_params* pin)
         if (!(p->contact_angle[w] > 0.0 && p->contact_angle[w] < 180.0)) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
+    if (s->p.dt == 0.0) {
+        /* automatic step: dx/2 unless the largest kinematic viscosity or thermal
+           diffusivity D needs 0.4 dx^2 / D */
+        double D = 0.0;
+        for (int k = 0; k < 3; k++) {
+            double nu = p->mu[k] / p->rho[k], al = p->lam[k] / (p->rho[k] * p->cp[k]);
+            if (nu > D) D = nu;
+            if (al > D) D = al;
+        }
+        double diff = D > 0.0 ? 0.4 * p->dx * p->dx / D : 0.5 * p->dx;
+        s->p.dt = 0.5 * p->dx < diff ? 0.5 * p->dx : diff;
+    }
     s->nx = p->nx; s->ny = p->ny;
     s->px = p->nx + 2 * G; s->py = p->ny + 2 * G;
     s->cpref = 0.5 * (p->cp[0] + p->cp[1]);        /* Sec. 3.2 */
@@ -767,7 +781,13 @@ int orc_init(orc_sim* s)
             double cp_sol = ct * p->cp[0] + (1.0 - ct) * p->cp[2];
             double cp_liq = ct * p->cp[1] + (1.0 - ct) * p->cp[2];
             /* inverse of Eq. 8 at T_init */
-            double He = p->t_init >= p->t_melt ? cp_liq * p->t_init + ct * p->latent : cp_sol * p->t_init;
+            double Ts = p->t_melt, Tl = p->t_liquidus, He;
+            if (p->t_init >= Tl)
+                He = cp_liq * p->t_init + ct * p->latent;
+            else if (p->t_init >= Ts)   /* only when Ts < Tl */
+                He = cp_sol * Ts + (p->t_init - Ts) / (Tl - Ts) * (cp_liq * Tl + ct * p->latent - cp_sol * Ts);
+            else
+                He = cp_sol * p->t_init;
             s->W[ORC_HE][c] = He;
             s->W[ORC_P][c] = 0.0;
             s->W[ORC_MX][c] = 0.0;

@@ -69,6 +69,7 @@ typedef struct orc_params {
     double mag_tol;       /* absolute target of ||r||_2 for mag_max_iters > 0            */
     double contact_angle[4]; /* wetting walls: contact angle through the liquid (degrees,
                                 0 < theta < 180; 90 is the mirror condition)             */
+    double t_liquidus;    /* Tl >= t_melt (the solidus Ts) of Eq. 8                      */
 } orc_params;
 
 typedef struct orc_obs {

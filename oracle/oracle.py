@@ -38,7 +38,7 @@ class Params(C.Structure):
         ("init_max", C.c_int), ("init_check", C.c_int),
         ("mag_method", C.c_int), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
         ("mag_max_iters", C.c_int), ("mag_tol", C.c_double),
-        ("contact_angle", C.c_double * 4),
+        ("contact_angle", C.c_double * 4), ("t_liquidus", C.c_double),
     ]
 
 
@@ -147,6 +147,7 @@ def make_params(prob: dict) -> Params:
     p.mag_tol = float(prob.get("mag_tol", 0.0))
     for k, a in enumerate(prob.get("contact_angle", [90.0] * 4)):
         p.contact_angle[k] = float(a)
+    p.t_liquidus = float(prob.get("t_liquidus", p.t_melt))
     if "latent" in prob and "h0" in prob:
         p.latent, p.h0 = float(prob["latent"]), float(prob["h0"])
     else:

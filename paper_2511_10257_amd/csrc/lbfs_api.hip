@@ -52,13 +52,27 @@ struct Layout {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// the automatic Runge-Kutta step: half a cell of the streaming speed (dx / 2, the
+// acoustic number cs dt / dx = 0.29) unless a diffusivity needs less (0.4 dx^2 / D_max,
+// D the kinematic viscosity and thermal diffusivity of every phase)
+double auto_dt(const lbfs_params& p)
+{
+    double dmax = 0.0;
+    for (int k = 0; k < 3; k++) {
+        dmax = std::fmax(dmax, p.mu[k] / p.rho[k]);
+        dmax = std::fmax(dmax, p.lambda[k] / (p.rho[k] * p.cp[k]));
+    }
+    const double dtd = dmax > 0.0 ? 0.4 * p.dx * p.dx / dmax : 0.5 * p.dx;
+    return std::fmin(0.5 * p.dx, dtd);
+}
+
 int validate(const lbfs_params* p)
 {
     if (!p) return LBFS_E_INVAL;
     if (p->abi_version != LBFS_ABI_VERSION) return LBFS_E_ABI;
     if (p->nx < 4 || p->ny < 4 || p->nx > (1 << 20) || p->ny > (1 << 20)) return LBFS_E_INVAL;
     if (p->precision != LBFS_FP32 && p->precision != LBFS_FP64) return LBFS_E_INVAL;
-    if (!finite_pos(p->dx) || !finite_pos(p->dt)) return LBFS_E_INVAL;
+    if (!finite_pos(p->dx) || !(p->dt == 0.0 || finite_pos(p->dt))) return LBFS_E_INVAL;   // 0: automatic
     if (p->dt_stream != 0.0 && std::fabs(p->dt_stream - 0.5 * p->dx) > 1e-12 * p->dx) return LBFS_E_INVAL;
     for (int k = 0; k < 3; k++) {
         if (!finite_pos(p->rho[k]) || !finite_pos(p->mu[k]) || !finite_pos(p->cp[k]) ||
@@ -68,6 +82,7 @@ int validate(const lbfs_params* p)
     }
     if (!std::isfinite(p->latent) || p->latent < 0.0) return LBFS_E_INVAL;
     if (!std::isfinite(p->t_melt) || !std::isfinite(p->t_init)) return LBFS_E_INVAL;
+    if (!std::isfinite(p->t_liquidus) || p->t_liquidus < p->t_melt) return LBFS_E_INVAL;
     if (!finite_pos(p->mu0) || !std::isfinite(p->h0) || p->h0 < 0.0) return LBFS_E_INVAL;
     if (!std::isfinite(p->field_angle_deg) || !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]))
         return LBFS_E_INVAL;
@@ -114,7 +129,7 @@ int validate(const lbfs_params* p)
         dmax = std::fmax(dmax, p->mu[k] / p->rho[k]);
         dmax = std::fmax(dmax, p->lambda[k] / (p->rho[k] * p->cp[k]));
     }
-    if (dmax * p->dt / (p->dx * p->dx) > 0.5) return LBFS_E_INVAL;
+    if (dmax * p->dt / (p->dx * p->dx) > 0.5) return LBFS_E_INVAL;   // (an automatic step is within)
     if (std::sqrt(1.0 / 3.0) * p->dt / p->dx > 1.0) return LBFS_E_INVAL;
     return LBFS_OK;
 }
@@ -467,6 +482,7 @@ void fill_coef(Coef<T>& K, const DevInst& I)
     }
     K.latent = T(I.latent);
     K.tm = T(I.tm);
+    K.tl = T(I.tl);
     K.dx = T(I.dx);
     K.dt = T(I.dt);
     K.cpref = T(I.cpref);
@@ -694,6 +710,7 @@ int lbfs_params_default(lbfs_params* p, int32_t nx, int32_t ny, int32_t precisio
     }
     p->latent = 10.0;
     p->t_melt = 0.0;
+    p->t_liquidus = 0.0;
     p->t_init = 0.0;
     p->mu0 = 1.0;
     p->h0 = 0.0;
@@ -799,6 +816,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     lbfs_solver* s = new (std::nothrow) lbfs_solver();
     if (!s) return LBFS_E_NOMEM;
     s->p = *p;
+    if (s->p.dt == 0.0) s->p.dt = auto_dt(*p);
     if (s->p.dt_stream == 0.0) s->p.dt_stream = 0.5 * p->dx;
     if (s->p.init_check == 0) s->p.init_check = 50;
     s->L = L;
@@ -860,8 +878,9 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     }
     I.latent = p->latent;
     I.tm = p->t_melt;
+    I.tl = p->t_liquidus;
     I.dx = p->dx;
-    I.dt = p->dt;
+    I.dt = s->p.dt;
     I.dts = s->p.dt_stream;
     I.cpref = 0.5 * (p->cp[0] + p->cp[1]);
     I.qg = p->mobility / ((p->tau_g - 0.5) * s->p.dt_stream);   // M_c = (tau_g - 1/2) Q_g delta_t

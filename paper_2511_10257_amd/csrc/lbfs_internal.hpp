@@ -69,7 +69,7 @@ struct Coef {
     T rho[3], mu[3], lam[3], cp[3], chi[3];   // [solid, liquid, gas] (Eq. 11)
     T tval[4];                                // fixed wall temperatures
     T wet[4];                                 // (4 / xi) cos(contact angle) per wall, 0 at 90 degrees
-    T latent, tm, dx, dt, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, vc;
+    T latent, tm, tl, dx, dt, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, vc;   // tm, tl: Ts, Tl
     T grav[2];
     T idx;      // 1 / dx
     T inv2dx;   // 1 / (2 dx)
@@ -103,7 +103,7 @@ struct DevInst {
     double tval[4];
     double wet[4];   // (4 / xi) cos(contact angle) per wall (0: mirror)
     double rho[3], mu_[3], lam[3], cp[3], chi[3];
-    double latent, tm, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;
+    double latent, tm, tl, dx, dt, dts, cpref, qg, tau_g, beta, kappa, mu0, h0x, h0y, xi;   // tm, tl: Ts, Tl
     double grav[2];
     double vc;       // 1 - rho_s / rho_l
     double mag_kdt;  // D dtau / dx^2 (magnetic pseudo-time solve)

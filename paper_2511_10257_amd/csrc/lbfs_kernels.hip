@@ -80,17 +80,17 @@ __device__ __forceinline__ float branch_quotient(float num, float den)
 }
 __device__ __forceinline__ double branch_quotient(double num, double den) { return num / den; }
 
-// Eq. 8 with Ts = Tl = Tm, local latent heat Ct L and branch heat capacities of the
-// solid-gas and liquid-gas mixtures
+// Eq. 8 with solidus Ts and liquidus Tl, local latent heat Ct L and branch heat
+// capacities of the solid-gas and liquid-gas mixtures
 template <typename T>
 __device__ __forceinline__ void enthalpy_state(const Coef<T>& K, T He, T C, T& Tt, T& Fl)
 {
     const T ct = clamp01(C);
     const T cps = ct * K.cp[0] + (T(1) - ct) * K.cp[2];
     const T cpl = ct * K.cp[1] + (T(1) - ct) * K.cp[2];
-    const T tm = K.tm;
-    const T Hes = cps * tm;
-    const T Hel = cpl * tm + ct * K.latent;
+    const T ts = K.tm, tl = K.tl;
+    const T Hes = cps * ts;
+    const T Hel = cpl * tl + ct * K.latent;
     // branch of Eq. 8, then the one quotient that branch needs
     const bool liq = He > Hel;
     const bool mushy = !liq && He >= Hes && Hel > Hes;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void enthalpy_state(const Coef<T>& K, T He, T C, T& T
     const T den = liq ? cpl : (mushy ? Hel - Hes : cps);
     const T q = branch_quotient(num, den);
     Fl = liq ? T(1) : (mushy ? clamp01(q) : T(0));
-    Tt = liq ? tm + q : (mushy ? tm : q);
+    Tt = liq ? tl + q : (mushy ? ts + Fl * (tl - ts) : q);
 }
 
 template <typename T>
@@ -1515,7 +1515,11 @@ __global__ __launch_bounds__(PT_TX* PT_TY) void k_init_fields(const DevInst* __r
     const double ct = C < 0.0 ? 0.0 : (C > 1.0 ? 1.0 : C);
     const double cps = ct * I.cp[0] + (1.0 - ct) * I.cp[2];
     const double cpl = ct * I.cp[1] + (1.0 - ct) * I.cp[2];
-    const double He = t_init >= I.tm ? cpl * t_init + ct * I.latent : cps * t_init;
+    // Eq. 8 inverted at T_init (the mushy branch only when Ts < Tl)
+    const double Hes = cps * I.tm, Hel = cpl * I.tl + ct * I.latent;
+    const double He = t_init >= I.tl ? cpl * t_init + ct * I.latent
+                    : t_init >= I.tm ? Hes + (t_init - I.tm) / (I.tl - I.tm) * (Hel - Hes)
+                                     : cps * t_init;
     reinterpret_cast<T*>(I.W[0])[o] = T(He);
     reinterpret_cast<T*>(I.W[1])[o] = T(0);
     reinterpret_cast<T*>(I.W[2])[o] = T(0);

@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("init_check", C.c_int32),
         ("mag_method", C.c_int32), ("mag_lbfs_d", C.c_double), ("mag_lbfs_dtau", C.c_double),
         ("mag_max_iters", C.c_int32), ("mag_tol", C.c_double),
-        ("contact_angle_deg", C.c_double * 4),
+        ("contact_angle_deg", C.c_double * 4), ("t_liquidus", C.c_double),
     ]
 
 
@@ -197,6 +197,7 @@ def make_params(prob: dict) -> Params:
     p.mag_tol = float(prob.get("mag_tol", 0.0))
     for k, a in enumerate(prob.get("contact_angle", [90.0] * 4)):
         p.contact_angle_deg[k] = float(a)
+    p.t_liquidus = float(prob.get("t_liquidus", p.t_melt))
     for key in ("init_max", "init_check"):
         if key in prob:
             setattr(p, key, int(prob[key]))

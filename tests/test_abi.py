@@ -34,7 +34,8 @@ def test_state_bytes_and_validation():
     assert 18 * 256 * 256 * 4 <= nb < 18 * 256 * 256 * 4 + 4 * 1024 * 1024
     p64 = lbfs.make_params(wl.droplet64())
     assert lbfs.state_bytes(p64) >= 18 * 64 * 64 * 8
-    for field, bad in (("nx", 3), ("dx", 0.0), ("tau_g", 0.5), ("precision", 7), ("dt", 100.0),
+    for field, bad in (("nx", 3), ("dx", 0.0), ("tau_g", 0.5), ("precision", 7), ("dt", 100.0), ("dt", -1.0),
+                       ("t_liquidus", -0.5),
                        ("sor_omega", 2.0), ("dt_stream", 0.3), ("abi_version", 99)):
         q = lbfs.make_params(wl.droplet64())
         setattr(q, field, bad)

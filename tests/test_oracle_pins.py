@@ -485,3 +485,42 @@ def test_dimensionless_groups_of_eq50():
     alpha_l = prob["lam"][1] / (prob["rho"][1] * prob["cp"][1])
     assert b["fourier"] - a["fourier"] == pytest.approx(alpha_l * 10 * prob["dt"] / 8.0 ** 2, rel=1e-12)
     assert b["peclet"] == pytest.approx(b["umax_drop"] * 16.0 / alpha_l, rel=1e-12)
+
+
+def test_enthalpy_map_with_a_melting_range():
+    """Eq. 8 with Ts < Tl: H_es = Cp,s Ts and H_el = Cp,l Tl + L bound the mushy branch,
+    where Fl and T are linear in He (T from Ts to Tl); T and Fl are continuous at both
+    ends, and the initial enthalpy inverts the map for T_init in every branch."""
+    prob = wl.with_changes(periodic_liquid(latent=10.0), t_melt=-0.4, t_liquidus=0.6)
+    cps, cpl = prob["cp"][0], prob["cp"][1]
+    Ts, Tl, L = -0.4, 0.6, 10.0
+    Hes, Hel = cps * Ts, cpl * Tl + L
+    for frac in (0.0, 0.3, 0.75, 1.0):
+        He = Hes + frac * (Hel - Hes)
+        T, Fl = orc.enthalpy_state(prob, He, 1.0)
+        assert abs(Fl - frac) < 1e-14 and abs(T - (Ts + frac * (Tl - Ts))) < 1e-14
+    for He, T_ref in ((Hes - 1e-9, Ts), (Hel + 1e-9, Tl)):
+        T, _ = orc.enthalpy_state(prob, He, 1.0)
+        assert abs(T - T_ref) < 1e-8
+    T, Fl = orc.enthalpy_state(prob, Hel + 2.0, 1.0)
+    assert Fl == 1.0 and abs(T - (Tl + 2.0 / cpl)) < 1e-14
+    T, Fl = orc.enthalpy_state(prob, Hes - 1.0, 1.0)
+    assert Fl == 0.0 and abs(T - (Hes - 1.0) / cps) < 1e-14
+    # the initial state inverts Eq. 8 (uniform liquid order parameter, no droplet)
+    for t_init in (-1.0, -0.1, 0.6, 1.3):
+        p = wl.with_changes(prob, t_init=t_init, init_kind="uniform", c_init=1.0)
+        o = orc.Oracle(p)
+        assert np.max(np.abs(o.get("T") - t_init)) < 1e-13, t_init
+
+
+def test_automatic_time_step():
+    """dt = 0 picks min(dx/2, 0.4 dx^2 / D_max): the workload's 0.5 when the gas
+    diffusivity (0.4) sets D_max, and the diffusive bound when it is larger."""
+    prob = wl.droplet_problem(16, 4.0, ste=0.1, bo_m=0.0, angle_deg=90.0, precision="fp64")
+    o = orc.Oracle(wl.with_changes(prob, dt=0.0), init=False)
+    o.step(2)
+    assert abs(o.observe()["t"] - 2 * 0.5) < 1e-15
+    hot = wl.with_changes(prob, dt=0.0, lam=[prob["lam"][0], prob["lam"][1], 0.1])   # alpha_g = 1.0
+    o = orc.Oracle(hot, init=False)
+    o.step(1)
+    assert abs(o.observe()["t"] - 0.4) < 1e-15
