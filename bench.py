@@ -84,6 +84,8 @@ def parse():
                     help="bracket the kernels of every n-th timed step with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-io", action="store_true",
+                    help="skip the rates with per-step observables or checkpoints over PCIe")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
@@ -200,6 +202,34 @@ def error_vs_oracle(solver, prob: dict) -> dict:
             "state": f"the solver's state at t = {t0:g} after the timed steps"}
 
 
+def host_boundary(solver, lbfs, cells: int, n: int) -> dict:
+    """Rates with host traffic over PCIe inside the loop (never the headline value): each
+    step followed by lbfs_observe (FP64 reductions, the observables struct to the host,
+    as the serving loop does between chunks), and each step followed by lbfs_save_state
+    (the whole state to a host buffer, a checkpoint every step)."""
+    import ctypes as C
+    lib = lbfs.lib()
+    nb = int(lib.lbfs_checkpoint_bytes(solver._h))
+    buf = C.create_string_buffer(nb)
+    solver.step(1)
+    solver.observe()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        solver.step(1)
+        solver.observe()
+    t1 = time.perf_counter()
+    lbfs._check(lib.lbfs_save_state(solver._h, buf, nb), "lbfs_save_state")
+    t2 = time.perf_counter()
+    for _ in range(n):
+        solver.step(1)
+        lbfs._check(lib.lbfs_save_state(solver._h, buf, nb), "lbfs_save_state")
+    t3 = time.perf_counter()
+    return {"observe_each_step_mlups": cells * n / (t1 - t0) / 1e6,
+            "checkpoint_each_step_mlups": cells * n / (t3 - t2) / 1e6,
+            "checkpoint_bytes": nb, "steps": n,
+            "note": "before the warm-up, outside the timed region; the timed value keeps the state resident"}
+
+
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict, mag_flops=None,
              mag_launches: int = 1, exclude=()) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step. The magnetic
@@ -283,6 +313,7 @@ def run_single(args, torch, lbfs, wl) -> dict:
         solver.set_tile_shapes(si, fused if args.mag_in_stage1 == "on" else (mi if mi != fused else 0))
     tuned = solver.autotune() if args.autotune == "on" else None
     shapes = shape_names(lbfs, prob["precision"], solver.tile_shapes_in_use())
+    host_io = None if args.no_host_io else host_boundary(solver, lbfs, cells, max(5, min(200, args.steps // 10)))
     solver.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -307,6 +338,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
         out["autotune"] = tuned
     out["liquid_fraction_reached"] = obs["liquid_fraction"]
     out["mag_residual_after_last_step"] = obs["mag_residual"]
+    if host_io is not None:
+        out["host_boundary"] = host_io
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
         if cells <= 1024 * 1024:

@@ -64,7 +64,7 @@ enum { LBFS_MAG_SWEEPS = 0, LBFS_MAG_LBFS = 1, LBFS_MAG_MULTIGRID = 2 };   /* pe
    clamped order parameter. */
 typedef struct lbfs_params {
     uint32_t abi_version;     /* = LBFS_ABI_VERSION                                 */
-    int32_t nx, ny;           /* cells, each >= 4                                   */
+    int32_t nx, ny;           /* cells, each 4..2^20, nx * ny <= 2^30               */
     int32_t precision;        /* lbfs_precision                                     */
     double dx;                /* cell size                                          */
     double dt;                /* Runge-Kutta time step; 0: min(dx/2, 0.4 dx^2 / D_max)

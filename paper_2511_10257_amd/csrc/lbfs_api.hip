@@ -71,6 +71,9 @@ int validate(const lbfs_params* p)
     if (!p) return LBFS_E_INVAL;
     if (p->abi_version != LBFS_ABI_VERSION) return LBFS_E_ABI;
     if (p->nx < 4 || p->ny < 4 || p->nx > (1 << 20) || p->ny > (1 << 20)) return LBFS_E_INVAL;
+    // at most 2^30 cells: every cell, face and padded-row index of the kernels then fits
+    // a 32-bit int
+    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 30)) return LBFS_E_INVAL;
     if (p->precision != LBFS_FP32 && p->precision != LBFS_FP64) return LBFS_E_INVAL;
     if (!finite_pos(p->dx) || !(p->dt == 0.0 || finite_pos(p->dt))) return LBFS_E_INVAL;   // 0: automatic
     if (p->dt_stream != 0.0 && std::fabs(p->dt_stream - 0.5 * p->dx) > 1e-12 * p->dx) return LBFS_E_INVAL;

@@ -40,6 +40,12 @@ def test_state_bytes_and_validation():
         q = lbfs.make_params(wl.droplet64())
         setattr(q, field, bad)
         assert lbfs.lib().lbfs_state_bytes(C.byref(q)) == 0, field
+    # edges up to 2^20 and at most 2^30 cells (32-bit kernel indices)
+    for nx, ny, ok in ((1 << 20, 1024, True), (1 << 20, 1025, False), ((1 << 20) + 1, 8, False),
+                       (32768, 32768, True), (32768, 32770, False)):
+        q = lbfs.make_params(wl.droplet64())
+        q.nx, q.ny = nx, ny
+        assert (lbfs.lib().lbfs_state_bytes(C.byref(q)) > 0) == ok, (nx, ny)
     q = lbfs.make_params(wl.neumann_problem(0.1, 250.0))
     assert lbfs.lib().lbfs_state_bytes(C.byref(q)) > 0
     q.ny = 5                     # odd periodic axis: no red-black colouring
