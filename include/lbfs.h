@@ -185,8 +185,10 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
               lbfs_solver** out);
 
 /* Enqueue nsteps time steps on the stream (asynchronous). On a non-default stream
-   the first call captures one step into a HIP graph and every step is one graph
-   launch (set LBFS_NO_GRAPH=1 in the environment to launch the kernels directly). */
+   the steps are replays of HIP graphs captured on first use: one replay covers 16
+   consecutive steps while at least 16 remain, one step otherwise (LBFS_GRAPH_STEPS=k
+   in the environment at init sets the 16, 1..64; LBFS_NO_GRAPH=1 launches the kernels
+   directly). The results are the same either way. */
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
 /* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
@@ -335,9 +337,9 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out);
    become free. */
 int lbfs_batch_retire(lbfs_batch* b, int32_t slot);
 
-/* Enqueue nsteps time steps of every live instance (asynchronous; one HIP graph
-   replay per step on a non-default stream, recaptured after admissions and
-   retirements). */
+/* Enqueue nsteps time steps of every live instance (asynchronous; HIP graph replays
+   of 16 steps or of one as in lbfs_step on a non-default stream, recaptured after
+   admissions and retirements). */
 int lbfs_batch_step(lbfs_batch* b, int32_t nsteps);
 
 /* lbfs_step_profiled for a batch: mean duration of each kernel phase over all live

@@ -207,8 +207,10 @@ struct Exec {
     int phase = 0;                       // potential buffer holding the current phi'
     bool use_graph = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing of the next launch (profiled steps)
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int graph_steps = 16;                // steps per replay of the multi-step graph
+    // graph[len][ph]: `len` = 0 one step, 1 graph_steps steps, from potential buffer ph
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
@@ -349,20 +351,24 @@ hipError_t exec_enqueue_step(Exec& E)
 
 void exec_drop_graphs(Exec& E)
 {
-    for (int k = 0; k < 2; k++) {
-        if (E.graph_exec[k]) (void)hipGraphExecDestroy(E.graph_exec[k]);
-        if (E.graph[k]) (void)hipGraphDestroy(E.graph[k]);
-        E.graph_exec[k] = nullptr;
-        E.graph[k] = nullptr;
-    }
+    for (int l = 0; l < 2; l++)
+        for (int k = 0; k < 2; k++) {
+            if (E.graph_exec[l][k]) (void)hipGraphExecDestroy(E.graph_exec[l][k]);
+            if (E.graph[l][k]) (void)hipGraphDestroy(E.graph[l][k]);
+            E.graph_exec[l][k] = nullptr;
+            E.graph[l][k] = nullptr;
+        }
 }
 
-// capture one time step starting from potential buffer `ph` into a HIP graph (once
-// per buffer); replays cost one launch per step
-hipError_t exec_ensure_graph(Exec& E, int ph)
+// capture one time step (len 0) or graph_steps consecutive steps (len 1) starting from
+// potential buffer `ph` into a HIP graph, once per length and buffer. A replay of the
+// longer graph costs one launch for graph_steps steps: the per-replay overhead of a graph
+// launch is several microseconds, as much as a graph gap between kernels.
+hipError_t exec_ensure_graph(Exec& E, int len, int ph)
 {
-    if (E.graph_exec[ph]) return hipSuccess;
+    if (E.graph_exec[len][ph]) return hipSuccess;
     const int saved = E.phase;
+    const bool saved_mres = E.mres_stage;
     E.phase = ph;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(E.stream, hipStreamCaptureModeRelaxed);
@@ -370,18 +376,30 @@ hipError_t exec_ensure_graph(Exec& E, int ph)
         E.phase = saved;
         return e;
     }
-    e = exec_enqueue_step(E);
+    const int n = len ? E.graph_steps : 1;
+    for (int k = 0; k < n && e == hipSuccess; k++) e = exec_enqueue_step(E);
     const hipError_t ec = hipStreamEndCapture(E.stream, &g);
     E.phase = saved;
+    E.mres_stage = saved_mres;
     if (e == hipSuccess) e = ec;
-    if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[ph], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[len][ph], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        E.graph_exec[ph] = nullptr;
+        E.graph_exec[len][ph] = nullptr;
         return e;
     }
-    E.graph[ph] = g;
+    E.graph[len][ph] = g;
     return hipSuccess;
+}
+
+// steps per replay of the multi-step graph: 16, or LBFS_GRAPH_STEPS (1..64) from the
+// environment (1: every replay is one step)
+int graph_steps_setting()
+{
+    const char* v = std::getenv("LBFS_GRAPH_STEPS");
+    if (!v || !*v) return 16;
+    const long k = std::strtol(v, nullptr, 10);
+    return k < 1 ? 1 : (k > 64 ? 64 : (int)k);
 }
 
 // potential-buffer flips of one step (one per magnetic launch)
@@ -393,17 +411,20 @@ int exec_step_flips(const Exec& E)
     return (launches * E.mag_chunks) & 1;
 }
 
-// one step, as a graph replay when graphs are on
-hipError_t exec_run_step(Exec& E)
+// up to `nmax` (>= 1) steps: graph_steps of them as one replay of the multi-step graph
+// when that many are wanted, else one step (a one-step replay, or direct launches when
+// graphs are off). Returns the steps enqueued, 0 on a HIP error.
+int exec_run_steps(Exec& E, int nmax)
 {
-    if (!E.use_graph) return exec_enqueue_step(E);
+    if (!E.use_graph) return exec_enqueue_step(E) == hipSuccess ? 1 : 0;
+    const int len = (E.graph_steps > 1 && nmax >= E.graph_steps) ? 1 : 0;
+    const int n = len ? E.graph_steps : 1;
     const int ph = E.phase;
-    hipError_t e = exec_ensure_graph(E, ph);
-    if (e != hipSuccess) return e;
-    e = hipGraphLaunch(E.graph_exec[ph], E.stream);
-    E.phase = ph ^ exec_step_flips(E);
+    if (exec_ensure_graph(E, len, ph) != hipSuccess) return 0;
+    if (hipGraphLaunch(E.graph_exec[len][ph], E.stream) != hipSuccess) return 0;
+    E.phase = ph ^ ((n * exec_step_flips(E)) & 1);
     E.mres_stage = E.fused;
-    return e;
+    return n;
 }
 
 // nsteps steps with HIP events around the kernel phases of every sample_every-th step;
@@ -434,18 +455,24 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
         slot++;
         return e;
     };
-    for (int n = 0; n < nsteps && rc == LBFS_OK; n++) {
-        hipError_t e;
+    for (int n = 0; n < nsteps && rc == LBFS_OK;) {
         if (n % sample_every == 0) {
+            hipError_t e;
             if (E.fused) e = timed(LBFS_K_STAGE1, [&] { return exec_stage_fused(E); });
             else e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E); });
             for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
-        } else {
-            e = exec_run_step(E);
+            if (e != hipSuccess) rc = LBFS_E_DEVICE;
+            after_step();
+            n++;
+            continue;
         }
-        if (e != hipSuccess) rc = LBFS_E_DEVICE;
-        after_step();
+        // the plain steps up to the next sampled one
+        const int next = std::min(nsteps, (n / sample_every + 1) * sample_every);
+        const int k = exec_run_steps(E, next - n);
+        if (k == 0) rc = LBFS_E_DEVICE;
+        for (int q = 0; q < k; q++) after_step();
+        n += k;
     }
     if (rc == LBFS_OK && hipStreamSynchronize(E.stream) != hipSuccess) rc = LBFS_E_DEVICE;
     for (int k = 0; k < LBFS_NKERNELS; k++) {
@@ -965,6 +992,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     s->hres[RES_MAGR2] = r * r;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
     E.use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
+    E.graph_steps = graph_steps_setting();
     *out = s;
     return LBFS_OK;
 }
@@ -978,11 +1006,13 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps)
 {
     if (!s || s->batched) return LBFS_E_STATE;
     if (nsteps < 0) return LBFS_E_INVAL;
-    for (int n = 0; n < nsteps; n++) {
-        if (exec_run_step(s->E) != hipSuccess) return LBFS_E_DEVICE;
-        s->t += s->p.dt;
-        s->step += 1;
+    for (int n = 0; n < nsteps;) {
+        const int k = exec_run_steps(s->E, nsteps - n);
+        if (k == 0) return LBFS_E_DEVICE;
+        for (int q = 0; q < k; q++) s->t += s->p.dt;
+        s->step += k;
         s->stepped_since_observe = true;
+        n += k;
     }
     return LBFS_OK;
 }
@@ -1624,6 +1654,7 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
     E.stream = b->stream;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
     E.use_graph = b->stream != nullptr && !(ng && ng[0] == '1');
+    E.graph_steps = graph_steps_setting();
     if (HIPFAIL(hipHostMalloc(&b->hres, sizeof(double) * NRES * max_slots, hipHostMallocDefault))) {
         delete b;
         return LBFS_E_DEVICE;
@@ -1720,9 +1751,11 @@ int lbfs_batch_step(lbfs_batch* b, int32_t nsteps)
     const int rc = batch_rebuild(b);
     if (rc != LBFS_OK) return rc;
     if (b->E.ninst == 0) return LBFS_OK;
-    for (int n = 0; n < nsteps; n++) {
-        if (exec_run_step(b->E) != hipSuccess) return LBFS_E_DEVICE;
-        batch_after_step(b);
+    for (int n = 0; n < nsteps;) {
+        const int k = exec_run_steps(b->E, nsteps - n);
+        if (k == 0) return LBFS_E_DEVICE;
+        for (int q = 0; q < k; q++) batch_after_step(b);
+        n += k;
     }
     return LBFS_OK;
 }

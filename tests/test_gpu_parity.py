@@ -264,6 +264,70 @@ def test_graph_replay_equals_direct_launches(monkeypatch):
     assert a.observe() == b.observe()
 
 
+@pytest.mark.parametrize("variant", ["sweeps", "sweeps5", "lbfs", "multigrid", "controlled", "fused"])
+def test_multi_step_graphs_equal_direct_launches(monkeypatch, variant):
+    """Replays of 8-step and 3-step graphs (with one-step replays for the remainder) give
+    the fields of direct launches bit for bit, for every magnetic method: the potential
+    buffer parity after a replay of n steps is that of n single steps."""
+    prob = wl.droplet_problem(96, 24.0, ste=0.1, bo_m=1.5, angle_deg=30.0, precision="fp32")
+    prob.update(dict(sweeps5=dict(sweeps=5), lbfs=dict(mag_method="lbfs", sweeps=3),
+                     multigrid=dict(mag_method="multigrid", sweeps=1),
+                     controlled=dict(sweeps=4, mag_max_iters=12, mag_tol=1e-30)).get(variant, {}))
+    monkeypatch.setenv("LBFS_NO_GRAPH", "1")
+    ref = lbfs.Solver(prob)
+    monkeypatch.delenv("LBFS_NO_GRAPH")
+    runs = []
+    for k in ("8", "3"):
+        monkeypatch.setenv("LBFS_GRAPH_STEPS", k)
+        runs.append(lbfs.Solver(prob))
+    monkeypatch.delenv("LBFS_GRAPH_STEPS")
+    for g in [ref] + runs:
+        if variant == "fused":
+            si, _ = g.tile_shapes_in_use()
+            g.set_tile_shapes(si, lbfs.mag_fused_index("fp32"))
+    for n in (19, 1, 8, 4):
+        for g in [ref] + runs:
+            g.step(n)
+        for g in runs:
+            for k in ("He", "p", "Mx", "My", "C", "phi", "S"):
+                assert np.array_equal(g.get(k), ref.get(k)), (variant, n, k)
+            assert g.observe() == ref.observe()
+    # profiled stepping through the same replays
+    kr = ref.step_profiled(30, 11)
+    for g in runs:
+        g.step_profiled(30, 11)
+        assert np.array_equal(g.get("phi"), ref.get("phi")) and np.array_equal(g.get("He"), ref.get("He"))
+    assert kr["stage3"][1] == 3
+
+
+def test_multi_step_graphs_in_a_batch(monkeypatch):
+    probs = [wl.droplet_problem(e, e / 4.0, ste=0.1, bo_m=1.0, angle_deg=a, precision="fp32")
+             for e, a in ((64, 0.0), (96, 45.0), (72, 90.0))]
+    budget = sum(lbfs.Batch.instance_bytes(p) for p in probs) + (1 << 20)
+    monkeypatch.setenv("LBFS_GRAPH_STEPS", "1")
+    b1 = lbfs.Batch(3, budget)
+    monkeypatch.setenv("LBFS_GRAPH_STEPS", "8")
+    b8 = lbfs.Batch(3, budget)
+    monkeypatch.delenv("LBFS_GRAPH_STEPS")
+    for b in (b1, b8):
+        for p in probs:
+            assert b.admit(p) is not None
+    for n in (21, 8):
+        b1.step(n)
+        b8.step(n)
+        o1, o8 = b1.observe(), b8.observe()
+        assert o1 == o8
+    b1.retire(1)
+    b8.retire(1)
+    b1.step(17)
+    b8.step(17)
+    for s in (0, 2):
+        for k in ("He", "C", "phi"):
+            assert np.array_equal(b1.slot(s).get(k), b8.slot(s).get(k)), (s, k)
+    b1.close()
+    b8.close()
+
+
 def test_profiled_steps_equal_plain_steps():
     prob = wl.droplet_problem(64, 16.0, ste=0.1, bo_m=1.0, angle_deg=90.0, precision="fp32")
     a = lbfs.Solver(prob)
