@@ -226,7 +226,7 @@ def test_rhs_at_full_size(which):
 
 
 def test_step_fp64_full_size_observables():
-    """1024^2 FP64 (8192 stage tiles over all XCDs): one step from the same state,
+    """1024^2 FP64 (some ten thousand stage tiles over all XCDs): one step from the same state,
     fields and the observables reduced by the last workgroup of the last stage."""
     prob = wl.with_changes(wl.droplet1024("fp64"), init_max=0)
     nx, ny = prob["nx"], prob["ny"]
