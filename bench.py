@@ -177,7 +177,26 @@ def cpu_baseline(prob: dict, budget_s: float, solver=None) -> dict:
     start = "the GPU solver's state after the timed steps" if large else "its initial state"
     return {"value": cells * steps / secs / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the {prob['nx']}x{prob['ny']} droplet from {start}, "
-                      f"FP64, single thread, {secs:.1f} s (init excluded)"}
+                      f"FP64, single thread, {secs:.1f} s (init excluded)",
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and the logical CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus_available": ncpu}
 
 
 def kernel_shape(kernel: str, shapes: dict) -> str:
