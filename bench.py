@@ -444,8 +444,9 @@ def run_serve(args, torch, lbfs, wl) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a "
-              f"single MI355X; see the multi-GPU design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs each "
+              f"solve or batch on a single MI355X, and sharding across GPUs exists as a design only",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
