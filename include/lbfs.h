@@ -206,8 +206,10 @@ enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUC
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches);
 
-/* Synchronise the stream and return the observables of the last step. Returns
-   LBFS_E_NONFINITE (with o filled) when the step produced a non-finite value. */
+/* Synchronise the stream and return the observables of the current state: after the
+   last step, or as last written by lbfs_write_field or lbfs_load_state (mag_residual
+   is the one the last magnetic phase left). Returns LBFS_E_NONFINITE (with o filled)
+   when the state holds a non-finite value. */
 int lbfs_observe(lbfs_solver* s, lbfs_observables* o);
 
 /* One evaluation of R(W) (Eq. 46) for the current state, with the Kelvin force of the
@@ -258,7 +260,8 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
  * kernel each have a small table of candidate tile shapes (cells per tile and threads
  * per workgroup); the results do not depend on the shape (each cell and face is
  * computed by the same arithmetic), only the time does. The first shape of each table
- * is the default (the magnetic kernel takes its second shape above 512 x 512 cells). */
+ * is the default, except for the magnetic kernel of a single solve: its third shape
+ * (64 x 16) above 2^17 cells and its second (64 x 32) above 512 x 512 cells. */
 
 #define LBFS_MAX_SHAPES 8
 
@@ -283,21 +286,20 @@ int lbfs_set_tile_shapes(lbfs_solver* s, int32_t stage_shape, int32_t mag_shape)
 /* The shapes the next launches use (indices into the tables of lbfs_tile_shape). */
 int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape, int32_t* mag_shape);
 
-/* Autotuner: time every stage shape (reps runs of Runge-Kutta stage 1 and twice stage 2,
-   which write only stage fields; stage 3 costs what stage 2 does) and then every
-   magnetic shape (reps magnetic phases of a
-   step, on the current potential, which is restored afterwards) on this solver's
-   current state, and keep the fastest of each (the default, shape 0, unless another
-   is faster by more than 2 %, the spread of such timings). Where the sweeps can run
-   inside stage 1, that variant (stage 1 with the sweeps and stage 2 twice) is timed
-   too and chosen when it beats the best stage pair plus the best magnetic launch by
-   2 %. chosen[2] receives the indices (chosen[1] the count of magnetic shapes for
-   the fused variant), ms[2*LBFS_MAX_SHAPES] the mean ms per timed run (stage shapes
-   first, magnetic shapes from index LBFS_MAX_SHAPES, then the time the fused sweeps
-   add to the stage pair; either may be NULL). The state is unchanged; until the
-   next step, mag_residual then reports the residual of the current potential with the
-   current permeability (a step reports it with the permeability of the step's start).
-   Synchronous. */
+/* Autotuner: time whole time steps (one untimed, then reps timed, kernels launched
+   directly) from this solver's current state with every stage shape (at the current
+   magnetic shape), then with every magnetic shape (at the fastest stage shape), and
+   keep the fastest of each: the default, shape 0, unless another is faster by more
+   than 2 %, the spread of such timings. Where the sweeps can run inside stage 1, that
+   variant is timed too and chosen when its step beats the best step by 2 %. Before
+   each candidate and at the end the state is loaded again from a host snapshot in the
+   checkpoint format (lbfs_save_state), so the state, clock and results are unchanged;
+   until the next step, mag_residual then reports the residual of the current
+   potential with the current permeability (a step reports it with the permeability
+   of the step's start). chosen[2] receives the indices (chosen[1] the count of
+   magnetic shapes for the fused variant), ms[2*LBFS_MAX_SHAPES] the mean ms per step
+   (stage shapes first, magnetic shapes from index LBFS_MAX_SHAPES, then the fused
+   step's time minus the best magnetic shape's); either may be NULL. Synchronous. */
 int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms);
 
 /* Release the handle (the device buffer stays the caller's). NULL is allowed; a handle
@@ -359,7 +361,8 @@ int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live);
 int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
 
 /* lbfs_set_tile_shapes and lbfs_autotune for a batch: one shape pair for all live
-   instances (and those admitted later), timed on the concatenated tiles. */
+   instances (and those admitted later), timed on whole steps of every live instance
+   (the sweeps inside stage 1 are not a batch candidate). */
 int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape, int32_t mag_shape);
 int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms);
 int lbfs_batch_tile_shapes_in_use(const lbfs_batch* b, int32_t* stage_shape, int32_t* mag_shape);

@@ -594,7 +594,8 @@ struct lbfs_solver {
     double t = 0.0;
     int64_t step = 0;
     double vol0 = 0.0;
-    bool stepped_since_observe = false;
+    bool stepped_since_observe = false;  // the observables must be reduced again
+    bool* owner_stale = nullptr;         // a batch member: its batch's flag of the same kind
     MgCtx mg;                            // multigrid plan (built on first use)
     void* field(int k) const { return base + L.off_fields + L.field_bytes * (size_t)k; }
     bool f64() const { return p.precision == LBFS_FP64; }
@@ -701,6 +702,14 @@ int copy_field_out(lbfs_solver* s, int k, double* host)
     return LBFS_OK;
 }
 
+// the state was written from outside a step: the next observe reduces it again (for a
+// batch member, the batch's next observe too)
+void mark_written(lbfs_solver* s)
+{
+    s->stepped_since_observe = true;
+    if (s->owner_stale) *s->owner_stale = true;
+}
+
 int copy_field_in(lbfs_solver* s, int k, const double* host)
 {
     const size_t es = s->L.esize, nx = s->p.nx, ny = s->p.ny;
@@ -711,6 +720,7 @@ int copy_field_in(lbfs_solver* s, int k, const double* host)
     HIPCHK(hipMemcpy2DAsync(s->field(k), (size_t)s->L.pitch * es, s->staging, nx * es, nx * es, ny,
                             hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    mark_written(s);
     return LBFS_OK;
 }
 
@@ -946,8 +956,10 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
         hipMemsetAsync(s->base + L.off_fields, 0, L.field_bytes * NFIELDS, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
-    // default shapes: the first of each table; the large magnetic tiles above 512 x 512
-    if (apply_shapes(s, 0, (size_t)p->nx * p->ny > (size_t)512 * 512 ? 1 : 0) != LBFS_OK)
+    // default shapes: the first stage shape; the magnetic shape by grid size (measured
+    // per step: 32 x 8 fastest on 128^2 and 256^2, 64 x 16 on 512^2 by 9%, 64 x 32 on 1024^2)
+    const size_t ncell = (size_t)p->nx * p->ny;
+    if (apply_shapes(s, 0, ncell > (size_t)512 * 512 ? 1 : (ncell > ((size_t)1 << 17) ? 2 : 0)) != LBFS_OK)
         return fail(LBFS_E_DEVICE);
 
     hipError_t e = s->f64()
@@ -1214,6 +1226,7 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes)
     s->t = h.t;
     s->step = h.step;
     s->vol0 = h.vol0;
+    mark_written(s);
     return LBFS_OK;
 }
 
@@ -1359,57 +1372,57 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     Exec& E = s->E;
     double t[2 * LBFS_MAX_SHAPES] = {0};
     const int phase0 = E.phase;
-    int rc = LBFS_OK;
-    // stage kernels: stage 1 and twice stage 2 (they write only the stage fields)
+    const int mag0 = E.mag_shape;
+    // Candidates are timed on whole time steps (direct launches), each from the same
+    // state: a host snapshot in the checkpoint format, loaded again before every
+    // candidate and at the end. (Timing stage 1 and stage 2 alone, which leave the
+    // state as it is, ranked tile shapes a few percent differently from whole steps.)
+    std::vector<char> snap(lbfs_checkpoint_bytes(s));
+    int rc = lbfs_save_state(s, snap.data(), snap.size());
+    auto restore = [&]() {
+        E.phase = phase0;
+        return lbfs_load_state(s, snap.data(), snap.size());
+    };
+    auto time_steps = [&](double* out) {
+        int r = restore();
+        if (r == LBFS_OK) r = time_launches(E.stream, reps, [&] { return exec_enqueue_step(E); }, out);
+        return r;
+    };
+    // stage shapes with the current magnetic shape, then magnetic shapes with the best
+    // stage shape
     int best_s = 0;
     for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
-        rc = apply_shapes(s, k, E.mag_shape);
-        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
+        rc = apply_shapes(s, k, mag0);
+        if (rc == LBFS_OK) rc = time_steps(&t[k]);
         if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
     }
-    // the sweeps inside stage 1 (its tiles plus a wider halo, one launch less per step):
-    // the fused stage 1 and stage 2 twice, timed before the potential is saved (stage 2
-    // writes the field that holds the copy) with the buffer parity kept, so the fused
-    // launches read the current potential and write only the other buffer; compared
-    // below with the best stage pair plus the best magnetic launch
-    double t_fused = 0.0;
-    if (rc == LBFS_OK && fusable(s->p)) {
-        rc = apply_shapes(s, best_s, NMAG_SHAPES);
-        if (rc == LBFS_OK)
-            rc = time_launches(E.stream, reps, [&] {
-                const int ph = E.phase;
-                hipError_t e = exec_stage_fused(E);
-                E.phase = ph;
-                if (e == hipSuccess) e = exec_stage(E, 2);
-                return e == hipSuccess ? exec_stage(E, 2) : e;
-            }, &t_fused);
-    }
-    bool saved = false;
-    if (rc == LBFS_OK) {
-        if (HIPFAIL(copy_phi(s, true))) rc = LBFS_E_DEVICE;
-        else saved = true;
-    }
-    // magnetic kernel: a step's worth of sweeps, on the potential restored afterwards
     int best_m = 0;
     for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
         rc = apply_shapes(s, best_s, k);
         double* tk = &t[LBFS_MAX_SHAPES + k];
-        if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag_step(E); }, tk);
+        if (rc == LBFS_OK) rc = time_steps(tk);
         if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
     }
+    // the sweeps inside stage 1 (its tiles plus a wider halo, one launch less per step)
     bool fuse = false;
-    if (rc == LBFS_OK && t_fused > 0.0) {
-        t[LBFS_MAX_SHAPES + NMAG_SHAPES] = t_fused - t[best_s];
-        fuse = clearly_faster(t_fused, t[best_s] + t[LBFS_MAX_SHAPES + best_m]);
+    if (rc == LBFS_OK && fusable(s->p)) {
+        double tf = 0.0;
+        rc = apply_shapes(s, best_s, NMAG_SHAPES);
+        if (rc == LBFS_OK) rc = time_steps(&tf);
+        if (rc == LBFS_OK) {
+            t[LBFS_MAX_SHAPES + NMAG_SHAPES] = tf - t[LBFS_MAX_SHAPES + best_m];
+            fuse = clearly_faster(tf, t[LBFS_MAX_SHAPES + best_m]);
+        }
     }
-    // restore the potential, keep the fastest shapes and recompute the residual partials
-    // of the restored potential on them (a sweep-free launch: a copy of the potential)
-    E.phase = phase0;
-    if (saved && HIPFAIL(copy_phi(s, false))) rc = LBFS_E_DEVICE;
+    // the state as it was, the fastest shapes, and the residual partials of the restored
+    // potential on them (a sweep-free launch: a copy of the potential)
+    const int rr = restore();
+    if (rc == LBFS_OK) rc = rr;
     if (rc == LBFS_OK) rc = apply_shapes(s, best_s, best_m);
     if (rc == LBFS_OK && fuse) rc = apply_shapes(s, best_s, NMAG_SHAPES);
     if (rc == LBFS_OK && (HIPFAIL(exec_mag(E, 0, 1.0, 1)) || HIPFAIL(hipStreamSynchronize(E.stream))))
         rc = LBFS_E_DEVICE;
+    s->stepped_since_observe = true;
     if (rc != LBFS_OK) return rc;
     if (chosen) {
         chosen[0] = best_s;
@@ -1722,6 +1735,7 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
         }
     }
     s->batched = true;
+    s->owner_stale = &b->stepped_since_observe;
     b->slots[slot] = Slot{s, off, need};
     b->dirty = true;
     b->stepped_since_observe = true;
@@ -1866,36 +1880,49 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
     int best_s = b->stage_shape, best_m = b->mag_shape;
     Exec& E = b->E;
     if (E.ninst > 0) {
+        // whole steps of every instance from host snapshots, as in lbfs_autotune
         const int phase0 = E.phase;
+        std::vector<std::vector<char>> snap(b->slots.size());
+        for (size_t i = 0; i < b->slots.size() && rc == LBFS_OK; i++)
+            if (lbfs_solver* q = b->slots[i].s) {
+                snap[i].resize(lbfs_checkpoint_bytes(q));
+                rc = lbfs_save_state(q, snap[i].data(), snap[i].size());
+            }
+        auto restore = [&]() {
+            E.phase = phase0;
+            int r = LBFS_OK;
+            for (size_t i = 0; i < b->slots.size() && r == LBFS_OK; i++)
+                if (lbfs_solver* q = b->slots[i].s) {
+                    q->E.phase = phase0;
+                    r = lbfs_load_state(q, snap[i].data(), snap[i].size());
+                }
+            return r;
+        };
+        auto time_steps = [&](double* out) {
+            int r = batch_rebuild(b);
+            if (r == LBFS_OK) r = restore();
+            if (r == LBFS_OK) r = time_launches(E.stream, reps, [&] { return exec_enqueue_step(E); }, out);
+            return r;
+        };
         best_s = 0;
         for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
             b->stage_shape = k;
             b->dirty = true;
-            rc = batch_rebuild(b);
-            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return stage_pair(E); }, &t[k]);
+            rc = time_steps(&t[k]);
             if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
         }
-        // the potentials are stashed only once every stage timing is done (stage 2 writes
-        // the stash field)
-        const bool stash = rc == LBFS_OK;
-        for (Slot& q : b->slots)
-            if (q.s && stash && HIPFAIL(copy_phi(q.s, true))) rc = LBFS_E_DEVICE;
         best_m = 0;
         b->stage_shape = best_s;
         for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
             b->mag_shape = k;
             b->dirty = true;
-            rc = batch_rebuild(b);
             double* tk = &t[LBFS_MAX_SHAPES + k];
-            if (rc == LBFS_OK) rc = time_launches(E.stream, reps, [&] { return exec_mag(E, E.sweeps, E.omega, 1); }, tk);
+            rc = time_steps(tk);
             if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
         }
-        E.phase = phase0;
-        for (Slot& q : b->slots)
-            if (q.s) {
-                q.s->E.phase = phase0;
-                if (stash && HIPFAIL(copy_phi(q.s, false))) rc = LBFS_E_DEVICE;
-            }
+        const int rr = restore();
+        if (rc == LBFS_OK) rc = rr;
+        b->stepped_since_observe = true;
         if (rc != LBFS_OK) return rc;
         rc = lbfs_batch_set_tile_shapes(b, best_s, best_m);
         if (rc == LBFS_OK) rc = batch_refresh_residual(b);

@@ -256,11 +256,13 @@ def mag_shape(index: int, precision: str = "fp32") -> tuple:
 
 
 def _tune_result(chosen, ms, precision: str) -> dict:
+    """ms per whole step for each stage shape and each magnetic shape, and (where it was
+    a candidate) the step with the sweeps inside stage 1 minus the best other step."""
     ns, nm = len(tile_shapes("stage", precision)), len(tile_shapes("mag", precision))
     out = {"stage_shape": chosen[0], "mag_shape": chosen[1],
            "stage_ms": [ms[k] for k in range(ns)], "mag_ms": [ms[MAX_SHAPES + k] for k in range(nm)]}
     if ms[MAX_SHAPES + nm] != 0.0:
-        out["fused_sweeps_added_ms"] = ms[MAX_SHAPES + nm]
+        out["fused_step_minus_best_ms"] = ms[MAX_SHAPES + nm]
     return out
 
 

@@ -52,6 +52,8 @@ def test_autotune_keeps_the_state(precision):
     b.step(10)
     before = a.observe()
     res = a.autotune(reps=3)
+    assert all(t > 0 for t in res["stage_ms"] + res["mag_ms"])
+    assert (a.observe()["t"], a.observe()["step"]) == (before["t"], before["step"])
     assert len(res["stage_ms"]) == len(lbfs.tile_shapes("stage", precision))
     assert all(t > 0 for t in res["stage_ms"] + res["mag_ms"])
     after = a.observe()
@@ -75,7 +77,13 @@ def test_batch_autotune_keeps_every_member():
     batch = lbfs.Batch(4, sum(lbfs.Batch.instance_bytes(p) for p in probs) + (1 << 20))
     slots = [batch.admit(p) for p in probs]
     batch.step(6)
+    before = batch.observe()
     res = batch.autotune(reps=3)
+    after = batch.observe()
+    for k in slots:
+        assert (after[k]["t"], after[k]["step"]) == (before[k]["t"], before[k]["step"])
+        assert after[k]["umax"] == before[k]["umax"]
+        assert after[k]["liquid_fraction"] == pytest.approx(before[k]["liquid_fraction"], rel=1e-12)
     assert 0 <= res["stage_shape"] < len(lbfs.tile_shapes("stage"))
     assert 0 <= res["mag_shape"] < len(lbfs.tile_shapes("mag"))
     batch.step(6)
@@ -153,3 +161,43 @@ def test_sweeps_inside_stage_one_need_a_fixed_small_count():
         assert ei.value.status == lbfs.LBFS_E_INVAL
         s.close()
     assert lbfs.shape_name(lbfs.mag_shape(fused)) == "in-stage-1"
+
+
+@pytest.mark.parametrize("edge, mag_shape", [(256, 0), (362, 0), (363, 2), (512, 2), (513, 1), (1024, 1)])
+def test_default_magnetic_shape_by_grid_size(edge, mag_shape):
+    """Without autotuning a single solve takes 32 x 8 magnetic tiles up to 2^17 cells,
+    64 x 16 up to 512^2 and 64 x 32 above; the stage shape is the table's first."""
+    prob = wl.with_changes(wl.droplet_problem(edge, edge / 4.0, ste=0.1, bo_m=0.5, angle_deg=90.0,
+                                              precision="fp32"), init_max=0)
+    s = lbfs.Solver(prob)
+    assert s.tile_shapes_in_use() == (0, mag_shape)
+
+
+def test_observables_follow_written_and_loaded_states():
+    """Writing fields or loading a checkpoint changes what the next observe reports, for a
+    single solve and for a batch member written through its borrowed handle."""
+    prob = _prob("fp32")
+    a = lbfs.Solver(prob)
+    a.step(7)
+    want = a.observe()
+    st = _fields(a)
+    b = lbfs.Solver(prob)
+    b.observe()
+    b.set_state(st)
+    got = b.observe()
+    for k in ("liquid_fraction", "volume", "umax", "solid_ratio", "height"):
+        assert got[k] == want[k], k
+    c = lbfs.Solver(prob)
+    c.observe()
+    c.load(a.save())
+    got = c.observe()
+    for k in ("liquid_fraction", "volume", "umax", "t", "step"):
+        assert got[k] == want[k], k
+    batch = lbfs.Batch(1, lbfs.Batch.instance_bytes(prob) + (1 << 20))
+    k = batch.admit(prob)
+    batch.observe()
+    batch.slot(k).set_state(st)
+    got = batch.observe()[k]
+    for key in ("liquid_fraction", "volume", "umax", "solid_ratio"):
+        assert got[key] == want[key], key
+    batch.close()
