@@ -179,6 +179,7 @@ struct MgCtx {
     char* scratch = nullptr;                     // base of the offsets
     void* phi[2] = {nullptr, nullptr};           // level-0 unknown, by potential parity
     int pitch = 0;                               // of the level-0 unknown
+    int fixed_walls = 0;                         // bit w: wall w (W, E, S, N) holds the potential
 };
 
 // V(2,2) cycles with the coarsest level by red-black SOR in one workgroup
@@ -260,7 +261,8 @@ hipError_t mg_run(const Exec& E, const MgCtx& M, int ncycles, hipEvent_t e0)
             e = launch_mg_coarsest<T>(M.nx[c], M.ny[c], P(c), U(c), B + M.f[c], B + M.wx[c], B + M.wy[c],
                                       MG_COARSE_SWEEPS, om, E.stream);
         for (int l = c - 1; l >= 0 && e == hipSuccess; l--) {
-            e = launch_mg_prolong<T>(M.nx[l], M.ny[l], P(l), U(l), M.nx[l + 1], M.ny[l + 1], U(l + 1), E.stream);
+            e = launch_mg_prolong<T>(M.nx[l], M.ny[l], P(l), U(l), M.nx[l + 1], M.ny[l + 1], U(l + 1),
+                                     M.fixed_walls, E.stream);
             if (e == hipSuccess)
                 e = launch_mg_smooth<T>(M.nx[l], M.ny[l], P(l), U(l), B + M.f[l], B + M.wx[l], B + M.wy[l], MG_POST,
                                         E.stream);
@@ -655,6 +657,9 @@ int mg_plan(lbfs_solver* s)
     M.phi[0] = s->field(15);
     M.phi[1] = s->field(17);
     M.pitch = s->L.pitch;
+    M.fixed_walls = 0;
+    for (int w = 0; w < 4; w++)
+        if (s->p.mag_bc[w]) M.fixed_walls |= 1 << w;
     s->E.mg = &s->mg;
     return LBFS_OK;
 }

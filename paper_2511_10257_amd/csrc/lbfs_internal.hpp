@@ -169,8 +169,11 @@ hipError_t launch_mg_smooth(int nx, int ny, int pitch, T* u, const T* f, const T
 template <typename T>
 hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T* ff, const T* wxf, const T* wyf,
                               int nxc, int nyc, T* fc, T* uc, hipStream_t stream);
+// fixed_walls: bit w set where wall w (W, E, S, N) holds the potential (the correction
+// vanishes there); other walls are insulating
 template <typename T>
-hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, hipStream_t stream);
+hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, int fixed_walls,
+                             hipStream_t stream);
 template <typename T>
 hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
                               double omega, hipStream_t stream);

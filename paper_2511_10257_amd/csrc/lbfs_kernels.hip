@@ -1758,20 +1758,30 @@ __global__ __launch_bounds__(256) void k_mg_restrict(int nxf, int nyf, int pitch
 
 // add the coarse correction to every child, interpolated bilinearly from the four
 // nearest coarse cells (9/16 its own, 3/16 each side neighbour, 1/16 the diagonal; a
-// neighbour beyond the domain repeats the cell)
+// neighbour beyond the domain is the cell's mirror image across the wall)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_prolong(int nxf, int nyf, int pitchf, T* __restrict__ uf, int nxc,
-                                                    int nyc, const T* __restrict__ uc)
+                                                    int nyc, const T* __restrict__ uc, int fixed_walls)
 {
     const int c = blockIdx.x * 256 + (int)threadIdx.x;
     if (c >= nxf * nyf) return;
     const int i = c % nxf, j = c / nxf;
     const int I = i / 2, J = j / 2;
     int In = I + ((i & 1) ? 1 : -1), Jn = J + ((j & 1) ? 1 : -1);
-    In = In < 0 || In >= nxc ? I : In;
-    Jn = Jn < 0 || Jn >= nyc ? J : Jn;
-    const T v = T(9.0 / 16.0) * uc[J * nxc + I] + T(3.0 / 16.0) * (uc[J * nxc + In] + uc[Jn * nxc + I]) +
-                T(1.0 / 16.0) * uc[Jn * nxc + In];
+    // beyond a wall the coarse correction continues as its mirror image: odd where the
+    // wall holds the potential (the correction is zero on the wall, half a coarse cell
+    // away), even at an insulating wall (zero normal derivative)
+    T sx = T(1), sy = T(1);
+    if (In < 0 || In >= nxc) {
+        sx = (fixed_walls >> (In < 0 ? 0 : 1)) & 1 ? T(-1) : T(1);
+        In = I;
+    }
+    if (Jn < 0 || Jn >= nyc) {
+        sy = (fixed_walls >> (Jn < 0 ? 2 : 3)) & 1 ? T(-1) : T(1);
+        Jn = J;
+    }
+    const T v = T(9.0 / 16.0) * uc[J * nxc + I] + T(3.0 / 16.0) * (sx * uc[J * nxc + In] + sy * uc[Jn * nxc + I]) +
+                T(1.0 / 16.0) * (sx * sy) * uc[Jn * nxc + In];
     uf[(size_t)j * pitchf + i] += v;
 }
 
@@ -1855,11 +1865,12 @@ hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T
 }
 
 template <typename T>
-hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, hipStream_t stream)
+hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, int fixed_walls,
+                             hipStream_t stream)
 {
     const int n = nxf * nyf;
     hipLaunchKernelGGL((k_mg_prolong<T>), dim3((n + 255) / 256), dim3(256), 0, stream, nxf, nyf, pitchf, uf, nxc, nyc,
-                       uc);
+                       uc, fixed_walls);
     return hipGetLastError();
 }
 
@@ -1891,7 +1902,7 @@ hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const
     template hipError_t launch_mg_smooth<T>(int, int, int, T*, const T*, const T*, const T*, int, hipStream_t); \
     template hipError_t launch_mg_restrict<T>(int, int, int, const T*, const T*, const T*, const T*, int, int, T*, T*, \
                                               hipStream_t);                                            \
-    template hipError_t launch_mg_prolong<T>(int, int, int, T*, int, int, const T*, hipStream_t);       \
+    template hipError_t launch_mg_prolong<T>(int, int, int, T*, int, int, const T*, int, hipStream_t);  \
     template hipError_t launch_mg_coarsest<T>(int, int, int, T*, const T*, const T*, const T*, int, double, \
                                               hipStream_t);
 

@@ -35,20 +35,21 @@ def test_cycles_converge_to_the_sweeps_fixed_point(shape):
     prob, o, g = case(*shape, seed=3)
     r0 = g.mag_sweeps(0)
     res = [g.mag_multigrid(1) for _ in range(25)]
-    # V(2,2) with mean-weight coarse operators: about a quarter per cycle here
-    assert res[11] < 1e-6 * r0 and res[-1] < 1e-12 * r0, res
+    # V(2,2): the first cycle removes most of the applied field's residual, later ones a
+    # tenth (even halvings) to a fifth (150 x 70, whose coarser levels have odd sizes)
+    assert res[0] < 0.05 * r0 and res[11] < 1e-6 * r0 and res[-1] < 1e-12 * r0, res
     assert all(b <= a * 1.0001 or b < 1e-13 * r0 for a, b in zip(res, res[1:]))
     converge_oracle(o)
     po, pg = o.get("phi"), g.get("phi")
     assert np.max(np.abs(pg - po)) <= 1e-8 * np.max(np.abs(po))
 
 
-def test_one_cycle_reduces_the_residual_tenfold_on_a_large_grid():
+def test_one_cycle_reduces_the_residual_a_hundredfold_on_a_large_grid():
     prob, _, g = case(512, 512, seed=4, precision="fp32", angle=0.0)
     r0 = g.mag_sweeps(0)
     r1 = g.mag_multigrid(1)
     r2 = g.mag_multigrid(1)
-    assert r1 < 0.1 * r0 and r2 < 0.3 * r1, (r0, r1, r2)
+    assert r1 < 0.01 * r0 and r2 < 0.1 * r1, (r0, r1, r2)
 
 
 @pytest.mark.parametrize("walls", [["fixed"] * 4, ["insulating", "insulating", "fixed", "fixed"]])
