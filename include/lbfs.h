@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBFS_ABI_VERSION 2u
+#define LBFS_ABI_VERSION 3u
 
 enum {
     LBFS_OK = 0,
@@ -147,6 +147,8 @@ typedef struct lbfs_observables {
     double centroid_x, centroid_y;
     double semi_axis_x, semi_axis_y;
     double semi_axis_major, semi_axis_minor, major_axis_deg;
+    double solid_height;      /* sum(Fs dx) along the column containing drop_cx: the
+                                 frozen part of the height (Fig. 17, freezing front)   */
     int64_t step;
     int32_t nonfinite;        /* 1 if a conserved value was not finite              */
 } lbfs_observables;

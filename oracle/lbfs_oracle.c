@@ -969,7 +969,7 @@ void orc_observe(orc_sim* s, orc_obs* o)
     int ic = (int)floor(s->p.drop_cx / dx);
     if (ic < 0) ic = 0;
     if (ic > nx - 1) ic = nx - 1;
-    double height = 0.0;
+    double height = 0.0, solid_height = 0.0;
     double mx = 0, my = 0, mxx = 0, myy = 0, mxy = 0;
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
@@ -987,7 +987,10 @@ void orc_observe(orc_sim* s, orc_obs* o)
             sc += ct; scfl += ct * Fl; sfs += fs;
             if (um > umax) umax = um;
             if (ct >= 0.5 && um > udrop) udrop = um;
-            if (i == ic) height += ct * dx;
+            if (i == ic) {
+                height += ct * dx;
+                solid_height += fs * dx;
+            }
             if (j == 0 && !s->p.periodic[1] && s->p.tbc[2] == 1) {
                 double lam = mix3(s->p.lam, fs, ct);
                 heat += -lam * (T - s->p.tval[2]) / (0.5 * dx) * dx;
@@ -1002,6 +1005,7 @@ void orc_observe(orc_sim* s, orc_obs* o)
     o->umax = umax;
     o->nonfinite = nonfinite;
     o->height = height;
+    o->solid_height = solid_height;
     o->umax_drop = udrop;
     o->wall_heat = heat;
     /* Eq. 50 with the liquid properties and the initial radius R0 */

@@ -89,6 +89,8 @@ typedef struct orc_obs {
     double centroid_x, centroid_y;        /* Ct-weighted centroid                   */
     double semi_axis_x, semi_axis_y;      /* 2 sqrt(Ct-weighted variance) along x, y */
     double semi_axis_major, semi_axis_minor, major_axis_deg;  /* principal axes   */
+    double solid_height;     /* sum(Fs dx) along the column through drop_cx: the frozen
+                                part of the droplet's height there (Fig. 17 reading) */
 } orc_obs;
 
 typedef struct orc_sim orc_sim;

@@ -47,7 +47,7 @@ class Obs(C.Structure):
         "t", "step", "liquid_fraction", "solid_ratio", "volume", "volume0",
         "mag_residual", "umax", "nonfinite", "height", "umax_drop", "wall_heat", "fourier", "peclet",
         "centroid_x", "centroid_y", "semi_axis_x", "semi_axis_y", "semi_axis_major", "semi_axis_minor",
-        "major_axis_deg")]
+        "major_axis_deg", "solid_height")]
 
 
 def build(force: bool = False) -> str:

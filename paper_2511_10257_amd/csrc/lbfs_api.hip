@@ -554,6 +554,7 @@ int fill_observables(const lbfs_params& p, double t, int64_t step, double vol0, 
     o->umax = r[RES_UMAX];
     o->umax_drop = r[RES_UDROP];
     o->height = r[RES_HEIGHT] * p.dx;
+    o->solid_height = r[RES_SOLIDH] * p.dx;
     o->wall_heat = r[RES_HEAT];
     // Eq. 50 with the liquid properties and the initial radius R0
     const double alpha_l = p.lambda[1] / (p.rho[1] * p.cp[1]);

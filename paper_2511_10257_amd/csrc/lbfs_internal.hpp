@@ -51,10 +51,10 @@ constexpr int PT_TX = 64, PT_TY = 4;
 
 // per-tile partial sums of the observables of a state (FP64)
 enum { PART_CT = 0, PART_CTFL, PART_FS, PART_UMAX, PART_NONFINITE, PART_UDROP, PART_HEIGHT,
-       PART_HEAT, PART_MX, PART_MY, PART_MXX, PART_MYY, PART_MXY, NPART };
+       PART_HEAT, PART_MX, PART_MY, PART_MXX, PART_MYY, PART_MXY, PART_SOLIDH, NPART };
 // per-instance results written by the reduction (FP64)
 enum { RES_CT = 0, RES_CTFL, RES_FS, RES_UMAX, RES_NONFINITE, RES_UDROP, RES_HEIGHT, RES_HEAT,
-       RES_MX, RES_MY, RES_MXX, RES_MYY, RES_MXY, RES_MAGR2, NRES };
+       RES_MX, RES_MY, RES_MXX, RES_MYY, RES_MXY, RES_SOLIDH, RES_MAGR2, NRES };
 
 struct Tile {
     int32_t inst;    // instance index

@@ -532,9 +532,9 @@ __device__ __forceinline__ double wave_max(double x)
 }
 
 // FP64 observables of one cell of the state Wn (He, p, Mx, My, C): clamped order
-// parameter, Ct Fl, Fs, |u|, non-finite flag, |u| inside the drop, height column, heat
-// into a fixed south wall (-lambda dT/dy over the half cell, times dx), and the first and
-// second moments of Ct about the origin (droplet centroid and axes).
+// parameter, Ct Fl, Fs, |u|, non-finite flag, |u| inside the drop, height column (Ct and
+// Fs), heat into a fixed south wall (-lambda dT/dy over the half cell, times dx), and the
+// first and second moments of Ct about the origin (droplet centroid and axes).
 template <typename T>
 __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int gx, int gy, double* pr)
 {
@@ -556,6 +556,7 @@ __device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int
     pr[PART_NONFINITE] = finite ? 0.0 : 1.0;
     pr[PART_UDROP] = ct1 >= T(0.5) ? um : 0.0;
     pr[PART_HEIGHT] = gx == I.col_height ? double(ct1) : 0.0;
+    pr[PART_SOLIDH] = gx == I.col_height ? double(fs1) : 0.0;
     const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx, c = double(ct1);
     pr[PART_MX] = c * x;
     pr[PART_MY] = c * y;
@@ -619,6 +620,7 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
         acc[RES_MXX] += p[PART_MXX];
         acc[RES_MYY] += p[PART_MYY];
         acc[RES_MXY] += p[PART_MXY];
+        acc[RES_SOLIDH] += p[PART_SOLIDH];
     }
     const int nm = mres_stage ? I.ntile_stage : I.ntile_mag;
     for (int t = tid; t < nm; t += NT) acc[RES_MAGR2] += I.mpart[t];

@@ -15,7 +15,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblbfs.so")
 
-LBFS_ABI_VERSION = 2
+LBFS_ABI_VERSION = 3
 LBFS_OK, LBFS_E_INVAL, LBFS_E_NOMEM, LBFS_E_NONFINITE, LBFS_E_DEVICE, LBFS_E_STATE, LBFS_E_ABI = (
     0, -1, -2, -3, -4, -5, -6)
 LBFS_FP32, LBFS_FP64 = 0, 1
@@ -69,7 +69,7 @@ class Observables(C.Structure):
         ("wall_heat", C.c_double), ("fourier", C.c_double), ("peclet", C.c_double),
         ("centroid_x", C.c_double), ("centroid_y", C.c_double), ("semi_axis_x", C.c_double),
         ("semi_axis_y", C.c_double), ("semi_axis_major", C.c_double), ("semi_axis_minor", C.c_double),
-        ("major_axis_deg", C.c_double),
+        ("major_axis_deg", C.c_double), ("solid_height", C.c_double),
         ("step", C.c_int64), ("nonfinite", C.c_int32),
     ]
 

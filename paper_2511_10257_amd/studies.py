@@ -10,8 +10,10 @@ paper's figures:
 - H/R0 against Fo (Fig. 11), with H the droplet height along the centre column;
 - Pe against Fo (Fig. 12, Eq. 50);
 - the solid ratio Q_L of Eq. 51 against Fo (Fig. 16);
-- the scaling of the final height with the freezing time, H_m/R0 against Ste Fo
-  (Fig. 17), as the slope of a least-squares line in log-log axes;
+- the scaling of Fig. 17 in two readings, each as the slope of a least-squares line in
+  log-log axes: the final height against the freezing time (one point per case, H_m/R0
+  against Ste Fo at freezing), and the rise of the freezing front (the frozen height
+  along the centre column, Hs/R0, against Ste Fo during freezing, every case pooled);
 - the dimensionless freezing time t* = (t(Bo_m) - t(0)) / t(0) per Ste and
   orientation (Fig. 18);
 - without freezing, the deformation ratio b/a of a suspended ferrofluid droplet in a
@@ -66,7 +68,8 @@ def run(cases: list[dict], chunk: int = 50, max_steps: int = 200000, done_fl: fl
         if slot is None:
             raise RuntimeError("the batch buffer does not hold every case")
         r0 = float(p["drop"][2])
-        rec = dict(case=p["case"], r0=r0, series=dict(step=[], fo=[], h_r0=[], pe=[], q_l=[], fl=[], wall_heat=[]),
+        rec = dict(case=p["case"], r0=r0, series=dict(step=[], fo=[], h_r0=[], hs_r0=[], pe=[], q_l=[], fl=[],
+                                                      wall_heat=[]),
                    frozen=False)
         results.append(rec)
         live[slot] = rec
@@ -82,6 +85,7 @@ def run(cases: list[dict], chunk: int = 50, max_steps: int = 200000, done_fl: fl
             s["step"].append(int(o["step"]))
             s["fo"].append(o["fourier"])
             s["h_r0"].append(o["height"] / rec["r0"])
+            s["hs_r0"].append(o["solid_height"] / rec["r0"])
             s["pe"].append(o["peclet"])
             s["q_l"].append(o["solid_ratio"])
             s["fl"].append(o["liquid_fraction"])
@@ -190,6 +194,34 @@ def scaling_slope(results: list[dict]) -> float:
     return float(np.polyfit(x, y, 1)[0])
 
 
+def front_scaling(results: list[dict], lo: float = 0.1, hi: float = 0.6) -> dict:
+    """Slope of log(Hs/R0) against log(Ste Fo) while the freezing front rises through the
+    centre column: over the observations of each frozen case whose frozen height lies
+    between lo and hi of its final value (a first solid layer has formed, and the front
+    is still below the apex, where the droplet narrows). The slope of all cases pooled,
+    and of each case alone."""
+    xs, ys, per = [], [], []
+    for r in results:
+        if not r.get("frozen"):
+            continue
+        s = r["series"]
+        hs, fo = np.array(s["hs_r0"]), np.array(s["fo"])
+        if hs.size == 0 or hs[-1] <= 0:
+            continue
+        keep = (hs >= lo * hs[-1]) & (hs <= hi * hs[-1]) & (fo > 0)
+        if keep.sum() < 2:
+            continue
+        x = np.log(r["case"]["ste"] * fo[keep])
+        y = np.log(hs[keep])
+        per.append(dict(r["case"], slope=float(np.polyfit(x, y, 1)[0]), points=int(keep.sum())))
+        xs.append(x)
+        ys.append(y)
+    if not xs:
+        return dict(slope=float("nan"), cases=per)
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    return dict(slope=float(np.polyfit(x, y, 1)[0]) if x.size >= 2 else float("nan"), cases=per)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--deformation", action="store_true",
@@ -237,7 +269,7 @@ def main(argv=None):
                      pe_max=max(r["series"]["pe"]) if r["series"]["pe"] else None)
                 for r in res]
     summary = dict(edge=args.edge, gas_lambda_ratio=args.gas_lambda_ratio, cases=per_case,
-                   t_star=t_star(res), scaling_slope=scaling_slope(res))
+                   t_star=t_star(res), scaling_slope=scaling_slope(res), front_scaling=front_scaling(res))
     print(json.dumps(summary))
     if args.out:
         with open(args.out, "w") as f:

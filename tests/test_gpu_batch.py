@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 STATE = ("He", "p", "Mx", "My", "C", "phi", "S", "T", "Fl")
 OBS = ("liquid_fraction", "solid_ratio", "volume", "volume0", "mag_residual", "umax", "umax_drop",
-       "height", "wall_heat", "step", "t")
+       "height", "solid_height", "wall_heat", "step", "t")
 
 
 def _mixed(precision: str):

@@ -140,7 +140,7 @@ def test_step_fp64_matches_oracle_on_64x64_states():
             a, b = g.get(name), o.get(name)
             assert rel_l2(a, b, fl[name]) < 1e-11, (n_before, name, rel_l2(a, b, fl[name]))
         ob, og = o.observe(), g.observe()
-        for key in ("liquid_fraction", "solid_ratio", "volume", "mag_residual", "umax", "height",
+        for key in ("liquid_fraction", "solid_ratio", "volume", "mag_residual", "umax", "height", "solid_height",
                     "wall_heat", "umax_drop", "fourier", "peclet", "t"):
             assert og[key] == pytest.approx(ob[key], rel=1e-9, abs=1e-14), key
 
@@ -244,7 +244,7 @@ def test_step_fp64_full_size_observables():
         assert rel_l2(g.get(name), o.get(name), fl[name]) < 1e-10, name
     ob, og = o.observe(), g.observe()
     # (the solid ratio is relative to the initial volume, which only the GPU side has here)
-    for key in ("liquid_fraction", "volume", "mag_residual", "umax", "height", "wall_heat"):
+    for key in ("liquid_fraction", "volume", "mag_residual", "umax", "height", "solid_height", "wall_heat"):
         assert og[key] == pytest.approx(ob[key], rel=1e-9, abs=1e-14), key
     # a second step exercises the reset of the completion counter
     o.step(1)

@@ -1,4 +1,4 @@
-"""Trend-level checks of the Sec. 5 studies (Figs. 11, 16, 18) on synthetic droplets.
+"""Trend-level checks of the Sec. 5 studies (Figs. 11, 16, 17, 18) on synthetic droplets.
 
 The paper's figures carry no numeric data, so these tests check directions only: the
 droplet grows taller while it freezes (the solid is less dense), a vertical field makes
@@ -45,6 +45,19 @@ def test_field_orientation_orders_the_freezing_rate(sweep):
     assert np.all(ql[v][half] < ql[n][half]) and np.all(ql[n][half] < ql[hz][half])
     for k in sweep:
         assert np.all(np.isfinite(fl[k]))
+
+
+def test_freezing_front_rises_as_the_square_root_of_ste_fo():
+    """Fig. 17 under the front reading: the frozen height along the centre column grows
+    as (Ste Fo)^0.5 while the front rises (0.54 here on 64^2, 0.52 on 128^2), with and
+    without the field."""
+    cases = studies.sweep_cases(64, [0.0, 16.0], [0.1], orientations=("vertical",), gas_lambda_ratio=0.036)
+    res = studies.run(cases, chunk=100, max_steps=100000)
+    out = studies.front_scaling(res)
+    assert len(out["cases"]) == 2
+    for c in out["cases"]:
+        assert 0.45 < c["slope"] < 0.6, c
+        assert c["points"] > 30
 
 
 def test_deformation_ratio_grows_with_the_magnetic_bond_number():

@@ -91,3 +91,28 @@ def test_shape_moments_recover_an_ellipse(theta_deg):
     # the axis-aligned variances: a^2 cos^2 + b^2 sin^2 along x
     ex = np.sqrt(a * a * np.cos(th) ** 2 + b * b * np.sin(th) ** 2)
     assert abs(ob["semi_axis_x"] - ex) < 0.3
+
+
+def test_solid_height_counts_the_frozen_part_of_the_centre_column():
+    """solid_height = sum over the column through drop_cx of Ct (1 - Fl) dx: a column with
+    k solid cells, one cell a quarter liquid and liquid above gives (k + 0.75) dx; order
+    parameter below one scales a cell by Ct; other columns do not count."""
+    n, k, dx = 32, 9, 1.0
+    p = wl.droplet_problem(n, 8.0, ste=0.1, bo_m=0.0, angle_deg=90.0, precision="fp64")
+    p.update(init_max=0)
+    o = orc.Oracle(p, init=False)
+    L = o.params.latent
+    ic = int(np.floor(p["drop"][0] / dx))
+    C = np.ones((n, n))
+    He = np.full((n, n), 2.0 * L)
+    He[:k, ic] = -0.5
+    He[k, ic] = 0.25 * L
+    He[:20, ic + 1] = -0.5          # a neighbouring column, frozen higher up
+    o.set("C", C)
+    o.set("He", He)
+    assert o.observe()["solid_height"] == pytest.approx((k + 0.75) * dx, rel=1e-14)
+    C[2, ic] = 0.6                  # solid cell with Ct = 0.6: Fs = 0.6
+    o.set("C", C)
+    o.set("He", He)
+    assert o.observe()["solid_height"] == pytest.approx((k - 0.4 + 0.75) * dx, rel=1e-14)
+    assert o.observe()["height"] == pytest.approx((n - 0.4) * dx, rel=1e-14)

@@ -1,4 +1,4 @@
-"""Host logic of the Sec. 5 study driver: case generation, t* and the Fig. 17 slope."""
+"""Host logic of the Sec. 5 study driver: case generation, t* and the Fig. 17 slopes."""
 import math
 
 import pytest
@@ -30,3 +30,25 @@ def test_t_star_and_scaling_slope():
     # points on H = (Ste Fo)^0.5 give the slope 0.5 exactly
     pts = [_res(s, 0.0, "none", 1.0, fo, math.sqrt(s * fo)) for s, fo in ((0.1, 2.0), (0.2, 3.0), (0.3, 0.7))]
     assert studies.scaling_slope(pts) == pytest.approx(0.5, abs=1e-12)
+
+
+def test_front_scaling_recovers_a_square_root_rise():
+    """Series with Hs/R0 = c sqrt(Ste Fo) (c differing between cases) give the slope 0.5
+    per case and pooled; points outside the 10-60% window of the final frozen height and
+    cases that did not freeze are left out."""
+    import numpy as np
+    res = []
+    for ste, c in ((0.1, 1.4), (0.2, 1.3), (0.3, 1.5)):
+        fo = np.linspace(0.001, 2.0, 400)
+        hs = c * np.sqrt(ste * fo)
+        hs[-5:] = hs[-6] * np.linspace(2.0, 3.0, 5)      # the apex: the front accelerates
+        res.append(dict(case=dict(ste=ste, bo_m=0.0, orientation="none"), frozen=True,
+                        series=dict(fo=list(fo), hs_r0=list(hs))))
+    res.append(dict(case=dict(ste=0.5, bo_m=0.0, orientation="none"), frozen=False,
+                    series=dict(fo=[1.0, 2.0], hs_r0=[5.0, 1.0])))
+    out = studies.front_scaling(res)
+    assert len(out["cases"]) == 3
+    for c in out["cases"]:
+        assert c["slope"] == pytest.approx(0.5, abs=1e-9)
+    # the prefactors differ between cases, so the pooled slope is 0.5 only approximately
+    assert out["slope"] == pytest.approx(0.5, abs=0.05)
