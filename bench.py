@@ -89,6 +89,9 @@ def parse():
                     help="skip the rates with per-step observables or checkpoints over PCIe")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--tile-shapes", default=None, metavar="STAGE,MAG",
+                    help="use these tile-shape indices instead of the defaults or the autotuner (counter "
+                         "runs: collecting counters distorts the autotuner's timings)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="time the candidate tile shapes first (auto: for the batch only; single solves "
                          "keep the default shapes, so that runs and profiles use the same kernels)")
@@ -343,7 +346,11 @@ def run_single(args, torch, lbfs, wl) -> dict:
         si, mi = solver.tile_shapes_in_use()
         fused = lbfs.mag_fused_index(prob["precision"])
         solver.set_tile_shapes(si, fused if args.mag_in_stage1 == "on" else (mi if mi != fused else 0))
-    tuned = solver.autotune() if args.autotune == "on" else None
+    if args.tile_shapes:
+        solver.set_tile_shapes(*(int(v) for v in args.tile_shapes.split(",")))
+        tuned = None
+    else:
+        tuned = solver.autotune() if args.autotune == "on" else None
     shapes = shape_names(lbfs, prob["precision"], solver.tile_shapes_in_use())
     host_io = None if args.no_host_io else host_boundary(solver, lbfs, cells, max(5, min(200, args.steps // 10)))
     solver.step(args.warmup)
@@ -361,7 +368,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
                 "mag_method": prob.get("mag_method", "sweeps"),
                 "mag_max_iters": prob.get("mag_max_iters", 0), "mag_tol": prob.get("mag_tol", 0.0),
                 "sweeps_per_step": prob["sweeps"], "reductions": "f64",
-                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default")})
+                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else
+                                    ("given" if args.tile_shapes else "default"))})
     profile_key = args.workload + ("-mag-lbfs" if args.mag_method == "lbfs" else "")
     out["roofline"] = roofline(kern, cells, prob["precision"], profile_key, shapes, mag_flops, mag_launches,
                                exclude=("mag",) if args.mag_method == "multigrid" else ())
@@ -388,7 +396,11 @@ def run_batch(args, torch, lbfs, wl) -> dict:
     for p in probs:
         if batch.admit(p) is None:
             raise RuntimeError("the batch buffer is too small for the workload")
-    tuned = batch.autotune(reps=10) if args.autotune in ("auto", "on") else None
+    if args.tile_shapes:
+        batch.set_tile_shapes(*(int(v) for v in args.tile_shapes.split(",")))
+        tuned = None
+    else:
+        tuned = batch.autotune(reps=10) if args.autotune in ("auto", "on") else None
     shapes = shape_names(lbfs, "fp32", batch.tile_shapes_in_use())
     batch.step(args.warmup)
     torch.cuda.synchronize()
@@ -403,7 +415,7 @@ def run_batch(args, torch, lbfs, wl) -> dict:
                {"workload": f"batch of {len(probs)} droplets, edges 64-256 (seed 1), FP32", "instances": len(probs),
                 "cells": cells, "edges": sorted({p["nx"] for p in probs}), "precision": "fp32",
                 "sweeps_per_step": probs[0]["sweeps"], "reductions": "f64",
-                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else "default"),
+                "tile_shapes": dict(shapes, chosen_by="autotuner" if tuned else ("given" if args.tile_shapes else "default")),
                 "launches_per_step": "one graph replay"})
     out["roofline"] = roofline(kern, cells, "fp32", args.workload, shapes)
     out.update(kernel_fields(kern))
