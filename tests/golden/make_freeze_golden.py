@@ -6,7 +6,9 @@ follows the droplet until it has frozen completely; Eq. 51 measures the frozen p
 The recorded value is the first step, checked after every step, at which it holds; the
 liquid fraction at a quarter, half and three quarters of that time is kept as well.
 
-Calls only the oracle.   python3 tests/golden/make_freeze_golden.py
+Calls only the oracle.   python3 tests/golden/make_freeze_golden.py [case ...]
+(named cases only: they are recomputed and merged into the existing file; the 128 x 128
+case takes about half an hour on one core)
 """
 from __future__ import annotations
 
@@ -23,6 +25,7 @@ from paper_2511_10257_amd import workloads as wl  # noqa: E402
 CASES = {
     "droplet32": dict(n=32, radius=8.0, ste=0.1, bo_m=1.0, angle_deg=45.0),
     "droplet64": dict(n=64, radius=16.0, ste=0.1, bo_m=0.5, angle_deg=90.0),
+    "droplet128": dict(n=128, radius=32.0, ste=0.1, bo_m=1.5, angle_deg=0.0),
 }
 THRESHOLD = 1e-3
 
@@ -44,8 +47,13 @@ def freeze(case: dict) -> dict:
 
 
 def main():
-    out = {name: freeze(case) for name, case in CASES.items()}
-    with open(os.path.join(HERE, "freeze_time.json"), "w") as f:
+    path = os.path.join(HERE, "freeze_time.json")
+    names = sys.argv[1:] or list(CASES)
+    out = json.load(open(path)) if sys.argv[1:] and os.path.exists(path) else {}
+    for name in names:
+        out[name] = freeze(CASES[name])
+    out = {name: out[name] for name in CASES if name in out}
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out, indent=1))
