@@ -85,6 +85,9 @@ def parse():
                          "between two sampled ones run as two 16-step graph replays)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-freeze-check", action="store_true",
+                    help="droplet256: skip solving the workload to freezing in FP32 and FP64 (about 10 s; "
+                         "also skipped with --no-cpu-baseline)")
     ap.add_argument("--no-host-io", action="store_true",
                     help="skip the rates with per-step observables or checkpoints over PCIe")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -265,6 +268,39 @@ def host_boundary(solver, lbfs, cells: int, n: int) -> dict:
             "note": "before the warm-up, outside the timed region; the timed value keeps the state resident"}
 
 
+def freezing_fp32_vs_fp64(lbfs, wl, prob: dict) -> dict:
+    """The workload solved to freezing (liquid fraction below 1e-3) in FP32 and in FP64 on
+    the GPU; the FP64 path is held to the oracle at rounding level by the parity tests.
+    FP64 is stepped in chunks of 2000 with a checkpoint before each, then one step at a
+    time from the last checkpoint; FP32 is stepped to 99% of the FP64 step, then one step
+    at a time."""
+    def exact(s, start, cap):
+        step = start
+        fl = s.observe()["liquid_fraction"]
+        while fl >= 1e-3 and step < cap:
+            s.step(1)
+            step += 1
+            fl = s.observe()["liquid_fraction"]
+        return step
+    t0 = time.perf_counter()
+    s64 = lbfs.Solver(wl.with_changes(prob, precision="fp64", init_tol=1e-9))
+    step, blob = 0, s64.save()
+    while s64.observe()["liquid_fraction"] >= 1e-3 and step < 1000000:
+        blob = s64.save()
+        s64.step(2000)
+        step += 2000
+    s64.load(blob)
+    n64 = exact(s64, max(0, step - 2000), step + 1)
+    s64.close()
+    s32 = lbfs.Solver(prob)
+    start = int(0.99 * n64)
+    s32.step(start)
+    n32 = exact(s32, start, int(1.02 * n64))
+    s32.close()
+    return {"fp32_freeze_step": n32, "fp64_freeze_step": n64, "rel_diff": abs(n32 - n64) / n64, "bound": 0.005,
+            "seconds": time.perf_counter() - t0}
+
+
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict, mag_flops=None,
              mag_launches: int = 1, exclude=()) -> dict:
     """Roofline of the kernel kind with the largest mean duration per step. The magnetic
@@ -384,6 +420,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, solver)
         if cells <= 1024 * 1024:
             out["error_vs_oracle"] = error_vs_oracle(solver, prob)
+        if args.workload == "droplet256" and args.mag_method == "sweeps" and not args.no_freeze_check:
+            out["freezing_fp32_vs_fp64"] = freezing_fp32_vs_fp64(lbfs, wl, prob)
     return out
 
 

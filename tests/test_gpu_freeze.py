@@ -47,3 +47,34 @@ def test_freezing_time_matches_oracle(name, precision):
     for q, v in g["fl_at"].items():
         assert abs(fl_at[q] - v) <= tol, (q, fl_at[q], v)
     s.close()
+
+
+def _freeze_step(s, start, cap):
+    """First step at which the liquid fraction is below 1e-3: the solver is stepped to
+    `start` (below the freezing time), then one step at a time."""
+    s.step(start)
+    step = start
+    fl = s.observe()["liquid_fraction"]
+    while fl >= 1e-3 and step < cap:
+        s.step(1)
+        step += 1
+        fl = s.observe()["liquid_fraction"]
+    return step
+
+
+def test_fp32_freezing_time_matches_fp64_on_the_256_droplet():
+    """The benchmark's 256^2 droplet solved to freezing in FP32 (FP64 reductions) and in
+    FP64 on the GPU (the FP64 path is held to the oracle at rounding level by the parity
+    tests): the freezing steps agree within 0.5 %."""
+    p32 = wl.droplet256()
+    p64 = wl.with_changes(p32, precision="fp64", init_tol=1e-9)
+    probe = lbfs.Solver(p64)
+    # coarse search for the FP64 freezing step, then the exact one
+    step = 0
+    while probe.observe()["liquid_fraction"] >= 1e-3 and step < 400000:
+        probe.step(2000)
+        step += 2000
+    n64 = _freeze_step(lbfs.Solver(p64), max(0, step - 2000), step + 1)
+    n32 = _freeze_step(lbfs.Solver(p32), int(0.99 * n64), int(1.02 * n64))
+    print(f"256^2 droplet: freezing step FP32 {n32}, FP64 {n64}")
+    assert abs(n32 - n64) <= 0.005 * n64
