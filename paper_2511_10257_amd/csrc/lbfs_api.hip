@@ -180,6 +180,18 @@ struct MgCtx {
     void* phi[2] = {nullptr, nullptr};           // level-0 unknown, by potential parity
     int pitch = 0;                               // of the level-0 unknown
     int fixed_walls = 0;                         // bit w: wall w (W, E, S, N) holds the potential
+    // per level, in level-0 cells: the cell width and the widths of the last column and
+    // row (narrower where a halving had an odd count)
+    int w[24] = {}, lastx[24] = {}, lasty[24] = {};
+    // launch argument of the coarsening and prolongation between levels l and l + 1
+    void geom(int l, int* g) const
+    {
+        g[0] = w[l];
+        g[1] = lastx[l];
+        g[2] = lasty[l];
+        g[3] = lastx[l + 1];
+        g[4] = lasty[l + 1];
+    }
 };
 
 // V(2,2) cycles with the coarsest level by red-black SOR in one workgroup
@@ -243,9 +255,12 @@ hipError_t mg_run(const Exec& E, const MgCtx& M, int ncycles, hipEvent_t e0)
     auto P = [&](int l) { return l == 0 ? M.pitch : M.nx[l]; };
     hipError_t e = launch_mg_setup0<T>(E.dinst, M.nx[0], M.ny[0], B + M.f[0], B + M.wx[0], B + M.wy[0], B + M.f[0],
                                        E.stream, e0);
-    for (int l = 0; l + 1 < M.L && e == hipSuccess; l++)
+    int g[5];
+    for (int l = 0; l + 1 < M.L && e == hipSuccess; l++) {
+        M.geom(l, g);
         e = launch_mg_coarsen<T>(M.nx[l], M.ny[l], B + M.wx[l], B + M.wy[l], M.nx[l + 1], M.ny[l + 1],
-                                 B + M.wx[l + 1], B + M.wy[l + 1], E.stream);
+                                 B + M.wx[l + 1], B + M.wy[l + 1], g, E.stream);
+    }
     const int c = M.L - 1;
     const int nmax = std::max(M.nx[c], M.ny[c]);
     const double om = 2.0 / (1.0 + std::sin(M_PI / std::max(nmax, 2)));
@@ -261,8 +276,9 @@ hipError_t mg_run(const Exec& E, const MgCtx& M, int ncycles, hipEvent_t e0)
             e = launch_mg_coarsest<T>(M.nx[c], M.ny[c], P(c), U(c), B + M.f[c], B + M.wx[c], B + M.wy[c],
                                       MG_COARSE_SWEEPS, om, E.stream);
         for (int l = c - 1; l >= 0 && e == hipSuccess; l--) {
+            M.geom(l, g);
             e = launch_mg_prolong<T>(M.nx[l], M.ny[l], P(l), U(l), M.nx[l + 1], M.ny[l + 1], U(l + 1),
-                                     M.fixed_walls, E.stream);
+                                     M.fixed_walls, g, E.stream);
             if (e == hipSuccess)
                 e = launch_mg_smooth<T>(M.nx[l], M.ny[l], P(l), U(l), B + M.f[l], B + M.wx[l], B + M.wy[l], MG_POST,
                                         E.stream);
@@ -639,16 +655,24 @@ int mg_plan(lbfs_solver* s)
     };
     int nx = s->p.nx, ny = s->p.ny;
     int L = 0;
+    int w = 1, lx = 1, ly = 1;
     while (true) {
         if (L >= 24) return LBFS_E_INVAL;
         M.nx[L] = nx;
         M.ny[L] = ny;
+        M.w[L] = w;
+        M.lastx[L] = lx;
+        M.lasty[L] = ly;
         M.wx[L] = take((size_t)(nx + 1) * ny);
         M.wy[L] = take((size_t)nx * (ny + 1));
         M.f[L] = take((size_t)nx * ny);
         M.u[L] = L == 0 ? 0 : take((size_t)nx * ny);
         L++;
         if (std::max(nx, ny) <= MG_COARSE) break;
+        // the last coarse cell covers the last two fine cells, or only the last one
+        lx = nx % 2 == 0 ? w + lx : lx;
+        ly = ny % 2 == 0 ? w + ly : ly;
+        w *= 2;
         nx = (nx + 1) / 2;
         ny = (ny + 1) / 2;
     }

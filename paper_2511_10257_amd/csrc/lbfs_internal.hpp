@@ -162,7 +162,7 @@ hipError_t launch_mg_setup0(const DevInst* insts, int nx, int ny, T* mu_tmp, T* 
                             hipEvent_t e0 = nullptr);
 template <typename T>
 hipError_t launch_mg_coarsen(int nxf, int nyf, const T* wxf, const T* wyf, int nxc, int nyc, T* wxc, T* wyc,
-                             hipStream_t stream);
+                             const int* geom, hipStream_t stream);
 template <typename T>
 hipError_t launch_mg_smooth(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
                             hipStream_t stream);
@@ -170,10 +170,12 @@ template <typename T>
 hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T* ff, const T* wxf, const T* wyf,
                               int nxc, int nyc, T* fc, T* uc, hipStream_t stream);
 // fixed_walls: bit w set where wall w (W, E, S, N) holds the potential (the correction
-// vanishes there); other walls are insulating
+// vanishes there); other walls are insulating. geom (coarsening and prolongation): the
+// fine level's cell width in level-0 cells, the widths of its last column and last row,
+// and those of the coarse level's last column and last row.
 template <typename T>
 hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, int fixed_walls,
-                             hipStream_t stream);
+                             const int* geom, hipStream_t stream);
 template <typename T>
 hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const T* wx, const T* wy, int sweeps,
                               double omega, hipStream_t stream);

@@ -1677,27 +1677,47 @@ __global__ __launch_bounds__(256) void k_mg_rhs0(const DevInst* __restrict__ ins
            ws * (j == 0 ? T(0.5) * hy : hy) - wn * (j == ny - 1 ? T(0.5) * hy : hy);
 }
 
-// coarse face weights: the mean of the one or two fine faces a coarse face covers
+// Cell widths along one axis of a multigrid level, in level-0 cells: every cell is w
+// wide but the last, which is `last` wide (less when a halving had an odd count).
+struct MgAxis {
+    int n, w, last;
+    __device__ __forceinline__ int width(int i) const { return i == n - 1 ? last : w; }
+    __device__ __forceinline__ int start(int i) const { return i * w; }
+    // distance between the centres of the cells on either side of face f (0..n), or from
+    // the centre of a boundary cell to its wall
+    __device__ __forceinline__ double face_dist(int f) const
+    {
+        return f == 0 ? 0.5 * width(0) : (f == n ? 0.5 * width(n - 1) : 0.5 * (width(f - 1) + width(f)));
+    }
+};
+
+// coarse face weights: a face weight is the permeability times the face's length over
+// the distance between the centres it connects (a two-dimensional conductance), so the
+// coarse weight is the sum over the one or two fine faces it covers of weight x fine
+// centre distance, over the coarse centre distance. For regular cells this is the mean
+// of the fine faces; it also holds where a halving of an odd count leaves a narrower
+// last cell.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_coarsen(int nxf, int nyf, const T* __restrict__ wxf,
                                                     const T* __restrict__ wyf, int nxc, int nyc, T* __restrict__ wxc,
-                                                    T* __restrict__ wyc)
+                                                    T* __restrict__ wyc, int wf, int lxf, int lyf, int lxc, int lyc)
 {
+    const MgAxis fx{nxf, wf, lxf}, fy{nyf, wf, lyf}, cx{nxc, 2 * wf, lxc}, cy{nyc, 2 * wf, lyc};
     const int nfx = (nxc + 1) * nyc, nfy = nxc * (nyc + 1);
     const int f = blockIdx.x * 256 + (int)threadIdx.x;
     if (f < nfx) {
         const int I = f % (nxc + 1), J = f / (nxc + 1);
         const int fi = min(2 * I, nxf);
-        T w = wxf[(2 * J) * (nxf + 1) + fi];
-        if (2 * J + 1 < nyf) w = T(0.5) * (w + wxf[(2 * J + 1) * (nxf + 1) + fi]);
-        wxc[f] = w;
+        T sum = wxf[(2 * J) * (nxf + 1) + fi];
+        if (2 * J + 1 < nyf) sum += wxf[(2 * J + 1) * (nxf + 1) + fi];
+        wxc[f] = sum * T(fx.face_dist(fi) / cx.face_dist(I));
     } else if (f < nfx + nfy) {
         const int g = f - nfx;
         const int I = g % nxc, J = g / nxc;
         const int fj = min(2 * J, nyf);
-        T w = wyf[fj * nxf + 2 * I];
-        if (2 * I + 1 < nxf) w = T(0.5) * (w + wyf[fj * nxf + 2 * I + 1]);
-        wyc[g] = w;
+        T sum = wyf[fj * nxf + 2 * I];
+        if (2 * I + 1 < nxf) sum += wyf[fj * nxf + 2 * I + 1];
+        wyc[g] = sum * T(fy.face_dist(fj) / cy.face_dist(J));
     }
 }
 
@@ -1758,32 +1778,61 @@ __global__ __launch_bounds__(256) void k_mg_restrict(int nxf, int nyf, int pitch
     uc[c] = T(0);
 }
 
+// the coarse cell a fine cell interpolates from besides its own, and that cell's weight,
+// along one axis: linear in the cell-centre positions; beyond a wall the neighbour is the
+// mirror image of the boundary cell (sign -1 at a fixed-potential wall)
+struct MgInterp {
+    int nb;
+    double t, sign;
+};
+__device__ __forceinline__ MgInterp mg_interp(const MgAxis& f, const MgAxis& c, int i, int I, bool fixed_lo,
+                                              bool fixed_hi)
+{
+    const double xf = f.start(i) + 0.5 * f.width(i);
+    const double xc = c.start(I) + 0.5 * c.width(I);
+    MgInterp r{I, 0.0, 1.0};
+    if (xf == xc) return r;
+    double xn;
+    if (xf < xc) {
+        if (I > 0) {
+            r.nb = I - 1;
+            xn = c.start(I - 1) + 0.5 * c.width(I - 1);
+        } else {
+            xn = -xc;   // mirror across the wall at 0
+            r.sign = fixed_lo ? -1.0 : 1.0;
+        }
+    } else {
+        if (I < c.n - 1) {
+            r.nb = I + 1;
+            xn = c.start(I + 1) + 0.5 * c.width(I + 1);
+        } else {
+            const double wall = c.start(I) + c.width(I);
+            xn = 2.0 * wall - xc;
+            r.sign = fixed_hi ? -1.0 : 1.0;
+        }
+    }
+    r.t = (xf - xc) / (xn - xc);
+    return r;
+}
+
 // add the coarse correction to every child, interpolated bilinearly from the four
-// nearest coarse cells (9/16 its own, 3/16 each side neighbour, 1/16 the diagonal; a
-// neighbour beyond the domain is the cell's mirror image across the wall)
+// nearest coarse cell centres (for regular cells 9/16 its own, 3/16 each side
+// neighbour, 1/16 the diagonal)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_prolong(int nxf, int nyf, int pitchf, T* __restrict__ uf, int nxc,
-                                                    int nyc, const T* __restrict__ uc, int fixed_walls)
+                                                    int nyc, const T* __restrict__ uc, int fixed_walls, int wf,
+                                                    int lxf, int lyf, int lxc, int lyc)
 {
     const int c = blockIdx.x * 256 + (int)threadIdx.x;
     if (c >= nxf * nyf) return;
     const int i = c % nxf, j = c / nxf;
     const int I = i / 2, J = j / 2;
-    int In = I + ((i & 1) ? 1 : -1), Jn = J + ((j & 1) ? 1 : -1);
-    // beyond a wall the coarse correction continues as its mirror image: odd where the
-    // wall holds the potential (the correction is zero on the wall, half a coarse cell
-    // away), even at an insulating wall (zero normal derivative)
-    T sx = T(1), sy = T(1);
-    if (In < 0 || In >= nxc) {
-        sx = (fixed_walls >> (In < 0 ? 0 : 1)) & 1 ? T(-1) : T(1);
-        In = I;
-    }
-    if (Jn < 0 || Jn >= nyc) {
-        sy = (fixed_walls >> (Jn < 0 ? 2 : 3)) & 1 ? T(-1) : T(1);
-        Jn = J;
-    }
-    const T v = T(9.0 / 16.0) * uc[J * nxc + I] + T(3.0 / 16.0) * (sx * uc[J * nxc + In] + sy * uc[Jn * nxc + I]) +
-                T(1.0 / 16.0) * (sx * sy) * uc[Jn * nxc + In];
+    const MgAxis fx{nxf, wf, lxf}, fy{nyf, wf, lyf}, cx{nxc, 2 * wf, lxc}, cy{nyc, 2 * wf, lyc};
+    const MgInterp ax = mg_interp(fx, cx, i, I, fixed_walls & 1, (fixed_walls >> 1) & 1);
+    const MgInterp ay = mg_interp(fy, cy, j, J, (fixed_walls >> 2) & 1, (fixed_walls >> 3) & 1);
+    const T wx0 = T(1.0 - ax.t), wx1 = T(ax.t * ax.sign), wy0 = T(1.0 - ay.t), wy1 = T(ay.t * ay.sign);
+    const T v = wy0 * (wx0 * uc[J * nxc + I] + wx1 * uc[J * nxc + ax.nb]) +
+                wy1 * (wx0 * uc[ay.nb * nxc + I] + wx1 * uc[ay.nb * nxc + ax.nb]);
     uf[(size_t)j * pitchf + i] += v;
 }
 
@@ -1837,11 +1886,11 @@ hipError_t launch_mg_setup0(const DevInst* insts, int nx, int ny, T* mu_tmp, T* 
 
 template <typename T>
 hipError_t launch_mg_coarsen(int nxf, int nyf, const T* wxf, const T* wyf, int nxc, int nyc, T* wxc, T* wyc,
-                             hipStream_t stream)
+                             const int* geom, hipStream_t stream)
 {
     const int nf = (nxc + 1) * nyc + nxc * (nyc + 1);
     hipLaunchKernelGGL((k_mg_coarsen<T>), dim3((nf + 255) / 256), dim3(256), 0, stream, nxf, nyf, wxf, wyf, nxc, nyc,
-                       wxc, wyc);
+                       wxc, wyc, geom[0], geom[1], geom[2], geom[3], geom[4]);
     return hipGetLastError();
 }
 
@@ -1868,11 +1917,11 @@ hipError_t launch_mg_restrict(int nxf, int nyf, int pitchf, const T* uf, const T
 
 template <typename T>
 hipError_t launch_mg_prolong(int nxf, int nyf, int pitchf, T* uf, int nxc, int nyc, const T* uc, int fixed_walls,
-                             hipStream_t stream)
+                             const int* geom, hipStream_t stream)
 {
     const int n = nxf * nyf;
     hipLaunchKernelGGL((k_mg_prolong<T>), dim3((n + 255) / 256), dim3(256), 0, stream, nxf, nyf, pitchf, uf, nxc, nyc,
-                       uc, fixed_walls);
+                       uc, fixed_walls, geom[0], geom[1], geom[2], geom[3], geom[4]);
     return hipGetLastError();
 }
 
@@ -1900,11 +1949,13 @@ hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const
     template hipError_t launch_derived<T>(const DevInst*, const Tile*, int, hipStream_t);                 \
     template hipError_t launch_wall_profile<T>(const DevInst*, int, double*, hipStream_t);                \
     template hipError_t launch_mg_setup0<T>(const DevInst*, int, int, T*, T*, T*, T*, hipStream_t, hipEvent_t); \
-    template hipError_t launch_mg_coarsen<T>(int, int, const T*, const T*, int, int, T*, T*, hipStream_t); \
+    template hipError_t launch_mg_coarsen<T>(int, int, const T*, const T*, int, int, T*, T*, const int*,     \
+                                             hipStream_t);                                                \
     template hipError_t launch_mg_smooth<T>(int, int, int, T*, const T*, const T*, const T*, int, hipStream_t); \
     template hipError_t launch_mg_restrict<T>(int, int, int, const T*, const T*, const T*, const T*, int, int, T*, T*, \
                                               hipStream_t);                                            \
-    template hipError_t launch_mg_prolong<T>(int, int, int, T*, int, int, const T*, int, hipStream_t);  \
+    template hipError_t launch_mg_prolong<T>(int, int, int, T*, int, int, const T*, int, const int*,     \
+                                             hipStream_t);                                                \
     template hipError_t launch_mg_coarsest<T>(int, int, int, T*, const T*, const T*, const T*, int, double, \
                                               hipStream_t);
 

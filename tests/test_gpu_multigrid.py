@@ -35,9 +35,9 @@ def test_cycles_converge_to_the_sweeps_fixed_point(shape):
     prob, o, g = case(*shape, seed=3)
     r0 = g.mag_sweeps(0)
     res = [g.mag_multigrid(1) for _ in range(25)]
-    # V(2,2): the first cycle removes most of the applied field's residual, later ones a
-    # tenth (even halvings) to a fifth (150 x 70, whose coarser levels have odd sizes)
-    assert res[0] < 0.05 * r0 and res[11] < 1e-6 * r0 and res[-1] < 1e-12 * r0, res
+    # V(2,2): the first cycle removes most of the applied field's residual, later ones
+    # reduce it 10-20 times each, also where halvings give odd sizes (150 x 70, 33 x 17)
+    assert res[0] < 0.02 * r0 and res[7] < 1e-8 * r0 and res[-1] < 1e-12 * r0, res
     assert all(b <= a * 1.0001 or b < 1e-13 * r0 for a, b in zip(res, res[1:]))
     converge_oracle(o)
     po, pg = o.get("phi"), g.get("phi")
