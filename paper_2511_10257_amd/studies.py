@@ -222,6 +222,25 @@ def front_scaling(results: list[dict], lo: float = 0.1, hi: float = 0.6) -> dict
     return dict(slope=float(np.polyfit(x, y, 1)[0]) if x.size >= 2 else float("nan"), cases=per)
 
 
+def write_csv(results: list[dict], directory: str) -> list[str]:
+    """One CSV per case: step, Fo, Ste Fo, H/R0, Hs/R0, Pe, Q_L, liquid fraction, wall heat."""
+    import os
+    os.makedirs(directory, exist_ok=True)
+    paths = []
+    for r in results:
+        c = r["case"]
+        path = os.path.join(directory, f"ste{c['ste']:g}_bo{c['bo_m']:g}_{c['orientation']}.csv")
+        s = r["series"]
+        with open(path, "w") as f:
+            f.write("step,fo,ste_fo,h_r0,hs_r0,pe,q_l,liquid_fraction,wall_heat\n")
+            for k in range(len(s["step"])):
+                f.write(f"{s['step'][k]},{s['fo'][k]:.9g},{c['ste'] * s['fo'][k]:.9g},{s['h_r0'][k]:.9g},"
+                        f"{s['hs_r0'][k]:.9g},{s['pe'][k]:.9g},{s['q_l'][k]:.9g},{s['fl'][k]:.9g},"
+                        f"{s['wall_heat'][k]:.9g}\n")
+        paths.append(path)
+    return paths
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--deformation", action="store_true",
@@ -238,6 +257,8 @@ def main(argv=None):
     ap.add_argument("--gas-lambda-ratio", type=float, default=None,
                     help="gas conductivity over the liquid's at the default gas diffusivity (air: 0.036)")
     ap.add_argument("--out", default=None, help="write the results as JSON here")
+    ap.add_argument("--csv", default=None, metavar="DIR",
+                    help="also write each case's time series (Figs. 11, 12, 16, 17) as a CSV file in DIR")
     args = ap.parse_args(argv)
     if args.static:
         res = static_freezing([float(t) for t in args.static.split(",")], nx=2 * args.edge, ny=args.edge,
@@ -263,6 +284,8 @@ def main(argv=None):
             print(f"studies: step {steps}, {nlive} cases still freezing", file=sys.stderr, flush=True)
 
     res = run(cases, chunk=args.chunk, max_steps=args.max_steps, progress=progress)
+    if args.csv:
+        write_csv(res, args.csv)
     per_case = [dict(r["case"], frozen=r.get("frozen", False), freeze_step=r.get("freeze_step"),
                      freeze_fo=r.get("freeze_fo"), hm_r0=r.get("hm_r0"),
                      h_r0_max=max(r["series"]["h_r0"]) if r["series"]["h_r0"] else None,

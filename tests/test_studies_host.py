@@ -52,3 +52,13 @@ def test_front_scaling_recovers_a_square_root_rise():
         assert c["slope"] == pytest.approx(0.5, abs=1e-9)
     # the prefactors differ between cases, so the pooled slope is 0.5 only approximately
     assert out["slope"] == pytest.approx(0.5, abs=0.05)
+
+
+def test_write_csv_one_file_per_case(tmp_path):
+    res = [dict(case=dict(ste=0.1, bo_m=4.0, orientation="vertical"),
+                series=dict(step=[50, 100], fo=[0.01, 0.02], h_r0=[1.0, 1.01], hs_r0=[0.1, 0.15], pe=[2.0, 1.0],
+                            q_l=[0.05, 0.1], fl=[0.9, 0.8], wall_heat=[-1.0, -0.9]))]
+    (path,) = studies.write_csv(res, str(tmp_path))
+    rows = open(path).read().splitlines()
+    assert path.endswith("ste0.1_bo4_vertical.csv") and len(rows) == 3
+    assert rows[0].startswith("step,fo,ste_fo") and rows[2].split(",")[2] == "0.002"
