@@ -80,9 +80,9 @@ def parse():
     ap.add_argument("--workload", default="droplet256",
                     choices=["droplet64", "droplet256", "droplet1024", "droplet1024-fp64", "droplet4096", "batch64",
                              "serve"])
-    ap.add_argument("--sample-every", type=int, default=33,
-                    help="bracket the kernels of every n-th timed step with HIP events (the 32 steps "
-                         "between two sampled ones run as two 16-step graph replays)")
+    ap.add_argument("--sample-every", type=int, default=97,
+                    help="bracket the kernels of every n-th timed step with HIP events (the 96 steps "
+                         "between two sampled ones run as six 16-step graph replays)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-freeze-check", action="store_true",
