@@ -85,6 +85,9 @@ def parse():
                          "between two sampled ones run as six 16-step graph replays)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--freeze-check", action="store_true",
+                    help="solve the workload to freezing in FP32 and in FP64 and report both freezing steps "
+                         "(single solves; about 17 minutes for droplet1024)")
     ap.add_argument("--no-freeze-check", action="store_true",
                     help="droplet256: skip solving the workload to freezing in FP32 and FP64 (about 10 s; "
                          "also skipped with --no-cpu-baseline)")
@@ -283,18 +286,26 @@ def freezing_fp32_vs_fp64(lbfs, wl, prob: dict) -> dict:
             fl = s.observe()["liquid_fraction"]
         return step
     t0 = time.perf_counter()
+    # chunks of about a hundredth of the freezing time (which grows as R^2)
+    chunk = 2000 * max(1, prob["nx"] // 256) ** 2
     s64 = lbfs.Solver(wl.with_changes(prob, precision="fp64", init_tol=1e-9))
     step, blob = 0, s64.save()
-    while s64.observe()["liquid_fraction"] >= 1e-3 and step < 1000000:
+    while s64.observe()["liquid_fraction"] >= 1e-3 and step < 500 * chunk:
         blob = s64.save()
-        s64.step(2000)
-        step += 2000
+        s64.step(chunk)
+        step += chunk
+        print(f"bench: freezing check, FP64 step {step}", file=sys.stderr, flush=True)
     s64.load(blob)
-    n64 = exact(s64, max(0, step - 2000), step + 1)
+    n64 = exact(s64, max(0, step - chunk), step + 1)
     s64.close()
     s32 = lbfs.Solver(prob)
-    start = int(0.99 * n64)
-    s32.step(start)
+    start, step = int(0.99 * n64), 0
+    while step < start:
+        k = min(chunk, start - step)
+        s32.step(k)
+        step += k
+        s32.observe()
+        print(f"bench: freezing check, FP32 step {step}", file=sys.stderr, flush=True)
     n32 = exact(s32, start, int(1.02 * n64))
     s32.close()
     return {"fp32_freeze_step": n32, "fp64_freeze_step": n64, "rel_diff": abs(n32 - n64) / n64, "bound": 0.005,
@@ -422,6 +433,8 @@ def run_single(args, torch, lbfs, wl) -> dict:
             out["error_vs_oracle"] = error_vs_oracle(solver, prob)
         if args.workload == "droplet256" and args.mag_method == "sweeps" and not args.no_freeze_check:
             out["freezing_fp32_vs_fp64"] = freezing_fp32_vs_fp64(lbfs, wl, prob)
+    if args.freeze_check and "freezing_fp32_vs_fp64" not in out:
+        out["freezing_fp32_vs_fp64"] = freezing_fp32_vs_fp64(lbfs, wl, prob)
     return out
 
 
