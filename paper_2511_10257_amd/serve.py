@@ -55,13 +55,14 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 256, precision: str = "fp32", chunk: int = 100,
                  done_fl: float = 1e-3, max_steps: int | None = None, device: str = "cuda:0",
-                 on_finish=None):
+                 on_finish=None, on_admit=None):
         self.batch = lbfs.Batch(max_slots, hbm_budget, precision=precision, device=device)
         self.precision = precision
         self.chunk = int(chunk)
         self.done_fl = float(done_fl)
         self.max_steps = max_steps
-        self.on_finish = on_finish
+        self.on_finish = on_finish    # (request, slot view) before a solve retires
+        self.on_admit = on_admit      # (request, slot view) after a solve is admitted
         self.live: dict[int, Request] = {}
         self.cell_steps = 0
         self.chunks = 0
@@ -80,6 +81,8 @@ class Server:
                 continue
             req.slot, req.admitted = slot, now
             self.live[slot] = req
+            if self.on_admit is not None:
+                self.on_admit(req, self.batch.slot(slot))
         waiting.extend(kept)
 
     def run(self, arrivals, clock: str = "wall", horizon: float | None = None, cap: float | None = None,
@@ -139,7 +142,8 @@ class Server:
                 self.cell_steps += n * req.cells
                 req.liquid_fraction = o["liquid_fraction"]
                 req.nonfinite = bool(o["nonfinite"])
-                frozen = o["liquid_fraction"] < self.done_fl
+                # (a non-finite state can read as frozen: the clamps of Eq. 8 map NaN to a bound)
+                frozen = o["liquid_fraction"] < self.done_fl and not req.nonfinite
                 over = self.max_steps is not None and req.steps >= self.max_steps
                 if frozen or over or req.nonfinite:
                     req.obs = o

@@ -80,3 +80,40 @@ def test_request_larger_than_budget_is_rejected():
     rep = srv.run([(0, prob), (10, small)], clock="steps")
     srv.close()
     assert rep["rejected"] == 1 and rep["completed"] == 1
+
+
+def test_a_non_finite_solve_is_retired_and_the_others_finish():
+    """Failure handling, forced from the host: right after admission one request's state
+    gets a non-finite enthalpy in one cell (through its slot handle); the server retires
+    it with the non-finite flag at the next observation, and the requests sharing its
+    launches still finish with the fields they have alone."""
+    arrivals = [(0, wl.droplet_problem(16, 4.0, ste=0.5, bo_m=0.5, angle_deg=90.0, precision="fp32")),
+                (0, wl.droplet_problem(20, 5.0, ste=0.3, bo_m=1.0, angle_deg=45.0, precision="fp32")),
+                (20, wl.droplet_problem(24, 6.0, ste=0.4, bo_m=1.0, angle_deg=0.0, precision="fp32"))]
+    captured = {}
+
+    def on_admit(req, view):
+        if req.rid == 1:
+            he = view.get("He")
+            he[3, 7] = np.inf
+            view.set("He", he)
+
+    def on_finish(req, view):
+        captured[req.rid] = ({f: view.get(f) for f in FIELDS}, req.steps, dict(req.obs), req.nonfinite)
+
+    budget = sum(lbfs.Batch.instance_bytes(p) for _, p in arrivals) + (1 << 16)
+    srv = serve.Server(hbm_budget=budget, max_slots=4, chunk=50, max_steps=20000, on_finish=on_finish,
+                       on_admit=on_admit)
+    rep = srv.run(arrivals, clock="steps")
+    srv.close()
+    assert rep["nonfinite"] == 1 and rep["completed"] == 2 and rep["unfinished_live"] == 0, rep
+    _, steps_bad, obs_bad, nonfinite = captured[1]
+    assert nonfinite and obs_bad["nonfinite"] == 1 and steps_bad == 50
+    for rid in (0, 2):
+        fields, steps, obs, nonfinite = captured[rid]
+        assert not nonfinite and obs["liquid_fraction"] < 1e-3
+        alone = lbfs.Solver(arrivals[rid][1])
+        alone.step(steps)
+        for f in FIELDS:
+            assert np.array_equal(fields[f], alone.get(f)), (rid, f)
+        alone.close()
