@@ -115,6 +115,7 @@ def deformation(n: int, bo_list, steps: int, chunk: int = 500, precision: str = 
     if None in slots:
         raise RuntimeError("the batch buffer does not hold every case")
     series = {s: dict(step=[], b_over_a=[], umax=[]) for s in slots}
+    bad = set()
     done = 0
     while done < steps:
         k = min(chunk, steps - done)
@@ -125,13 +126,16 @@ def deformation(n: int, bo_list, steps: int, chunk: int = 500, precision: str = 
             series[s]["step"].append(int(o["step"]))
             series[s]["b_over_a"].append(o["semi_axis_y"] / o["semi_axis_x"] if o["semi_axis_x"] > 0 else float("nan"))
             series[s]["umax"].append(o["umax"])
+            if o["nonfinite"]:
+                bad.add(s)
     batch.close()
     out = []
     for p, s in zip(cases, slots):
         ba = np.array(series[s]["b_over_a"])
         tail = ba[len(ba) - max(1, len(ba) // 3):]
         out.append(dict(bo_m=p["bo_m"], radius=p["drop"][2], b_over_a=float(np.mean(tail)),
-                        b_over_a_spread=float(np.max(tail) - np.min(tail)), series=series[s]))
+                        b_over_a_spread=float(np.max(tail) - np.min(tail)), nonfinite=s in bad,
+                        series=series[s]))
     return out
 
 
