@@ -308,7 +308,18 @@ def freezing_fp32_vs_fp64(lbfs, wl, prob: dict) -> dict:
         print(f"bench: freezing check, FP32 step {step}", file=sys.stderr, flush=True)
     n32 = exact(s32, start, int(1.02 * n64))
     s32.close()
+    # the FP64 path's own throughput on the same workload (graph replays, state resident)
+    p64 = lbfs.Solver(wl.with_changes(prob, precision="fp64", init_tol=1e-9))
+    p64.step(200)
+    p64.observe()
+    n = 2000
+    t1 = time.perf_counter()
+    p64.step(n)
+    p64.observe()
+    t2 = time.perf_counter()
+    p64.close()
     return {"fp32_freeze_step": n32, "fp64_freeze_step": n64, "rel_diff": abs(n32 - n64) / n64, "bound": 0.005,
+            "fp64_mlups": prob["nx"] * prob["ny"] * n / (t2 - t1) / 1e6,
             "seconds": time.perf_counter() - t0}
 
 
