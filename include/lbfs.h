@@ -6,7 +6,9 @@
  * One time step (Table 1 of the paper, "computational procedure"):
  *   1. magnetic potential: the compact system that the magnetic LBFS of Sec. 3.1
  *      (Eqs. 12-18) reaches at delta_t = dx/2, i.e. Eq. 4 with face permeabilities,
- *      relaxed by `sweeps` red-black Gauss-Seidel/SOR sweeps (warm started);
+ *      relaxed by `sweeps` red-black Gauss-Seidel/SOR sweeps (warm started), by
+ *      `sweeps` SSP-RK3 pseudo-steps of Eq. 17 itself, or by multigrid cycles
+ *      (mag_method), optionally repeated until a residual target (mag_max_iters);
  *   2. Kelvin force F_mg = (mu0 chi / 2) grad |H|^2 (Eq. 6), held over the stages;
  *   3. three stages of strong-stability-preserving third-order Runge-Kutta (Eq. 46)
  *      on W = (He, p, rho cs^2 u, rho cs^2 v, C) (Eq. 39), each stage computing the
