@@ -14,8 +14,11 @@
  *      on W = (He, p, rho cs^2 u, rho cs^2 v, C) (Eq. 39), each stage computing the
  *      LBFS face fluxes (Eq. 44 reconstruction, Eq. 45 compatibility, star
  *      distributions Eqs. 16/22/32/33, moments Eq. 43) and the sources (Eq. 41);
- *   4. Eq. 8 (liquid fraction and temperature) after the step (Table 1 (d)), the
- *      lagged dFs/dt of Eqs. 9-10 and FP64 reductions of the observables.
+ *   4. Eq. 8 (liquid fraction and temperature) after the step (Table 1 (d)) and the
+ *      lagged dFs/dt of Eqs. 9-10.
+ * The observables (Eq. 51 and the quantities of Figs. 11, 12 and 15) are reduced in
+ * FP64 only when lbfs_observe is called, the "if output required" branch of Table 1;
+ * a step writes no partial sums.
  * Lattice units: c = 1, cs^2 = 1/3, streaming step delta_t = dx/2.
  *
  * Conventions
@@ -182,9 +185,14 @@ int lbfs_params_from_dimless(lbfs_params* p, double ste, double t_wall, double b
 /* Bytes of device memory one solver needs for these parameters; 0 if invalid. */
 size_t lbfs_state_bytes(const lbfs_params* p);
 
-/* Validate p, carve the state out of dev_buf (>= lbfs_state_bytes(p) bytes, caller
-   owned), initialise the fields (droplet or uniform) and converge the magnetic
-   potential. stream is a hipStream_t (NULL = default stream). Synchronous. */
+/* The "Initialization" block of Table 1: validate p, carve the state out of dev_buf
+   (>= lbfs_state_bytes(p) bytes, caller owned; LBFS_E_NOMEM if smaller), initialise
+   the fields (the half droplet on the cold wall of Fig. 8, or a uniform state: He
+   from Eq. 8 inverted at t_init, fluid at rest, p = 0) and converge the magnetic
+   potential of Eq. 4 for that state. stream is a hipStream_t (NULL = default stream).
+   *out receives the handle (owned by the library, released by lbfs_destroy).
+   LBFS_E_ABI on an abi_version mismatch, LBFS_E_INVAL on invalid parameters,
+   LBFS_E_DEVICE if a HIP call fails. Synchronous. */
 int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
               lbfs_solver** out);
 
@@ -197,8 +205,9 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
 /* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
    per 4 sweeps: permeability, sweeps, residual) and the three Runge-Kutta stages
-   (the third also applies Eq. 8 and writes per-tile FP64 partial sums). REDUCE, the
-   reduction of those partials, runs in lbfs_observe and is not timed here. */
+   (the third also applies Eq. 8 and stores the lagged dFs/dt). REDUCE, the FP64
+   reduction of the observables (per-tile partial sums, then one sum per instance),
+   runs in lbfs_observe and is not timed here. */
 enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUCE, LBFS_NKERNELS };
 
 /* lbfs_step with the kernel phases of every sample_every-th step timed: their launches
@@ -210,10 +219,15 @@ enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUC
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches);
 
-/* Synchronise the stream and return the observables of the current state: after the
-   last step, or as last written by lbfs_write_field or lbfs_load_state (mag_residual
-   is the one the last magnetic phase left). Returns LBFS_E_NONFINITE (with o filled)
-   when the state holds a non-finite value. */
+/* The "if output required" branch of Table 1. Synchronise the stream, reduce the
+   current state in FP64 (fixed order) and return its observables in *o (caller owned):
+   the solid ratio Q_L of Eq. 51, the liquid fraction, the height and frozen height
+   along the centre column (Fig. 11, Fig. 17), the wall heat (Fig. 15), max |u| and the
+   Peclet and Fourier numbers of Eq. 50 (Fig. 12), and the droplet shape moments. The
+   state is the one after the last step, or as last written by lbfs_write_field or
+   lbfs_load_state (mag_residual is the one the last magnetic phase left). Returns
+   LBFS_E_NONFINITE (with o filled) when the state holds a non-finite value,
+   LBFS_E_INVAL on a NULL argument. */
 int lbfs_observe(lbfs_solver* s, lbfs_observables* o);
 
 /* One evaluation of R(W) (Eq. 46) for the current state, with the Kelvin force of the

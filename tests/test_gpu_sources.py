@@ -1,0 +1,179 @@
+"""The HIP path (through the C ABI) on the closed-form source-term cases of the oracle
+pins: direct forcing, volume change, the order-parameter budget, the non-conservative
+pressure and enthalpy sources, the Kelvin force of a quadratic potential and the lagged
+solid-fraction rate. FP64 must match the oracle to rounding and the closed forms to
+their tolerance; FP32 within the per-step bound on the state."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2511_10257_amd import lbfs, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CS2 = 1.0 / 3.0
+NAMES = ("He", "p", "Mx", "My", "C", "S")
+# per-cell scale below which a field counts as zero in FP32 (orders of magnitude under
+# each field's size in these cases: He ~ 1-10, p ~ 1e-3, M ~ 1e-3, C ~ 1, S ~ 1e-3)
+FP32_FLOOR = dict(He=1e-3, p=1e-6, Mx=1e-9, My=1e-9, C=1e-3, S=1e-9)
+
+
+def rk3_gain(z):
+    return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0
+
+
+def box(nx=16, ny=8, latent=10.0, dt=0.5, periodic=(1, 1), precision="fp64", **kw):
+    p = wl.droplet_problem(nx, nx / 4.0, ste=0.1, bo_m=0.0, angle_deg=0.0, precision=precision, ny=ny)
+    p.update(periodic=list(periodic), init_kind="uniform", c_init=1.0, latent=latent, h0=0.0,
+             init_max=0, sweeps=0, mag_bc=["insulating"] * 4, chi=[0.0, 0.0, 0.0], dt=dt)
+    p.update(kw)
+    return p
+
+
+def uniform(prob, **v):
+    return {k: np.full((prob["ny"], prob["nx"]), float(x)) for k, x in v.items()}
+
+
+def both(prob, state, steps=1):
+    """Oracle (FP64) and HIP solver of prob from the same state, each advanced `steps`."""
+    o = orc.Oracle(dict(prob, precision="fp64"), init=False)
+    g = lbfs.Solver(prob)
+    o.set_state(state)
+    g.set_state(state)
+    if steps:
+        o.step(steps)
+        g.step(steps)
+    return o, g
+
+
+def assert_step_parity(o, g, precision):
+    for k in NAMES:
+        a, b = g.get(k), o.get(k)
+        nb = np.linalg.norm(b)
+        if precision == "fp64":
+            assert np.max(np.abs(a - b)) <= 1e-12 * (np.max(np.abs(b)) + 1e-300), k
+        else:
+            # relative L2 against the field's own norm; the small floor only admits FP32
+            # round-off where the oracle's field is zero
+            err = np.linalg.norm(a - b)
+            assert err <= 1e-5 * max(nb, FP32_FLOOR[k] * math.sqrt(b.size)), (k, err, nb)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("He,C,fs", [(-0.3, 1.0, 1.0), (5.0, 1.0, 0.5), (-0.2, 0.6, 0.6), (12.0, 1.0, 0.0)])
+def test_direct_forcing(precision, He, C, fs):
+    prob = box(dt=0.25, precision=precision)
+    st = uniform(prob, He=He, C=C, p=1e-3, Mx=2e-3, My=-1.3e-3, S=0.0, phi=0.0)
+    o, g = both(prob, st)
+    assert_step_parity(o, g, precision)
+    tol = 1e-17 if precision == "fp64" else 1e-9
+    assert np.max(np.abs(g.get("Mx") - 2e-3 * rk3_gain(-fs))) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_volume_change_uniform_liquid(precision):
+    prob = box(precision=precision)
+    vc = 1.0 - prob["rho"][0] / prob["rho"][1]
+    st = uniform(prob, He=12.0, C=1.0, p=1e-3, Mx=0.0, My=0.0, S=2e-3, phi=0.0)
+    o, g = both(prob, st)
+    assert_step_parity(o, g, precision)
+    tol = 1e-15 if precision == "fp64" else 3e-7
+    assert np.max(np.abs(g.get("C") - rk3_gain(vc * 2e-3 * 0.5))) < tol
+    expect_p = 1e-3 + 0.5 * prob["rho"][1] * CS2 * vc * 2e-3
+    assert np.max(np.abs(g.get("p") - expect_p)) < (1e-18 if precision == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_volume_change_gas_liquid_mixture(precision):
+    prob = box(precision=precision)
+    st = uniform(prob, He=20.0, C=0.5, p=0.0, Mx=0.0, My=0.0, S=-3e-3, phi=0.0)
+    o, g = both(prob, st)
+    assert_step_parity(o, g, precision)
+
+
+def test_order_parameter_budget_of_one_rhs():
+    """sum R_C = (1 - rho_s/rho_l) sum(S C) on the GPU (FP64), as in the oracle."""
+    prob = wl.droplet_problem(24, 6.0, ste=0.1, bo_m=1.0, angle_deg=30.0, precision="fp64")
+    prob["init_max"] = 0
+    vc = 1.0 - prob["rho"][0] / prob["rho"][1]
+    st = wl.smooth_state(24, 24, seed=7, latent=10.0, h0=0.01, angle_deg=30.0)
+    st["S"] = np.random.default_rng(11).normal(scale=2e-3, size=(24, 24))
+    o, g = both(prob, st, steps=0)
+    Rg, Ro = g.rhs(), o.rhs()
+    src = vc * math.fsum((st["S"] * st["C"]).ravel())
+    assert abs(math.fsum(Rg[4].ravel()) - src) < 1e-12 * np.sum(np.abs(vc * st["S"] * st["C"]))
+    for k in range(5):
+        assert np.max(np.abs(Rg[k] - Ro[k])) <= 1e-10 * np.max(np.abs(Ro[k])), k
+
+
+@pytest.mark.parametrize("U", [1e-3, 5e-4])
+def test_uniform_flow_across_a_density_gradient(U):
+    n = 32
+    prob = box(nx=n, ny=4, latent=1.0)
+    x = np.arange(n) + 0.5
+    C = np.tile(0.5 + 0.3 * np.sin(2 * np.pi * x / n), (4, 1))
+    rho = C * prob["rho"][1] + (1.0 - C) * prob["rho"][2]
+    st = dict(He=np.full_like(C, 5.0), C=C, p=np.zeros_like(C), Mx=rho * CS2 * U, My=np.zeros_like(C),
+              S=np.zeros_like(C), phi=np.zeros_like(C))
+    o, g = both(prob, st, steps=0)
+    Rg, Ro = g.rhs(), o.rhs()
+    conv = CS2 * U * (np.roll(rho, -1, 1) - np.roll(rho, 1, 1)) / 2.0
+    assert np.max(np.abs(Rg[1])) < 2e-3 * np.max(np.abs(conv))
+    assert np.max(np.abs(Rg[1] - Ro[1])) < 1e-12 * np.max(np.abs(conv))
+
+
+@pytest.mark.parametrize("U", [1e-3, 5e-4])
+def test_divergent_flow_at_uniform_temperature(U):
+    n = 32
+    prob = box(nx=n, ny=4, latent=10.0)
+    x = np.arange(n) + 0.5
+    u = np.tile(U * np.sin(2 * np.pi * x / n), (4, 1))
+    rho_l, cp_l = prob["rho"][1], prob["cp"][1]
+    st = dict(He=np.full_like(u, 10.0 + cp_l * 0.5), C=np.ones_like(u), p=np.zeros_like(u),
+              Mx=rho_l * CS2 * u, My=np.zeros_like(u), S=np.zeros_like(u), phi=np.zeros_like(u))
+    o, g = both(prob, st, steps=0)
+    Rg, Ro = g.rhs(), o.rhs()
+    src = cp_l * 0.5 * (np.roll(u, -1, 1) - np.roll(u, 1, 1)) / 2.0
+    assert np.max(np.abs(Rg[0])) < 2e-3 * np.max(np.abs(src))
+    assert np.max(np.abs(Rg[0] - Ro[0])) < 1e-12 * np.max(np.abs(src))
+
+
+def test_kelvin_force_of_a_quadratic_potential():
+    """The momentum right-hand side of a state at rest with uniform pressure and a
+    quadratic potential: the GPU's R_M equals the oracle's, whose Kelvin force is pinned
+    to mu0 chi (a^2 (x - x0), b^2 (y - y0)) by the closed form."""
+    n = 20
+    chi = [0.7, 1.3, 0.1]
+    prob = box(nx=n, ny=n, periodic=(0, 0), chi=chi, mu0=1.7, mag_bc=["fixed"] * 4)
+    rng = np.random.default_rng(5)
+    C = rng.uniform(-0.1, 1.1, size=(n, n))
+    He = rng.uniform(-3.0, 14.0, size=(n, n))
+    y, x = np.mgrid[0:n, 0:n] + 0.5
+    a, b, x0, y0 = 0.03, 0.02, 8.3, 11.6
+    st = dict(He=He, C=C, p=np.zeros_like(C), Mx=np.zeros_like(C), My=np.zeros_like(C), S=np.zeros_like(C),
+              phi=-a * (x - x0) ** 2 / 2 - b * (y - y0) ** 2 / 2)
+    o, g = both(prob, st, steps=0)
+    Rg, Ro = g.rhs(), o.rhs()
+    for k in range(5):
+        assert np.max(np.abs(Rg[k] - Ro[k])) <= 1e-10 * np.max(np.abs(Ro[k])), k
+    # the Kelvin part of R_M in the inner cells: cs^2 mu0 chi a^2 (x - x0) dominates it
+    Fx = o.get("Fmgx")
+    assert np.max(np.abs(CS2 * Fx[2:-2, 2:-2])) > 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lagged_solid_fraction_rate_of_a_conducting_mushy_row(precision):
+    k, L, ct = 0.05, 10.0, 0.8
+    rho = [0.9, 1.0, 0.1]
+    prob = box(nx=8, ny=6, latent=L, periodic=(1, 0), rho=rho, lam=[k * r for r in rho],
+               thermal_bc=["adiabatic", "adiabatic", "fixed", "adiabatic"], thermal_val=[0.0, 0.0, -1.0, 0.0],
+               precision=precision)
+    st = uniform(prob, He=0.5 * ct * L, C=ct, p=0.0, Mx=0.0, My=0.0, S=0.0, phi=0.0)
+    o, g = both(prob, st)
+    He, S = g.get("He"), g.get("S")
+    tol = 1e-15 if precision == "fp64" else 2e-6
+    assert np.max(np.abs(He[0] - (0.5 * ct * L - 2.0 * k * 0.5))) < tol * L
+    assert np.max(np.abs(S[0] - 2.0 * k / L)) < (1e-15 if precision == "fp64" else 1e-6)
+    assert np.max(np.abs(S[1:])) < 1e-15
