@@ -23,6 +23,10 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int NFIELDS = 18;   // W[5], W1[5], W2[5], phi[0], S, phi[1]
+// The order parameter C of W, W1 and W2 is stored in FP64 in both precisions: in FP64
+// in fields 4, 9 and 14, in FP32 in three FP64 fields after the 18 (fields 4, 9 and 14
+// are then unused, and stay in place so that fields 5-14 remain one scratch range).
+constexpr int NCFIELDS = 3;
 constexpr uint32_t CKPT_MAGIC = 0x5346424cu;   // "LBFS"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -43,10 +47,10 @@ void append_tiles(std::vector<Tile>& out, int inst, int nx, int ny, TileShape S)
 // largest tile count of any candidate shape, so the tile shapes can change at run time.
 struct Layout {
     int pitch = 0;
-    size_t esize = 0, field_bytes = 0;
+    size_t esize = 0, field_bytes = 0, cfield_bytes = 0;
     int cap_stage = 0, cap_mag = 0, tiles_pt_x = 0, tiles_pt_y = 0;
     size_t off_inst = 0, off_tstage = 0, off_tmag = 0, off_tpt = 0, off_part = 0, off_mpart = 0, off_res = 0,
-           off_fields = 0, total = 0;
+           off_fields = 0, off_cfields = 0, total = 0;
     int ntile_pt() const { return tiles_pt_x * tiles_pt_y; }
 };
 
@@ -164,6 +168,11 @@ Layout make_layout(const lbfs_params* p)
     L.off_mpart = off; off = align_up(off + sizeof(double) * (std::max(L.cap_mag, L.cap_stage) + 1), ALIGN);
     L.off_res = off; off = align_up(off + sizeof(double) * NRES, ALIGN);
     L.off_fields = off; off += L.field_bytes * NFIELDS;
+    L.off_cfields = off;
+    if (p->precision != LBFS_FP64) {
+        L.cfield_bytes = align_up((size_t)L.pitch * p->ny * sizeof(double), ALIGN);
+        off += L.cfield_bytes * NCFIELDS;
+    }
     L.total = off + ALIGN;   // room to align the caller's base pointer
     return L;
 }
@@ -618,6 +627,14 @@ struct lbfs_solver {
     MgCtx mg;                            // multigrid plan (built on first use)
     void* field(int k) const { return base + L.off_fields + L.field_bytes * (size_t)k; }
     bool f64() const { return p.precision == LBFS_FP64; }
+    // field k of the state (0-14: W, W1, W2; 15-17: phi[0], S, phi[1]), with the order
+    // parameter of W, W1 and W2 where it is stored, and its element size
+    static bool is_c(int k) { return k < 15 && k % 5 == 4; }
+    void* sfield(int k) const
+    {
+        return is_c(k) && !f64() ? base + L.off_cfields + L.cfield_bytes * (size_t)(k / 5) : field(k);
+    }
+    size_t sesize(int k) const { return is_c(k) ? sizeof(double) : L.esize; }
 };
 
 // a failed HIP call: with LBFS_DEBUG=1 in the environment, name it on stderr
@@ -723,12 +740,12 @@ int field_index(int field)
 
 int copy_field_out(lbfs_solver* s, int k, double* host)
 {
-    const size_t es = s->L.esize, nx = s->p.nx, ny = s->p.ny;
-    HIPCHK(hipMemcpy2DAsync(s->staging, nx * es, s->field(k), (size_t)s->L.pitch * es, nx * es, ny,
+    const size_t es = s->sesize(k), nx = s->p.nx, ny = s->p.ny;
+    HIPCHK(hipMemcpy2DAsync(s->staging, nx * es, s->sfield(k), (size_t)s->L.pitch * es, nx * es, ny,
                             hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     for (size_t q = 0; q < nx * ny; q++)
-        host[q] = s->f64() ? static_cast<double*>(s->staging)[q] : (double)static_cast<float*>(s->staging)[q];
+        host[q] = es == 8 ? static_cast<double*>(s->staging)[q] : (double)static_cast<float*>(s->staging)[q];
     return LBFS_OK;
 }
 
@@ -742,12 +759,12 @@ void mark_written(lbfs_solver* s)
 
 int copy_field_in(lbfs_solver* s, int k, const double* host)
 {
-    const size_t es = s->L.esize, nx = s->p.nx, ny = s->p.ny;
+    const size_t es = s->sesize(k), nx = s->p.nx, ny = s->p.ny;
     for (size_t q = 0; q < nx * ny; q++) {
-        if (s->f64()) static_cast<double*>(s->staging)[q] = host[q];
+        if (es == 8) static_cast<double*>(s->staging)[q] = host[q];
         else static_cast<float*>(s->staging)[q] = (float)host[q];
     }
-    HIPCHK(hipMemcpy2DAsync(s->field(k), (size_t)s->L.pitch * es, s->staging, nx * es, nx * es, ny,
+    HIPCHK(hipMemcpy2DAsync(s->sfield(k), (size_t)s->L.pitch * es, s->staging, nx * es, nx * es, ny,
                             hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     mark_written(s);
@@ -917,9 +934,9 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     DevInst& I = s->hinst;
     std::memset(&I, 0, sizeof I);
     for (int k = 0; k < 5; k++) {
-        I.W[k] = s->field(k);
-        I.W1[k] = s->field(5 + k);
-        I.W2[k] = s->field(10 + k);
+        I.W[k] = s->sfield(k);
+        I.W1[k] = s->sfield(5 + k);
+        I.W2[k] = s->sfield(10 + k);
     }
     I.phi[0] = s->field(15);
     I.phi[1] = s->field(17);
@@ -983,7 +1000,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     append_tiles(tp, 0, p->nx, p->ny, TileShape{PT_TX, PT_TY, PT_TX * PT_TY});
     if (hipMemcpyAsync(s->dtiles_pt, tp.data(), sizeof(Tile) * tp.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemsetAsync(s->base + L.off_part, 0, L.off_fields - L.off_part, s->stream) != hipSuccess ||
-        hipMemsetAsync(s->base + L.off_fields, 0, L.field_bytes * NFIELDS, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->base + L.off_fields, 0, L.total - ALIGN - L.off_fields, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
     // default shapes: the first stage shape; the magnetic shape by grid size (measured
@@ -1209,12 +1226,16 @@ struct CkptHeader {
     int64_t step;
 };
 constexpr int CKPT_FIELDS[7] = {0, 1, 2, 3, 4, -2, 16};   // -2: current potential buffer
+// element size of checkpoint field q (the order parameter is FP64 in both precisions)
+size_t ckpt_esize(const lbfs_solver* s, int q) { return CKPT_FIELDS[q] == 4 ? sizeof(double) : s->L.esize; }
 }  // namespace
 
 size_t lbfs_checkpoint_bytes(const lbfs_solver* s)
 {
     if (!s) return 0;
-    return sizeof(CkptHeader) + 7 * (size_t)s->p.nx * s->p.ny * s->L.esize;
+    size_t b = sizeof(CkptHeader);
+    for (int q = 0; q < 7; q++) b += (size_t)s->p.nx * s->p.ny * ckpt_esize(s, q);
+    return b;
 }
 
 int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes)
@@ -1224,13 +1245,14 @@ int lbfs_save_state(lbfs_solver* s, void* host, size_t bytes)
     CkptHeader h{CKPT_MAGIC, LBFS_ABI_VERSION, s->p.nx, s->p.ny, s->p.precision, 0, s->t, s->vol0, s->step};
     std::memcpy(host, &h, sizeof h);
     char* dst = static_cast<char*>(host) + sizeof h;
-    const size_t es = s->L.esize, row = (size_t)s->p.nx * es, fb = row * s->p.ny;
     for (int q = 0; q < 7; q++) {
+        const size_t es = ckpt_esize(s, q), row = (size_t)s->p.nx * es, fb = row * s->p.ny;
         const int f = CKPT_FIELDS[q] == -2 ? s->phi_field() : CKPT_FIELDS[q];
-        HIPCHK(hipMemcpy2DAsync(s->staging, row, s->field(f), (size_t)s->L.pitch * es, row, s->p.ny,
+        HIPCHK(hipMemcpy2DAsync(s->staging, row, s->sfield(f), (size_t)s->L.pitch * es, row, s->p.ny,
                                 hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
-        std::memcpy(dst + q * fb, s->staging, fb);
+        std::memcpy(dst, s->staging, fb);
+        dst += fb;
     }
     return LBFS_OK;
 }
@@ -1245,11 +1267,12 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes)
         h.precision != s->p.precision)
         return LBFS_E_INVAL;
     const char* src = static_cast<const char*>(host) + sizeof h;
-    const size_t es = s->L.esize, row = (size_t)s->p.nx * es, fb = row * s->p.ny;
     for (int q = 0; q < 7; q++) {
-        std::memcpy(s->staging, src + q * fb, fb);
+        const size_t es = ckpt_esize(s, q), row = (size_t)s->p.nx * es, fb = row * s->p.ny;
+        std::memcpy(s->staging, src, fb);
+        src += fb;
         const int f = CKPT_FIELDS[q] == -2 ? s->phi_field() : CKPT_FIELDS[q];
-        HIPCHK(hipMemcpy2DAsync(s->field(f), (size_t)s->L.pitch * es, s->staging, row, row, s->p.ny,
+        HIPCHK(hipMemcpy2DAsync(s->sfield(f), (size_t)s->L.pitch * es, s->staging, row, row, s->p.ny,
                                 hipMemcpyHostToDevice, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }

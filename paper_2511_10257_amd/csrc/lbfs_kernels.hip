@@ -338,7 +338,7 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
     const int par0 = (ox + oy) & 1;                  // colour of region cell (0, 0)
     const GLOBAL T* phin = gp<T>(I.phi[pin]);
     const GLOBAL T* He_ = gp<T>(I.W[0]);
-    const GLOBAL T* C_ = gp<T>(I.W[4]);
+    const GLOBAL double* C_ = gp<double>(I.W[4]);
     // 1. load the region (all loads of this thread in flight together): permeability in
     //    natural layout (0 outside the domain), potential by colour
     {
@@ -363,7 +363,7 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
             vin[it] = in;
             const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
             vHe[it] = He_[o];
-            vC[it] = C_[o];
+            vC[it] = T(C_[o]);
             vph[it] = phin[o];
         }
 #pragma unroll
@@ -489,7 +489,10 @@ struct StageLds {
     static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
     T q[NQ][NR];
     T muc[NR];          // valid on tile + 2
-    T g[NV][2][NG];     // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He
+    union {
+        T g[NV][2][NG];     // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He (phases C-D)
+        double cd[NR];      // the order parameter in FP64 (phases A-B)
+    };
     T h2[NG];           // |H|^2
     T fx[5][NFX];
     T fy[5][NFY];
@@ -536,28 +539,30 @@ __device__ __forceinline__ double wave_max(double x)
 // Fs), heat into a fixed south wall (-lambda dT/dy over the half cell, times dx), and the
 // first and second moments of Ct about the origin (droplet centroid and axes).
 template <typename T>
-__device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, int gx, int gy, double* pr)
+__device__ __forceinline__ void cell_partials(const DevInst& I, const T* Wn, double Cd, int gx, int gy, double* pr)
 {
     T T1, Fl1;
     const Coef<T>& K = coef<T>(I);
-    enthalpy_state<T>(K, Wn[0], Wn[4], T1, Fl1);
-    const T ct1 = clamp01(Wn[4]);
+    enthalpy_state<T>(K, Wn[0], T(Cd), T1, Fl1);
+    const T ct1 = clamp01(T(Cd));
     const T fs1 = ct1 * (T(1) - Fl1);
     const T rho1 = mix3<T>(K.rho, fs1, ct1);
+    const double ctd = clamp01(Cd);   // (the clamped order parameter of the sums in FP64)
     const double u1 = double(Wn[2]) * 3.0 / double(rho1), v1 = double(Wn[3]) * 3.0 / double(rho1);
     const double um = sqrt(u1 * u1 + v1 * v1);
     bool finite = true;
 #pragma unroll
-    for (int k = 0; k < 5; k++) finite = finite && isfinite(double(Wn[k]));
-    pr[PART_CT] = double(ct1);
-    pr[PART_CTFL] = double(ct1) * double(Fl1);
-    pr[PART_FS] = double(fs1);
+    for (int k = 0; k < 4; k++) finite = finite && isfinite(double(Wn[k]));
+    finite = finite && isfinite(Cd);
+    pr[PART_CT] = ctd;
+    pr[PART_CTFL] = ctd * double(Fl1);
+    pr[PART_FS] = ctd * (1.0 - double(Fl1));
     pr[PART_UMAX] = um;
     pr[PART_NONFINITE] = finite ? 0.0 : 1.0;
-    pr[PART_UDROP] = ct1 >= T(0.5) ? um : 0.0;
-    pr[PART_HEIGHT] = gx == I.col_height ? double(ct1) : 0.0;
-    pr[PART_SOLIDH] = gx == I.col_height ? double(fs1) : 0.0;
-    const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx, c = double(ct1);
+    pr[PART_UDROP] = ctd >= 0.5 ? um : 0.0;
+    pr[PART_HEIGHT] = gx == I.col_height ? ctd : 0.0;
+    pr[PART_SOLIDH] = gx == I.col_height ? pr[PART_FS] : 0.0;
+    const double x = (gx + 0.5) * I.dx, y = (gy + 0.5) * I.dx, c = ctd;
     pr[PART_MX] = c * x;
     pr[PART_MY] = c * y;
     pr[PART_MXX] = c * x * x;
@@ -658,9 +663,13 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     const T dx = K.dx;
     const T inv2dx = K.inv2dx;
 
+    // He, p, Mx, My in the instance precision; the order parameter C (index 4) is stored
+    // in FP64 in both precisions
     T* const* Wbase = reinterpret_cast<T* const*>(I.W);
     T* const* Win = STAGE == 2 ? reinterpret_cast<T* const*>(I.W1)
                   : STAGE == 3 ? reinterpret_cast<T* const*>(I.W2) : Wbase;
+    const GLOBAL double* Cbase = gp<double>(I.W[4]);
+    const GLOBAL double* Cin = gp<double>(STAGE == 2 ? I.W1[4] : STAGE == 3 ? I.W2[4] : I.W[4]);
     const GLOBAL T* phi = gp<T>(I.phi[pidx]);
 
     // cell owned by this thread (phase E). With EARLY, stages 0 and 1 fetch its point
@@ -711,13 +720,16 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             I.mpart[tile.idx] = acc;
         }
     }
-    T cWin[5], cWb[5], cS = T(0);
+    T cWin[4], cWb[4], cS = T(0);
+    double cCin = 0.0, cCb = 0.0;
     auto load_own = [&] {
 #pragma unroll
-        for (int k = 0; k < 5; k++) {
+        for (int k = 0; k < 4; k++) {
             cWin[k] = STAGE >= 1 ? gp<T>(Win[k])[o] : T(0);
             cWb[k] = STAGE >= 2 ? gp<T>(Wbase[k])[o] : T(0);
         }
+        cCin = STAGE >= 1 ? Cin[o] : 0.0;
+        cCb = STAGE >= 2 ? Cbase[o] : 0.0;
         cS = gp<T>(I.S)[o];
     };
     if constexpr (early) load_own();
@@ -726,7 +738,8 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     //      this thread is issued before the first one is used. A tile whose halo lies
     //      inside the domain (most of them) takes a path without images or mirrors.
     const bool interior = x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= nx && y0 + TY + 3 <= ny;
-    auto store_cell = [&](int r, const Prim<T>& q, T ph) {
+    auto store_cell = [&](int r, const Prim<T>& q, T ph, double cdv) {
+        s.cd[r] = cdv;
         s.q[Q_P][r] = q.p;
         s.q[Q_U][r] = q.u;
         s.q[Q_V][r] = q.v;
@@ -741,25 +754,32 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     };
     constexpr int NIT = (L::NR + NT - 1) / NT;
     if (interior) {
-        T vW[NIT][5], vph[NIT];
+        T vW[NIT][4], vph[NIT];
+        double vC[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             const int rr = r < L::NR ? r : L::NR - 1;
             const size_t oh = (size_t)(y0 - 3 + rr / L::RX) * pitch + (x0 - 3 + rr % L::RX);
 #pragma unroll
-            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            for (int k = 0; k < 4; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            vC[it] = Cin[oh];
             if constexpr (FUSE) vph[it] = mphi(x0 - 3 + rr % L::RX, y0 - 3 + rr / L::RX);
             else vph[it] = phi[oh];
         }
+        // (the FP64 order parameter shares LDS with the magnetic block of FUSE: every
+        // potential is read before the first is overwritten)
+        if constexpr (FUSE) __syncthreads();
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             if (r >= L::NR) break;
-            store_cell(r, primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]), vph[it]);
+            store_cell(r, primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], T(vC[it])), vph[it],
+                       vC[it]);
         }
     } else {
-        T vW[NIT][5], vph[NIT];
+        T vW[NIT][4], vph[NIT];
+        double vC[NIT];
         int vwx[NIT], vwy[NIT], vdx[NIT], vdy[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
@@ -775,54 +795,63 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             vdy[it] = sy - hy;
             const size_t oh = (size_t)sy * pitch + sx;
 #pragma unroll
-            for (int k = 0; k < 5; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            for (int k = 0; k < 4; k++) vW[it][k] = gp<T>(Win[k])[oh];
+            vC[it] = Cin[oh];
             // (the block holds periodic images in place and zeros beyond walls: a wall
             // ghost reads its mirror cell)
             if constexpr (FUSE) vph[it] = mphi(wx >= 0 ? sx : hx, wy >= 0 ? sy : hy);
             else vph[it] = phi[oh];
         }
+        if constexpr (FUSE) __syncthreads();
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             if (r >= L::NR) break;
-            Prim<T> q = primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], vW[it][4]);
+            double cdv = vC[it];
+            Prim<T> q = primitives<T>(K, vW[it][0], vW[it][1], vW[it][2], vW[it][3], T(cdv));
             T ph = vph[it];
             const int wx = vwx[it], wy = vwy[it];
             // a wetting wall adds the contact-angle gradient to the mirrored order
-            // parameter over the |vd| cells between ghost and mirror cell
-            auto wet = [&](T c, T wk, int vd) {
-                const T cc = clamp01(c);
-                return c + T(vd < 0 ? -vd : vd) * dx * wk * cc * (T(1) - cc);
+            // parameter over the |vd| cells between ghost and mirror cell (in FP64, the
+            // precision of the stored order parameter)
+            auto wet = [&](double c, double wk, int vd) {
+                const double cc = clamp01(c);
+                return c + double(vd < 0 ? -vd : vd) * I.dx * wk * cc * (1.0 - cc);
             };
             if (wx >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
                 if (I.tbc[wx]) q.Tt = T(2) * K.tval[wx] - q.Tt;
                 ph = I.mbc[wx] ? -ph : ph - K.h0x * T(vdx[it]) * dx;
-                if (K.wet[wx] != T(0)) q.C = wet(q.C, K.wet[wx], vdx[it]);
+                if (I.wet[wx] != 0.0) cdv = wet(cdv, I.wet[wx], vdx[it]);
             }
             if (wy >= 0) {
                 q.u = -q.u;
                 q.v = -q.v;
                 if (I.tbc[wy]) q.Tt = T(2) * K.tval[wy] - q.Tt;
                 ph = I.mbc[wy] ? -ph : ph - K.h0y * T(vdy[it]) * dx;
-                if (K.wet[wy] != T(0)) q.C = wet(q.C, K.wet[wy], vdy[it]);
+                if (I.wet[wy] != 0.0) cdv = wet(cdv, I.wet[wy], vdy[it]);
             }
-            store_cell(r, q, ph);
+            q.C = T(cdv);
+            store_cell(r, q, ph, cdv);
         }
     }
     __syncthreads();
 
-    // ---- B: chemical potential on tile + 2 (mu_c = 2 beta C (C-1)(2C-1) - kappa lap C)
+    // ---- B: chemical potential on tile + 2 (mu_c = 2 beta C (C-1)(2C-1) - kappa lap C),
+    //      in FP64 from the FP64 order parameter: in the bulk phases mu_c is nearly
+    //      zero, and the rounding of C to FP32, amplified by kappa / dx^2 in the
+    //      Laplacian, would dominate it and the capillary force
     {
-        const T beta = K.beta, kappa = K.kappa, idx2 = K.idx2;
+        const Coef<double>& KD = coef<double>(I);
+        const double beta = KD.beta, kappa = KD.kappa, idx2 = KD.idx2;
         for (int r = tid; r < L::NR; r += NT) {
             const int lx = r % L::RX, ly = r / L::RX;
             if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
-            const T* C = s.q[Q_C];
-            const T c = C[r];
-            const T lap = (C[r + 1] + C[r - 1] + C[r + L::RX] + C[r - L::RX] - T(4) * c) * idx2;
-            s.muc[r] = T(2) * beta * c * (c - T(1)) * (T(2) * c - T(1)) - kappa * lap;
+            const double* C = s.cd;
+            const double c = C[r];
+            const double lap = (C[r + 1] + C[r - 1] + C[r + L::RX] + C[r - L::RX] - 4.0 * c) * idx2;
+            s.muc[r] = T(2.0 * beta * c * (c - 1.0) * (2.0 * c - 1.0) - kappa * lap);
         }
     }
     __syncthreads();
@@ -948,7 +977,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
         if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
-        else { Cn = cWb[4]; Hen = cWb[0]; }
+        else { Cn = T(cCb); Hen = cWb[0]; }
         T Tn, Fln;
         enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
         const T ctn = clamp01(Cn);
@@ -983,27 +1012,34 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             const T div = (s.fx[k][fW + 1] - s.fx[k][fW] + s.fy[k][fS + TX] - s.fy[k][fS]) * idx;
             Rk[k] = -div + src[k];
         }
+        // (the order parameter is combined in FP64: its increment dt R_C is small)
+        const double dRc = double(dt) * double(Rk[4]);
         if (STAGE == 0) {
 #pragma unroll
-            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = Rk[k];
+            for (int k = 0; k < 4; k++) gp<T>(I.W1[k])[o] = Rk[k];
+            gp<double>(I.W1[4])[o] = double(Rk[4]);
         } else if (STAGE == 1) {
 #pragma unroll
-            for (int k = 0; k < 5; k++) gp<T>(I.W1[k])[o] = cWin[k] + dt * Rk[k];
+            for (int k = 0; k < 4; k++) gp<T>(I.W1[k])[o] = cWin[k] + dt * Rk[k];
+            gp<double>(I.W1[4])[o] = cCin + dRc;
         } else if (STAGE == 2) {
 #pragma unroll
-            for (int k = 0; k < 5; k++)
+            for (int k = 0; k < 4; k++)
                 gp<T>(I.W2[k])[o] = T(0.75) * cWb[k] + T(0.25) * (cWin[k] + dt * Rk[k]);
+            gp<double>(I.W2[4])[o] = 0.75 * cCb + 0.25 * (cCin + dRc);
         } else {
-            T Wn[5];
+            T Wn[4];
 #pragma unroll
-            for (int k = 0; k < 5; k++) {
+            for (int k = 0; k < 4; k++) {
                 Wn[k] = cWb[k] * T(1.0 / 3.0) + T(2.0 / 3.0) * (cWin[k] + dt * Rk[k]);
                 gp<T>(Wbase[k])[o] = Wn[k];
             }
+            const double Cn1 = cCb * (1.0 / 3.0) + (2.0 / 3.0) * (cCin + dRc);
+            gp<double>(I.W[4])[o] = Cn1;
             // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
             T T1, Fl1;
-            enthalpy_state<T>(K, Wn[0], Wn[4], T1, Fl1);
-            const T ct1 = clamp01(Wn[4]);
+            enthalpy_state<T>(K, Wn[0], T(Cn1), T1, Fl1);
+            const T ct1 = clamp01(T(Cn1));
             gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) * idt;
         }
     }
@@ -1075,11 +1111,11 @@ __global__ __launch_bounds__(256) void k_state_partials(const DevInst* __restric
         const int gx = tile.x0 + c % TX, gy = tile.y0 + c / TX;
         if (gx >= I.nx || gy >= I.ny) continue;
         const size_t o = (size_t)gy * I.pitch + gx;
-        T Wn[5];
+        T Wn[4];
 #pragma unroll
-        for (int k = 0; k < 5; k++) Wn[k] = reinterpret_cast<const T*>(I.W[k])[o];
+        for (int k = 0; k < 4; k++) Wn[k] = reinterpret_cast<const T*>(I.W[k])[o];
         double q[NPART];
-        cell_partials<T>(I, Wn, gx, gy, q);
+        cell_partials<T>(I, Wn, reinterpret_cast<const double*>(I.W[4])[o], gx, gy, q);
 #pragma unroll
         for (int k = 0; k < NPART; k++) pr[k] = part_is_max(k) ? fmax(pr[k], q[k]) : pr[k] + q[k];
     }
@@ -1244,7 +1280,7 @@ __global__ __launch_bounds__(NT) void k_mag_lbfs(const DevInst* __restrict__ ins
     const int ox = tile.x0 - L::H, oy = tile.y0 - L::H;
     const GLOBAL T* phin = gp<T>(I.phi[pin]);
     const GLOBAL T* He_ = gp<T>(I.W[0]);
-    const GLOBAL T* C_ = gp<T>(I.W[4]);
+    const GLOBAL double* C_ = gp<double>(I.W[4]);
     T cq[NIT];   // current value of each owned cell
     // 1. load the region: potential into ph[0], permeability into ph[1] (0 outside the
     //    domain, where the potential is 0 too)
@@ -1269,7 +1305,7 @@ __global__ __launch_bounds__(NT) void k_mag_lbfs(const DevInst* __restrict__ ins
             vin[it] = in;
             const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
             vHe[it] = He_[o];
-            vC[it] = C_[o];
+            vC[it] = T(C_[o]);
             cq[it] = phin[o];
         }
 #pragma unroll
@@ -1526,7 +1562,7 @@ __global__ __launch_bounds__(PT_TX* PT_TY) void k_init_fields(const DevInst* __r
     reinterpret_cast<T*>(I.W[1])[o] = T(0);
     reinterpret_cast<T*>(I.W[2])[o] = T(0);
     reinterpret_cast<T*>(I.W[3])[o] = T(0);
-    reinterpret_cast<T*>(I.W[4])[o] = T(C);
+    reinterpret_cast<double*>(I.W[4])[o] = C;
     reinterpret_cast<T*>(I.S)[o] = T(0);
     reinterpret_cast<T*>(I.phi[0])[o] = T(0);
     reinterpret_cast<T*>(I.phi[1])[o] = T(0);
@@ -1543,8 +1579,8 @@ __global__ __launch_bounds__(PT_TX* PT_TY) void k_derived(const DevInst* __restr
     if (gx >= I.nx || gy >= I.ny) return;
     const size_t o = (size_t)gy * I.pitch + gx;
     T Tt, Fl;
-    enthalpy_state<T>(coef<T>(I), reinterpret_cast<const T*>(I.W[0])[o], reinterpret_cast<const T*>(I.W[4])[o], Tt,
-                      Fl);
+    enthalpy_state<T>(coef<T>(I), reinterpret_cast<const T*>(I.W[0])[o], T(reinterpret_cast<const double*>(I.W[4])[o]),
+                      Tt, Fl);
     reinterpret_cast<T*>(I.W1[0])[o] = Tt;
     reinterpret_cast<T*>(I.W1[1])[o] = Fl;
 }
@@ -1561,11 +1597,11 @@ __global__ __launch_bounds__(256) void k_wall_profile(const DevInst* __restrict_
     if (i >= I.nx) return;
     const Coef<T>& K = coef<T>(I);
     const GLOBAL T* He = gp<T>(I.W[0]);
-    const GLOBAL T* C = gp<T>(I.W[4]);
+    const GLOBAL double* C = gp<double>(I.W[4]);
     T T0, F0, T1, F1;
-    enthalpy_state<T>(K, He[i], C[i], T0, F0);
-    enthalpy_state<T>(K, He[I.pitch + i], C[I.pitch + i], T1, F1);
-    const T ct = clamp01(C[i]);
+    enthalpy_state<T>(K, He[i], T(C[i]), T0, F0);
+    enthalpy_state<T>(K, He[I.pitch + i], T(C[I.pitch + i]), T1, F1);
+    const T ct = clamp01(T(C[i]));
     const double lam = double(mix3<T>(K.lam, ct * (T(1) - F0), ct));
     out[i] = I.heat_on ? -lam * (9.0 * double(T0) - double(T1) - 8.0 * I.tval[2]) / (3.0 * I.dx) : 0.0;
 }
@@ -1623,7 +1659,7 @@ __global__ __launch_bounds__(256) void k_mg_mu0(const DevInst* __restrict__ inst
     const int i = c % I.nx, j = c / I.nx;
     const size_t o = (size_t)j * I.pitch + i;
     const Coef<T>& K = coef<T>(I);
-    const T C = gp<T>(I.W[4])[o];
+    const T C = T(gp<double>(I.W[4])[o]);
     T Tt, Fl;
     enthalpy_state<T>(K, gp<T>(I.W[0])[o], C, Tt, Fl);
     const T ct = clamp01(C);
