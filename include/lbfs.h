@@ -203,6 +203,14 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
    directly). The results are the same either way. */
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
+/* Capture and instantiate now every HIP graph that lbfs_step and lbfs_step_profiled
+   replay (one step, and the multi-step replay, from either potential buffer), so that
+   the first steps after init, lbfs_set_tile_shapes or lbfs_autotune do not pay for the
+   capture. Enqueues no work; the state and the clock are unchanged. Does nothing where
+   steps are not graph replays (default stream, LBFS_NO_GRAPH=1). LBFS_E_STATE on a
+   borrowed batch handle, LBFS_E_DEVICE if a capture fails. */
+int lbfs_prepare(lbfs_solver* s);
+
 /* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
    per 4 sweeps: permeability, sweeps, residual) and the three Runge-Kutta stages
    (the third also applies Eq. 8 and stores the lagged dFs/dt). REDUCE, the FP64
@@ -361,6 +369,11 @@ int lbfs_batch_retire(lbfs_batch* b, int32_t slot);
    of 16 steps or of one as in lbfs_step on a non-default stream, recaptured after
    admissions and retirements). */
 int lbfs_batch_step(lbfs_batch* b, int32_t nsteps);
+
+/* lbfs_prepare for a batch: rebuilds the launch lists after admissions and retirements
+   and captures the step graphs of the live instances (recaptured after the next
+   admission or retirement). */
+int lbfs_batch_prepare(lbfs_batch* b);
 
 /* lbfs_step_profiled for a batch: mean duration of each kernel phase over all live
    instances. */

@@ -454,6 +454,19 @@ int exec_run_steps(Exec& E, int nmax)
     return n;
 }
 
+// capture every graph exec_run_steps can replay (one step and graph_steps steps, from
+// either potential buffer) without running it
+hipError_t exec_prepare(Exec& E)
+{
+    if (!E.use_graph || E.ninst == 0) return hipSuccess;
+    for (int len = 0; len < (E.graph_steps > 1 ? 2 : 1); len++)
+        for (int ph = 0; ph < 2; ph++) {
+            const hipError_t e = exec_ensure_graph(E, len, ph);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
 // nsteps steps with HIP events around the kernel phases of every sample_every-th step;
 // after_step() runs on the host after each enqueued step
 template <typename F>
@@ -494,9 +507,16 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
             n++;
             continue;
         }
-        // the plain steps up to the next sampled one
+        // the plain steps up to the next sampled one: multi-step graph replays, and direct
+        // launches for a remainder shorter than one (a one-step graph replay costs a few
+        // microseconds more than the same kernels launched directly)
         const int next = std::min(nsteps, (n / sample_every + 1) * sample_every);
-        const int k = exec_run_steps(E, next - n);
+        int k;
+        if (!E.use_graph || E.graph_steps <= 1 || next - n >= E.graph_steps) {
+            k = exec_run_steps(E, next - n);
+        } else {
+            k = exec_enqueue_step(E) == hipSuccess ? 1 : 0;   // (flips the potential buffer itself)
+        }
         if (k == 0) rc = LBFS_E_DEVICE;
         for (int q = 0; q < k; q++) after_step();
         n += k;
@@ -1073,6 +1093,13 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps)
         s->stepped_since_observe = true;
         n += k;
     }
+    return LBFS_OK;
+}
+
+int lbfs_prepare(lbfs_solver* s)
+{
+    if (!s || s->batched) return LBFS_E_STATE;
+    HIPCHK(exec_prepare(s->E));
     return LBFS_OK;
 }
 
@@ -1824,6 +1851,15 @@ int lbfs_batch_step(lbfs_batch* b, int32_t nsteps)
         for (int q = 0; q < k; q++) batch_after_step(b);
         n += k;
     }
+    return LBFS_OK;
+}
+
+int lbfs_batch_prepare(lbfs_batch* b)
+{
+    if (!b) return LBFS_E_STATE;
+    const int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    HIPCHK(exec_prepare(b->E));
     return LBFS_OK;
 }
 

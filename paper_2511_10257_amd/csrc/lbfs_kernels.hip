@@ -738,8 +738,10 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     //      this thread is issued before the first one is used. A tile whose halo lies
     //      inside the domain (most of them) takes a path without images or mirrors.
     const bool interior = x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= nx && y0 + TY + 3 <= ny;
+    // (in FP64 the order parameter of s.q is the FP64 one: no second copy)
+    constexpr bool cd_copy = sizeof(T) < sizeof(double);
     auto store_cell = [&](int r, const Prim<T>& q, T ph, double cdv) {
-        s.cd[r] = cdv;
+        if constexpr (cd_copy) s.cd[r] = cdv;
         s.q[Q_P][r] = q.p;
         s.q[Q_U][r] = q.u;
         s.q[Q_V][r] = q.v;
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         }
         // (the FP64 order parameter shares LDS with the magnetic block of FUSE: every
         // potential is read before the first is overwritten)
-        if constexpr (FUSE) __syncthreads();
+        if constexpr (FUSE && cd_copy) __syncthreads();
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
@@ -802,7 +804,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             if constexpr (FUSE) vph[it] = mphi(wx >= 0 ? sx : hx, wy >= 0 ? sy : hy);
             else vph[it] = phi[oh];
         }
-        if constexpr (FUSE) __syncthreads();
+        if constexpr (FUSE && cd_copy) __syncthreads();
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
@@ -848,7 +850,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         for (int r = tid; r < L::NR; r += NT) {
             const int lx = r % L::RX, ly = r / L::RX;
             if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
-            const double* C = s.cd;
+            const double* C = cd_copy ? s.cd : reinterpret_cast<const double*>(s.q[Q_C]);
             const double c = C[r];
             const double lap = (C[r + 1] + C[r - 1] + C[r + L::RX] + C[r - L::RX] - 4.0 * c) * idx2;
             s.muc[r] = T(2.0 * beta * c * (c - 1.0) * (2.0 * c - 1.0) - kappa * lap);

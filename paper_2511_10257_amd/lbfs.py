@@ -26,13 +26,13 @@ NKERNELS = len(KERNELS)
 # every symbol include/lbfs.h declares
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
-    "lbfs_step", "lbfs_step_profiled", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
+    "lbfs_step", "lbfs_step_profiled", "lbfs_prepare", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
     "lbfs_mag_pseudo_steps", "lbfs_mag_multigrid", "lbfs_wall_heat_profile", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
     "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
-    "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_observe", "lbfs_batch_slot",
+    "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_prepare", "lbfs_batch_observe", "lbfs_batch_slot",
     "lbfs_batch_info", "lbfs_batch_destroy", "lbfs_batch_set_tile_shapes", "lbfs_batch_autotune",
     "lbfs_batch_tile_shapes_in_use",
 )
@@ -102,6 +102,7 @@ def lib():
             "lbfs_init": (C.c_int, [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbfs_step": (C.c_int, [vp, i32]),
             "lbfs_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
+            "lbfs_prepare": (C.c_int, [vp]),
             "lbfs_observe": (C.c_int, [vp, C.POINTER(Observables)]),
             "lbfs_rhs": (C.c_int, [vp, dp]),
             "lbfs_mag_sweeps": (C.c_int, [vp, i32, C.c_double, dp]),
@@ -130,6 +131,7 @@ def lib():
             "lbfs_batch_retire": (C.c_int, [vp, i32]),
             "lbfs_batch_step": (C.c_int, [vp, i32]),
             "lbfs_batch_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
+            "lbfs_batch_prepare": (C.c_int, [vp]),
             "lbfs_batch_observe": (C.c_int, [vp, C.POINTER(Observables), C.POINTER(C.c_uint8)]),
             "lbfs_batch_slot": (C.c_int, [vp, i32, C.POINTER(vp)]),
             "lbfs_batch_info": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
@@ -375,6 +377,10 @@ class Solver(_Instance):
     def step(self, n: int = 1) -> None:
         _check(lib().lbfs_step(self._h, int(n)), "lbfs_step")
 
+    def prepare(self) -> None:
+        """Capture every step graph now (no step runs; the state is unchanged)."""
+        _check(lib().lbfs_prepare(self._h), "lbfs_prepare")
+
     def step_profiled(self, n: int, sample_every: int = 10) -> dict:
         """Steps with HIP events around the kernels of every sample_every-th step;
         returns {kernel kind: (mean ms per launch, timed launches)}."""
@@ -480,6 +486,10 @@ class Batch:
 
     def step(self, n: int = 1) -> None:
         _check(lib().lbfs_batch_step(self._h, int(n)), "lbfs_batch_step")
+
+    def prepare(self) -> None:
+        """Capture the step graphs of the live instances now (no step runs)."""
+        _check(lib().lbfs_batch_prepare(self._h), "lbfs_batch_prepare")
 
     def step_profiled(self, n: int, sample_every: int = 10) -> dict:
         ms = (C.c_double * NKERNELS)()

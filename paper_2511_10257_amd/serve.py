@@ -170,6 +170,9 @@ def report(reqs, elapsed: float, cell_steps: int, clock: str, unfinished_live: i
         "p50": float(np.percentile(lat, 50)) if done else None,
         "p99": float(np.percentile(lat, 99)) if done else None,
         "cell_steps": int(cell_steps),
+        # cell updates one completed solve needed (its cells times its steps), on average
+        "cell_steps_per_completed": (float(np.mean([r.cells * r.steps for r in reqs if r.latency is not None]))
+                                     if done else None),
     }
     if clock == "wall" and elapsed > 0:
         out["mlups"] = cell_steps / elapsed / 1e6

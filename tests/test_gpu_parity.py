@@ -350,3 +350,35 @@ def test_sweep_counts_match_oracle(sweeps):
     fl = floors(prob)
     for name in ("phi", "Mx", "He"):
         assert rel_l2(g.get(name), o.get(name), fl[name]) < 1e-11, (sweeps, name)
+
+
+def test_prepared_graphs_give_the_same_steps():
+    """lbfs_prepare captures every step graph up front (no step runs): the state is
+    unchanged by it, and the steps that follow equal those of a solver that captures on
+    first use, bit for bit; the same for a batch."""
+    prob = wl.droplet_problem(96, 24.0, ste=0.1, bo_m=1.5, angle_deg=30.0, precision="fp32")
+    a = lbfs.Solver(prob)
+    b = lbfs.Solver(prob)
+    before = {k: b.get(k) for k in ("He", "phi", "C")}
+    b.prepare()
+    for k, v in before.items():
+        assert np.array_equal(b.get(k), v), k
+    assert b.observe()["step"] == 0
+    for n in (1, 16, 3, 17):
+        a.step(n)
+        b.step(n)
+    for k in ("He", "p", "Mx", "My", "C", "phi", "S"):
+        assert np.array_equal(a.get(k), b.get(k)), k
+    probs = [wl.droplet_problem(e, e / 4.0, ste=0.1, bo_m=1.0, angle_deg=ang, precision="fp32")
+             for e, ang in ((64, 0.0), (80, 60.0))]
+    budget = sum(lbfs.Batch.instance_bytes(p) for p in probs) + (1 << 20)
+    b1, b2 = lbfs.Batch(2, budget), lbfs.Batch(2, budget)
+    for bb in (b1, b2):
+        for p in probs:
+            assert bb.admit(p) is not None
+    b2.prepare()
+    b1.step(21)
+    b2.step(21)
+    assert b1.observe() == b2.observe()
+    b1.close()
+    b2.close()
