@@ -910,6 +910,63 @@ static int apply_shapes(lbfs_solver* s, int si, int mi)
     return LBFS_OK;
 }
 
+// the parameters of an instance in its descriptor (dt and dt_stream already resolved),
+// with the coefficient blocks of both precisions
+static void fill_params(DevInst& I, const lbfs_params& p, int pitch)
+{
+    I.nx = p.nx;
+    I.ny = p.ny;
+    I.pitch = pitch;
+    I.per_x = p.periodic[0];
+    I.per_y = p.periodic[1];
+    for (int w = 0; w < 4; w++) {
+        I.tbc[w] = p.thermal_bc[w];
+        I.mbc[w] = p.mag_bc[w];
+        I.tval[w] = p.thermal_val[w];
+        // wetting: n.grad C = -(4/xi) cos(theta) C (1 - C) at the wall (exactly the
+        // mirror at 90 degrees)
+        I.wet[w] = p.contact_angle_deg[w] == 90.0 ? 0.0 : 4.0 / p.xi * std::cos(p.contact_angle_deg[w] * M_PI / 180.0);
+    }
+    int col = (int)std::floor(p.drop_cx / p.dx);
+    I.col_height = col < 0 ? 0 : (col > p.nx - 1 ? p.nx - 1 : col);
+    I.heat_on = (!p.periodic[1] && p.thermal_bc[2] == LBFS_TBC_FIXED) ? 1 : 0;
+    for (int k = 0; k < 3; k++) {
+        I.rho[k] = p.rho[k]; I.mu_[k] = p.mu[k]; I.lam[k] = p.lambda[k]; I.cp[k] = p.cp[k]; I.chi[k] = p.chi[k];
+    }
+    I.latent = p.latent;
+    I.tm = p.t_melt;
+    I.tl = p.t_liquidus;
+    I.dx = p.dx;
+    I.dt = p.dt;
+    I.dts = p.dt_stream;
+    I.cpref = 0.5 * (p.cp[0] + p.cp[1]);
+    I.qg = p.mobility / ((p.tau_g - 0.5) * p.dt_stream);   // M_c = (tau_g - 1/2) Q_g delta_t
+    I.tau_g = p.tau_g;
+    I.beta = 12.0 * p.sigma / p.xi;
+    I.kappa = 1.5 * p.xi * p.sigma;
+    I.mu0 = p.mu0;
+    const double th = p.field_angle_deg * M_PI / 180.0;
+    I.h0x = p.h0 * std::cos(th);
+    I.h0y = p.h0 * std::sin(th);
+    I.xi = p.xi;
+    I.grav[0] = p.gravity[0];
+    I.grav[1] = p.gravity[1];
+    I.vc = 1.0 - p.rho[0] / p.rho[1];
+    {
+        // the automatic pseudo-time step dx^2 / (4 D mu_max): every row of the discrete
+        // operator sums in absolute value to at most 8 D mu_max / dx^2, and SSP-RK3 is
+        // stable on the negative real axis to about -2.51; the mixture permeability
+        // never exceeds that of the most permeable phase
+        double mmax = 1.0 + p.chi[0];
+        for (int k = 1; k < 3; k++) mmax = std::max(mmax, 1.0 + p.chi[k]);
+        I.mag_kdt = p.mag_lbfs_dtau > 0.0 ? p.mag_lbfs_d * p.mag_lbfs_dtau / (p.dx * p.dx)
+                                           : 1.0 / (4.0 * p.mu0 * mmax);
+    }
+    I.mag_tol = p.mag_tol;
+    fill_coef(I.cf, I);
+    fill_coef(I.cd, I);
+}
+
 static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream, lbfs_solver** out)
 {
     if (!out) return LBFS_E_INVAL;
@@ -964,57 +1021,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     I.part = reinterpret_cast<double*>(s->base + L.off_part);
     I.mpart = reinterpret_cast<double*>(s->base + L.off_mpart);
     I.result = reinterpret_cast<double*>(s->base + L.off_res);
-    I.nx = p->nx;
-    I.ny = p->ny;
-    I.pitch = L.pitch;
-    I.per_x = p->periodic[0];
-    I.per_y = p->periodic[1];
-    for (int w = 0; w < 4; w++) {
-        I.tbc[w] = p->thermal_bc[w];
-        I.mbc[w] = p->mag_bc[w];
-        I.tval[w] = p->thermal_val[w];
-        // wetting: n.grad C = -(4/xi) cos(theta) C (1 - C) at the wall (exactly the
-        // mirror at 90 degrees)
-        I.wet[w] = p->contact_angle_deg[w] == 90.0 ? 0.0 : 4.0 / p->xi * std::cos(p->contact_angle_deg[w] * M_PI / 180.0);
-    }
-    int col = (int)std::floor(p->drop_cx / p->dx);
-    I.col_height = col < 0 ? 0 : (col > p->nx - 1 ? p->nx - 1 : col);
-    I.heat_on = (!p->periodic[1] && p->thermal_bc[2] == LBFS_TBC_FIXED) ? 1 : 0;
-    for (int k = 0; k < 3; k++) {
-        I.rho[k] = p->rho[k]; I.mu_[k] = p->mu[k]; I.lam[k] = p->lambda[k]; I.cp[k] = p->cp[k]; I.chi[k] = p->chi[k];
-    }
-    I.latent = p->latent;
-    I.tm = p->t_melt;
-    I.tl = p->t_liquidus;
-    I.dx = p->dx;
-    I.dt = s->p.dt;
-    I.dts = s->p.dt_stream;
-    I.cpref = 0.5 * (p->cp[0] + p->cp[1]);
-    I.qg = p->mobility / ((p->tau_g - 0.5) * s->p.dt_stream);   // M_c = (tau_g - 1/2) Q_g delta_t
-    I.tau_g = p->tau_g;
-    I.beta = 12.0 * p->sigma / p->xi;
-    I.kappa = 1.5 * p->xi * p->sigma;
-    I.mu0 = p->mu0;
-    const double th = p->field_angle_deg * M_PI / 180.0;
-    I.h0x = p->h0 * std::cos(th);
-    I.h0y = p->h0 * std::sin(th);
-    I.xi = p->xi;
-    I.grav[0] = p->gravity[0];
-    I.grav[1] = p->gravity[1];
-    I.vc = 1.0 - p->rho[0] / p->rho[1];
-    {
-        // the automatic pseudo-time step dx^2 / (4 D mu_max): every row of the discrete
-        // operator sums in absolute value to at most 8 D mu_max / dx^2, and SSP-RK3 is
-        // stable on the negative real axis to about -2.51; the mixture permeability
-        // never exceeds that of the most permeable phase
-        double mmax = 1.0 + p->chi[0];
-        for (int k = 1; k < 3; k++) mmax = std::max(mmax, 1.0 + p->chi[k]);
-        I.mag_kdt = p->mag_lbfs_dtau > 0.0 ? p->mag_lbfs_d * p->mag_lbfs_dtau / (p->dx * p->dx)
-                                           : 1.0 / (4.0 * p->mu0 * mmax);
-    }
-    I.mag_tol = p->mag_tol;
-    fill_coef(I.cf, I);
-    fill_coef(I.cd, I);
+    fill_params(I, s->p, L.pitch);
 
     std::vector<Tile> tp;
     append_tiles(tp, 0, p->nx, p->ny, TileShape{PT_TX, PT_TY, PT_TX * PT_TY});
