@@ -332,6 +332,33 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms);
    owned by a batch (lbfs_batch_slot) is left alone. */
 void lbfs_destroy(lbfs_solver* s);
 
+/* ------------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): lbfs_step without a solver or a
+ * device buffer. The caller owns the state, in device memory on the current device,
+ * seven nx*ny row-major arrays (row pitch nx) in the storage lbfs_init uses:
+ *   fields[0..3] He, p, rho cs^2 u, rho cs^2 v   (float for LBFS_FP32, double for FP64)
+ *   fields[4]    C, the order parameter           (double in both precisions)
+ *   fields[5]    phi - phi0: the potential minus the applied-field potential
+ *                phi0 = -h0 (x cos a + y sin a), a the field angle (float / double)
+ *   fields[6]    the lagged dFs/dt                 (float / double)
+ * nsteps time steps of the problem p are enqueued on `stream` (a hipStream_t of the
+ * current device; asynchronous, direct launches, the arithmetic of lbfs_step, so the
+ * same fields bit for bit) and the new state is left in the same arrays. The stage
+ * fields, the second potential buffer, the descriptor, the tile lists and the residual
+ * partials live in the library's static scratch of the current device, at most
+ * LBFS_STATIC_SCRATCH_BYTES: 48 B per cell in FP32 and 80 B in FP64 plus the lists,
+ * i.e. up to about 1.3 M cells in FP32 (1024 x 1024 fits) and 0.8 M in FP64. The
+ * function allocates nothing. Every call on a device uses that device's one scratch:
+ * calls that overlap on one device (other streams, other threads) race; calls on one
+ * stream are ordered. Every value a step reads from the scratch is written earlier in
+ * the same call. No observables are reduced (read them through a solver).
+ * LBFS_E_INVAL on invalid parameters, a NULL field, nsteps < 0, multigrid or
+ * convergence control (mag_max_iters > 0); LBFS_E_NOMEM if the problem does not fit
+ * the scratch; LBFS_E_DEVICE if a HIP call fails. */
+#define LBFS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps, void* stream);
+
 /* ------------------------------------------------------------------ batches
  * Many independent problems (different sizes, fields, Stefan and magnetic Bond numbers)
  * advanced together: every kernel of a step runs once over the concatenated tiles of

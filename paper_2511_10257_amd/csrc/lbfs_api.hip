@@ -14,6 +14,7 @@
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1325,6 +1326,149 @@ static void destroy_solver(lbfs_solver* s)
     if (s->hres) (void)hipHostFree(s->hres);
     if (s->staging) (void)hipHostFree(s->staging);
     delete s;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ static scratch
+//
+// lbfs_step_fields works in this array: the stage fields W1 and W2, the second potential
+// buffer, the descriptor, the tile lists and the residual partials of one instance. Each
+// device that runs the library holds its own copy until the process ends. In host code
+// the name is only a stand-in: the device address comes from hipGetSymbolAddress, once
+// per device, and only that address is passed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[LBFS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+char* scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of the current device's scratch (looked up on its first use)
+int static_scratch(char** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES) return LBFS_E_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_addr[dev]) {
+        void* a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return LBFS_E_DEVICE;
+        scratch_addr[dev] = static_cast<char*>(a);
+    }
+    *out = scratch_addr[dev];
+    return LBFS_OK;
+}
+
+static_assert(sizeof(DevInst) <= 3072, "the descriptor travels as a kernel argument");
+
+// the descriptor into device memory without a host-to-device copy
+__global__ void k_write_desc(DevInst d, DevInst* dst)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+
+// the row-major tile list of one instance (the order append_tiles gives)
+__global__ void k_fill_tiles(Tile* out, int nx, int tx, int ty, int ntiles)
+{
+    const int i = blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (i >= ntiles) return;
+    const int ntx = (nx + tx - 1) / tx;
+    out[i] = Tile{0, (i % ntx) * tx, (i / ntx) * ty, i};
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps, void* stream)
+{
+    if (!p || !fields) return LBFS_E_INVAL;
+    const int v = validate(p);
+    if (v != LBFS_OK) return v;
+    if (nsteps < 0) return LBFS_E_INVAL;
+    for (int k = 0; k < 7; k++)
+        if (!fields[k]) return LBFS_E_INVAL;
+    if (p->mag_method == LBFS_MAG_MULTIGRID || p->mag_max_iters > 0) return LBFS_E_INVAL;
+    lbfs_params q = *p;
+    if (q.dt == 0.0) q.dt = auto_dt(*p);
+    if (q.dt_stream == 0.0) q.dt_stream = 0.5 * q.dx;
+    const bool f64 = q.precision == LBFS_FP64;
+    const size_t es = f64 ? 8 : 4, n = (size_t)q.nx * q.ny;
+    // the tile shapes a solver of this size starts with
+    const TileShape SS = stage_shape(f64, 0);
+    const int mshape = n > (size_t)512 * 512 ? 1 : (n > ((size_t)1 << 17) ? 2 : 0);
+    const TileShape MS = MAG_SHAPES[mshape];
+    const int nts = count_tiles(q.nx, q.ny, SS), ntm = count_tiles(q.nx, q.ny, MS);
+    // layout of the scratch for this problem
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = align_up(off + b, ALIGN);
+        return o;
+    };
+    const size_t o_inst = take(sizeof(DevInst));
+    const size_t o_ts = take(sizeof(Tile) * nts), o_tm = take(sizeof(Tile) * ntm);
+    const size_t o_mpart = take(sizeof(double) * (std::max(nts, ntm) + 1));
+    const size_t o_res = take(sizeof(double) * NRES);
+    size_t o_w1[5], o_w2[5];
+    for (int k = 0; k < 5; k++) o_w1[k] = take(n * (k == 4 ? sizeof(double) : es));
+    for (int k = 0; k < 5; k++) o_w2[k] = take(n * (k == 4 ? sizeof(double) : es));
+    const size_t o_phi1 = take(n * es);
+    if (off > LBFS_STATIC_SCRATCH_BYTES) return LBFS_E_NOMEM;
+    char* base = nullptr;
+    const int rs = static_scratch(&base);
+    if (rs != LBFS_OK) return rs;
+
+    DevInst I;
+    std::memset(&I, 0, sizeof I);
+    for (int k = 0; k < 5; k++) {
+        I.W[k] = fields[k];
+        I.W1[k] = base + o_w1[k];
+        I.W2[k] = base + o_w2[k];
+    }
+    I.phi[0] = fields[5];
+    I.phi[1] = base + o_phi1;
+    I.S = fields[6];
+    I.part = nullptr;   // (observables are not reduced here)
+    I.mpart = reinterpret_cast<double*>(base + o_mpart);
+    I.result = reinterpret_cast<double*>(base + o_res);
+    I.ntile_stage = nts;
+    I.ntile_mag = ntm;
+    fill_params(I, q, q.nx);   // caller fields: row pitch nx
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevInst* dinst = reinterpret_cast<DevInst*>(base + o_inst);
+    Tile* ts = reinterpret_cast<Tile*>(base + o_ts);
+    Tile* tm = reinterpret_cast<Tile*>(base + o_tm);
+    hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, st, I, dinst);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_fill_tiles, dim3((nts + 255) / 256), dim3(256), 0, st, ts, q.nx, SS.tx, SS.ty, nts);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_fill_tiles, dim3((ntm + 255) / 256), dim3(256), 0, st, tm, q.nx, MS.tx, MS.ty, ntm);
+    HIPCHK(hipGetLastError());
+
+    Exec E;
+    E.f64 = f64;
+    E.stage_shape = 0;
+    E.mag_shape = mshape;
+    E.sweeps = q.sweeps;
+    E.omega = q.sor_omega;
+    E.mag_method = q.mag_method;
+    E.mag_chunks = 1;
+    E.stream = st;
+    E.dinst = dinst;
+    E.ninst = 1;
+    E.tiles_stage = ts;
+    E.nstage = nts;
+    E.tiles_mag = tm;
+    E.nmag = ntm;
+    E.phase = 0;
+    E.use_graph = false;
+    for (int k = 0; k < nsteps; k++) HIPCHK(exec_enqueue_step(E));
+    // the potential ends in the caller's field
+    if (E.phase != 0) HIPCHK(hipMemcpyAsync(fields[5], base + o_phi1, n * es, hipMemcpyDeviceToDevice, st));
+    return LBFS_OK;
 }
 
 void lbfs_destroy(lbfs_solver* s)

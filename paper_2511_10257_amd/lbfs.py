@@ -29,7 +29,7 @@ EXPORTS = (
     "lbfs_step", "lbfs_step_profiled", "lbfs_prepare", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
     "lbfs_mag_pseudo_steps", "lbfs_mag_multigrid", "lbfs_wall_heat_profile", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
-    "lbfs_load_state", "lbfs_destroy", "lbfs_strerror",
+    "lbfs_load_state", "lbfs_destroy", "lbfs_strerror", "lbfs_step_fields",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
     "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
     "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_prepare", "lbfs_batch_observe", "lbfs_batch_slot",
@@ -116,6 +116,7 @@ def lib():
             "lbfs_save_state": (C.c_int, [vp, vp, C.c_size_t]),
             "lbfs_load_state": (C.c_int, [vp, vp, C.c_size_t]),
             "lbfs_destroy": (None, [vp]),
+            "lbfs_step_fields": (C.c_int, [C.POINTER(Params), C.POINTER(vp), i32, vp]),
             "lbfs_strerror": (C.c_char_p, [C.c_int]),
             "lbfs_tile_shape": (C.c_int, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),

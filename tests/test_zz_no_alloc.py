@@ -1,0 +1,67 @@
+"""lbfs_step_fields, the entry point that allocates nothing (the library's static
+scratch holds the stage fields and lists), against lbfs_step on a solver: the same
+state in the same storage, the same number of steps, the same fields bit for bit. Two
+calls in a row, the second on a smaller grid (the scratch keeps the first call's
+contents), in FP32 and in FP64; a problem larger than the scratch is refused."""
+import ctypes as C
+import struct
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2511_10257_amd import lbfs, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+HEADER = struct.Struct("<IIiiiiddq")   # the checkpoint header of lbfs_save_state
+
+
+def native_state(solver, prob):
+    """The solver's state in its own storage, from its checkpoint: He, p, Mx, My (the
+    instance precision), C (FP64), phi - phi0 and S (the instance precision)."""
+    blob = solver.save()
+    n = prob["nx"] * prob["ny"]
+    t = np.float64 if prob["precision"] == "fp64" else np.float32
+    off, out = HEADER.size, []
+    for k in range(7):
+        dt = np.float64 if k == 4 else t
+        a = np.frombuffer(blob, dtype=dt, count=n, offset=off).reshape(prob["ny"], prob["nx"]).copy()
+        off += a.nbytes
+        out.append(a)
+    return out
+
+
+def step_fields(prob, arrays, nsteps):
+    dev = [torch.from_numpy(a).to("cuda:0") for a in arrays]
+    ptrs = (C.c_void_p * 7)(*[t.data_ptr() for t in dev])
+    params = lbfs.make_params(prob)
+    stream = torch.cuda.current_stream().cuda_stream
+    rc = lbfs.lib().lbfs_step_fields(C.byref(params), ptrs, int(nsteps), C.c_void_p(stream))
+    torch.cuda.synchronize()
+    return rc, [t.cpu().numpy() for t in dev]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_step_fields_equals_solver_steps_twice_second_smaller(precision):
+    cases = [(wl.droplet_problem(96, 20.0, ste=0.1, bo_m=1.5, angle_deg=30.0, precision=precision, ny=80), 19),
+             (wl.droplet_problem(64, 14.0, ste=0.15, bo_m=0.7, angle_deg=80.0, precision=precision, ny=48), 6)]
+    for prob, nsteps in cases:
+        s = lbfs.Solver(prob)
+        s.step(5)                          # a state with flow, freezing and a settled potential
+        start = native_state(s, prob)
+        s.step(nsteps)
+        ref = native_state(s, prob)
+        rc, got = step_fields(prob, start, nsteps)
+        assert rc == lbfs.LBFS_OK, lbfs.strerror(rc)
+        for k, (a, b) in enumerate(zip(got, ref)):
+            assert np.array_equal(a, b), (prob["nx"], prob["ny"], k, float(np.max(np.abs(a - b))))
+        s.close()
+
+
+def test_step_fields_refuses_what_does_not_fit():
+    prob = wl.droplet_problem(1536, 384.0, ste=0.1, bo_m=1.0, angle_deg=0.0, precision="fp32")
+    n = prob["nx"] * prob["ny"]
+    arrays = [np.zeros((prob["ny"], prob["nx"]), dtype=np.float64 if k == 4 else np.float32) for k in range(7)]
+    rc, _ = step_fields(prob, arrays, 1)
+    assert rc == lbfs.LBFS_E_NOMEM and n * 48 > (64 << 20)
