@@ -307,7 +307,7 @@ def kernel_shape(kernel: str, shapes: dict) -> str:
     early-load mark of a stage shape applies to stages 0 and 1 only."""
     if kernel == "mag":
         return shapes["mag"]
-    return shapes["stage"] if kernel in ("stage0", "stage1") else shapes["stage"].rstrip("e")
+    return shapes["stage"] if kernel in ("stage0", "stage1") else shapes["stage"].replace("e", "")
 
 
 def error_vs_oracle(source, solvers: dict, prob: dict) -> dict:

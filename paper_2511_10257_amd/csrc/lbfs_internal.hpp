@@ -19,21 +19,25 @@ struct TileShape {
     int tx, ty, nt;
     int early = 0;   // stage kernels: stage 0/1 load the owned cell's values before the halo
 };
-// Small workgroups: with the stage kernels' register use (about 90 VGPRs in FP32, 180 in
+// Small workgroups: with the stage kernels' register use (69 VGPRs in FP32, about 150 in
 // FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
 // other's barrier and LDS waits better than one large one, although small tiles
-// recompute more halo cells (3x for 8 x 8) and faces (2.25 per cell).
-// Tiles with a face count just under a multiple of 64 ((TX+1)TY + TX(TY+1)) and a halo
-// that fits the workgroup in one round keep every lane of the face phase busy. Loading
-// the owned cell's values early hides their latency but holds registers through the
-// face phase; whether that costs a wave per SIMD depends on the shape, so both are
-// candidates. In FP64, 12 x 8 (212 faces on four waves, a 252-cell halo in one round)
-// beat 8 x 8 by 6% per step on a 1024^2 grid and tied on 256^2.
-constexpr int NSTAGE_SHAPES = 6;
+// recompute more halo cells (2.6x for 10 x 10) and faces (2.2 per cell).
+// The face phase gives each wave faces of one axis: the x-faces ((TX+1) TY) and the
+// y-faces (TX (TY+1)) are each rounded up to whole waves, so 10 x 10 (110 + 110 faces on
+// four waves, a 256-cell halo region in one round, 22 KB of LDS in FP32: seven
+// workgroups and seven waves per SIMD) keeps the lanes busy; 7599 against 6804 MLUPS for
+// 10 x 8 (4 face waves for 178 faces) on a 1024^2 grid, 3362 against 3206 for 12 x 8 in
+// FP64. Loading the owned cell's values early hides their latency but holds registers
+// through the face phase; whether that costs a wave per SIMD depends on the shape, so
+// both are candidates.
+constexpr int NSTAGE_SHAPES = 7;
 constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
-    {10, 8, 256, 0}, {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {8, 8, 192, 0}, {16, 8, 320, 0}};
+    {10, 10, 256, 0}, {10, 8, 256, 0}, {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {8, 8, 192, 0},
+    {8, 12, 256, 0}};
 constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
-    {12, 8, 256, 0}, {8, 8, 256, 0}, {12, 7, 256, 0}, {10, 8, 256, 0}, {8, 7, 192, 0}, {8, 8, 192, 0}};
+    {10, 10, 256, 0}, {12, 8, 256, 0}, {8, 8, 256, 0}, {12, 7, 256, 0}, {10, 8, 256, 0}, {8, 7, 192, 0},
+    {8, 8, 192, 0}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
 // (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1 (a
 // larger tile recomputes fewer halo cells: 2.0x for 64 x 32 against 2.7x for 64 x 16).

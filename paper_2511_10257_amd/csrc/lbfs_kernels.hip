@@ -480,22 +480,34 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
 
 // ------------------------------------------------------------- stage kernel
 
-enum { Q_P = 0, Q_U, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_MU, Q_LAM, Q_CP, Q_PHI, NQ };
+// cell fields of the region in LDS: the first Q_P are read until the end of the stage;
+// p, mu, lambda, phi' and mu_c (after them) are dead once the face fluxes are computed,
+// and the fluxes take their place
+enum { Q_U = 0, Q_V, Q_RHO, Q_C, Q_T, Q_HE, Q_CP, Q_P, Q_MU, Q_LAM, Q_PHI, NQ };
 
 template <typename T, int TX, int TY, int NT>
 struct StageLds {
     static constexpr int RX = TX + 6, RY = TY + 6, NR = RX * RY;   // tile + 3
     static constexpr int GX = TX + 2, GY = TY + 2, NG = GX * GY;   // tile + 1
     static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
-    T q[NQ][NR];
-    T muc[NR];          // valid on tile + 2
+    // the magnetic block of the sweeps run inside stage 1 (tile + a halo of 2 MAG_KMAX + 3)
+    static constexpr int MRX = TX + 4 * MAG_KMAX + 6, MRY = TY + 4 * MAG_KMAX + 6;
+    static constexpr int MB = MRX * MRY + MRX * MRY / 2 * 2;
+    static_assert(5 * (NFX + NFY) <= (NQ + 1 - Q_P) * NR, "the fluxes fit in the dead cell fields");
+    T qbuf[(NQ + 1) * NR];   // q(k) for k < NQ, then mu_c (valid on tile + 2)
     union {
-        T g[NV][2][NG];     // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He (phases C-D)
-        double cd[NR];      // the order parameter in FP64 (phases A-B)
+        struct {
+            T g[NV][2][NG];  // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He (phases C-E)
+            T h2[NG];        // |H|^2
+        };
+        double cd[NR];       // the order parameter in FP64 (phases A-B)
+        T mblk[MB];          // the magnetic block (stage 1 with the sweeps, phases M-A)
     };
-    T h2[NG];           // |H|^2
-    T fx[5][NFX];
-    T fy[5][NFY];
+    __device__ T* q(int k) { return qbuf + k * NR; }
+    __device__ const T* q(int k) const { return qbuf + k * NR; }
+    __device__ T* muc() { return qbuf + NQ * NR; }
+    __device__ T* fx(int k) { return qbuf + Q_P * NR + k * NFX; }
+    __device__ T* fy(int k) { return qbuf + Q_P * NR + 5 * NFX + k * NFY; }
 };
 
 // gather one side of a face from LDS; axis 0: x-face (n = x, t = y), 1: y-face
@@ -503,14 +515,14 @@ template <typename T, typename L>
 __device__ __forceinline__ void gather_side(const L& s, int r, int gidx, int axis, Side<T>& o)
 {
     const int in = axis == 0 ? 0 : 1, it = 1 - in;
-    o.v[V_P] = s.q[Q_P][r];
-    o.v[V_UN] = axis == 0 ? s.q[Q_U][r] : s.q[Q_V][r];
-    o.v[V_UT] = axis == 0 ? s.q[Q_V][r] : s.q[Q_U][r];
-    o.v[V_RHO] = s.q[Q_RHO][r];
-    o.v[V_C] = s.q[Q_C][r];
-    o.v[V_MUC] = s.muc[r];
-    o.v[V_T] = s.q[Q_T][r];
-    o.v[V_HE] = s.q[Q_HE][r];
+    o.v[V_P] = s.q(Q_P)[r];
+    o.v[V_UN] = axis == 0 ? s.q(Q_U)[r] : s.q(Q_V)[r];
+    o.v[V_UT] = axis == 0 ? s.q(Q_V)[r] : s.q(Q_U)[r];
+    o.v[V_RHO] = s.q(Q_RHO)[r];
+    o.v[V_C] = s.q(Q_C)[r];
+    o.v[V_MUC] = s.qbuf[NQ * L::NR + r];
+    o.v[V_T] = s.q(Q_T)[r];
+    o.v[V_HE] = s.q(Q_HE)[r];
     // gradient slots: 0 p, 1 u, 2 v, 3 rho, 4 C, 5 muc, 6 T, 7 He
     const int slot[NV] = {0, axis == 0 ? 1 : 2, axis == 0 ? 2 : 1, 3, 4, 5, 6, 7};
 #pragma unroll
@@ -518,9 +530,50 @@ __device__ __forceinline__ void gather_side(const L& s, int r, int gidx, int axi
         o.gn[k] = s.g[slot[k]][in][gidx];
         o.gt[k] = s.g[slot[k]][it][gidx];
     }
-    o.mu = s.q[Q_MU][r];
-    o.lam = s.q[Q_LAM][r];
-    o.cp = s.q[Q_CP][r];
+    o.mu = s.q(Q_MU)[r];
+    o.lam = s.q(Q_LAM)[r];
+    o.cp = s.q(Q_CP)[r];
+}
+
+// the LBFS flux of face fi of one axis (AX 0: x-face, cells L = (cx-1, cy), R = (cx, cy);
+// 1: y-face, L = (cx, cy-1), R = (cx, cy)) of a tile, with the wall conditions, into F
+// (He, p, normal and tangential momentum, C)
+template <typename T, int TX, int TY, int AX, typename L>
+__device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst& I, int x0, int y0, int fi,
+                                           T F[5])
+{
+    int cx, cy, lxL, lyL;
+    if constexpr (AX == 0) {
+        cx = fi % (TX + 1); cy = fi / (TX + 1);
+        lxL = cx - 1; lyL = cy;
+    } else {
+        cx = fi % TX; cy = fi / TX;
+        lxL = cx; lyL = cy - 1;
+    }
+    const int rL = (lyL + 3) * L::RX + (lxL + 3), rR = (cy + 3) * L::RX + (cx + 3);
+    const int gL = (lyL + 1) * L::GX + (lxL + 1), gR = (cy + 1) * L::GX + (cx + 1);
+    Side<T> SL, SR;
+    gather_side<T>(s, rL, gL, AX, SL);
+    gather_side<T>(s, rR, gR, AX, SR);
+    face_flux<T>(K, SL, SR, F);
+    // walls: no mass or order-parameter flux; heat through the half cell
+    const int gface = AX == 0 ? x0 + cx : y0 + cy;
+    const int nax = AX == 0 ? I.nx : I.ny;
+    const int per = AX == 0 ? I.per_x : I.per_y;
+    if (!per && (gface == 0 || gface == nax)) {
+        const bool lo = gface == 0;
+        const int wall = AX == 0 ? (lo ? 0 : 1) : (lo ? 2 : 3);
+        const int rc = lo ? rR : rL;
+        F[1] = T(0);
+        F[4] = T(0);
+        if (I.tbc[wall]) {
+            const T k = s.q(Q_LAM)[rc] * rcp_bounded(s.q(Q_RHO)[rc]);
+            const T Tc = s.q(Q_T)[rc], Tw = K.tval[wall];
+            F[0] = lo ? -k * (Tc - Tw) * K.i_halfdx : -k * (Tw - Tc) * K.i_halfdx;
+        } else {
+            F[0] = T(0);
+        }
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double x)
@@ -647,7 +700,7 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
 // NT >= every per-tile work count (halo cells, gradient cells, faces), so each phase
 // is one round; the first TX*TY threads own the tile's cells.
 template <typename T, int TX, int TY, int NT, int STAGE, int EARLY, int FUSE>
-__global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
+__global__ __launch_bounds__(NT, (NT == 256 && sizeof(T) == 4) ? 7 : 1) void k_stage(const DevInst* __restrict__ insts,
                                               const Tile* __restrict__ tiles, int pidx, int nsweeps, double omega)
 {
     using L = StageLds<T, TX, TY, NT>;
@@ -690,7 +743,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     //      arrays, which phases C and D fill only after A.
     constexpr int HM = 2 * MAG_KMAX + 3;
     using GM = MagGeom<TX, TY, HM>;
-    T (*const mph)[GM::HALF] = reinterpret_cast<T (*)[GM::HALF]>(&s.g[0][0][0]);
+    T (*const mph)[GM::HALF] = reinterpret_cast<T (*)[GM::HALF]>(&s.mblk[0]);
     const int mpar0 = (x0 - HM + y0 - HM) & 1;
     auto mphi = [&](int px, int py) {   // potential of grid cell (px, py) from the block
         int lxm = px - x0 + HM, lym = py - y0 + HM;
@@ -699,9 +752,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         return mph[(mpar0 + lxm + lym) & 1][lym * GM::RXH + (lxm >> 1)];
     };
     if constexpr (FUSE) {
-        static_assert(sizeof(T) * (2 * GM::HALF + GM::NR) <=
-                          sizeof(s.g) + sizeof(s.h2) + sizeof(s.fx) + sizeof(s.fy),
-                      "the magnetic block fits in the face-phase arrays");
+        static_assert(2 * GM::HALF + GM::NR <= L::MB, "the magnetic block fits in its LDS");
         __shared__ double mred[NT / 64];
         T* const mmu = &mph[0][0] + 2 * GM::HALF;
         const double r2 = mag_block<T, TX, TY, NT, HM>(I, x0, y0, pidx, nsweeps, omega, 1, mph, mmu);
@@ -742,17 +793,17 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     constexpr bool cd_copy = sizeof(T) < sizeof(double);
     auto store_cell = [&](int r, const Prim<T>& q, T ph, double cdv) {
         if constexpr (cd_copy) s.cd[r] = cdv;
-        s.q[Q_P][r] = q.p;
-        s.q[Q_U][r] = q.u;
-        s.q[Q_V][r] = q.v;
-        s.q[Q_RHO][r] = q.rho;
-        s.q[Q_C][r] = q.C;
-        s.q[Q_T][r] = q.Tt;
-        s.q[Q_HE][r] = q.He;
-        s.q[Q_MU][r] = q.mu;
-        s.q[Q_LAM][r] = q.lam;
-        s.q[Q_CP][r] = q.cp;
-        s.q[Q_PHI][r] = ph;
+        s.q(Q_P)[r] = q.p;
+        s.q(Q_U)[r] = q.u;
+        s.q(Q_V)[r] = q.v;
+        s.q(Q_RHO)[r] = q.rho;
+        s.q(Q_C)[r] = q.C;
+        s.q(Q_T)[r] = q.Tt;
+        s.q(Q_HE)[r] = q.He;
+        s.q(Q_MU)[r] = q.mu;
+        s.q(Q_LAM)[r] = q.lam;
+        s.q(Q_CP)[r] = q.cp;
+        s.q(Q_PHI)[r] = ph;
     };
     constexpr int NIT = (L::NR + NT - 1) / NT;
     if (interior) {
@@ -850,10 +901,10 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         for (int r = tid; r < L::NR; r += NT) {
             const int lx = r % L::RX, ly = r / L::RX;
             if (lx < 1 || lx >= L::RX - 1 || ly < 1 || ly >= L::RY - 1) continue;
-            const double* C = cd_copy ? s.cd : reinterpret_cast<const double*>(s.q[Q_C]);
+            const double* C = cd_copy ? s.cd : reinterpret_cast<const double*>(s.q(Q_C));
             const double c = C[r];
             const double lap = (C[r + 1] + C[r - 1] + C[r + L::RX] + C[r - L::RX] - 4.0 * c) * idx2;
-            s.muc[r] = T(2.0 * beta * c * (c - 1.0) * (2.0 * c - 1.0) - kappa * lap);
+            s.muc()[r] = T(2.0 * beta * c * (c - 1.0) * (2.0 * c - 1.0) - kappa * lap);
         }
     }
     __syncthreads();
@@ -877,7 +928,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
             if (mx < 0 || mx >= nx || my < 0 || my >= ny || mlx < 1 || mlx > L::RX - 2 || mly < 1 ||
                 mly > L::RY - 2)
                 continue;
-            s.muc[r] = s.muc[mly * L::RX + mlx];
+            s.muc()[r] = s.muc()[mly * L::RX + mlx];
         }
         __syncthreads();
     }
@@ -887,7 +938,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
     for (int gi = tid; gi < L::NG; gi += NT) {
         const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
         const int r = ly * L::RX + lx;
-        const T* src[NV] = {s.q[Q_P], s.q[Q_U], s.q[Q_V], s.q[Q_RHO], s.q[Q_C], s.muc, s.q[Q_T], s.q[Q_HE]};
+        const T* src[NV] = {s.q(Q_P), s.q(Q_U), s.q(Q_V), s.q(Q_RHO), s.q(Q_C), s.muc(), s.q(Q_T), s.q(Q_HE)};
 #pragma unroll
         for (int k = 0; k < NV; k++) {
             s.g[k][0][gi] = (src[k][r + 1] - src[k][r - 1]) * inv2dx;
@@ -897,7 +948,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         const bool wallx = !interior && !I.per_x && (gx < 0 || gx >= nx);
         const bool wally = !interior && !I.per_y && (gy < 0 || gy >= ny);
         if (!wallx && !wally) {
-            const T* P = s.q[Q_PHI];
+            const T* P = s.q(Q_PHI);
             const T Hx = h0x - (P[r + 1] - P[r - 1]) * inv2dx;
             const T Hy = h0y - (P[r + L::RX] - P[r - L::RX]) * inv2dx;
             s.h2[gi] = Hx * Hx + Hy * Hy;
@@ -923,47 +974,40 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         s.h2[gi] = (mwx || mwy) ? T(0) : s.h2[mg];
     }
 
-    // ---- D: LBFS fluxes of all faces of the tile
-    for (int f = tid; f < L::NFX + L::NFY; f += NT) {
-        const bool xf = f < L::NFX;
-        const int fi = xf ? f : f - L::NFX;
-        int cx, cy, lxL, lyL, lxR, lyR;   // tile coords of L and R cells
-        if (xf) {
-            cx = fi % (TX + 1); cy = fi / (TX + 1);
-            lxL = cx - 1; lyL = cy; lxR = cx; lyR = cy;
-        } else {
-            cx = fi % TX; cy = fi / TX;
-            lxL = cx; lyL = cy - 1; lxR = cx; lyR = cy;
-        }
-        const int rL = (lyL + 3) * L::RX + (lxL + 3), rR = (lyR + 3) * L::RX + (lxR + 3);
-        const int gL = (lyL + 1) * L::GX + (lxL + 1), gR = (lyR + 1) * L::GX + (lxR + 1);
-        Side<T> SL, SR;
-        gather_side<T>(s, rL, gL, xf ? 0 : 1, SL);
-        gather_side<T>(s, rR, gR, xf ? 0 : 1, SR);
-        T F[5];
-        face_flux<T>(K, SL, SR, F);
-        // walls: no mass or order-parameter flux; heat through the half cell
-        const int gface = xf ? x0 + cx : y0 + cy;
-        const int nax = xf ? nx : ny;
-        const bool per = xf ? I.per_x : I.per_y;
-        if (!per && (gface == 0 || gface == nax)) {
-            const bool lo = gface == 0;
-            const int wall = xf ? (lo ? 0 : 1) : (lo ? 2 : 3);
-            const int rc = lo ? rR : rL;
-            F[1] = T(0);
-            F[4] = T(0);
-            if (I.tbc[wall]) {
-                const T k = s.q[Q_LAM][rc] * rcp_bounded(s.q[Q_RHO][rc]);
-                const T Tc = s.q[Q_T][rc], Tw = K.tval[wall];
-                F[0] = lo ? -k * (Tc - Tw) * K.i_halfdx : -k * (Tw - Tc) * K.i_halfdx;
-            } else {
-                F[0] = T(0);
+    // ---- D: LBFS fluxes of all faces of the tile: x-faces on the first NXT threads,
+    //      y-faces on the next NYT (whole waves each), so the axis is the same on every lane
+    //      of a wave and the LDS offsets and the component swap are constants. Every face
+    //      of every tile shape goes through the same two instantiations of the flux.
+    //      The fluxes stay in registers until every face has read its cells, then take
+    //      the place of the cell fields that are dead from here on.
+    {
+        constexpr int NXT = (L::NFX + 63) / 64 * 64, NYT = (L::NFY + 63) / 64 * 64;
+        constexpr int NRND = (NXT + NYT + NT - 1) / NT;
+        T Fr[NRND][5];
+#pragma unroll
+        for (int k = 0; k < NRND; k++) {
+            const int f = tid + k * NT;
+            if (f >= NXT + NYT) break;
+            if (__builtin_amdgcn_readfirstlane(f) < NXT) {
+                if (f < L::NFX) split_face<T, TX, TY, 0>(s, K, I, x0, y0, f, Fr[k]);
+            } else if (f - NXT < L::NFY) {
+                split_face<T, TX, TY, 1>(s, K, I, x0, y0, f - NXT, Fr[k]);
             }
         }
-        if (xf) {
-            s.fx[0][fi] = F[0]; s.fx[1][fi] = F[1]; s.fx[2][fi] = F[2]; s.fx[3][fi] = F[3]; s.fx[4][fi] = F[4];
-        } else {
-            s.fy[0][fi] = F[0]; s.fy[1][fi] = F[1]; s.fy[2][fi] = F[3]; s.fy[3][fi] = F[2]; s.fy[4][fi] = F[4];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NRND; k++) {
+            const int f = tid + k * NT;
+            if (f >= NXT + NYT) break;
+            const T* F = Fr[k];
+            if (f < NXT) {
+                if (f < L::NFX) {
+                    s.fx(0)[f] = F[0]; s.fx(1)[f] = F[1]; s.fx(2)[f] = F[2]; s.fx(3)[f] = F[3]; s.fx(4)[f] = F[4];
+                }
+            } else if (f - NXT < L::NFY) {
+                const int fi = f - NXT;
+                s.fy(0)[fi] = F[0]; s.fy(1)[fi] = F[1]; s.fy(2)[fi] = F[3]; s.fy(3)[fi] = F[2]; s.fy(4)[fi] = F[4];
+            }
         }
     }
     __syncthreads();
@@ -978,7 +1022,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         const T cs2 = T(1.0 / 3.0);
         // Kelvin force from the step-start state (Eq. 6)
         T Cn, Hen;
-        if (STAGE <= 1) { Cn = s.q[Q_C][r]; Hen = s.q[Q_HE][r]; }
+        if (STAGE <= 1) { Cn = s.q(Q_C)[r]; Hen = s.q(Q_HE)[r]; }
         else { Cn = T(cCb); Hen = cWb[0]; }
         T Tn, Fln;
         enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
@@ -987,22 +1031,18 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         const T kmg = T(0.5) * K.mu0 * chi;
         const T fmx = kmg * (s.h2[gi + 1] - s.h2[gi - 1]) * inv2dx;
         const T fmy = kmg * (s.h2[gi + L::GX] - s.h2[gi - L::GX]) * inv2dx;
-        // stage-state cell fields
-        const T* U = s.q[Q_U];
-        const T* V = s.q[Q_V];
-        const T* RH = s.q[Q_RHO];
-        const T divu = (U[r + 1] - U[r - 1]) * inv2dx + (V[r + L::RX] - V[r - L::RX]) * inv2dx;
-        const T drx = (RH[r + 1] - RH[r - 1]) * inv2dx, dry = (RH[r + L::RX] - RH[r - L::RX]) * inv2dx;
-        const T dmx = (s.muc[r + 1] - s.muc[r - 1]) * inv2dx;
-        const T dmy = (s.muc[r + L::RX] - s.muc[r - L::RX]) * inv2dx;
-        const T c = s.q[Q_C][r], rho = RH[r], u = U[r], v = V[r];
+        // stage-state cell fields; the central gradients phase C left in LDS
+        const T divu = s.g[1][0][gi] + s.g[2][1][gi];
+        const T drx = s.g[3][0][gi], dry = s.g[3][1][gi];
+        const T dmx = s.g[5][0][gi], dmy = s.g[5][1][gi];
+        const T c = s.q(Q_C)[r], rho = s.q(Q_RHO)[r], u = s.q(Q_U)[r], v = s.q(Q_V)[r];
         T Tc, Flc;
-        enthalpy_state<T>(K, s.q[Q_HE][r], c, Tc, Flc);
+        enthalpy_state<T>(K, s.q(Q_HE)[r], c, Tc, Flc);
         const T fs = clamp01(c) * (T(1) - Flc);
         const T Sv = cS;
         const T vc = K.vc;
         T src[5];
-        src[0] = s.q[Q_CP][r] * s.q[Q_T][r] * divu;
+        src[0] = s.q(Q_CP)[r] * s.q(Q_T)[r] * divu;
         src[1] = cs2 * (u * drx + v * dry) + rho * cs2 * vc * Sv;
         src[2] = cs2 * (-c * dmx + fmx + rho * K.grav[0] - rho * u * fs * idt);
         src[3] = cs2 * (-c * dmy + fmy + rho * K.grav[1] - rho * v * fs * idt);
@@ -1011,7 +1051,7 @@ __global__ __launch_bounds__(NT) void k_stage(const DevInst* __restrict__ insts,
         T Rk[5];
 #pragma unroll
         for (int k = 0; k < 5; k++) {
-            const T div = (s.fx[k][fW + 1] - s.fx[k][fW] + s.fy[k][fS + TX] - s.fy[k][fS]) * idx;
+            const T div = (s.fx(k)[fW + 1] - s.fx(k)[fW] + s.fy(k)[fS + TX] - s.fy(k)[fS]) * idx;
             Rk[k] = -div + src[k];
         }
         // (the order parameter is combined in FP64: its increment dt R_C is small)
