@@ -197,18 +197,21 @@ int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
               lbfs_solver** out);
 
 /* Enqueue nsteps time steps on the stream (asynchronous). On a non-default stream
-   the steps are replays of HIP graphs captured on first use: one replay covers 16
-   consecutive steps while at least 16 remain, one step otherwise (LBFS_GRAPH_STEPS=k
-   in the environment at init sets the 16, 1..64; LBFS_NO_GRAPH=1 launches the kernels
-   directly). The results are the same either way. */
+   the steps are replays of HIP graphs captured on first use: each replay covers the
+   longest of 16, 8, 4 or 2 consecutive steps that the steps still to go fill, and a
+   last single step is launched directly (LBFS_GRAPH_STEPS=k in the environment at init
+   sets the longest length, 1..64, the others being the powers of two below it;
+   LBFS_NO_GRAPH=1 launches every kernel directly). The results are the same either
+   way. */
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
 /* Capture and instantiate now every HIP graph that lbfs_step and lbfs_step_profiled
-   replay (one step, and the multi-step replay, from either potential buffer), so that
-   the first steps after init, lbfs_set_tile_shapes or lbfs_autotune do not pay for the
-   capture. Enqueues no work; the state and the clock are unchanged. Does nothing where
-   steps are not graph replays (default stream, LBFS_NO_GRAPH=1). LBFS_E_STATE on a
-   borrowed batch handle, LBFS_E_DEVICE if a capture fails. */
+   replay (every length, from either potential buffer), and create the timing events of
+   a profiled run that samples up to 16 steps, so that the first steps after init,
+   lbfs_set_tile_shapes or lbfs_autotune pay for neither. Enqueues no work; the state
+   and the clock are unchanged. Captures nothing where steps are not graph replays
+   (default stream, LBFS_NO_GRAPH=1). LBFS_E_STATE on a borrowed batch handle,
+   LBFS_E_DEVICE if a capture or an event creation fails. */
 int lbfs_prepare(lbfs_solver* s);
 
 /* Kernel kinds of one step, for lbfs_step_profiled: the magnetic phase (one launch
@@ -393,8 +396,8 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out);
 int lbfs_batch_retire(lbfs_batch* b, int32_t slot);
 
 /* Enqueue nsteps time steps of every live instance (asynchronous; HIP graph replays
-   of 16 steps or of one as in lbfs_step on a non-default stream, recaptured after
-   admissions and retirements). */
+   of 16, 8, 4 or 2 steps and a last single step launched directly, as in lbfs_step on
+   a non-default stream, recaptured after admissions and retirements). */
 int lbfs_batch_step(lbfs_batch* b, int32_t nsteps);
 
 /* lbfs_prepare for a batch: rebuilds the launch lists after admissions and retirements

@@ -230,11 +230,38 @@ struct Exec {
     int phase = 0;                       // potential buffer holding the current phi'
     bool use_graph = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing of the next launch (profiled steps)
-    int graph_steps = 16;                // steps per replay of the multi-step graph
-    // graph[len][ph]: `len` = 0 one step, 1 graph_steps steps, from potential buffer ph
-    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int graph_steps = 1;                 // steps per replay of the longest graph
+    // graph[li][ph]: glen[li] consecutive steps from potential buffer ph; the lengths are
+    // the powers of two below graph_steps, then graph_steps itself
+    static constexpr int NGLEN = 8;
+    int glen[NGLEN] = {1};
+    int nglen = 1;
+    hipGraph_t graph[NGLEN][2] = {};
+    hipGraphExec_t graph_exec[NGLEN][2] = {};
+    // timing events of the profiled steps, created ahead (lbfs_prepare) or on first need
+    // and kept, so that a profiled run creates none while the device waits
+    std::vector<hipEvent_t> evpool;
 };
+
+// at least n events in the pool
+hipError_t exec_events(Exec& E, size_t n)
+{
+    while (E.evpool.size() < n) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        E.evpool.push_back(e);
+    }
+    return hipSuccess;
+}
+
+void exec_set_graph_steps(Exec& E, int gs)
+{
+    E.graph_steps = gs;
+    E.nglen = 0;
+    for (int l = 1; l < gs && E.nglen < Exec::NGLEN - 1; l *= 2) E.glen[E.nglen++] = l;
+    E.glen[E.nglen++] = gs;
+}
 
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 {
@@ -379,7 +406,7 @@ hipError_t exec_enqueue_step(Exec& E)
 
 void exec_drop_graphs(Exec& E)
 {
-    for (int l = 0; l < 2; l++)
+    for (int l = 0; l < Exec::NGLEN; l++)
         for (int k = 0; k < 2; k++) {
             if (E.graph_exec[l][k]) (void)hipGraphExecDestroy(E.graph_exec[l][k]);
             if (E.graph[l][k]) (void)hipGraphDestroy(E.graph[l][k]);
@@ -388,13 +415,20 @@ void exec_drop_graphs(Exec& E)
         }
 }
 
-// capture one time step (len 0) or graph_steps consecutive steps (len 1) starting from
-// potential buffer `ph` into a HIP graph, once per length and buffer. A replay of the
-// longer graph costs one launch for graph_steps steps: the per-replay overhead of a graph
-// launch is several microseconds, as much as a graph gap between kernels.
-hipError_t exec_ensure_graph(Exec& E, int len, int ph)
+void exec_release(Exec& E)
 {
-    if (E.graph_exec[len][ph]) return hipSuccess;
+    exec_drop_graphs(E);
+    for (hipEvent_t e : E.evpool) (void)hipEventDestroy(e);
+    E.evpool.clear();
+}
+
+// capture glen[li] consecutive time steps starting from potential buffer `ph` into a HIP
+// graph, once per length and buffer. A replay of a longer graph costs one launch for all
+// its steps: the per-replay overhead of a graph launch is several microseconds, as much
+// as a graph gap between kernels.
+hipError_t exec_ensure_graph(Exec& E, int li, int ph)
+{
+    if (E.graph_exec[li][ph]) return hipSuccess;
     const int saved = E.phase;
     const bool saved_mres = E.mres_stage;
     E.phase = ph;
@@ -404,19 +438,19 @@ hipError_t exec_ensure_graph(Exec& E, int len, int ph)
         E.phase = saved;
         return e;
     }
-    const int n = len ? E.graph_steps : 1;
+    const int n = E.glen[li];
     for (int k = 0; k < n && e == hipSuccess; k++) e = exec_enqueue_step(E);
     const hipError_t ec = hipStreamEndCapture(E.stream, &g);
     E.phase = saved;
     E.mres_stage = saved_mres;
     if (e == hipSuccess) e = ec;
-    if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[len][ph], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[li][ph], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        E.graph_exec[len][ph] = nullptr;
+        E.graph_exec[li][ph] = nullptr;
         return e;
     }
-    E.graph[len][ph] = g;
+    E.graph[li][ph] = g;
     return hipSuccess;
 }
 
@@ -439,30 +473,39 @@ int exec_step_flips(const Exec& E)
     return (launches * E.mag_chunks) & 1;
 }
 
-// up to `nmax` (>= 1) steps: graph_steps of them as one replay of the multi-step graph
-// when that many are wanted, else one step (a one-step replay, or direct launches when
-// graphs are off). Returns the steps enqueued, 0 on a HIP error.
+// up to `nmax` (>= 1) steps as one replay of the longest graph that many steps fill, or
+// one step by direct launches where no graph of two or more steps fits (or graphs are
+// off): a one-step graph replay costs a few microseconds more than the same kernels
+// launched directly. Returns the steps enqueued, 0 on a HIP error.
 int exec_run_steps(Exec& E, int nmax)
 {
-    if (!E.use_graph) return exec_enqueue_step(E) == hipSuccess ? 1 : 0;
-    const int len = (E.graph_steps > 1 && nmax >= E.graph_steps) ? 1 : 0;
-    const int n = len ? E.graph_steps : 1;
+    int li = 0;
+    if (E.use_graph)
+        while (li + 1 < E.nglen && E.glen[li + 1] <= nmax) li++;
+    if (!E.use_graph || E.glen[li] < 2) return exec_enqueue_step(E) == hipSuccess ? 1 : 0;
+    const int n = E.glen[li];
     const int ph = E.phase;
-    if (exec_ensure_graph(E, len, ph) != hipSuccess) return 0;
-    if (hipGraphLaunch(E.graph_exec[len][ph], E.stream) != hipSuccess) return 0;
+    if (exec_ensure_graph(E, li, ph) != hipSuccess) return 0;
+    if (hipGraphLaunch(E.graph_exec[li][ph], E.stream) != hipSuccess) return 0;
     E.phase = ph ^ ((n * exec_step_flips(E)) & 1);
     E.mres_stage = E.fused;
     return n;
 }
 
-// capture every graph exec_run_steps can replay (one step and graph_steps steps, from
-// either potential buffer) without running it
+// the timing events of profiled runs sampling up to this many steps are made ahead
+constexpr int PREPARED_SAMPLES = 16;
+constexpr int EVENTS_PER_SAMPLE = 8;   // start and end of the four kernel phases
+
+// capture every graph exec_run_steps can replay (every length, from either potential
+// buffer) without running it, and create the timing events of a profiled run
 hipError_t exec_prepare(Exec& E)
 {
+    const hipError_t ee = exec_events(E, (size_t)PREPARED_SAMPLES * EVENTS_PER_SAMPLE);
+    if (ee != hipSuccess) return ee;
     if (!E.use_graph || E.ninst == 0) return hipSuccess;
-    for (int len = 0; len < (E.graph_steps > 1 ? 2 : 1); len++)
-        for (int ph = 0; ph < 2; ph++) {
-            const hipError_t e = exec_ensure_graph(E, len, ph);
+    for (int li = 0; li < E.nglen; li++)
+        for (int ph = 0; ph < 2 && E.glen[li] >= 2; ph++) {
+            const hipError_t e = exec_ensure_graph(E, li, ph);
             if (e != hipSuccess) return e;
         }
     return hipSuccess;
@@ -475,15 +518,10 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
 {
     const int nsample = (nsteps + sample_every - 1) / sample_every;
     if (nsample > 4096) return LBFS_E_INVAL;
-    const int per_step = 4;
-    std::vector<hipEvent_t> ev((size_t)nsample * per_step * 2, nullptr);
+    const int per_step = EVENTS_PER_SAMPLE / 2;
+    if (exec_events(E, (size_t)nsample * EVENTS_PER_SAMPLE) != hipSuccess) return LBFS_E_DEVICE;
+    const std::vector<hipEvent_t>& ev = E.evpool;
     std::vector<int> kind((size_t)nsample * per_step, 0);
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto& f : ev)
-                if (f) (void)hipEventDestroy(f);
-            return LBFS_E_DEVICE;
-        }
     int rc = LBFS_OK;
     size_t slot = 0;
     // the launch itself timestamps the kernel's start and end into the events
@@ -508,16 +546,9 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
             n++;
             continue;
         }
-        // the plain steps up to the next sampled one: multi-step graph replays, and direct
-        // launches for a remainder shorter than one (a one-step graph replay costs a few
-        // microseconds more than the same kernels launched directly)
+        // the plain steps up to the next sampled one
         const int next = std::min(nsteps, (n / sample_every + 1) * sample_every);
-        int k;
-        if (!E.use_graph || E.graph_steps <= 1 || next - n >= E.graph_steps) {
-            k = exec_run_steps(E, next - n);
-        } else {
-            k = exec_enqueue_step(E) == hipSuccess ? 1 : 0;   // (flips the potential buffer itself)
-        }
+        const int k = exec_run_steps(E, next - n);
         if (k == 0) rc = LBFS_E_DEVICE;
         for (int q = 0; q < k; q++) after_step();
         n += k;
@@ -539,7 +570,6 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
         }
     for (int k = 0; k < LBFS_NKERNELS; k++)
         if (launches[k] > 0) kernel_ms[k] /= launches[k];
-    for (auto& e : ev) (void)hipEventDestroy(e);
     return rc;
 }
 
@@ -1079,7 +1109,7 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     s->hres[RES_MAGR2] = r * r;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
     E.use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
-    E.graph_steps = graph_steps_setting();
+    exec_set_graph_steps(E, graph_steps_setting());
     *out = s;
     return LBFS_OK;
 }
@@ -1322,7 +1352,7 @@ static void destroy_solver(lbfs_solver* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    exec_drop_graphs(s->E);
+    exec_release(s->E);
     if (s->hres) (void)hipHostFree(s->hres);
     if (s->staging) (void)hipHostFree(s->staging);
     delete s;
@@ -1898,7 +1928,7 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
     E.stream = b->stream;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
     E.use_graph = b->stream != nullptr && !(ng && ng[0] == '1');
-    E.graph_steps = graph_steps_setting();
+    exec_set_graph_steps(E, graph_steps_setting());
     if (HIPFAIL(hipHostMalloc(&b->hres, sizeof(double) * NRES * max_slots, hipHostMallocDefault))) {
         delete b;
         return LBFS_E_DEVICE;
@@ -2189,7 +2219,7 @@ void lbfs_batch_destroy(lbfs_batch* b)
 {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
-    exec_drop_graphs(b->E);
+    exec_release(b->E);
     for (Slot& q : b->slots)
         if (q.s) destroy_solver(q.s);
     if (b->hres) (void)hipHostFree(b->hres);

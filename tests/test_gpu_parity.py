@@ -266,9 +266,10 @@ def test_graph_replay_equals_direct_launches(monkeypatch):
 
 @pytest.mark.parametrize("variant", ["sweeps", "sweeps5", "lbfs", "multigrid", "controlled", "fused"])
 def test_multi_step_graphs_equal_direct_launches(monkeypatch, variant):
-    """Replays of 8-step and 3-step graphs (with one-step replays for the remainder) give
-    the fields of direct launches bit for bit, for every magnetic method: the potential
-    buffer parity after a replay of n steps is that of n single steps."""
+    """Replays of graphs of up to 8 and up to 3 steps (8, 4, 2 and 3, 2, with single steps
+    launched directly) give the fields of direct launches bit for bit, for every
+    magnetic method: the potential buffer parity after a replay of n steps is that of n
+    single steps."""
     prob = wl.droplet_problem(96, 24.0, ste=0.1, bo_m=1.5, angle_deg=30.0, precision="fp32")
     prob.update(dict(sweeps5=dict(sweeps=5), lbfs=dict(mag_method="lbfs", sweeps=3),
                      multigrid=dict(mag_method="multigrid", sweeps=1),
