@@ -168,114 +168,112 @@ struct Side {
 // Eq. 45 gives the face state; the star distributions (Eqs. 16, 22, 32, 33 with the
 // viscous sign) give F = (3/2 - tau) M_eq(face) + (tau - 1/2) M(surrounding), where
 // M_eq(face) are the closed-form moments of the face equilibria (D2Q9 identities).
+// The terms linear in p, mu_c and T are summed over the nine points in closed form
+// (the points are linear reconstructions, so their weighted sums are combinations of
+// the two sides' values and gradients); the terms in Gamma and C e.u are summed point
+// by point, per weight class.
 // Output: F[0] He, F[1] p, F[2] normal momentum, F[3] tangential momentum, F[4] C.
 template <typename T>
-__device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, const Side<T>& R,
-                                          T F[5])
+__device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, const Side<T>& R, T F[5])
 {
-    // the compiler may reorder these sums and products (rounding-level differences, no
-    // change of what is computed)
 #pragma clang fp reassociate(on)
     const T h = T(0.5) * K.dx;
-    // reconstructions at the nine points, per variable
-    T rc[NV][9];
+    const T hh = T(0.5) * h;
+    // value at the face centre, the point on the face line: the mean of the two
+    // reconstructions ((L + h dL/dn) + (R - h dR/dn)) / 2
+    auto mid = [&](int k) { return T(0.5) * (L.v[k] + R.v[k]) + hh * (L.gn[k] - R.gn[k]); };
+    // the variables that enter the equilibria nonlinearly, at the nine points
+    enum { U = 0, W, RH, TT, CC, NN };
+    constexpr int VK[NN] = {V_UN, V_UT, V_RHO, V_T, V_C};
+    T x[NN][9];
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-        const T m = T(0.5) * ((L.v[k] + h * L.gn[k]) + (R.v[k] - h * R.gn[k]));
-        const T gt = T(0.5) * (L.gt[k] + R.gt[k]);
-        rc[k][0] = m;
-        rc[k][1] = L.v[k];
-        rc[k][2] = m - h * gt;
-        rc[k][3] = R.v[k];
-        rc[k][4] = m + h * gt;
-        rc[k][5] = L.v[k] - h * L.gt[k];
-        rc[k][6] = R.v[k] - h * R.gt[k];
-        rc[k][7] = R.v[k] + h * R.gt[k];
-        rc[k][8] = L.v[k] + h * L.gt[k];
+    for (int j = 0; j < NN; j++) {
+        const int k = VK[j];
+        const T m = mid(k), d = hh * (L.gt[k] + R.gt[k]);
+        x[j][0] = m;
+        x[j][1] = L.v[k];
+        x[j][2] = m - d;
+        x[j][3] = R.v[k];
+        x[j][4] = m + d;
+        x[j][5] = L.v[k] - h * L.gt[k];
+        x[j][6] = R.v[k] - h * R.gt[k];
+        x[j][7] = R.v[k] + h * R.gt[k];
+        x[j][8] = L.v[k] + h * L.gt[k];
     }
-    const T rho_f = rc[V_RHO][0];
+    const T* un = x[U];
+    const T* ut = x[W];
+    // Gamma_a = e.u + 1.5 (e.u)^2 - 0.5 |u|^2 per point, written for its e
+    T gam[9], eu[9];
+    gam[0] = T(-0.5) * (un[0] * un[0] + ut[0] * ut[0]);
+    eu[1] = un[1];
+    eu[3] = -un[3];
+    eu[2] = ut[2];
+    eu[4] = -ut[4];
+    gam[1] = un[1] * un[1] + un[1] - T(0.5) * (ut[1] * ut[1]);
+    gam[3] = un[3] * un[3] - un[3] - T(0.5) * (ut[3] * ut[3]);
+    gam[2] = ut[2] * ut[2] + ut[2] - T(0.5) * (un[2] * un[2]);
+    gam[4] = ut[4] * ut[4] - ut[4] - T(0.5) * (un[4] * un[4]);
+    // diagonals: |u|^2 = (e.u)^2 - 2 e_n e_t u_n u_t, so Gamma = e.u + (e.u)^2 + e_n e_t u_n u_t
+    eu[5] = un[5] + ut[5];
+    eu[6] = ut[6] - un[6];
+    eu[7] = -(un[7] + ut[7]);
+    eu[8] = un[8] - ut[8];
+    gam[5] = eu[5] * eu[5] + eu[5] + un[5] * ut[5];
+    gam[6] = eu[6] * eu[6] + eu[6] - un[6] * ut[6];
+    gam[7] = eu[7] * eu[7] + eu[7] + un[7] * ut[7];
+    gam[8] = eu[8] * eu[8] + eu[8] - un[8] * ut[8];
+    T X[9], Y[9], Z[9];
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        X[a] = x[RH][a] * gam[a];   // rho Gamma
+        Y[a] = x[TT][a] * gam[a];   // T Gamma
+        Z[a] = a ? x[CC][a] * eu[a] : T(0);   // C e.u
+    }
+    // sums over the axis points (weight 1/9) and the diagonals (1/36): plain, times e_n,
+    // times e_t, times e_n e_t
+    const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+    const T xa = X[5] + X[8], xb = X[6] + X[7], xc = X[5] - X[8], xd = X[6] - X[7];
+    const T A = w0 * X[0] + w1 * ((X[1] + X[3]) + (X[2] + X[4])) + w2 * (xa + xb);
+    const T An = w1 * (X[1] - X[3]) + w2 * (xa - xb);
+    const T At = w1 * (X[2] - X[4]) + w2 * (xc + xd);
+    const T gp = gam[5] + gam[7], gq = gam[6] + gam[8];
+    const T G2 = w1 * (gam[1] + gam[3]) + w2 * (gp + gq);
+    const T Gnt = w2 * (gp - gq);
+    const T ya = Y[5] + Y[8], yb = Y[6] + Y[7];
+    const T B = w0 * Y[0] + w1 * ((Y[1] + Y[3]) + (Y[2] + Y[4])) + w2 * (ya + yb);
+    const T Bn = w1 * (Y[1] - Y[3]) + w2 * (ya - yb);
+    const T za = Z[5] + Z[8], zb = Z[6] + Z[7];
+    const T E = w1 * ((Z[1] + Z[3]) + (Z[2] + Z[4])) + w2 * (za + zb);
+    const T En = w1 * (Z[1] - Z[3]) + w2 * (za - zb);
+
+    const T rho_f = x[RH][0];
     const T irho_f = rcp_bounded(rho_f);
     const T mu_f = T(0.5) * (L.mu + R.mu);
     const T lam_f = T(0.5) * (L.lam + R.lam);
     const T cp_f = T(0.5) * (L.cp + R.cp);
     const T cpref = K.cpref;
     const T Q = K.qg;
-    // tau_f = 1/2 + mu / (rho cs^2 delta_t), tau_h = 1/2 + lambda / (rho Cp,ref cs^2 delta_t)
     const T tau_f = T(0.5) + mu_f * irho_f * K.tauf_k;
     const T tau_h = T(0.5) + lam_f * irho_f * K.tauh_k;
     const T tau_g = K.tau_g;
-
-    // (e_n, e_t) of the nine points in the face frame. The sums over the points are
-    // taken per weight class (centre 4/9, axis 1/9, diagonal 1/36) without the weight,
-    // which is applied once per class at the end.
-    constexpr int EN[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr int ET[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     const T c3 = T(3) * cp_f;
-    T S0c, Hsc;
-    T S0a = 0, Hsa = 0, Sna = 0, Mnna = 0, Hna = 0, Sta = 0, Csa = 0, Gna = 0;
-    T S0d = 0, Hsd = 0, Snd = 0, Mnnd = 0, Hnd = 0, Std = 0, Mntd = 0, Csd = 0, Gnd = 0;
-    {
-        // centre: e = 0, Gamma = -|u|^2 / 2 (no mass, momentum or C moment)
-        const T un = rc[V_UN][0], ut = rc[V_UT][0];
-        const T gam = T(-0.5) * (un * un + ut * ut);
-        S0c = rc[V_P][0] + rc[V_RHO][0] * gam;
-        Hsc = rc[V_T][0] * (cpref + c3 * gam);
-    }
-#pragma unroll
-    for (int a = 1; a < 9; a++) {
-        const T un = rc[V_UN][a], ut = rc[V_UT][a];
-        const T eu = T(EN[a]) * un + T(ET[a]) * ut;
-        // Gamma_a = e.u + 1.5 (e.u)^2 - 0.5 |u|^2
-        const T gam = (T(1.5) * eu) * eu + eu - T(0.5) * (un * un + ut * ut);
-        const T pa = rc[V_P][a];
-        const T A = pa + rc[V_RHO][a] * gam;                  // f_eq / w
-        const T Hq = rc[V_T][a] * (cpref + c3 * gam);         // h_eq / w (a > 0)
-        const T G = Q * rc[V_MUC][a] + rc[V_C][a] * eu;       // g_eq / (3 w)
-        if (a < 5) {
-            S0a += A;
-            Hsa += Hq;
-            Csa += G;
-            if (EN[a] != 0) {
-                const T B = pa + rho_f * gam;                 // f_eqm / w
-                Sna += T(EN[a]) * A;
-                Mnna += B;
-                Hna += T(EN[a]) * Hq;
-                Gna += T(EN[a]) * G;
-            } else {
-                Sta += T(ET[a]) * A;
-            }
-        } else {
-            const T B = pa + rho_f * gam;
-            S0d += A;
-            Hsd += Hq;
-            Csd += G;
-            Snd += T(EN[a]) * A;
-            Mnnd += B;
-            Hnd += T(EN[a]) * Hq;
-            Gnd += T(EN[a]) * G;
-            Std += T(ET[a]) * A;
-            Mntd += T(EN[a] * ET[a]) * B;
-        }
-    }
-    const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
-    const T S0 = w0 * S0c + w1 * S0a + w2 * S0d;
-    const T Hs = w0 * Hsc + w1 * Hsa + w2 * Hsd;
-    const T Sn = w1 * Sna + w2 * Snd;
-    const T St = w1 * Sta + w2 * Std;
-    const T Mnn = w1 * Mnna + w2 * Mnnd;
-    const T Mnt = w2 * Mntd;
-    const T Hn = w1 * Hna + w2 * Hnd;
-    const T Cs = T(3) * (w1 * Csa + w2 * Csd);
-    const T Gn = T(3) * (w1 * Gna + w2 * Gnd);
+    // the parts linear in p, mu_c and T summed in closed form over the nine points
+    const T pS = L.v[V_P] + R.v[V_P];
+    const T S0 = T(2.0 / 3.0) * mid(V_P) + T(1.0 / 6.0) * pS + A;
+    const T Sn = T(1.0 / 6.0) * (L.v[V_P] - R.v[V_P]) + An;
+    const T St = -(h * T(1.0 / 6.0)) * (L.gt[V_P] + R.gt[V_P]) + At;
+    const T Mnn = T(1.0 / 6.0) * pS + rho_f * G2;
+    const T Mnt = (h * T(1.0 / 18.0)) * (R.gt[V_P] - L.gt[V_P]) + rho_f * Gnt;
+    const T Hn = (cpref * T(1.0 / 6.0)) * (L.v[V_T] - R.v[V_T]) + c3 * Bn;
+    const T Gn = (T(0.5) * Q) * (L.v[V_MUC] - R.v[V_MUC]) + T(3) * En;
     // Eq. 45: face state
     const T p_f = S0;
     const T un_f = T(3) * Sn * irho_f;
     const T ut_f = T(3) * St * irho_f;
-    const T C_f = rc[V_C][0] - T(3) * Q * T(5.0 / 9.0) * rc[V_MUC][0] + Cs;
-    const T He_f = rc[V_HE][0] - cpref * rc[V_T][0] + Hs;
+    const T C_f = x[CC][0] - (Q * hh) * (L.gn[V_MUC] - R.gn[V_MUC]) + T(3) * E;
+    const T He_f = mid(V_HE) - (cpref * h * T(1.0 / 6.0)) * (L.gn[V_T] - R.gn[V_T]) + c3 * B;
     T T_f, Fl_f;
     enthalpy_state<T>(K, He_f, C_f, T_f, Fl_f);
-    // Eqs. 40 and 43 through the star distributions
     F[1] = Sn;
     F[2] = (T(1.5) - tau_f) * (p_f + rho_f * un_f * un_f) * T(1.0 / 3.0) + (tau_f - T(0.5)) * Mnn;
     F[3] = (T(1.5) - tau_f) * (rho_f * un_f * ut_f) * T(1.0 / 3.0) + (tau_f - T(0.5)) * Mnt;
