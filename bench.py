@@ -528,9 +528,11 @@ def timed_steps(args, torch, solver) -> tuple:
     solver.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kern = solver.step_profiled(args.steps, args.sample_every)
+    solver.step_profiled_start(args.steps, args.sample_every)
     torch.cuda.synchronize()
-    return kern, time.perf_counter() - t0, nsettle
+    secs = time.perf_counter() - t0
+    # (the sampled launches' event times are read after the clock stopped)
+    return solver.profile_result(), secs, nsettle
 
 
 def single_problem(args, wl, workload: str) -> tuple:
@@ -697,9 +699,10 @@ def run_batch(args, torch, lbfs, wl, cpu_all=None) -> dict:
     batch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kern = batch.step_profiled(args.steps, args.sample_every)
+    batch.step_profiled_start(args.steps, args.sample_every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    kern = batch.profile_result()
     obs = batch.observe()
     secs = t1 - t0
     fl = [o["liquid_fraction"] for o in obs.values()]

@@ -230,6 +230,16 @@ enum { LBFS_K_MAG = 0, LBFS_K_STAGE1, LBFS_K_STAGE2, LBFS_K_STAGE3, LBFS_K_REDUC
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches);
 
+/* lbfs_step_profiled in two calls, so that a caller can time the steps alone with its
+   own clock (start, synchronise the stream, read the clock, then collect):
+   lbfs_step_profiled_start enqueues the steps and their timing events and returns at
+   once (asynchronous, like lbfs_step); lbfs_profile_result waits for the stream and
+   writes kernel_ms and launches as lbfs_step_profiled does. One profiled run may be
+   pending per solver: LBFS_E_STATE from a start (or lbfs_step_profiled) while one is
+   pending, and from a result call with none pending. */
+int lbfs_step_profiled_start(lbfs_solver* s, int32_t nsteps, int32_t sample_every);
+int lbfs_profile_result(lbfs_solver* s, double* kernel_ms, int32_t* launches);
+
 /* The "if output required" branch of Table 1. Synchronise the stream, reduce the
    current state in FP64 (fixed order) and return its observables in *o (caller owned):
    the solid ratio Q_L of Eq. 51, the liquid fraction, the height and frozen height
@@ -409,6 +419,9 @@ int lbfs_batch_prepare(lbfs_batch* b);
    instances. */
 int lbfs_batch_step_profiled(lbfs_batch* b, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                              int32_t* launches);
+/* lbfs_step_profiled_start and lbfs_profile_result for a batch. */
+int lbfs_batch_step_profiled_start(lbfs_batch* b, int32_t nsteps, int32_t sample_every);
+int lbfs_batch_profile_result(lbfs_batch* b, double* kernel_ms, int32_t* launches);
 
 /* Synchronise and fill out[max_slots] and live[max_slots] (1 for an occupied slot;
    out[k] is zeroed for a free slot). One reduction launch covers all instances.

@@ -35,13 +35,20 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int tiles_of(int n, int t) { return (n + t - 1) / t; }
 int count_tiles(int nx, int ny, TileShape S) { return tiles_of(nx, S.tx) * tiles_of(ny, S.ty); }
 
-// tiles of one instance (inst: its index in the descriptor array), row-major order;
-// idx numbers them inside the instance (the slot of its partial sums)
-void append_tiles(std::vector<Tile>& out, int inst, int nx, int ny, TileShape S)
+// tiles of one instance (inst: its index in the descriptor array), row-major or, with
+// `blocked`, in the order of tile_at; idx numbers them row-major inside the instance (the
+// slot of its partial sums, which are reduced in that order). The magnetic kernels take
+// the blocked order: their tiles are whole cache lines wide and their halo is deep. The
+// stage tiles are not: a block edge inside a cache line makes two XCDs read and write
+// parts of that line, which cost more than the halo saved (measured).
+void append_tiles(std::vector<Tile>& out, int inst, int nx, int ny, TileShape S, bool blocked = false)
 {
-    int idx = 0;
-    for (int ty = 0; ty < tiles_of(ny, S.ty); ty++)
-        for (int tx = 0; tx < tiles_of(nx, S.tx); tx++) out.push_back(Tile{inst, tx * S.tx, ty * S.ty, idx++});
+    const int ntx = tiles_of(nx, S.tx), nty = tiles_of(ny, S.ty);
+    for (int k = 0; k < ntx * nty; k++) {
+        int tx = k % ntx, ty = k / ntx;
+        if (blocked) tile_at(k, ntx, nty, S.tx, S.ty, tx, ty);
+        out.push_back(Tile{inst, tx * S.tx, ty * S.ty, ty * ntx + tx});
+    }
 }
 
 // Segments of one instance's state. Tile lists and partial sums have room for the
@@ -241,6 +248,10 @@ struct Exec {
     // timing events of the profiled steps, created ahead (lbfs_prepare) or on first need
     // and kept, so that a profiled run creates none while the device waits
     std::vector<hipEvent_t> evpool;
+    // the profiled run enqueued and not yet read: kernel kind of each timed launch
+    bool prof_pending = false;
+    std::vector<int> prof_kind;
+    size_t prof_slots = 0;
 };
 
 // at least n events in the pool
@@ -511,22 +522,24 @@ hipError_t exec_prepare(Exec& E)
     return hipSuccess;
 }
 
-// nsteps steps with HIP events around the kernel phases of every sample_every-th step;
-// after_step() runs on the host after each enqueued step
+// Enqueue nsteps steps with HIP events around the kernel phases of every
+// sample_every-th step; after_step() runs on the host after each enqueued step. The
+// timings are read by exec_profiled_result (one profiled run pending at a time).
 template <typename F>
-int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int32_t* launches, F&& after_step)
+int exec_profiled_start(Exec& E, int nsteps, int sample_every, F&& after_step)
 {
+    if (E.prof_pending) return LBFS_E_STATE;
     const int nsample = (nsteps + sample_every - 1) / sample_every;
     if (nsample > 4096) return LBFS_E_INVAL;
     const int per_step = EVENTS_PER_SAMPLE / 2;
     if (exec_events(E, (size_t)nsample * EVENTS_PER_SAMPLE) != hipSuccess) return LBFS_E_DEVICE;
     const std::vector<hipEvent_t>& ev = E.evpool;
-    std::vector<int> kind((size_t)nsample * per_step, 0);
+    E.prof_kind.assign((size_t)nsample * per_step, 0);
     int rc = LBFS_OK;
     size_t slot = 0;
     // the launch itself timestamps the kernel's start and end into the events
     auto timed = [&](int k, auto&& launch) -> hipError_t {
-        kind[slot] = k;
+        E.prof_kind[slot] = k;
         E.ev0 = ev[2 * slot];
         E.ev1 = ev[2 * slot + 1];
         const hipError_t e = launch();
@@ -553,20 +566,30 @@ int exec_profiled(Exec& E, int nsteps, int sample_every, double* kernel_ms, int3
         for (int q = 0; q < k; q++) after_step();
         n += k;
     }
-    if (rc == LBFS_OK && hipStreamSynchronize(E.stream) != hipSuccess) rc = LBFS_E_DEVICE;
+    E.prof_slots = slot;
+    E.prof_pending = rc == LBFS_OK;
+    return rc;
+}
+
+// wait for the pending profiled run and average its timed launches per kernel kind
+int exec_profiled_result(Exec& E, double* kernel_ms, int32_t* launches)
+{
+    if (!E.prof_pending) return LBFS_E_STATE;
+    E.prof_pending = false;
+    int rc = hipStreamSynchronize(E.stream) == hipSuccess ? LBFS_OK : LBFS_E_DEVICE;
     for (int k = 0; k < LBFS_NKERNELS; k++) {
         kernel_ms[k] = 0.0;
         launches[k] = 0;
     }
     if (rc == LBFS_OK)
-        for (size_t q = 0; q < slot; q++) {
+        for (size_t q = 0; q < E.prof_slots; q++) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess) {
+            if (hipEventElapsedTime(&ms, E.evpool[2 * q], E.evpool[2 * q + 1]) != hipSuccess) {
                 rc = LBFS_E_DEVICE;
                 break;
             }
-            kernel_ms[kind[q]] += ms;
-            launches[kind[q]] += 1;
+            kernel_ms[E.prof_kind[q]] += ms;
+            launches[E.prof_kind[q]] += 1;
         }
     for (int k = 0; k < LBFS_NKERNELS; k++)
         if (launches[k] > 0) kernel_ms[k] /= launches[k];
@@ -920,7 +943,7 @@ static int apply_shapes(lbfs_solver* s, int si, int mi)
     if (fuse) mi = s->E.mag_shape;
     std::vector<Tile> ts, tm;
     append_tiles(ts, 0, s->p.nx, s->p.ny, stage_shape(s->f64(), si));
-    append_tiles(tm, 0, s->p.nx, s->p.ny, MAG_SHAPES[mi]);
+    append_tiles(tm, 0, s->p.nx, s->p.ny, MAG_SHAPES[mi], true);
     HIPCHK(hipStreamSynchronize(s->stream));   // launches in flight read the old lists
     exec_drop_graphs(s->E);
     Exec& E = s->E;
@@ -1141,16 +1164,31 @@ int lbfs_prepare(lbfs_solver* s)
     return LBFS_OK;
 }
 
+int lbfs_step_profiled_start(lbfs_solver* s, int32_t nsteps, int32_t sample_every)
+{
+    if (!s || s->batched) return LBFS_E_STATE;
+    if (nsteps < 0 || sample_every < 1) return LBFS_E_INVAL;
+    return exec_profiled_start(s->E, nsteps, sample_every, [&] {
+        s->t += s->p.dt;
+        s->step += 1;
+        s->stepped_since_observe = true;
+    });
+}
+
+int lbfs_profile_result(lbfs_solver* s, double* kernel_ms, int32_t* launches)
+{
+    if (!s || s->batched) return LBFS_E_STATE;
+    if (!kernel_ms || !launches) return LBFS_E_INVAL;
+    return exec_profiled_result(s->E, kernel_ms, launches);
+}
+
 int lbfs_step_profiled(lbfs_solver* s, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                        int32_t* launches)
 {
     if (!s || s->batched) return LBFS_E_STATE;
     if (nsteps < 0 || sample_every < 1 || !kernel_ms || !launches) return LBFS_E_INVAL;
-    return exec_profiled(s->E, nsteps, sample_every, kernel_ms, launches, [&] {
-        s->t += s->p.dt;
-        s->step += 1;
-        s->stepped_since_observe = true;
-    });
+    const int rc = lbfs_step_profiled_start(s, nsteps, sample_every);
+    return rc == LBFS_OK ? lbfs_profile_result(s, kernel_ms, launches) : rc;
 }
 
 int lbfs_observe(lbfs_solver* s, lbfs_observables* o)
@@ -1398,13 +1436,15 @@ __global__ void k_write_desc(DevInst d, DevInst* dst)
     if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
 }
 
-// the row-major tile list of one instance (the order append_tiles gives)
-__global__ void k_fill_tiles(Tile* out, int nx, int tx, int ty, int ntiles)
+// the tile list of one instance of ntiles = ntx x nty tiles (the list append_tiles gives)
+__global__ void k_fill_tiles(Tile* out, int nx, int tw, int th, int ntiles, int blocked)
 {
     const int i = blockIdx.x * blockDim.x + (int)threadIdx.x;
     if (i >= ntiles) return;
-    const int ntx = (nx + tx - 1) / tx;
-    out[i] = Tile{0, (i % ntx) * tx, (i / ntx) * ty, i};
+    const int ntx = (nx + tw - 1) / tw, nty = ntiles / ntx;
+    int tx = i % ntx, ty = i / ntx;
+    if (blocked) tile_at(i, ntx, nty, tw, th, tx, ty);
+    out[i] = Tile{0, tx * tw, ty * th, ty * ntx + tx};
 }
 
 }  // namespace
@@ -1473,9 +1513,9 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     Tile* tm = reinterpret_cast<Tile*>(base + o_tm);
     hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, st, I, dinst);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_fill_tiles, dim3((nts + 255) / 256), dim3(256), 0, st, ts, q.nx, SS.tx, SS.ty, nts);
+    hipLaunchKernelGGL(k_fill_tiles, dim3((nts + 255) / 256), dim3(256), 0, st, ts, q.nx, SS.tx, SS.ty, nts, 0);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_fill_tiles, dim3((ntm + 255) / 256), dim3(256), 0, st, tm, q.nx, MS.tx, MS.ty, ntm);
+    hipLaunchKernelGGL(k_fill_tiles, dim3((ntm + 255) / 256), dim3(256), 0, st, tm, q.nx, MS.tx, MS.ty, ntm, 1);
     HIPCHK(hipGetLastError());
 
     Exec E;
@@ -1854,7 +1894,7 @@ int batch_rebuild(lbfs_batch* b)
         I.ntile_mag = count_tiles(s->p.nx, s->p.ny, MS);
         insts.push_back(I);
         append_tiles(ts, c, s->p.nx, s->p.ny, SS);
-        append_tiles(tm, c, s->p.nx, s->p.ny, MS);
+        append_tiles(tm, c, s->p.nx, s->p.ny, MS, true);
     }
     if ((int)ts.size() > b->cap_stage || (int)tm.size() > b->cap_mag) return LBFS_E_STATE;
     if (!insts.empty()) {
@@ -2044,15 +2084,31 @@ int lbfs_batch_prepare(lbfs_batch* b)
     return LBFS_OK;
 }
 
+int lbfs_batch_step_profiled_start(lbfs_batch* b, int32_t nsteps, int32_t sample_every)
+{
+    if (!b) return LBFS_E_STATE;
+    if (nsteps < 0 || sample_every < 1) return LBFS_E_INVAL;
+    if (b->E.prof_pending) return LBFS_E_STATE;
+    const int rc = batch_rebuild(b);
+    if (rc != LBFS_OK) return rc;
+    if (b->E.ninst == 0) nsteps = 0;
+    return exec_profiled_start(b->E, nsteps, sample_every, [&] { batch_after_step(b); });
+}
+
+int lbfs_batch_profile_result(lbfs_batch* b, double* kernel_ms, int32_t* launches)
+{
+    if (!b) return LBFS_E_STATE;
+    if (!kernel_ms || !launches) return LBFS_E_INVAL;
+    return exec_profiled_result(b->E, kernel_ms, launches);
+}
+
 int lbfs_batch_step_profiled(lbfs_batch* b, int32_t nsteps, int32_t sample_every, double* kernel_ms,
                              int32_t* launches)
 {
     if (!b) return LBFS_E_STATE;
     if (nsteps < 0 || sample_every < 1 || !kernel_ms || !launches) return LBFS_E_INVAL;
-    const int rc = batch_rebuild(b);
-    if (rc != LBFS_OK) return rc;
-    if (b->E.ninst == 0) nsteps = 0;
-    return exec_profiled(b->E, nsteps, sample_every, kernel_ms, launches, [&] { batch_after_step(b); });
+    const int rc = lbfs_batch_step_profiled_start(b, nsteps, sample_every);
+    return rc == LBFS_OK ? lbfs_batch_profile_result(b, kernel_ms, launches) : rc;
 }
 
 int lbfs_batch_observe(lbfs_batch* b, lbfs_observables* out, uint8_t* live)

@@ -19,7 +19,7 @@ struct TileShape {
     int tx, ty, nt;
     int early = 0;   // stage kernels: stage 0/1 load the owned cell's values before the halo
 };
-// Small workgroups: with the stage kernels' register use (69 VGPRs in FP32, about 150 in
+// Small workgroups: with the stage kernels' register use (72 VGPRs in FP32, about 150 in
 // FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
 // other's barrier and LDS waits better than one large one, although small tiles
 // recompute more halo cells (2.6x for 10 x 10) and faces (2.2 per cell).
@@ -63,8 +63,52 @@ enum { RES_CT = 0, RES_CTFL, RES_FS, RES_UMAX, RES_NONFINITE, RES_UDROP, RES_HEI
 struct Tile {
     int32_t inst;    // instance index
     int32_t x0, y0;  // origin (cells)
-    int32_t idx;     // tile index inside its instance (partials slot)
+    int32_t idx;     // row-major tile index inside its instance (partials slot)
 };
+
+// Position k of an instance's tile list -> tile (tx, ty) of its ntx x nty tiles of tw x
+// th cells. Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2, and the kernels hand each XCD one contiguous eighth of the list (xcd_tile). This
+// order lists the tiles as 8 rectangular blocks, row-major inside each, so that an
+// eighth is a compact rectangle: the halo cells it re-reads across XCD boundaries lie
+// along its perimeter, shorter than that of a full-width strip of the same area (the
+// row-major order). The blocks split the grid into
+// bx x (8 / bx), bx in {1, 2, 4, 8}, the most square in cells; a grid of fewer tiles
+// than that is listed row-major.
+__host__ __device__ inline void tile_at(int k, int ntx, int nty, int tw, int th, int& tx, int& ty)
+{
+    int bx = 0;
+    long best = 0;
+    for (int b = 1; b <= 8; b *= 2) {
+        const int c = 8 / b;
+        if (b > ntx || c > nty) continue;
+        const long per = (long)ntx * tw / b + (long)nty * th / c;   // block half-perimeter (cells)
+        if (bx == 0 || per < best) {
+            bx = b;
+            best = per;
+        }
+    }
+    if (bx == 0) {
+        tx = k % ntx;
+        ty = k / ntx;
+        return;
+    }
+    const int by = 8 / bx;
+    for (int j = 0; j < by; j++) {
+        const int y0 = j * nty / by, y1 = (j + 1) * nty / by;
+        for (int i = 0; i < bx; i++) {
+            const int x0 = i * ntx / bx, x1 = (i + 1) * ntx / bx;
+            const int n = (x1 - x0) * (y1 - y0);
+            if (k < n) {
+                tx = x0 + k % (x1 - x0);
+                ty = y0 + k / (x1 - x0);
+                return;
+            }
+            k -= n;
+        }
+    }
+    tx = ty = 0;   // (k beyond the grid: not reached for k < ntx nty)
+}
 
 // Parameters of one instance in one precision, with the derived constants the kernels
 // need precomputed on the host: the kernels read them as uniform scalars (no per-thread

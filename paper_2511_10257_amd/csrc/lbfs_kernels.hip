@@ -171,82 +171,95 @@ struct Side {
 // The terms linear in p, mu_c and T are summed over the nine points in closed form
 // (the points are linear reconstructions, so their weighted sums are combinations of
 // the two sides' values and gradients); the terms in Gamma and C e.u are summed point
-// by point, per weight class.
+// by point: those of each side's own three points (its cell centre and two diagonals)
+// from that side's values alone (side_part), then those of the face line.
 // Output: F[0] He, F[1] p, F[2] normal momentum, F[3] tangential momentum, F[4] C.
+// What one side of a face contributes, computed from that side alone: its axis point
+// (the cell centre, e = (sgn, 0)) and its two diagonal points (v -+ h dv/dt, e =
+// (sgn, +-1)), summed with their weights, and the values the rest of the face needs.
+// sgn = +1 for L (e_n = +1 points), -1 for R.
 template <typename T>
-__device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, const Side<T>& R, T F[5])
+struct SidePart {
+    T A, At, G2, Gnt, B, E;   // this side's share of the sums named in face_flux
+    T hv[NV];                 // v + sgn h dv/dn (half of the face-centre reconstruction)
+    T gt[NV];                 // dv/dt
+    T vp, vt, vmu, gnt, gnmu; // p, T, mu_c and the normal gradients of T and mu_c
+    T mu, lam, cp;
+};
+
+template <typename T, int SGN>
+__device__ __forceinline__ void side_part(const Coef<T>& K, const Side<T>& S, SidePart<T>& o)
+{
+#pragma clang fp reassociate(on)
+    const T h = T(0.5) * K.dx;
+    const T sg = T(SGN);
+    const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+    const T un = S.v[V_UN], ut = S.v[V_UT];
+    // axis point: Gamma = sgn u_n + u_n^2 - u_t^2 / 2
+    const T G = un * un + sg * un - T(0.5) * (ut * ut);
+    // diagonals P (e_t = +1, at v - h dv/dt) and M (e_t = -1, at v + h dv/dt); with
+    // |u|^2 = (e.u)^2 - 2 e_n e_t u_n u_t, Gamma = e.u + (e.u)^2 + e_n e_t u_n u_t
+    const T unP = un - h * S.gt[V_UN], utP = ut - h * S.gt[V_UT];
+    const T unM = un + h * S.gt[V_UN], utM = ut + h * S.gt[V_UT];
+    const T euP = sg * unP + utP, euM = sg * unM - utM;
+    const T gP = euP * euP + euP + sg * (unP * utP);
+    const T gM = euM * euM + euM - sg * (unM * utM);
+    const T rP = S.v[V_RHO] - h * S.gt[V_RHO], rM = S.v[V_RHO] + h * S.gt[V_RHO];
+    const T tP = S.v[V_T] - h * S.gt[V_T], tM = S.v[V_T] + h * S.gt[V_T];
+    const T cP = S.v[V_C] - h * S.gt[V_C], cM = S.v[V_C] + h * S.gt[V_C];
+    const T XP = rP * gP, XM = rM * gM;
+    o.A = w1 * (S.v[V_RHO] * G) + w2 * (XP + XM);
+    o.At = w2 * (XP - XM);
+    o.G2 = w1 * G + w2 * (gP + gM);
+    o.Gnt = w2 * (gP - gM);
+    o.B = w1 * (S.v[V_T] * G) + w2 * (tP * gP + tM * gM);
+    o.E = w1 * (S.v[V_C] * (sg * un)) + w2 * (cP * euP + cM * euM);
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        o.hv[k] = S.v[k] + sg * h * S.gn[k];
+        o.gt[k] = S.gt[k];
+    }
+    o.vp = S.v[V_P];
+    o.vt = S.v[V_T];
+    o.vmu = S.v[V_MUC];
+    o.gnt = S.gn[V_T];
+    o.gnmu = S.gn[V_MUC];
+    o.mu = S.mu;
+    o.lam = S.lam;
+    o.cp = S.cp;
+}
+
+template <typename T>
+__device__ __forceinline__ void face_flux(const Coef<T>& K, const SidePart<T>& L, const SidePart<T>& R, T F[5])
 {
 #pragma clang fp reassociate(on)
     const T h = T(0.5) * K.dx;
     const T hh = T(0.5) * h;
-    // value at the face centre, the point on the face line: the mean of the two
-    // reconstructions ((L + h dL/dn) + (R - h dR/dn)) / 2
-    auto mid = [&](int k) { return T(0.5) * (L.v[k] + R.v[k]) + hh * (L.gn[k] - R.gn[k]); };
-    // the variables that enter the equilibria nonlinearly, at the nine points
-    enum { U = 0, W, RH, TT, CC, NN };
-    constexpr int VK[NN] = {V_UN, V_UT, V_RHO, V_T, V_C};
-    T x[NN][9];
-#pragma unroll
-    for (int j = 0; j < NN; j++) {
-        const int k = VK[j];
-        const T m = mid(k), d = hh * (L.gt[k] + R.gt[k]);
-        x[j][0] = m;
-        x[j][1] = L.v[k];
-        x[j][2] = m - d;
-        x[j][3] = R.v[k];
-        x[j][4] = m + d;
-        x[j][5] = L.v[k] - h * L.gt[k];
-        x[j][6] = R.v[k] - h * R.gt[k];
-        x[j][7] = R.v[k] + h * R.gt[k];
-        x[j][8] = L.v[k] + h * L.gt[k];
-    }
-    const T* un = x[U];
-    const T* ut = x[W];
-    // Gamma_a = e.u + 1.5 (e.u)^2 - 0.5 |u|^2 per point, written for its e
-    T gam[9], eu[9];
-    gam[0] = T(-0.5) * (un[0] * un[0] + ut[0] * ut[0]);
-    eu[1] = un[1];
-    eu[3] = -un[3];
-    eu[2] = ut[2];
-    eu[4] = -ut[4];
-    gam[1] = un[1] * un[1] + un[1] - T(0.5) * (ut[1] * ut[1]);
-    gam[3] = un[3] * un[3] - un[3] - T(0.5) * (ut[3] * ut[3]);
-    gam[2] = ut[2] * ut[2] + ut[2] - T(0.5) * (un[2] * un[2]);
-    gam[4] = ut[4] * ut[4] - ut[4] - T(0.5) * (un[4] * un[4]);
-    // diagonals: |u|^2 = (e.u)^2 - 2 e_n e_t u_n u_t, so Gamma = e.u + (e.u)^2 + e_n e_t u_n u_t
-    eu[5] = un[5] + ut[5];
-    eu[6] = ut[6] - un[6];
-    eu[7] = -(un[7] + ut[7]);
-    eu[8] = un[8] - ut[8];
-    gam[5] = eu[5] * eu[5] + eu[5] + un[5] * ut[5];
-    gam[6] = eu[6] * eu[6] + eu[6] - un[6] * ut[6];
-    gam[7] = eu[7] * eu[7] + eu[7] + un[7] * ut[7];
-    gam[8] = eu[8] * eu[8] + eu[8] - un[8] * ut[8];
-    T X[9], Y[9], Z[9];
-#pragma unroll
-    for (int a = 0; a < 9; a++) {
-        X[a] = x[RH][a] * gam[a];   // rho Gamma
-        Y[a] = x[TT][a] * gam[a];   // T Gamma
-        Z[a] = a ? x[CC][a] * eu[a] : T(0);   // C e.u
-    }
-    // sums over the axis points (weight 1/9) and the diagonals (1/36): plain, times e_n,
-    // times e_t, times e_n e_t
-    const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
-    const T xa = X[5] + X[8], xb = X[6] + X[7], xc = X[5] - X[8], xd = X[6] - X[7];
-    const T A = w0 * X[0] + w1 * ((X[1] + X[3]) + (X[2] + X[4])) + w2 * (xa + xb);
-    const T An = w1 * (X[1] - X[3]) + w2 * (xa - xb);
-    const T At = w1 * (X[2] - X[4]) + w2 * (xc + xd);
-    const T gp = gam[5] + gam[7], gq = gam[6] + gam[8];
-    const T G2 = w1 * (gam[1] + gam[3]) + w2 * (gp + gq);
-    const T Gnt = w2 * (gp - gq);
-    const T ya = Y[5] + Y[8], yb = Y[6] + Y[7];
-    const T B = w0 * Y[0] + w1 * ((Y[1] + Y[3]) + (Y[2] + Y[4])) + w2 * (ya + yb);
-    const T Bn = w1 * (Y[1] - Y[3]) + w2 * (ya - yb);
-    const T za = Z[5] + Z[8], zb = Z[6] + Z[7];
-    const T E = w1 * ((Z[1] + Z[3]) + (Z[2] + Z[4])) + w2 * (za + zb);
-    const T En = w1 * (Z[1] - Z[3]) + w2 * (za - zb);
+    const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0);
+    // the face centre (point 0) and the face-line points 2 (e = (0, +1), at m - h gt)
+    // and 4 (e = (0, -1), at m + h gt), gt the mean tangential gradient
+    auto mid = [&](int k) { return T(0.5) * (L.hv[k] + R.hv[k]); };
+    auto dt = [&](int k) { return hh * (L.gt[k] + R.gt[k]); };
+    const T un0 = mid(V_UN), ut0 = mid(V_UT), r0 = mid(V_RHO), t0 = mid(V_T), c0 = mid(V_C);
+    const T dun = dt(V_UN), dut = dt(V_UT), dr = dt(V_RHO), dtt = dt(V_T), dc = dt(V_C);
+    const T un2 = un0 - dun, ut2 = ut0 - dut, un4 = un0 + dun, ut4 = ut0 + dut;
+    const T g0 = T(-0.5) * (un0 * un0 + ut0 * ut0);
+    const T g2 = ut2 * ut2 + ut2 - T(0.5) * (un2 * un2);
+    const T g4 = ut4 * ut4 - ut4 - T(0.5) * (un4 * un4);
+    const T X2 = (r0 - dr) * g2, X4 = (r0 + dr) * g4;
+    // Sums over the nine points of rho Gamma (A, and times e_n, e_t: An, At), of Gamma
+    // times e_n^2 and e_n e_t (G2, Gnt), of T Gamma (B, Bn) and of C e.u (E, En)
+    const T A = w0 * (r0 * g0) + w1 * (X2 + X4) + (L.A + R.A);
+    const T An = L.A - R.A;
+    const T At = w1 * (X2 - X4) + (L.At + R.At);
+    const T G2 = L.G2 + R.G2;
+    const T Gnt = L.Gnt - R.Gnt;
+    const T B = w0 * (t0 * g0) + w1 * ((t0 - dtt) * g2 + (t0 + dtt) * g4) + (L.B + R.B);
+    const T Bn = L.B - R.B;
+    const T E = w1 * ((c0 - dc) * ut2 - (c0 + dc) * ut4) + (L.E + R.E);
+    const T En = L.E - R.E;
 
-    const T rho_f = x[RH][0];
+    const T rho_f = r0;
     const T irho_f = rcp_bounded(rho_f);
     const T mu_f = T(0.5) * (L.mu + R.mu);
     const T lam_f = T(0.5) * (L.lam + R.lam);
@@ -258,20 +271,20 @@ __device__ __forceinline__ void face_flux(const Coef<T>& K, const Side<T>& L, co
     const T tau_g = K.tau_g;
     const T c3 = T(3) * cp_f;
     // the parts linear in p, mu_c and T summed in closed form over the nine points
-    const T pS = L.v[V_P] + R.v[V_P];
+    const T pS = L.vp + R.vp;
     const T S0 = T(2.0 / 3.0) * mid(V_P) + T(1.0 / 6.0) * pS + A;
-    const T Sn = T(1.0 / 6.0) * (L.v[V_P] - R.v[V_P]) + An;
+    const T Sn = T(1.0 / 6.0) * (L.vp - R.vp) + An;
     const T St = -(h * T(1.0 / 6.0)) * (L.gt[V_P] + R.gt[V_P]) + At;
     const T Mnn = T(1.0 / 6.0) * pS + rho_f * G2;
     const T Mnt = (h * T(1.0 / 18.0)) * (R.gt[V_P] - L.gt[V_P]) + rho_f * Gnt;
-    const T Hn = (cpref * T(1.0 / 6.0)) * (L.v[V_T] - R.v[V_T]) + c3 * Bn;
-    const T Gn = (T(0.5) * Q) * (L.v[V_MUC] - R.v[V_MUC]) + T(3) * En;
+    const T Hn = (cpref * T(1.0 / 6.0)) * (L.vt - R.vt) + c3 * Bn;
+    const T Gn = (T(0.5) * Q) * (L.vmu - R.vmu) + T(3) * En;
     // Eq. 45: face state
     const T p_f = S0;
     const T un_f = T(3) * Sn * irho_f;
     const T ut_f = T(3) * St * irho_f;
-    const T C_f = x[CC][0] - (Q * hh) * (L.gn[V_MUC] - R.gn[V_MUC]) + T(3) * E;
-    const T He_f = mid(V_HE) - (cpref * h * T(1.0 / 6.0)) * (L.gn[V_T] - R.gn[V_T]) + c3 * B;
+    const T C_f = c0 - (Q * hh) * (L.gnmu - R.gnmu) + T(3) * E;
+    const T He_f = mid(V_HE) - (cpref * h * T(1.0 / 6.0)) * (L.gnt - R.gnt) + c3 * B;
     T T_f, Fl_f;
     enthalpy_state<T>(K, He_f, C_f, T_f, Fl_f);
     F[1] = Sn;
@@ -550,10 +563,18 @@ __device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst
     }
     const int rL = (lyL + 3) * L::RX + (lxL + 3), rR = (cy + 3) * L::RX + (cx + 3);
     const int gL = (lyL + 1) * L::GX + (lxL + 1), gR = (cy + 1) * L::GX + (cx + 1);
-    Side<T> SL, SR;
-    gather_side<T>(s, rL, gL, AX, SL);
-    gather_side<T>(s, rR, gR, AX, SR);
-    face_flux<T>(K, SL, SR, F);
+    SidePart<T> PL, PR;
+    {
+        Side<T> S;
+        gather_side<T>(s, rL, gL, AX, S);
+        side_part<T, 1>(K, S, PL);
+    }
+    {
+        Side<T> S;
+        gather_side<T>(s, rR, gR, AX, S);
+        side_part<T, -1>(K, S, PR);
+    }
+    face_flux<T>(K, PL, PR, F);
     // walls: no mass or order-parameter flux; heat through the half cell
     const int gface = AX == 0 ? x0 + cx : y0 + cy;
     const int nax = AX == 0 ? I.nx : I.ny;

@@ -26,13 +26,15 @@ NKERNELS = len(KERNELS)
 # every symbol include/lbfs.h declares
 EXPORTS = (
     "lbfs_params_default", "lbfs_params_from_dimless", "lbfs_state_bytes", "lbfs_init",
-    "lbfs_step", "lbfs_step_profiled", "lbfs_prepare", "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
+    "lbfs_step", "lbfs_step_profiled", "lbfs_step_profiled_start", "lbfs_profile_result", "lbfs_prepare",
+    "lbfs_observe", "lbfs_rhs", "lbfs_mag_sweeps",
     "lbfs_mag_pseudo_steps", "lbfs_mag_multigrid", "lbfs_wall_heat_profile", "lbfs_read_field",
     "lbfs_write_field", "lbfs_set_time", "lbfs_checkpoint_bytes", "lbfs_save_state",
     "lbfs_load_state", "lbfs_destroy", "lbfs_strerror", "lbfs_step_fields",
     "lbfs_tile_shape", "lbfs_set_tile_shapes", "lbfs_tile_shapes_in_use", "lbfs_autotune",
     "lbfs_batch_instance_bytes", "lbfs_batch_create", "lbfs_batch_admit", "lbfs_batch_retire",
-    "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_prepare", "lbfs_batch_observe", "lbfs_batch_slot",
+    "lbfs_batch_step", "lbfs_batch_step_profiled", "lbfs_batch_step_profiled_start", "lbfs_batch_profile_result",
+    "lbfs_batch_prepare", "lbfs_batch_observe", "lbfs_batch_slot",
     "lbfs_batch_info", "lbfs_batch_destroy", "lbfs_batch_set_tile_shapes", "lbfs_batch_autotune",
     "lbfs_batch_tile_shapes_in_use",
 )
@@ -102,6 +104,8 @@ def lib():
             "lbfs_init": (C.c_int, [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbfs_step": (C.c_int, [vp, i32]),
             "lbfs_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
+            "lbfs_step_profiled_start": (C.c_int, [vp, i32, i32]),
+            "lbfs_profile_result": (C.c_int, [vp, dp, C.POINTER(C.c_int32)]),
             "lbfs_prepare": (C.c_int, [vp]),
             "lbfs_observe": (C.c_int, [vp, C.POINTER(Observables)]),
             "lbfs_rhs": (C.c_int, [vp, dp]),
@@ -132,6 +136,8 @@ def lib():
             "lbfs_batch_retire": (C.c_int, [vp, i32]),
             "lbfs_batch_step": (C.c_int, [vp, i32]),
             "lbfs_batch_step_profiled": (C.c_int, [vp, i32, i32, dp, C.POINTER(C.c_int32)]),
+            "lbfs_batch_step_profiled_start": (C.c_int, [vp, i32, i32]),
+            "lbfs_batch_profile_result": (C.c_int, [vp, dp, C.POINTER(C.c_int32)]),
             "lbfs_batch_prepare": (C.c_int, [vp]),
             "lbfs_batch_observe": (C.c_int, [vp, C.POINTER(Observables), C.POINTER(C.c_uint8)]),
             "lbfs_batch_slot": (C.c_int, [vp, i32, C.POINTER(vp)]),
@@ -390,6 +396,17 @@ class Solver(_Instance):
         _check(lib().lbfs_step_profiled(self._h, int(n), int(sample_every), ms, cnt), "lbfs_step_profiled")
         return _kernel_times(ms, cnt)
 
+    def step_profiled_start(self, n: int, sample_every: int = 10) -> None:
+        """step_profiled without waiting: enqueue the steps and their timing events."""
+        _check(lib().lbfs_step_profiled_start(self._h, int(n), int(sample_every)), "lbfs_step_profiled_start")
+
+    def profile_result(self) -> dict:
+        """Wait for the run step_profiled_start enqueued; its kernel times as step_profiled."""
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        _check(lib().lbfs_profile_result(self._h, ms, cnt), "lbfs_profile_result")
+        return _kernel_times(ms, cnt)
+
     def mag_sweeps(self, n: int, omega: float = 1.0) -> float:
         r = C.c_double()
         _check(lib().lbfs_mag_sweeps(self._h, int(n), float(omega), C.byref(r)), "lbfs_mag_sweeps")
@@ -497,6 +514,16 @@ class Batch:
         cnt = (C.c_int32 * NKERNELS)()
         _check(lib().lbfs_batch_step_profiled(self._h, int(n), int(sample_every), ms, cnt),
                "lbfs_batch_step_profiled")
+        return _kernel_times(ms, cnt)
+
+    def step_profiled_start(self, n: int, sample_every: int = 10) -> None:
+        _check(lib().lbfs_batch_step_profiled_start(self._h, int(n), int(sample_every)),
+               "lbfs_batch_step_profiled_start")
+
+    def profile_result(self) -> dict:
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        _check(lib().lbfs_batch_profile_result(self._h, ms, cnt), "lbfs_batch_profile_result")
         return _kernel_times(ms, cnt)
 
     def observe(self, allow_nonfinite: bool = False) -> dict:

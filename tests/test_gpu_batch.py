@@ -134,6 +134,13 @@ def test_batch_profiled_equals_plain():
     assert kern["stage1"][1] == 3 and kern["mag"][1] == 3
     for x, y in zip(s1, s2):
         _same(b1.slot(x), b2.slot(y), "profiled batch")
+    # the two-call form
+    b1.step(9)
+    b2.step_profiled_start(9, 4)
+    kern = b2.profile_result()
+    assert kern["stage2"][1] == 3
+    for x, y in zip(s1, s2):
+        _same(b1.slot(x), b2.slot(y), "profiled batch, two calls")
     b1.close()
     b2.close()
 

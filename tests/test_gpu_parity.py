@@ -340,6 +340,30 @@ def test_profiled_steps_equal_plain_steps():
         assert np.array_equal(a.get(k), b.get(k)), k
 
 
+def test_profiled_start_and_result():
+    """The two-call form: the same steps and timed launches as the one-call form; a second
+    start while a run is pending, and a result with none pending, are refused."""
+    prob = wl.droplet_problem(64, 16.0, ste=0.1, bo_m=1.0, angle_deg=90.0, precision="fp32")
+    a = lbfs.Solver(prob)
+    b = lbfs.Solver(prob)
+    ka = a.step_profiled(23, 6)
+    b.step_profiled_start(23, 6)
+    with pytest.raises(lbfs.LbfsError):
+        b.step_profiled_start(5, 1)
+    with pytest.raises(lbfs.LbfsError):
+        b.step_profiled(5, 1)
+    kb = b.profile_result()
+    with pytest.raises(lbfs.LbfsError):
+        b.profile_result()
+    assert {k: v[1] for k, v in ka.items()} == {k: v[1] for k, v in kb.items()}
+    assert kb["stage3"][1] == 4 and kb["stage3"][0] > 0
+    for k in ("He", "p", "Mx", "My", "C", "phi", "S"):
+        assert np.array_equal(a.get(k), b.get(k)), k
+    assert a.observe() == b.observe()
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("sweeps", [0, 1, 9])
 def test_sweep_counts_match_oracle(sweeps):
     """The magnetic phase runs in launches of at most four sweeps; any count matches."""
