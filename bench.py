@@ -168,7 +168,7 @@ def sample_every_for(steps: int) -> int:
 def kernel_sources_digest() -> str:
     h = hashlib.sha256()
     # the kernel sources and the build script (its compiler flags shape the kernels too)
-    for name in ("csrc/lbfs_kernels.hip", "csrc/lbfs_internal.hpp", "build.py"):
+    for name in ("csrc/lbfs_kernels.hip", "csrc/lbfs_face.hpp", "csrc/lbfs_internal.hpp", "build.py"):
         with open(os.path.join(ROOT, "paper_2511_10257_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -904,6 +904,26 @@ void orc_face_fluxes(orc_sim* s, double* fx, double* fy)
     }
 }
 
+void orc_face_inputs(orc_sim* s, double* out)
+{
+    primitives(s, s->W);
+    int nx = s->nx, ny = s->ny;
+    size_t n = (size_t)nx * ny;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            int c = IX(s, i, j);
+            size_t o = (size_t)j * nx + i;
+            for (int v = 0; v < NREC; v++) {
+                out[(size_t)v * n + o] = s->val[v][c];
+                out[(size_t)(NREC + v) * n + o] = s->gx[v][c];
+                out[(size_t)(2 * NREC + v) * n + o] = s->gy[v][c];
+            }
+            out[(size_t)(3 * NREC) * n + o] = s->mu[c];
+            out[(size_t)(3 * NREC + 1) * n + o] = s->lam[c];
+            out[(size_t)(3 * NREC + 2) * n + o] = s->cp[c];
+        }
+}
+
 void orc_get(orc_sim* s, int field, double* out)
 {
     int nx = s->nx, ny = s->ny;

@@ -105,6 +105,10 @@ int orc_init(orc_sim* s);                    /* initial fields + converged magne
 void orc_step(orc_sim* s, int nsteps);
 void orc_rhs(orc_sim* s, double* R);         /* R(W) of Eq. 46 for the current state; R is 5*nx*ny, field-major */
 void orc_face_fluxes(orc_sim* s, double* fx, double* fy); /* fx: 5*(nx+1)*ny, fy: 5*nx*(ny+1) */
+/* The inputs of the face fluxes for the current state, per cell (nx*ny each, row-major):
+   the eight reconstructed variables p, u, v, rho, C, mu_c, T, He, their central x and y
+   gradients (8 + 8 blocks), then mu, lambda and Cp of Eq. 11; 27*nx*ny values. */
+void orc_face_inputs(orc_sim* s, double* out);
 void orc_get(orc_sim* s, int field, double* out);          /* nx*ny, row-major (j*nx+i) */
 void orc_set(orc_sim* s, int field, const double* in);
 void orc_set_time(orc_sim* s, double t, double step);

@@ -88,6 +88,7 @@ def load(path: str):
     L.orc_step.argtypes = [C.c_void_p, C.c_int]
     L.orc_rhs.argtypes = [C.c_void_p, dp]
     L.orc_face_fluxes.argtypes = [C.c_void_p, dp, dp]
+    L.orc_face_inputs.argtypes = [C.c_void_p, dp]
     L.orc_get.argtypes = [C.c_void_p, C.c_int, dp]
     L.orc_set.argtypes = [C.c_void_p, C.c_int, dp]
     L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_double]
@@ -206,6 +207,13 @@ class Oracle:
         fy = np.zeros(5 * self.nx * (self.ny + 1))
         self._L.orc_face_fluxes(self._h, _dp(fx), _dp(fy))
         return fx.reshape(5, self.ny, self.nx + 1), fy.reshape(5, self.ny + 1, self.nx)
+
+    def face_inputs(self) -> np.ndarray:
+        """Inputs of the face fluxes per cell, (27, ny, nx): p, u, v, rho, C, mu_c, T, He,
+        their x gradients, their y gradients, then mu, lambda and Cp."""
+        out = np.zeros(27 * self.n)
+        self._L.orc_face_inputs(self._h, _dp(out))
+        return out.reshape(27, self.ny, self.nx)
 
     def get(self, name: str) -> np.ndarray:
         out = np.zeros(self.n)

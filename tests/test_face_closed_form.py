@@ -1,0 +1,95 @@
+"""The library's face flux, run on the host in FP64, against the oracle's literal face
+flux (the nine reconstructions of Eq. 44, the equilibria of Eqs. 20/28/29 and f^{eq-m},
+the Eq. 45 face state, the star distributions and the Eq. 43 moments, point by point).
+
+The library evaluates the same flux in closed form at delta_t = dx/2: the terms linear
+in p, mu_c and T summed over the nine points in closed form, Gamma and C e.u point by
+point, each side's own three points from that side alone (lbfs_face.hpp). Both sides of
+the comparison take the same per-cell inputs, the oracle's own primitives and central
+gradients of a seeded state, so the check isolates the face algebra. Every interior
+x- and y-face of several states is compared (walls take their own fluxes in both).
+"""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2511_10257_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def face_host(tmp_path_factory):
+    if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
+        pytest.skip("hipcc is not available")
+    exe = str(tmp_path_factory.mktemp("face") / "face_flux_host")
+    csrc = os.path.join(ROOT, "paper_2511_10257_amd", "csrc")
+    cmd = [HIPCC if os.path.exists(HIPCC) else "hipcc", "-O2", "-std=c++17", "--offload-arch=gfx950",
+           "-I", os.path.join(ROOT, "include"), "-I", csrc, os.path.join(ROOT, "tests", "face_flux_host.cpp"),
+           "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return exe
+
+
+def run_host(exe, params, sides):
+    """sides: (nfaces, 2, 27) -> (nfaces, 5) fluxes of the library's face algebra."""
+    blob = struct.pack("<i", len(sides)) + np.asarray(params, dtype="<f8").tobytes() + \
+        np.ascontiguousarray(sides, dtype="<f8").tobytes()
+    out = subprocess.run([exe], input=blob, capture_output=True, check=True).stdout
+    return np.frombuffer(out, dtype="<f8").reshape(-1, 5).copy()
+
+
+def side_inputs(inp, i, j, axis):
+    """27 side values of cell (i, j) in the face frame of `axis` (0: n = x, 1: n = y)."""
+    v, gx, gy = inp[0:8, j, i], inp[8:16, j, i], inp[16:24, j, i]
+    perm = [0, 1, 2, 3, 4, 5, 6, 7] if axis == 0 else [0, 2, 1, 3, 4, 5, 6, 7]
+    gn, gt = (gx, gy) if axis == 0 else (gy, gx)
+    return np.concatenate([v[perm], gn[perm], gt[perm], inp[24:27, j, i]])
+
+
+def params_of(o):
+    p = o.params
+    dts = p.dt_stream
+    cpref = 0.5 * (p.cp[0] + p.cp[1])
+    qg = p.mobility / ((p.tau_g - 0.5) * dts)
+    return [p.dx, cpref, qg, 3.0 / dts, 3.0 / (cpref * dts), p.tau_g, p.cp[0], p.cp[1], p.cp[2],
+            p.t_melt, p.t_liquidus, p.latent]
+
+
+@pytest.mark.parametrize("seed,angle,tl", [(3, 90.0, None), (8, 30.0, None), (13, 0.0, 0.04)])
+def test_closed_form_face_flux_matches_the_literal_procedure(face_host, seed, angle, tl):
+    nx, ny = 22, 18
+    prob = wl.droplet_problem(nx, 5.0, ste=0.1, bo_m=1.0, angle_deg=angle, precision="fp64", ny=ny)
+    prob["init_max"] = 0
+    if tl is not None:
+        prob["t_liquidus"] = tl   # a melting range: the mushy branch of Eq. 8 with Ts < Tl
+    o = orc.Oracle(prob, init=False)
+    o.set_state(wl.smooth_state(nx, ny, seed=seed, latent=o.params.latent, h0=o.params.h0, angle_deg=angle))
+    fx, fy = o.face_fluxes()
+    inp = o.face_inputs()
+    sides, ref = [], []
+    for j in range(ny):
+        for i in range(1, nx):
+            sides.append([side_inputs(inp, i - 1, j, 0), side_inputs(inp, i, j, 0)])
+            ref.append(fx[:, j, i])
+    nxf = len(sides)
+    for j in range(1, ny):
+        for i in range(nx):
+            sides.append([side_inputs(inp, i, j - 1, 1), side_inputs(inp, i, j, 1)])
+            ref.append(fy[:, j, i])
+    got = run_host(face_host, params_of(o), np.array(sides))
+    ref = np.array(ref)
+    # the face frame's normal and tangential momentum fluxes are (Mx, My) on x-faces
+    # and (My, Mx) on y-faces
+    got[nxf:, [2, 3]] = got[nxf:, [3, 2]]
+    for k, name in enumerate(("He", "p", "Mx", "My", "C")):
+        scale = np.max(np.abs(ref[:, k]))
+        assert scale > 0, name
+        err = np.max(np.abs(got[:, k] - ref[:, k]))
+        assert err <= 1e-12 * scale, (name, err, scale)
