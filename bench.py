@@ -482,6 +482,38 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
     return roof
 
 
+def measured_valu(workload: str) -> float | None:
+    """Issued VALU lane-operations per cell and stage (mean of the three stage kernels)
+    from the committed rocprofv3 counter summary, if it was taken on the current kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_sources_digest():
+        return None
+    vals = [float(x) for x in re.findall(r"^\|\s*stage[123]\s*\|[^|]*\|[^|]*\|[^|]*\|\s*([0-9.]+)\s*\|", text, re.M)]
+    return sum(vals) / len(vals) if vals else None
+
+
+def whole_step(cells: int, precision: str, ms_per_step: float, workload: str) -> dict:
+    """The whole step against the HBM peak: the survey's bytes per cell-step (63 field
+    accesses of 4 B with perfect on-chip reuse; 8 B in FP64) and the least bytes of this
+    layout (each kernel's fields once, the order parameter in FP64), over the measured
+    time per step; and the issued VALU lane-operations per cell and stage when a counter
+    summary of the current kernels exists."""
+    scale = 2.0 if precision == "fp64" else 1.0
+    survey = sum(ALG_BYTES_FP32.values()) * scale
+    least = sum(MIN_BYTES[precision].values())
+    step_s = ms_per_step * 1e-3
+    return {"survey_bytes_per_cell_step": survey, "least_bytes_per_cell_step": least,
+            "hbm_frac_survey_bytes": survey * cells / step_s / 1e9 / HBM_PEAK_GBS,
+            "hbm_frac_least_bytes": least * cells / step_s / 1e9 / HBM_PEAK_GBS,
+            "issued_valu_lane_ops_per_cell_stage": measured_valu(workload) if precision == "fp32" else None,
+            "survey_flop_per_cell_stage": ALG_FLOPS["stage1"]}
+
+
 def kernel_fields(kern: dict) -> dict:
     share = {k: kern[k][0] for k in kern}
     total = sum(share.values()) or 1.0
@@ -636,6 +668,7 @@ def run_single(args, torch, lbfs, wl, cpu_all=None) -> dict:
     profile_key = args.workload + ("-mag-lbfs" if args.mag_method == "lbfs" else "")
     out["roofline"] = roofline(kern, cells, prob["precision"], profile_key, shapes, mag_flops, mag_launches,
                                exclude=("mag",) if args.mag_method == "multigrid" else ())
+    out["whole_step"] = whole_step(cells, prob["precision"], out["ms_per_step"], profile_key)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned
@@ -714,6 +747,7 @@ def run_batch(args, torch, lbfs, wl, cpu_all=None) -> dict:
                 "launches_per_step": "one graph replay", "sample_every": args.sample_every,
                 "settle_steps": nsettle})
     out["roofline"] = roofline(kern, cells, "fp32", args.workload, shapes)
+    out["whole_step"] = whole_step(cells, "fp32", out["ms_per_step"], args.workload)
     out.update(kernel_fields(kern))
     if tuned:
         out["autotune"] = tuned
