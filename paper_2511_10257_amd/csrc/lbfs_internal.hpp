@@ -19,7 +19,7 @@ struct TileShape {
     int tx, ty, nt;
     int early = 0;   // stage kernels: stage 0/1 load the owned cell's values before the halo
 };
-// Small workgroups: with the stage kernels' register use (72 VGPRs in FP32, about 150 in
+// Small workgroups: with the stage kernels' register use (69 VGPRs in FP32, 128 to 156 in
 // FP64) only a few waves fit per SIMD, and several small workgroups per CU hide each
 // other's barrier and LDS waits better than one large one, although small tiles
 // recompute more halo cells (2.6x for 10 x 10) and faces (2.2 per cell).
@@ -27,16 +27,18 @@ struct TileShape {
 // y-faces (TX (TY+1)) are each rounded up to whole waves, so 10 x 10 (110 + 110 faces on
 // four waves, a 256-cell halo region in one round, 22 KB of LDS in FP32: seven
 // workgroups and seven waves per SIMD) keeps the lanes busy; 7599 against 6804 MLUPS for
-// 10 x 8 (4 face waves for 178 faces) on a 1024^2 grid, 3362 against 3206 for 12 x 8 in
-// FP64. Loading the owned cell's values early hides their latency but holds registers
-// through the face phase; whether that costs a wave per SIMD depends on the shape, so
-// both are candidates.
+// 10 x 8 (4 face waves for 178 faces) on a 1024^2 grid. In FP64 the 10 x 10 tile needs
+// 44 KB of LDS (three workgroups per CU); 10 x 8 needs 38 KB, so four fit, and the stage
+// kernel is held to 128 VGPRs for four waves per SIMD: 3642 against 3553 MLUPS for
+// 10 x 10 and 3386 for 12 x 8 on a 1024^2 grid. Loading the owned cell's values early
+// hides their latency but holds registers through the face phase; whether that costs a
+// wave per SIMD depends on the shape, so both are candidates.
 constexpr int NSTAGE_SHAPES = 7;
 constexpr TileShape STAGE_SHAPES_F32[NSTAGE_SHAPES] = {
     {10, 10, 256, 0}, {10, 8, 256, 0}, {12, 7, 256, 1}, {12, 7, 256, 0}, {12, 8, 256, 0}, {8, 8, 192, 0},
     {8, 12, 256, 0}};
 constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
-    {10, 10, 256, 0}, {12, 8, 256, 0}, {8, 8, 256, 0}, {12, 7, 256, 0}, {10, 8, 256, 0}, {8, 7, 192, 0},
+    {10, 8, 256, 0}, {10, 10, 256, 0}, {12, 8, 256, 0}, {8, 8, 256, 0}, {12, 7, 256, 0}, {8, 7, 192, 0},
     {8, 8, 192, 0}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
 // (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1 (a

@@ -527,9 +527,11 @@ __device__ __forceinline__ void instance_reduce(const DevInst& I, int tid, doubl
 }
 
 // NT >= every per-tile work count (halo cells, gradient cells, faces), so each phase
-// is one round; the first TX*TY threads own the tile's cells.
+// is one round; the first TX*TY threads own the tile's cells. The register bound asks
+// for seven 256-thread workgroups per CU in FP32 (69 VGPRs) and four in FP64 (128),
+// which is what the LDS of the default tiles allows.
 template <typename T, int TX, int TY, int NT, int STAGE, int EARLY, int FUSE>
-__global__ __launch_bounds__(NT, (NT == 256 && sizeof(T) == 4) ? 7 : 1) void k_stage(const DevInst* __restrict__ insts,
+__global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void k_stage(const DevInst* __restrict__ insts,
                                               const Tile* __restrict__ tiles, int pidx, int nsweeps, double omega)
 {
     using L = StageLds<T, TX, TY, NT>;
