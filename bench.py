@@ -95,7 +95,8 @@ def parse():
                              "serve"])
     ap.add_argument("--sample-every", type=int, default=None,
                     help="bracket the kernels of every n-th timed step with HIP events (default: 97, "
-                         "the 96 steps between two sampled ones running as six 16-step graph replays, "
+                         "the 96 steps between two sampled ones running as six 16-step graph replays on "
+                         "grids under 2^19 cells and as direct launches on larger ones, "
                          "or fewer, so that at least three steps are sampled)")
     ap.add_argument("--settle-seconds", type=float, default=1.0,
                     help="untimed steps for about this long before the warm-up, so that the GPU runs at its "
@@ -160,7 +161,7 @@ def parse():
 
 
 def sample_every_for(steps: int) -> int:
-    """97 (six 16-step graph replays between sampled steps), or fewer so that at least
+    """97 (six 16-step graph replays between sampled steps on small grids), or fewer so that at least
     three of the timed steps are sampled."""
     return max(1, min(97, -(-steps // 3)))
 

@@ -196,13 +196,14 @@ size_t lbfs_state_bytes(const lbfs_params* p);
 int lbfs_init(const lbfs_params* p, void* dev_buf, size_t bytes, void* stream,
               lbfs_solver** out);
 
-/* Enqueue nsteps time steps on the stream (asynchronous). On a non-default stream
-   the steps are replays of HIP graphs captured on first use: each replay covers the
-   longest of 16, 8, 4 or 2 consecutive steps that the steps still to go fill, and a
-   last single step is launched directly (LBFS_GRAPH_STEPS=k in the environment at init
-   sets the longest length, 1..64, the others being the powers of two below it;
-   LBFS_NO_GRAPH=1 launches every kernel directly). The results are the same either
-   way. */
+/* Enqueue nsteps time steps on the stream (asynchronous). On a non-default stream and
+   a grid of fewer than 2^19 cells the steps are replays of HIP graphs captured on first
+   use: each replay covers the longest of 16, 8, 4 or 2 consecutive steps that the steps
+   still to go fill, and a last single step is launched directly (LBFS_GRAPH_STEPS=k in
+   the environment at init sets the longest length, 1..64, the others being the powers
+   of two below it). Larger grids launch their kernels directly, where graphs gain
+   nothing (LBFS_GRAPH=1 at init replays graphs there too); LBFS_NO_GRAPH=1 launches
+   directly at every size. The results are the same either way. */
 int lbfs_step(lbfs_solver* s, int32_t nsteps);
 
 /* Capture and instantiate now every HIP graph that lbfs_step and lbfs_step_profiled
@@ -210,7 +211,7 @@ int lbfs_step(lbfs_solver* s, int32_t nsteps);
    a profiled run that samples up to 16 steps, so that the first steps after init,
    lbfs_set_tile_shapes or lbfs_autotune pay for neither. Enqueues no work; the state
    and the clock are unchanged. Captures nothing where steps are not graph replays
-   (default stream, LBFS_NO_GRAPH=1). LBFS_E_STATE on a borrowed batch handle,
+   (default stream, large grids, LBFS_NO_GRAPH=1). LBFS_E_STATE on a borrowed batch handle,
    LBFS_E_DEVICE if a capture or an event creation fails. */
 int lbfs_prepare(lbfs_solver* s);
 

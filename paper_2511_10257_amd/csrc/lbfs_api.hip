@@ -1131,7 +1131,13 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     s->vol0 = s->hres[RES_CT] * p->dx * p->dx;
     s->hres[RES_MAGR2] = r * r;
     const char* ng = std::getenv("LBFS_NO_GRAPH");
-    E.use_graph = s->stream != nullptr && !(ng && ng[0] == '1');
+    // graph replays pay where the kernels are short enough for the host's launches to
+    // lag (256^2: 25.7 against 26.7 us per step); from about 2^19 cells on direct launches
+    // are as fast or faster (1024^2: 133.3 against 135.1 us), so large grids launch
+    // directly unless LBFS_GRAPH=1
+    const char* gf = std::getenv("LBFS_GRAPH");
+    const bool small = (int64_t)p->nx * p->ny < ((int64_t)1 << 19);
+    E.use_graph = s->stream != nullptr && !(ng && ng[0] == '1') && (small || (gf && gf[0] == '1'));
     exec_set_graph_steps(E, graph_steps_setting());
     *out = s;
     return LBFS_OK;
