@@ -357,10 +357,14 @@ hipError_t exec_mg(Exec& E, int ncycles, int residual)
 // instance only copies its potential (the launch count, and with it the buffer flips,
 // stays fixed and the step can be captured in a graph). The timing events bracket the
 // whole phase.
-hipError_t exec_mag_step(Exec& E)
+// the magnetic phase of one step; `resid`: also the FP64 residual partials of its last
+// launch, which lbfs_observe reduces (the convergence control needs them after every
+// chunk, and multigrid writes them anyway)
+hipError_t exec_mag_step(Exec& E, bool resid)
 {
     hipError_t e = hipSuccess;
     E.mres_stage = false;
+    const int r = (resid || E.mag_chunks > 1) ? 1 : 0;
     if (E.mag_method == LBFS_MAG_MULTIGRID) return exec_mg(E, E.sweeps, 1);
     for (int c = 0; c < E.mag_chunks && e == hipSuccess; c++) {
         const hipEvent_t a = c == 0 ? E.ev0 : nullptr, b = c == E.mag_chunks - 1 ? E.ev1 : nullptr;
@@ -368,11 +372,11 @@ hipError_t exec_mag_step(Exec& E)
         if (gate) e = launch_mag_gate(E.dinst, E.ninst, E.stream);
         if (e != hipSuccess) break;
         if (E.mag_method == LBFS_MAG_LBFS) {
-            e = exec_mag_lbfs(E, E.sweeps, 1, a, b, gate);
+            e = exec_mag_lbfs(E, E.sweeps, r, a, b, gate);
         } else {
-            e = E.f64 ? launch_mag<double>(E.mag_shape, E.sweeps, E.omega, 1, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+            e = E.f64 ? launch_mag<double>(E.mag_shape, E.sweeps, E.omega, r, &E.phase, E.dinst, E.tiles_mag, E.nmag,
                                            E.stream, a, b, gate)
-                      : launch_mag<float>(E.mag_shape, E.sweeps, E.omega, 1, &E.phase, E.dinst, E.tiles_mag, E.nmag,
+                      : launch_mag<float>(E.mag_shape, E.sweeps, E.omega, r, &E.phase, E.dinst, E.tiles_mag, E.nmag,
                                           E.stream, a, b, gate);
         }
     }
@@ -408,9 +412,9 @@ hipError_t exec_stage_fused(Exec& E)
 
 // one time step: magnetic phase and three Runge-Kutta stages, or the fused stage 1
 // and stages 2 and 3 (the observables of the state are summed when they are read)
-hipError_t exec_enqueue_step(Exec& E)
+hipError_t exec_enqueue_step(Exec& E, bool resid = true)
 {
-    hipError_t e = E.fused ? exec_stage_fused(E) : exec_mag_step(E);
+    hipError_t e = E.fused ? exec_stage_fused(E) : exec_mag_step(E, resid);
     for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
     return e;
 }
@@ -450,7 +454,9 @@ hipError_t exec_ensure_graph(Exec& E, int li, int ph)
         return e;
     }
     const int n = E.glen[li];
-    for (int k = 0; k < n && e == hipSuccess; k++) e = exec_enqueue_step(E);
+    // (the magnetic residual in the last step only: a replay ends every run of steps
+    // that lbfs_observe can follow)
+    for (int k = 0; k < n && e == hipSuccess; k++) e = exec_enqueue_step(E, k == n - 1);
     const hipError_t ec = hipStreamEndCapture(E.stream, &g);
     E.phase = saved;
     E.mres_stage = saved_mres;
@@ -487,13 +493,15 @@ int exec_step_flips(const Exec& E)
 // up to `nmax` (>= 1) steps as one replay of the longest graph that many steps fill, or
 // one step by direct launches where no graph of two or more steps fits (or graphs are
 // off): a one-step graph replay costs a few microseconds more than the same kernels
-// launched directly. Returns the steps enqueued, 0 on a HIP error.
+// launched directly. The magnetic residual is written by the last step of a replay and
+// by a direct step that is the last one asked for (nmax == 1), so the last step of any
+// run leaves it. Returns the steps enqueued, 0 on a HIP error.
 int exec_run_steps(Exec& E, int nmax)
 {
     int li = 0;
     if (E.use_graph)
         while (li + 1 < E.nglen && E.glen[li + 1] <= nmax) li++;
-    if (!E.use_graph || E.glen[li] < 2) return exec_enqueue_step(E) == hipSuccess ? 1 : 0;
+    if (!E.use_graph || E.glen[li] < 2) return exec_enqueue_step(E, nmax == 1) == hipSuccess ? 1 : 0;
     const int n = E.glen[li];
     const int ph = E.phase;
     if (exec_ensure_graph(E, li, ph) != hipSuccess) return 0;
@@ -551,7 +559,7 @@ int exec_profiled_start(Exec& E, int nsteps, int sample_every, F&& after_step)
         if (n % sample_every == 0) {
             hipError_t e;
             if (E.fused) e = timed(LBFS_K_STAGE1, [&] { return exec_stage_fused(E); });
-            else e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E); });
+            else e = timed(LBFS_K_MAG, [&] { return exec_mag_step(E, n == nsteps - 1); });
             for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
             if (e != hipSuccess) rc = LBFS_E_DEVICE;
@@ -1541,7 +1549,7 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     E.nmag = ntm;
     E.phase = 0;
     E.use_graph = false;
-    for (int k = 0; k < nsteps; k++) HIPCHK(exec_enqueue_step(E));
+    for (int k = 0; k < nsteps; k++) HIPCHK(exec_enqueue_step(E, k == nsteps - 1));
     // the potential ends in the caller's field
     if (E.phase != 0) HIPCHK(hipMemcpyAsync(fields[5], base + o_phi1, n * es, hipMemcpyDeviceToDevice, st));
     return LBFS_OK;
