@@ -563,7 +563,17 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool inside = tid < TX * TY && gx < nx && gy < ny;
-    const size_t o = inside ? (size_t)gy * pitch + gx : 0;
+    // the owned cell's element of a field: the tile origin's address (uniform, in scalar
+    // registers) plus a 32-bit byte offset, so the accesses of every field share one
+    // vector offset instead of a 64-bit address each
+    const size_t t0 = (size_t)y0 * pitch + x0;
+    const uint32_t ob = inside ? (uint32_t)(ly * pitch + lx) : 0u;
+    auto own = [&](void* field) -> GLOBAL T& {
+        return *(GLOBAL T*)((GLOBAL char*)(gp<T>(field) + t0) + ob * (uint32_t)sizeof(T));
+    };
+    auto own_d = [&](void* field) -> GLOBAL double& {
+        return *(GLOBAL double*)((GLOBAL char*)(gp<double>(field) + t0) + ob * 8u);
+    };
     constexpr bool early = EARLY && STAGE <= 1;
 
     // ---- M (FUSE): the step's magnetic phase for this tile: red-black sweeps of the tile
@@ -607,12 +617,12 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
     auto load_own = [&] {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            cWin[k] = STAGE >= 1 ? gp<T>(Win[k])[o] : T(0);
-            cWb[k] = STAGE >= 2 ? gp<T>(Wbase[k])[o] : T(0);
+            cWin[k] = STAGE >= 1 ? own(Win[k]) : T(0);
+            cWb[k] = STAGE >= 2 ? own(Wbase[k]) : T(0);
         }
-        cCin = STAGE >= 1 ? Cin[o] : 0.0;
-        cCb = STAGE >= 2 ? Cbase[o] : 0.0;
-        cS = gp<T>(I.S)[o];
+        cCin = STAGE >= 1 ? own_d(STAGE == 2 ? I.W1[4] : STAGE == 3 ? I.W2[4] : I.W[4]) : 0.0;
+        cCb = STAGE >= 2 ? own_d(I.W[4]) : 0.0;
+        cS = own(I.S);
     };
     if constexpr (early) load_own();
 
@@ -640,16 +650,20 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
     if (interior) {
         T vW[NIT][4], vph[NIT];
         double vC[NIT];
+        // (addresses from the region origin (x0 - 3, y0 - 3), which lies inside the
+        // domain here: a uniform base plus a 32-bit byte offset per cell)
+        const size_t h0 = (size_t)(y0 - 3) * pitch + (x0 - 3);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int r = tid + it * NT;
             const int rr = r < L::NR ? r : L::NR - 1;
-            const size_t oh = (size_t)(y0 - 3 + rr / L::RX) * pitch + (x0 - 3 + rr % L::RX);
+            const uint32_t oh = (uint32_t)((rr / L::RX) * pitch + rr % L::RX);
 #pragma unroll
-            for (int k = 0; k < 4; k++) vW[it][k] = gp<T>(Win[k])[oh];
-            vC[it] = Cin[oh];
+            for (int k = 0; k < 4; k++)
+                vW[it][k] = *(const GLOBAL T*)((const GLOBAL char*)(gp<T>(Win[k]) + h0) + oh * (uint32_t)sizeof(T));
+            vC[it] = *(const GLOBAL double*)((const GLOBAL char*)(Cin + h0) + oh * 8u);
             if constexpr (FUSE) vph[it] = mphi(x0 - 3 + rr % L::RX, y0 - 3 + rr / L::RX);
-            else vph[it] = phi[oh];
+            else vph[it] = *(const GLOBAL T*)((const GLOBAL char*)(phi + h0) + oh * (uint32_t)sizeof(T));
         }
         // (the FP64 order parameter shares LDS with the magnetic block of FUSE: every
         // potential is read before the first is overwritten)
@@ -889,31 +903,30 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         const double dRc = double(dt) * double(Rk[4]);
         if (STAGE == 0) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) gp<T>(I.W1[k])[o] = Rk[k];
-            gp<double>(I.W1[4])[o] = double(Rk[4]);
+            for (int k = 0; k < 4; k++) own(I.W1[k]) = Rk[k];
+            own_d(I.W1[4]) = double(Rk[4]);
         } else if (STAGE == 1) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) gp<T>(I.W1[k])[o] = cWin[k] + dt * Rk[k];
-            gp<double>(I.W1[4])[o] = cCin + dRc;
+            for (int k = 0; k < 4; k++) own(I.W1[k]) = cWin[k] + dt * Rk[k];
+            own_d(I.W1[4]) = cCin + dRc;
         } else if (STAGE == 2) {
 #pragma unroll
-            for (int k = 0; k < 4; k++)
-                gp<T>(I.W2[k])[o] = T(0.75) * cWb[k] + T(0.25) * (cWin[k] + dt * Rk[k]);
-            gp<double>(I.W2[4])[o] = 0.75 * cCb + 0.25 * (cCin + dRc);
+            for (int k = 0; k < 4; k++) own(I.W2[k]) = T(0.75) * cWb[k] + T(0.25) * (cWin[k] + dt * Rk[k]);
+            own_d(I.W2[4]) = 0.75 * cCb + 0.25 * (cCin + dRc);
         } else {
             T Wn[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 Wn[k] = cWb[k] * T(1.0 / 3.0) + T(2.0 / 3.0) * (cWin[k] + dt * Rk[k]);
-                gp<T>(Wbase[k])[o] = Wn[k];
+                own(Wbase[k]) = Wn[k];
             }
             const double Cn1 = cCb * (1.0 / 3.0) + (2.0 / 3.0) * (cCin + dRc);
-            gp<double>(I.W[4])[o] = Cn1;
+            own_d(I.W[4]) = Cn1;
             // Table 1 (d): Eq. 8 after the step; lagged dFs/dt for the next step
             T T1, Fl1;
             enthalpy_state<T>(K, Wn[0], T(Cn1), T1, Fl1);
             const T ct1 = clamp01(T(Cn1));
-            gp<T>(I.S)[o] = -ct1 * (Fl1 - Fln) * idt;
+            own(I.S) = -ct1 * (Fl1 - Fln) * idt;
         }
     }
 }
