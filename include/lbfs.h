@@ -359,10 +359,11 @@ void lbfs_destroy(lbfs_solver* s);
  * nsteps time steps of the problem p are enqueued on `stream` (a hipStream_t of the
  * current device; asynchronous, direct launches, the arithmetic of lbfs_step, so the
  * same fields bit for bit) and the new state is left in the same arrays. The stage
- * fields, the second potential buffer, the descriptor, the tile lists and the residual
- * partials live in the library's static scratch of the current device, at most
- * LBFS_STATIC_SCRATCH_BYTES: 48 B per cell in FP32 and 80 B in FP64 plus the lists,
- * i.e. up to about 1.3 M cells in FP32 (1024 x 1024 fits) and 0.8 M in FP64. The
+ * fields, the second potential buffer, the three fields stage 1 leaves for stages 2
+ * and 3, the descriptor, the tile lists and the residual partials live in the
+ * library's static scratch of the current device, at most LBFS_STATIC_SCRATCH_BYTES:
+ * 64 B per cell in FP32 and 112 B in FP64 plus the lists, i.e. up to about 1.3 M cells
+ * in FP32 (1024 x 1024 fits) and 0.74 M in FP64. The
  * function allocates nothing. Every call on a device uses that device's one scratch:
  * calls that overlap on one device (other streams, other threads) race; calls on one
  * stream are ordered. Every value a step reads from the scratch is written earlier in
@@ -370,7 +371,7 @@ void lbfs_destroy(lbfs_solver* s);
  * LBFS_E_INVAL on invalid parameters, a NULL field, nsteps < 0, multigrid or
  * convergence control (mag_max_iters > 0); LBFS_E_NOMEM if the problem does not fit
  * the scratch; LBFS_E_DEVICE if a HIP call fails. */
-#define LBFS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define LBFS_STATIC_SCRATCH_BYTES ((size_t)80 << 20)
 int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps, void* stream);
 
 /* ------------------------------------------------------------------ batches

@@ -180,6 +180,10 @@ Layout make_layout(const lbfs_params* p)
     if (p->precision != LBFS_FP64) {
         L.cfield_bytes = align_up((size_t)L.pitch * p->ny * sizeof(double), ALIGN);
         off += L.cfield_bytes * NCFIELDS;
+    } else {
+        // the three fields stage 1 leaves for stages 2 and 3 (in FP32 they take the unused
+        // FP32 slots of the order parameter)
+        off += L.field_bytes * 3;
     }
     L.total = off + ALIGN;   // room to align the caller's base pointer
     return L;
@@ -1080,6 +1084,9 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
     I.phi[0] = s->field(15);
     I.phi[1] = s->field(17);
     I.S = s->field(16);
+    for (int k = 0; k < 3; k++)
+        I.kf[k] = s->f64() ? static_cast<void*>(s->base + L.off_cfields + L.field_bytes * (size_t)k)
+                           : s->field(4 + 5 * k);
     I.part = reinterpret_cast<double*>(s->base + L.off_part);
     I.mpart = reinterpret_cast<double*>(s->base + L.off_mpart);
     I.result = reinterpret_cast<double*>(s->base + L.off_res);
@@ -1499,6 +1506,8 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     for (int k = 0; k < 5; k++) o_w1[k] = take(n * (k == 4 ? sizeof(double) : es));
     for (int k = 0; k < 5; k++) o_w2[k] = take(n * (k == 4 ? sizeof(double) : es));
     const size_t o_phi1 = take(n * es);
+    size_t o_kf[3];
+    for (int k = 0; k < 3; k++) o_kf[k] = take(n * es);
     if (off > LBFS_STATIC_SCRATCH_BYTES) return LBFS_E_NOMEM;
     char* base = nullptr;
     const int rs = static_scratch(&base);
@@ -1514,6 +1523,7 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     I.phi[0] = fields[5];
     I.phi[1] = base + o_phi1;
     I.S = fields[6];
+    for (int k = 0; k < 3; k++) I.kf[k] = base + o_kf[k];
     I.part = nullptr;   // (observables are not reduced here)
     I.mpart = reinterpret_cast<double*>(base + o_mpart);
     I.result = reinterpret_cast<double*>(base + o_res);

@@ -141,6 +141,9 @@ struct DevInst {
     void* W2[5];     // stage-2 output
     void* phi[2];    // potential minus the applied-field potential, double buffered
     void* S;         // lagged dFs/dt
+    void* kf[3];     // written by stage 1 for stages 2 and 3: the Kelvin force (x, y) of the
+                     // step (the potential and the step-start state do not change within
+                     // it) and the liquid fraction of the step-start state
     double* part;    // [ntile_stage][NPART]
     double* mpart;   // residual partials of the magnetic phase (one per magnetic tile, or one
                      // per stage tile when stage 1 runs the phase), then the convergence flag

@@ -575,6 +575,11 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         return *(GLOBAL double*)((GLOBAL char*)(gp<double>(field) + t0) + ob * 8u);
     };
     constexpr bool early = EARLY && STAGE <= 1;
+    // The Kelvin force (Eq. 6) takes chi from the step-start state and |H|^2 from the
+    // step's potential, which the stages do not change: stages 0 (R(W) alone) and 1
+    // compute it, stage 1 leaves it in I.kf with the step-start liquid fraction, and
+    // stages 2 and 3 read them (the potential is then not loaded at all).
+    constexpr bool KELVIN = STAGE <= 1;
 
     // ---- M (FUSE): the step's magnetic phase for this tile: red-black sweeps of the tile
     //      plus a halo of 2*MAG_KMAX+3 cells in LDS (the arithmetic of k_mag_fused, so
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         s.q(Q_MU)[r] = q.mu;
         s.q(Q_LAM)[r] = q.lam;
         s.q(Q_CP)[r] = q.cp;
-        s.q(Q_PHI)[r] = ph;
+        if constexpr (KELVIN) s.q(Q_PHI)[r] = ph;
     };
     constexpr int NIT = (L::NR + NT - 1) / NT;
     if (interior) {
@@ -663,7 +668,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
                 vW[it][k] = *(const GLOBAL T*)((const GLOBAL char*)(gp<T>(Win[k]) + h0) + oh * (uint32_t)sizeof(T));
             vC[it] = *(const GLOBAL double*)((const GLOBAL char*)(Cin + h0) + oh * 8u);
             if constexpr (FUSE) vph[it] = mphi(x0 - 3 + rr % L::RX, y0 - 3 + rr / L::RX);
-            else vph[it] = *(const GLOBAL T*)((const GLOBAL char*)(phi + h0) + oh * (uint32_t)sizeof(T));
+            else if constexpr (KELVIN)
+                vph[it] = *(const GLOBAL T*)((const GLOBAL char*)(phi + h0) + oh * (uint32_t)sizeof(T));
+            else vph[it] = T(0);
         }
         // (the FP64 order parameter shares LDS with the magnetic block of FUSE: every
         // potential is read before the first is overwritten)
@@ -698,7 +705,8 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
             // (the block holds periodic images in place and zeros beyond walls: a wall
             // ghost reads its mirror cell)
             if constexpr (FUSE) vph[it] = mphi(wx >= 0 ? sx : hx, wy >= 0 ? sy : hy);
-            else vph[it] = phi[oh];
+            else if constexpr (KELVIN) vph[it] = phi[oh];
+            else vph[it] = T(0);
         }
         if constexpr (FUSE && cd_copy) __syncthreads();
 #pragma unroll
@@ -792,7 +800,7 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const bool wallx = !interior && !I.per_x && (gx < 0 || gx >= nx);
         const bool wally = !interior && !I.per_y && (gy < 0 || gy >= ny);
-        if (!wallx && !wally) {
+        if (KELVIN && !wallx && !wally) {
             const T* P = s.q(Q_PHI);
             const T Hx = h0x - (P[r + 1] - P[r - 1]) * inv2dx;
             const T Hy = h0y - (P[r + L::RX] - P[r - L::RX]) * inv2dx;
@@ -801,7 +809,7 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
     }
     __syncthreads();
     // |H|^2 of wall ghosts mirrors the interior cell (no wall ghosts on interior tiles)
-    for (int gi = tid; gi < (interior ? 0 : L::NG); gi += NT) {
+    for (int gi = tid; gi < (interior || !KELVIN ? 0 : L::NG); gi += NT) {
         const int lx = gi % L::GX + 2, ly = gi / L::GX + 2;
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const bool wallx = !I.per_x && (gx < 0 || gx >= nx);
@@ -866,16 +874,26 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         const T idt = K.idt, idx = K.idx;
         const T cs2 = T(1.0 / 3.0);
         // Kelvin force from the step-start state (Eq. 6)
-        T Cn, Hen;
-        if (STAGE <= 1) { Cn = s.q(Q_C)[r]; Hen = s.q(Q_HE)[r]; }
-        else { Cn = T(cCb); Hen = cWb[0]; }
-        T Tn, Fln;
-        enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
-        const T ctn = clamp01(Cn);
-        const T chi = mix3<T>(K.chi, ctn * (T(1) - Fln), ctn);
-        const T kmg = T(0.5) * K.mu0 * chi;
-        const T fmx = kmg * (s.h2[gi + 1] - s.h2[gi - 1]) * inv2dx;
-        const T fmy = kmg * (s.h2[gi + L::GX] - s.h2[gi - L::GX]) * inv2dx;
+        T fmx, fmy, Fln;
+        if constexpr (KELVIN) {
+            const T Cn = s.q(Q_C)[r], Hen = s.q(Q_HE)[r];
+            T Tn;
+            enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
+            const T ctn = clamp01(Cn);
+            const T chi = mix3<T>(K.chi, ctn * (T(1) - Fln), ctn);
+            const T kmg = T(0.5) * K.mu0 * chi;
+            fmx = kmg * (s.h2[gi + 1] - s.h2[gi - 1]) * inv2dx;
+            fmy = kmg * (s.h2[gi + L::GX] - s.h2[gi - L::GX]) * inv2dx;
+            if constexpr (STAGE == 1) {
+                own(I.kf[0]) = fmx;
+                own(I.kf[1]) = fmy;
+                own(I.kf[2]) = Fln;
+            }
+        } else {
+            fmx = own(I.kf[0]);
+            fmy = own(I.kf[1]);
+            Fln = STAGE == 3 ? own(I.kf[2]) : T(0);
+        }
         // stage-state cell fields; the central gradients phase C left in LDS
         const T divu = s.g[1][0][gi] + s.g[2][1][gi];
         const T drx = s.g[3][0][gi], dry = s.g[3][1][gi];

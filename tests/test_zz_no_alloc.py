@@ -64,4 +64,4 @@ def test_step_fields_refuses_what_does_not_fit():
     n = prob["nx"] * prob["ny"]
     arrays = [np.zeros((prob["ny"], prob["nx"]), dtype=np.float64 if k == 4 else np.float32) for k in range(7)]
     rc, _ = step_fields(prob, arrays, 1)
-    assert rc == lbfs.LBFS_E_NOMEM and n * 48 > (64 << 20)
+    assert rc == lbfs.LBFS_E_NOMEM and n * 64 > (80 << 20)
