@@ -330,7 +330,9 @@ int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape, int32_t*
    directly) from this solver's current state with every stage shape (at the current
    magnetic shape), then with every magnetic shape (at the fastest stage shape), and
    keep the fastest of each: the default, shape 0, unless another is faster by more
-   than 2 %, the spread of such timings. Where the sweeps can run inside stage 1, that
+   than 2 %, the spread of such timings. Every candidate is timed twice, in a forward
+   and a backward pass over the list, and keeps the shorter time, so that a clock that
+   still rises or falls favours no position in the list. Where the sweeps can run inside stage 1, that
    variant is timed too and chosen when its step beats the best step by 2 %. Before
    each candidate and at the end the state is loaded again from a host snapshot in the
    checkpoint format (lbfs_save_state), so the state, clock and results are unchanged;

@@ -1619,6 +1619,26 @@ int time_launches(hipStream_t stream, int reps, F&& f, double* ms)
 // faster by more than the run-to-run spread of such timings (2 %)
 bool clearly_faster(double t, double best) { return t < 0.98 * best; }
 
+// Time candidates 0..n-1 with time_one(k, &ms) in two passes, forward then backward, and
+// keep each candidate's shorter time: a drifting clock (the GPU's, rising after the host
+// copies that restore the state) then favours neither end of the list. Returns the
+// index of the fastest, the default 0 unless a candidate is clearly faster.
+template <typename F>
+int time_candidates(int n, double* t, int& rc, F&& time_one)
+{
+    for (int pass = 0; pass < 2; pass++)
+        for (int j = 0; j < n && rc == LBFS_OK; j++) {
+            const int k = pass ? n - 1 - j : j;
+            double ms = 0.0;
+            rc = time_one(k, &ms);
+            if (rc == LBFS_OK) t[k] = pass ? std::min(t[k], ms) : ms;
+        }
+    int best = 0;
+    for (int k = 1; k < n && rc == LBFS_OK; k++)
+        if (clearly_faster(t[k], t[best])) best = k;
+    return best;
+}
+
 // stand-in for the three Runge-Kutta stages of a step: stage 1, then stage 2 twice
 // (stage 3 writes the state; its cost follows stage 2's, which reads as many fields).
 // Both write only the stage fields W1 and W2, so timing them leaves the state as it is.
@@ -1715,19 +1735,14 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     };
     // stage shapes with the current magnetic shape, then magnetic shapes with the best
     // stage shape
-    int best_s = 0;
-    for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
-        rc = apply_shapes(s, k, mag0);
-        if (rc == LBFS_OK) rc = time_steps(&t[k]);
-        if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
-    }
-    int best_m = 0;
-    for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
-        rc = apply_shapes(s, best_s, k);
-        double* tk = &t[LBFS_MAX_SHAPES + k];
-        if (rc == LBFS_OK) rc = time_steps(tk);
-        if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
-    }
+    const int best_s = time_candidates(NSTAGE_SHAPES, t, rc, [&](int k, double* ms) {
+        int r = apply_shapes(s, k, mag0);
+        return r == LBFS_OK ? time_steps(ms) : r;
+    });
+    const int best_m = time_candidates(NMAG_SHAPES, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
+        int r = apply_shapes(s, best_s, k);
+        return r == LBFS_OK ? time_steps(ms) : r;
+    });
     // the sweeps inside stage 1 (its tiles plus a wider halo, one launch less per step)
     bool fuse = false;
     if (rc == LBFS_OK && fusable(s->p)) {
@@ -2254,22 +2269,17 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
             if (r == LBFS_OK) r = time_launches(E.stream, reps, [&] { return exec_enqueue_step(E); }, out);
             return r;
         };
-        best_s = 0;
-        for (int k = 0; k < NSTAGE_SHAPES && rc == LBFS_OK; k++) {
+        best_s = time_candidates(NSTAGE_SHAPES, t, rc, [&](int k, double* ms) {
             b->stage_shape = k;
             b->dirty = true;
-            rc = time_steps(&t[k]);
-            if (rc == LBFS_OK && clearly_faster(t[k], t[best_s])) best_s = k;
-        }
-        best_m = 0;
+            return time_steps(ms);
+        });
         b->stage_shape = best_s;
-        for (int k = 0; k < NMAG_SHAPES && rc == LBFS_OK; k++) {
+        best_m = time_candidates(NMAG_SHAPES, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
             b->mag_shape = k;
             b->dirty = true;
-            double* tk = &t[LBFS_MAX_SHAPES + k];
-            rc = time_steps(tk);
-            if (rc == LBFS_OK && clearly_faster(*tk, t[LBFS_MAX_SHAPES + best_m])) best_m = k;
-        }
+            return time_steps(ms);
+        });
         const int rr = restore();
         if (rc == LBFS_OK) rc = rr;
         b->stepped_since_observe = true;
