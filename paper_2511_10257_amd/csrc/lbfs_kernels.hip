@@ -60,7 +60,7 @@ __device__ __forceinline__ T mix3(const T* g, T fs, T ct)
 
 template <typename T>
 struct Prim {
-    T p, u, v, rho, C, Tt, He, mu, lam, cp, fs;
+    T p, u, v, rho, C, Tt, He, mu, lam, cp, fs, Fl;
 };
 
 template <typename T>
@@ -70,6 +70,7 @@ __device__ __forceinline__ Prim<T> primitives(const Coef<T>& K, T He, T p, T Mx,
     T Fl;
     enthalpy_state<T>(K, He, C, q.Tt, Fl);
     const T ct = clamp01(C);
+    q.Fl = Fl;
     q.fs = ct * (T(1) - Fl);
     q.rho = mix3<T>(K.rho, q.fs, ct);
     q.mu = mix3<T>(K.mu, q.fs, ct);
@@ -315,7 +316,8 @@ struct StageLds {
     static constexpr int MRX = TX + 4 * MAG_KMAX + 6, MRY = TY + 4 * MAG_KMAX + 6;
     static constexpr int MB = MRX * MRY + MRX * MRY / 2 * 2;
     static_assert(5 * (NFX + NFY) <= (NQ + 1 - Q_P) * NR, "the fluxes fit in the dead cell fields");
-    T qbuf[(NQ + 1) * NR];   // q(k) for k < NQ, then mu_c (valid on tile + 2)
+    T qbuf[(NQ + 1) * NR];   // q(k) for k < NQ, then mu_c
+    T fl[TX * TY];           // liquid fraction of the tile's cells (phases A-E)
     union {
         struct {
             T g[NV][2][NG];  // d/dx, d/dy of p, u, v, rho, C, mu_c, T, He (phases C-E)
@@ -650,6 +652,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         s.q(Q_LAM)[r] = q.lam;
         s.q(Q_CP)[r] = q.cp;
         if constexpr (KELVIN) s.q(Q_PHI)[r] = ph;
+        // the tile's own cells keep their liquid fraction for phase E
+        const int tx = r % L::RX - 3, ty = r / L::RX - 3;
+        if ((unsigned)tx < (unsigned)TX && (unsigned)ty < (unsigned)TY) s.fl[ty * TX + tx] = q.Fl;
     };
     constexpr int NIT = (L::NR + NT - 1) / NT;
     if (interior) {
@@ -873,12 +878,14 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         const T dt = K.dt;
         const T idt = K.idt, idx = K.idx;
         const T cs2 = T(1.0 / 3.0);
+        // the liquid fraction of this stage's state, from phase A (stages 0 and 1 take
+        // the step-start state)
+        const T Flc = s.fl[tid];
         // Kelvin force from the step-start state (Eq. 6)
         T fmx, fmy, Fln;
         if constexpr (KELVIN) {
-            const T Cn = s.q(Q_C)[r], Hen = s.q(Q_HE)[r];
-            T Tn;
-            enthalpy_state<T>(K, Hen, Cn, Tn, Fln);
+            const T Cn = s.q(Q_C)[r];
+            Fln = Flc;
             const T ctn = clamp01(Cn);
             const T chi = mix3<T>(K.chi, ctn * (T(1) - Fln), ctn);
             const T kmg = T(0.5) * K.mu0 * chi;
@@ -899,8 +906,6 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
         const T drx = s.g[3][0][gi], dry = s.g[3][1][gi];
         const T dmx = s.g[5][0][gi], dmy = s.g[5][1][gi];
         const T c = s.q(Q_C)[r], rho = s.q(Q_RHO)[r], u = s.q(Q_U)[r], v = s.q(Q_V)[r];
-        T Tc, Flc;
-        enthalpy_state<T>(K, s.q(Q_HE)[r], c, Tc, Flc);
         const T fs = clamp01(c) * (T(1) - Flc);
         const T Sv = cS;
         const T vc = K.vc;
