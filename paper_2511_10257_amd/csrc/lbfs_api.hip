@@ -1450,6 +1450,9 @@ int static_scratch(char** out)
 }
 
 static_assert(sizeof(DevInst) <= 3072, "the descriptor travels as a kernel argument");
+// the autotuners' timing arrays: every stage shape, then every magnetic shape and the
+// fused variant, each within LBFS_MAX_SHAPES
+static_assert(NSTAGE_SHAPES <= LBFS_MAX_SHAPES && NMAG_SHAPES < LBFS_MAX_SHAPES, "shape tables fit the ABI arrays");
 
 // the descriptor into device memory without a host-to-device copy
 __global__ void k_write_desc(DevInst d, DevInst* dst)

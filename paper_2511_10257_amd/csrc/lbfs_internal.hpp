@@ -41,8 +41,9 @@ constexpr TileShape STAGE_SHAPES_F64[NSTAGE_SHAPES] = {
     {10, 8, 256, 0}, {10, 10, 256, 0}, {12, 8, 256, 0}, {8, 8, 256, 0}, {12, 7, 256, 0}, {8, 7, 192, 0},
     {8, 8, 192, 0}};
 // fused magnetic kernel: interior tile shapes; one launch does up to MAG_KMAX sweeps
-// (LDS halo 2*MAG_KMAX+1). Without autotuning, grids above 512 x 512 use shape 1 (a
-// larger tile recomputes fewer halo cells: 2.0x for 64 x 32 against 2.7x for 64 x 16).
+// (LDS halo 2*MAG_KMAX, one ring more in a launch that computes the residual). Without
+// autotuning, grids above 512 x 512 use shape 1 (a larger tile recomputes fewer halo
+// cells: 1.9x for 64 x 32 against 2.5x for 64 x 16).
 constexpr int MAG_KMAX = 4;
 constexpr int NMAG_SHAPES = 5;
 constexpr TileShape MAG_SHAPES[NMAG_SHAPES] = {{32, 8, 704}, {64, 32, 1024}, {64, 16, 1024}, {64, 8, 1024},

@@ -1100,20 +1100,23 @@ hipError_t launch_mag_gate(const DevInst* insts, int ninst, hipStream_t stream)
     return hipGetLastError();
 }
 
-template <typename T, int MTX, int MTY>
+// The halo: after nsweeps <= MAG_KMAX sweeps the cells at least 2 nsweeps from the
+// region edge are exact, so a halo of 2 MAG_KMAX keeps the tile exact and one more ring
+// keeps its neighbours exact for the residual (RES = 1).
+template <typename T, int MTX, int MTY, int RES>
 struct MagLds {
-    using G = MagGeom<MTX, MTY, 2 * MAG_KMAX + 1>;
+    using G = MagGeom<MTX, MTY, 2 * MAG_KMAX + RES>;
     T ph[2][G::HALF];   // potential by colour
     T mu[G::NR];        // permeability, natural layout (set-up only); 0 outside the domain
     double red[16];
 };
 
-template <typename T, int MTX, int MTY, int NT>
+template <typename T, int MTX, int MTY, int NT, int RES>
 __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ insts,
                                                   const Tile* __restrict__ tiles, int nsweeps, double omega,
-                                                  int residual, int pin, int gate)
+                                                  int pin, int gate)
 {
-    using L = MagLds<T, MTX, MTY>;
+    using L = MagLds<T, MTX, MTY, RES>;
     using G = typename L::G;
     static_assert(NT % 64 == 0 && NT / 64 <= 16, "whole waves");
     __shared__ L s;
@@ -1123,7 +1126,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
         copy_tile<T, MTX, MTY, NT>(I, tile, pin);
         return;
     }
-    const double r2 = mag_block<T, MTX, MTY, NT, G::H>(I, tile.x0, tile.y0, pin, nsweeps, omega, residual, s.ph, s.mu);
+    const double r2 = mag_block<T, MTX, MTY, NT, G::H>(I, tile.x0, tile.y0, pin, nsweeps, omega, RES, s.ph, s.mu);
     // write the tile in natural order (coalesced)
     GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
     const int par0 = (tile.x0 - G::H + tile.y0 - G::H) & 1;
@@ -1134,7 +1137,7 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
         const int lx = tx + G::H, ly = ty + G::H;
         phout[(size_t)gy * I.pitch + gx] = s.ph[(par0 + lx + ly) & 1][ly * G::RXH + (lx >> 1)];
     }
-    if (residual) {
+    if constexpr (RES) {
         const double w = wave_sum(r2);
         if (threadIdx.x % 64 == 0) s.red[threadIdx.x / 64] = w;
         __syncthreads();
@@ -1389,8 +1392,10 @@ hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, in
     if constexpr (K < NMAG_SHAPES) {
         constexpr TileShape M = MAG_SHAPES[K];
         if (shape == K)
-            return launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt>, dim3(ntiles), dim3(M.nt), stream, e0, e1, insts,
-                                tiles, nsweeps, omega, res, pin, gate);
+            return res ? launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 1>, dim3(ntiles), dim3(M.nt), stream, e0, e1,
+                                      insts, tiles, nsweeps, omega, pin, gate)
+                       : launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 0>, dim3(ntiles), dim3(M.nt), stream, e0, e1,
+                                      insts, tiles, nsweeps, omega, pin, gate);
         return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, pin,
                                         gate);
     } else {
