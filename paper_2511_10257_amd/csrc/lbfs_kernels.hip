@@ -359,11 +359,12 @@ __device__ __forceinline__ void gather_side(const L& s, int r, int gidx, int axi
 }
 
 // the LBFS flux of face fi of one axis (AX 0: x-face, cells L = (cx-1, cy), R = (cx, cy);
-// 1: y-face, L = (cx, cy-1), R = (cx, cy)) of a tile, with the wall conditions, into F
-// (He, p, normal and tangential momentum, C)
+// 1: y-face, L = (cx, cy-1), R = (cx, cy)) of a tile, with the wall conditions (only a
+// tile with a side on the domain edge, edge != 0, has wall faces), into F (He, p, normal
+// and tangential momentum, C)
 template <typename T, int TX, int TY, int AX, typename L>
-__device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst& I, int x0, int y0, int fi,
-                                           T F[5])
+__device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst& I, int x0, int y0, bool edge,
+                                           int fi, T F[5])
 {
     int cx, cy, lxL, lyL;
     if constexpr (AX == 0) {
@@ -381,6 +382,9 @@ __device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst
         gather_side<T>(s, rL, gL, AX, S);
         side_part<T, 1>(K, S, PL);
     }
+    // (a compiler fence: each side's fields are read from one base address, rather than
+    // each field plane of both sides from a base of its own)
+    asm volatile("" ::: "memory");
     {
         Side<T> S;
         gather_side<T>(s, rR, gR, AX, S);
@@ -391,7 +395,7 @@ __device__ __forceinline__ void split_face(L& s, const Coef<T>& K, const DevInst
     const int gface = AX == 0 ? x0 + cx : y0 + cy;
     const int nax = AX == 0 ? I.nx : I.ny;
     const int per = AX == 0 ? I.per_x : I.per_y;
-    if (!per && (gface == 0 || gface == nax)) {
+    if (edge && !per && (gface == 0 || gface == nax)) {
         const bool lo = gface == 0;
         const int wall = AX == 0 ? (lo ? 0 : 1) : (lo ? 2 : 3);
         const int rc = lo ? rR : rL;
@@ -837,8 +841,10 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
     //      of a wave and the LDS offsets and the component swap are constants. Every face
     //      of every tile shape goes through the same two instantiations of the flux.
     //      The fluxes stay in registers until every face has read its cells, then take
-    //      the place of the cell fields that are dead from here on.
+    //      the place of the cell fields that are dead from here on. Lanes past an axis's
+    //      last face repeat that face (no masked lanes in the flux); they store nothing.
     {
+        const bool edge = x0 == 0 || y0 == 0 || x0 + TX >= nx || y0 + TY >= ny;
         constexpr int NXT = (L::NFX + 63) / 64 * 64, NYT = (L::NFY + 63) / 64 * 64;
         constexpr int NRND = (NXT + NYT + NT - 1) / NT;
         T Fr[NRND][5];
@@ -847,9 +853,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
             const int f = tid + k * NT;
             if (f >= NXT + NYT) break;
             if (__builtin_amdgcn_readfirstlane(f) < NXT) {
-                if (f < L::NFX) split_face<T, TX, TY, 0>(s, K, I, x0, y0, f, Fr[k]);
-            } else if (f - NXT < L::NFY) {
-                split_face<T, TX, TY, 1>(s, K, I, x0, y0, f - NXT, Fr[k]);
+                split_face<T, TX, TY, 0>(s, K, I, x0, y0, edge, f < L::NFX ? f : L::NFX - 1, Fr[k]);
+            } else {
+                split_face<T, TX, TY, 1>(s, K, I, x0, y0, edge, f - NXT < L::NFY ? f - NXT : L::NFY - 1, Fr[k]);
             }
         }
         __syncthreads();
