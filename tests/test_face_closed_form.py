@@ -62,11 +62,14 @@ def params_of(o):
             p.t_melt, p.t_liquidus, p.latent]
 
 
-@pytest.mark.parametrize("seed,angle,tl", [(3, 90.0, None), (8, 30.0, None), (13, 0.0, 0.04)])
-def test_closed_form_face_flux_matches_the_literal_procedure(face_host, seed, angle, tl):
+@pytest.mark.parametrize("seed,angle,tl,dx", [(3, 90.0, None, 1.0), (8, 30.0, None, 1.0), (13, 0.0, 0.04, 1.0),
+                                              (21, 60.0, None, 0.5)])
+def test_closed_form_face_flux_matches_the_literal_procedure(face_host, seed, angle, tl, dx):
     nx, ny = 22, 18
     prob = wl.droplet_problem(nx, 5.0, ste=0.1, bo_m=1.0, angle_deg=angle, precision="fp64", ny=ny)
     prob["init_max"] = 0
+    if dx != 1.0:   # delta_t = dx/2 on another mesh spacing
+        prob.update(dx=dx, dt=0.5 * dx, dt_stream=0.5 * dx)
     if tl is not None:
         prob["t_liquidus"] = tl   # a melting range: the mushy branch of Eq. 8 with Ts < Tl
     o = orc.Oracle(prob, init=False)
