@@ -59,10 +59,21 @@ ALG_FLOPS = {"mag": 55.0, "stage1": 1800.0, "stage2": 1800.0, "stage3": 1800.0, 
 ALG_BYTES_FP32 = {"mag": 52.0, "stage1": 48.0, "stage2": 68.0, "stage3": 72.0, "reduce": 0.0}
 # The bytes these kernels have to move at the least (each field once, the order
 # parameter in FP64 in both precisions; stage 1 also writes the step's Kelvin force and
-# step-start liquid fraction, which stages 2 and 3 read instead of the potential):
-# FP32 and FP64
-MIN_BYTES = {"fp32": {"mag": 20.0, "stage1": 68.0, "stage2": 84.0, "stage3": 92.0, "reduce": 0.0},
-             "fp64": {"mag": 32.0, "stage1": 120.0, "stage2": 144.0, "stage3": 160.0, "reduce": 0.0}}
+# step-start liquid fraction, which stages 2 and 3 read instead of the potential; stage 3
+# also writes the permeability of the new state, which the sweeps read instead of He and
+# C): FP32 and FP64
+MIN_BYTES = {"fp32": {"mag": 12.0, "stage1": 68.0, "stage2": 84.0, "stage3": 96.0, "reduce": 0.0},
+             "fp64": {"mag": 24.0, "stage1": 120.0, "stage2": 144.0, "stage3": 168.0, "reduce": 0.0}}
+# a magnetic phase that computes the permeability from He and C (the pseudo-time solve)
+MIN_BYTES_MAG_FROM_STATE = {"fp32": 20.0, "fp64": 32.0}
+
+
+def min_bytes(precision: str, kind: str, workload: str = "") -> float:
+    """Least bytes per cell of one launch of `kind` (MIN_BYTES), for the magnetic phase
+    of a workload whose name ends in -mag-lbfs the figure with He and C read."""
+    if kind == "mag" and workload.endswith("-mag-lbfs"):
+        return MIN_BYTES_MAG_FROM_STATE[precision]
+    return MIN_BYTES[precision][kind]
 # The operation count of the oracle's literal per-face procedure (nine equilibria of
 # each kind built point by point), measured by compiling the oracle with a counting
 # number type (oracle/opcount.py) on the 256 x 256 droplet: 13993 per cell-step, of which
@@ -455,11 +466,11 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
     dominant = max(share, key=share.get)
     scale = 2.0 if precision == "fp64" else 1.0
     alg_bytes = ALG_BYTES_FP32[dominant] * scale * cells
-    min_bytes = MIN_BYTES[precision][dominant] * cells
+    least = min_bytes(precision, dominant, workload) * cells
     alg_flops = ALG_FLOPS[dominant] * cells
     if dominant == "mag" and (mag_flops is not None or mag_launches != 1):
         alg_bytes *= mag_launches
-        min_bytes *= mag_launches
+        least *= mag_launches
         alg_flops = (mag_flops if mag_flops is not None else ALG_FLOPS["mag"]) * cells
     dur_s = kern[dominant][0] * 1e-3
     gbs = alg_bytes / dur_s / 1e9
@@ -467,8 +478,8 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
     traffic = measured_traffic(dominant, workload, kernel_shape(dominant, shapes))
     hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
-           "min_bytes_per_launch": min_bytes,
-           "min_bytes_frac": min_bytes / dur_s / 1e9 / HBM_PEAK_GBS}
+           "min_bytes_per_launch": least,
+           "min_bytes_frac": least / dur_s / 1e9 / HBM_PEAK_GBS}
     vpeak = VALU_PEAK_TFLOPS[precision]
     alu = {"bound": "alu", "achieved": tflops, "peak": vpeak, "unit": "TFLOP/s", "frac": tflops / vpeak,
            "traffic": traffic, "algorithmic_flops_per_launch": alg_flops,
@@ -508,7 +519,7 @@ def whole_step(cells: int, precision: str, ms_per_step: float, workload: str) ->
     summary of the current kernels exists."""
     scale = 2.0 if precision == "fp64" else 1.0
     survey = sum(ALG_BYTES_FP32.values()) * scale
-    least = sum(MIN_BYTES[precision].values())
+    least = sum(min_bytes(precision, k, workload) for k in MIN_BYTES[precision])
     step_s = ms_per_step * 1e-3
     return {"survey_bytes_per_cell_step": survey, "least_bytes_per_cell_step": least,
             "hbm_frac_survey_bytes": survey * cells / step_s / 1e9 / HBM_PEAK_GBS,

@@ -239,6 +239,9 @@ struct Exec {
     const Tile* tiles_mag = nullptr;
     int nmag = 0;
     int phase = 0;                       // potential buffer holding the current phi'
+    // kf[0] of every instance holds the permeability of its current state (left there by
+    // stage 3 of the last step, and no write of the state since)
+    bool mu_ready = false;
     bool use_graph = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing of the next launch (profiled steps)
     int graph_steps = 1;                 // steps per replay of the longest graph
@@ -281,10 +284,11 @@ void exec_set_graph_steps(Exec& E, int gs)
 hipError_t exec_mag(Exec& E, int nsweeps, double omega, int residual)
 {
     E.mres_stage = false;
-    return E.f64 ? launch_mag<double>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag,
+    const int mi = E.mu_ready ? 1 : 0;
+    return E.f64 ? launch_mag<double>(E.mag_shape, nsweeps, omega, residual, mi, &E.phase, E.dinst, E.tiles_mag,
                                       E.nmag, E.stream, E.ev0, E.ev1)
-                 : launch_mag<float>(E.mag_shape, nsweeps, omega, residual, &E.phase, E.dinst, E.tiles_mag, E.nmag,
-                                     E.stream, E.ev0, E.ev1);
+                 : launch_mag<float>(E.mag_shape, nsweeps, omega, residual, mi, &E.phase, E.dinst, E.tiles_mag,
+                                     E.nmag, E.stream, E.ev0, E.ev1);
 }
 
 hipError_t exec_mag_lbfs(Exec& E, int nsteps, int residual, hipEvent_t e0, hipEvent_t e1, int gate)
@@ -378,10 +382,11 @@ hipError_t exec_mag_step(Exec& E, bool resid)
         if (E.mag_method == LBFS_MAG_LBFS) {
             e = exec_mag_lbfs(E, E.sweeps, r, a, b, gate);
         } else {
-            e = E.f64 ? launch_mag<double>(E.mag_shape, E.sweeps, E.omega, r, &E.phase, E.dinst, E.tiles_mag, E.nmag,
-                                           E.stream, a, b, gate)
-                      : launch_mag<float>(E.mag_shape, E.sweeps, E.omega, r, &E.phase, E.dinst, E.tiles_mag, E.nmag,
-                                          E.stream, a, b, gate);
+            const int mi = E.mu_ready ? 1 : 0;
+            e = E.f64 ? launch_mag<double>(E.mag_shape, E.sweeps, E.omega, r, mi, &E.phase, E.dinst, E.tiles_mag,
+                                           E.nmag, E.stream, a, b, gate)
+                      : launch_mag<float>(E.mag_shape, E.sweeps, E.omega, r, mi, &E.phase, E.dinst, E.tiles_mag,
+                                          E.nmag, E.stream, a, b, gate);
         }
     }
     return e;
@@ -420,6 +425,7 @@ hipError_t exec_enqueue_step(Exec& E, bool resid = true)
 {
     hipError_t e = E.fused ? exec_stage_fused(E) : exec_mag_step(E, resid);
     for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++) e = exec_stage(E, st);
+    if (e == hipSuccess) E.mu_ready = true;   // (stage 3 left the permeability in kf[0])
     return e;
 }
 
@@ -449,8 +455,11 @@ hipError_t exec_ensure_graph(Exec& E, int li, int ph)
 {
     if (E.graph_exec[li][ph]) return hipSuccess;
     const int saved = E.phase;
-    const bool saved_mres = E.mres_stage;
+    const bool saved_mres = E.mres_stage, saved_mu = E.mu_ready;
     E.phase = ph;
+    // (a replay always follows a step: exec_run_steps runs one directly while the
+    // permeability is not in kf[0])
+    E.mu_ready = true;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(E.stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
@@ -464,6 +473,7 @@ hipError_t exec_ensure_graph(Exec& E, int li, int ph)
     const hipError_t ec = hipStreamEndCapture(E.stream, &g);
     E.phase = saved;
     E.mres_stage = saved_mres;
+    E.mu_ready = saved_mu;
     if (e == hipSuccess) e = ec;
     if (e == hipSuccess) e = hipGraphInstantiate(&E.graph_exec[li][ph], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -505,7 +515,7 @@ int exec_run_steps(Exec& E, int nmax)
     int li = 0;
     if (E.use_graph)
         while (li + 1 < E.nglen && E.glen[li + 1] <= nmax) li++;
-    if (!E.use_graph || E.glen[li] < 2) return exec_enqueue_step(E, nmax == 1) == hipSuccess ? 1 : 0;
+    if (!E.use_graph || E.glen[li] < 2 || !E.mu_ready) return exec_enqueue_step(E, nmax == 1) == hipSuccess ? 1 : 0;
     const int n = E.glen[li];
     const int ph = E.phase;
     if (exec_ensure_graph(E, li, ph) != hipSuccess) return 0;
@@ -567,6 +577,7 @@ int exec_profiled_start(Exec& E, int nsteps, int sample_every, F&& after_step)
             for (int st = E.fused ? 2 : 1; st <= 3 && e == hipSuccess; st++)
                 e = timed(LBFS_K_STAGE1 + st - 1, [&] { return exec_stage(E, st); });
             if (e != hipSuccess) rc = LBFS_E_DEVICE;
+            else E.mu_ready = true;
             after_step();
             n++;
             continue;
@@ -710,6 +721,7 @@ struct lbfs_solver {
     double vol0 = 0.0;
     bool stepped_since_observe = false;  // the observables must be reduced again
     bool* owner_stale = nullptr;         // a batch member: its batch's flag of the same kind
+    bool* owner_mu = nullptr;            // a batch member: its batch's permeability flag
     MgCtx mg;                            // multigrid plan (built on first use)
     void* field(int k) const { return base + L.off_fields + L.field_bytes * (size_t)k; }
     bool f64() const { return p.precision == LBFS_FP64; }
@@ -841,6 +853,9 @@ void mark_written(lbfs_solver* s)
 {
     s->stepped_since_observe = true;
     if (s->owner_stale) *s->owner_stale = true;
+    // (and the next magnetic phase computes the permeability itself)
+    s->E.mu_ready = false;
+    if (s->owner_mu) *s->owner_mu = false;
 }
 
 int copy_field_in(lbfs_solver* s, int k, const double* host)
@@ -1947,6 +1962,7 @@ int batch_rebuild(lbfs_batch* b)
         HIPCHK(hipStreamSynchronize(b->stream));
     }
     Exec& E = b->E;
+    E.mu_ready = false;   // (a new member's kf[0] holds no permeability yet)
     E.dinst = b->meta_inst();
     E.ninst = (int)insts.size();
     E.tiles_stage = b->meta_stage();
@@ -2079,6 +2095,7 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     }
     s->batched = true;
     s->owner_stale = &b->stepped_since_observe;
+    s->owner_mu = &b->E.mu_ready;
     b->slots[slot] = Slot{s, off, need};
     b->dirty = true;
     b->stepped_since_observe = true;

@@ -144,7 +144,9 @@ struct DevInst {
     void* S;         // lagged dFs/dt
     void* kf[3];     // written by stage 1 for stages 2 and 3: the Kelvin force (x, y) of the
                      // step (the potential and the step-start state do not change within
-                     // it) and the liquid fraction of the step-start state
+                     // it) and the liquid fraction of the step-start state; from stage 3
+                     // to the next step's stage 1, kf[0] holds the permeability of the
+                     // state (for the magnetic phase)
     double* part;    // [ntile_stage][NPART]
     double* mpart;   // residual partials of the magnetic phase (one per magnetic tile, or one
                      // per stage tile when stage 1 runs the phase), then the convergence flag
@@ -190,11 +192,13 @@ hipError_t launch_stage_fused(int shape, int pidx, int nsweeps, double omega, co
                               hipEvent_t e1 = nullptr);
 // magnetic phase: permeability, nsweeps red-black sweeps with factor omega, and the
 // residual partials when residual != 0, on tiles of MAG_SHAPES[shape]. Reads the
-// potential buffer *pidx and flips *pidx once per launch.
+// potential buffer *pidx and flips *pidx once per launch. With muin != 0 the
+// permeability is read from kf[0], which stage 3 fills with that of the state it
+// writes; the caller passes muin only when no other write of the state came since.
 // With gate != 0 an instance whose convergence flag is set only copies its potential
 // to the other buffer (the flip stays uniform) and keeps its residual partials.
 template <typename T>
-hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int muin, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr, int gate = 0);
 // magnetic phase by the LBFS pseudo-time solve: permeability, nsteps SSP-RK3 steps of

@@ -58,6 +58,14 @@ __device__ __forceinline__ T mix3(const T* g, T fs, T ct)
     return fs * g[0] + (T(1) - fs) * ct * g[1] + (T(1) - fs) * (T(1) - ct) * g[2];
 }
 
+// Eq. 2 with Eq. 11: the permeability mu0 (1 + chi) of a cell from its clamped order
+// parameter and liquid fraction (the magnetic kernels, and stage 3 for the next step)
+template <typename T>
+__device__ __forceinline__ T mag_permeability(const Coef<T>& K, T ct, T Fl)
+{
+    return K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+}
+
 template <typename T>
 struct Prim {
     T p, u, v, rho, C, Tt, He, mu, lam, cp, fs, Fl;
@@ -146,7 +154,11 @@ struct MagGeom {
 // Each thread owns fixed cells of both colours and keeps their face weights, constant
 // term and 1 / sum of weights in registers; a pass costs four LDS reads and one write
 // per cell, and reads only the other colour's array (contiguous, conflict free).
-template <typename T, int MTX, int MTY, int NT, int H>
+//
+// MUIN = 1: the permeability of the state is read from I.kf[0], where stage 3 of the
+// step before left it (the same arithmetic on the same values), instead of being
+// computed from He and C.
+template <typename T, int MTX, int MTY, int NT, int H, int MUIN = 0>
 __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, int pin, int nsweeps, double omega,
                                             int residual, T (*ph)[MagGeom<MTX, MTY, H>::HALF], T* mu)
 {
@@ -161,6 +173,7 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
     const GLOBAL T* phin = gp<T>(I.phi[pin]);
     const GLOBAL T* He_ = gp<T>(I.W[0]);
     const GLOBAL double* C_ = gp<double>(I.W[4]);
+    const GLOBAL T* Mu_ = gp<T>(I.kf[0]);
     // 1. load the region (all loads of this thread in flight together): permeability in
     //    natural layout (0 outside the domain), potential by colour
     {
@@ -184,8 +197,13 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
             in = in && sx >= 0 && sx < nx && sy >= 0 && sy < ny;
             vin[it] = in;
             const size_t o = in ? (size_t)sy * I.pitch + sx : 0;
-            vHe[it] = He_[o];
-            vC[it] = T(C_[o]);
+            if constexpr (MUIN) {
+                vHe[it] = Mu_[o];   // (the permeability)
+                vC[it] = T(0);
+            } else {
+                vHe[it] = He_[o];
+                vC[it] = T(C_[o]);
+            }
             vph[it] = phin[o];
         }
 #pragma unroll
@@ -195,10 +213,13 @@ __device__ __forceinline__ double mag_block(const DevInst& I, int x0, int y0, in
             const int lx = r % G::RX, ly = r / G::RX;
             T m = T(0);
             if (vin[it]) {
-                T Tt, Fl;
-                enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
-                const T ct = clamp01(vC[it]);
-                m = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+                if constexpr (MUIN) {
+                    m = vHe[it];
+                } else {
+                    T Tt, Fl;
+                    enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
+                    m = mag_permeability<T>(K, clamp01(vC[it]), Fl);
+                }
             }
             mu[r] = m;
             ph[(par0 + lx + ly) & 1][ly * G::RXH + (lx >> 1)] = vin[it] ? vph[it] : T(0);
@@ -956,6 +977,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? (sizeof(T) == 4 ? 7 : 4) : 1) void 
             enthalpy_state<T>(K, Wn[0], T(Cn1), T1, Fl1);
             const T ct1 = clamp01(T(Cn1));
             own(I.S) = -ct1 * (Fl1 - Fln) * idt;
+            // the permeability of the new state, for the next step's magnetic phase (in
+            // the Kelvin-force field, which stage 1 of that step rewrites after it)
+            own(I.kf[0]) = mag_permeability<T>(K, ct1, Fl1);
         }
     }
 }
@@ -1117,7 +1141,7 @@ struct MagLds {
     double red[16];
 };
 
-template <typename T, int MTX, int MTY, int NT, int RES>
+template <typename T, int MTX, int MTY, int NT, int RES, int MUIN>
 __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ insts,
                                                   const Tile* __restrict__ tiles, int nsweeps, double omega,
                                                   int pin, int gate)
@@ -1132,7 +1156,8 @@ __global__ __launch_bounds__(NT) void k_mag_fused(const DevInst* __restrict__ in
         copy_tile<T, MTX, MTY, NT>(I, tile, pin);
         return;
     }
-    const double r2 = mag_block<T, MTX, MTY, NT, G::H>(I, tile.x0, tile.y0, pin, nsweeps, omega, RES, s.ph, s.mu);
+    const double r2 =
+        mag_block<T, MTX, MTY, NT, G::H, MUIN>(I, tile.x0, tile.y0, pin, nsweeps, omega, RES, s.ph, s.mu);
     // write the tile in natural order (coalesced)
     GLOBAL T* phout = gp<T>(I.phi[pin ^ 1]);
     const int par0 = (tile.x0 - G::H + tile.y0 - G::H) & 1;
@@ -1234,8 +1259,7 @@ __global__ __launch_bounds__(NT) void k_mag_lbfs(const DevInst* __restrict__ ins
             if (vin[it]) {
                 T Tt, Fl;
                 enthalpy_state<T>(K, vHe[it], vC[it], Tt, Fl);
-                const T ct = clamp01(vC[it]);
-                mu = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+                mu = mag_permeability<T>(K, clamp01(vC[it]), Fl);
             } else {
                 cq[it] = T(0);
             }
@@ -1390,19 +1414,28 @@ hipError_t launch_mag_lbfs(int shape, int nsteps, int residual, int* pidx, const
     return hipSuccess;
 }
 
-// one launch of the fused magnetic kernel on tiles of MAG_SHAPES[shape]
+// one launch of the fused magnetic kernel on tiles of MAG_SHAPES[shape]; res: with the
+// residual (and its halo ring), muin: the permeability read from the Kelvin-force field
 template <typename T, int K>
 hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, int ntiles, hipStream_t stream,
-                          hipEvent_t e0, hipEvent_t e1, int nsweeps, double omega, int res, int pin, int gate)
+                          hipEvent_t e0, hipEvent_t e1, int nsweeps, double omega, int res, int muin, int pin,
+                          int gate)
 {
     if constexpr (K < NMAG_SHAPES) {
         constexpr TileShape M = MAG_SHAPES[K];
-        if (shape == K)
-            return res ? launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 1>, dim3(ntiles), dim3(M.nt), stream, e0, e1,
-                                      insts, tiles, nsweeps, omega, pin, gate)
-                       : launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 0>, dim3(ntiles), dim3(M.nt), stream, e0, e1,
-                                      insts, tiles, nsweeps, omega, pin, gate);
-        return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, pin,
+        if (shape == K) {
+            const dim3 g(ntiles), b(M.nt);
+            if (res)
+                return muin ? launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 1, 1>, g, b, stream, e0, e1, insts, tiles,
+                                           nsweeps, omega, pin, gate)
+                            : launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 1, 0>, g, b, stream, e0, e1, insts, tiles,
+                                           nsweeps, omega, pin, gate);
+            return muin ? launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 0, 1>, g, b, stream, e0, e1, insts, tiles,
+                                       nsweeps, omega, pin, gate)
+                        : launch_timed(k_mag_fused<T, M.tx, M.ty, M.nt, 0, 0>, g, b, stream, e0, e1, insts, tiles,
+                                       nsweeps, omega, pin, gate);
+        }
+        return launch_mag_idx<T, K + 1>(shape, insts, tiles, ntiles, stream, e0, e1, nsweeps, omega, res, muin, pin,
                                         gate);
     } else {
         return hipErrorInvalidValue;
@@ -1410,7 +1443,7 @@ hipError_t launch_mag_idx(int shape, const DevInst* insts, const Tile* tiles, in
 }
 
 template <typename T>
-hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* pidx, const DevInst* insts,
+hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int muin, int* pidx, const DevInst* insts,
                       const Tile* tiles, int ntiles, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, int gate)
 {
     if (ntiles <= 0) return hipSuccess;
@@ -1425,7 +1458,7 @@ hipError_t launch_mag(int shape, int nsweeps, double omega, int residual, int* p
         const int res = residual && nsweeps == 0;
         const hipEvent_t a = first ? e0 : nullptr, b = nsweeps == 0 ? e1 : nullptr;
         const hipError_t e =
-            launch_mag_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, omega, res, *pidx, gate);
+            launch_mag_idx<T, 0>(shape, insts, tiles, ntiles, stream, a, b, k, omega, res, muin, *pidx, gate);
         if (e != hipSuccess) return e;
         *pidx ^= 1;
         first = false;
@@ -1582,8 +1615,7 @@ __global__ __launch_bounds__(256) void k_mg_mu0(const DevInst* __restrict__ inst
     const T C = T(gp<double>(I.W[4])[o]);
     T Tt, Fl;
     enthalpy_state<T>(K, gp<T>(I.W[0])[o], C, Tt, Fl);
-    const T ct = clamp01(C);
-    mu[c] = K.mu0 * (T(1) + mix3<T>(K.chi, ct * (T(1) - Fl), ct));
+    mu[c] = mag_permeability<T>(K, clamp01(C), Fl);
 }
 
 // level-0 face weights from the permeability: the mean of two cells, 2 mu_c towards a
@@ -1895,7 +1927,7 @@ hipError_t launch_mg_coarsest(int nx, int ny, int pitch, T* u, const T* f, const
                                         hipEvent_t);                                                   \
     template hipError_t launch_stage_fused<T>(int, int, int, double, const DevInst*, const Tile*, int, hipStream_t, \
                                               hipEvent_t, hipEvent_t);                                 \
-    template hipError_t launch_mag<T>(int, int, double, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
+    template hipError_t launch_mag<T>(int, int, double, int, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
                                       hipEvent_t, hipEvent_t, int);                                    \
     template hipError_t launch_mag_lbfs<T>(int, int, int, int*, const DevInst*, const Tile*, int, hipStream_t, \
                                            hipEvent_t, hipEvent_t, int);                               \
