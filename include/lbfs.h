@@ -283,7 +283,10 @@ int lbfs_mag_multigrid(lbfs_solver* s, int32_t ncycles, double* residual);
    Also valid on a borrowed batch handle. Synchronous. */
 int lbfs_wall_heat_profile(lbfs_solver* s, double* host_q, size_t n);
 
-/* Copy a field to / from a host FP64 array of n = nx*ny values. Synchronous. */
+/* Copy a field to / from a host FP64 array of n = nx*ny values. Synchronous. After a
+   write (as after lbfs_load_state) the next magnetic phase derives the permeability
+   from the written state itself; otherwise it reads the one the last step's stage 3
+   left. */
 int lbfs_read_field(lbfs_solver* s, int32_t field, double* host, size_t n);
 int lbfs_write_field(lbfs_solver* s, int32_t field, const double* host, size_t n);
 

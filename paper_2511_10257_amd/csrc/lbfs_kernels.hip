@@ -3,14 +3,16 @@
 // Kernels (all driven by tile lists, see lbfs_internal.hpp):
 //   k_stage<T,TX,TY,NT,ST>  fused Runge-Kutta stage: LDS-staged halo of the cell
 //                           fields, Eq. 8 / Eq. 11 derived fields, chemical potential,
-//                           central gradients, Kelvin force, LBFS fluxes of every face
-//                           of the tile, sources (Eq. 41), residual (Eq. 42) and the
-//                           SSP-RK3 combination (Eq. 46); the last stage also applies
-//                           Eq. 8 for the lagged dFs/dt.
+//                           central gradients, Kelvin force (stage 1; stages 2 and 3
+//                           read it), LBFS fluxes of every face of the tile, sources
+//                           (Eq. 41), residual (Eq. 42) and the SSP-RK3 combination
+//                           (Eq. 46); the last stage also applies Eq. 8 for the lagged
+//                           dFs/dt and leaves the new state's permeability for the
+//                           next step's sweeps.
 //   k_state_partials        FP64 per-tile partial sums of the observables of a state.
-//   k_mag_fused             permeability (Eq. 2 with Eq. 11), red-black sweeps of the
-//                           compact magnetic system (temporally blocked in LDS) and
-//                           the FP64 residual.
+//   k_mag_fused             permeability (Eq. 2 with Eq. 11, or read where stage 3
+//                           left it), red-black sweeps of the compact magnetic system
+//                           (temporally blocked in LDS) and the FP64 residual.
 //   k_mag_lbfs              the same phase by the magnetic LBFS pseudo-time solve
 //                           (Eq. 17, SSP-RK3 steps temporally blocked in LDS).
 //   k_reduce                fixed-order FP64 reduction of the partials per instance.
