@@ -179,12 +179,22 @@ def sample_every_for(steps: int) -> int:
     return max(1, min(97, -(-steps // 3)))
 
 
+def _code_only(src: str) -> str:
+    """C++ source without its comments and with runs of white space made one space (the
+    sources hold no string literal with comment markers)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_sources_digest() -> str:
+    """Hash of the code the kernels are built from: the kernel sources without their
+    comments, and the build script (its compiler flags shape the kernels too)."""
     h = hashlib.sha256()
-    # the kernel sources and the build script (its compiler flags shape the kernels too)
     for name in ("csrc/lbfs_kernels.hip", "csrc/lbfs_face.hpp", "csrc/lbfs_internal.hpp", "build.py"):
-        with open(os.path.join(ROOT, "paper_2511_10257_amd", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2511_10257_amd", name), encoding="utf-8") as f:
+            text = f.read()
+        h.update((text if name.endswith(".py") else _code_only(text)).encode())
     return h.hexdigest()[:16]
 
 
