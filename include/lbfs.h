@@ -443,7 +443,9 @@ int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
 
 /* lbfs_set_tile_shapes and lbfs_autotune for a batch: one shape pair for all live
    instances (and those admitted later), timed on whole steps of every live instance
-   (the sweeps inside stage 1 are not a batch candidate). */
+   (the sweeps inside stage 1 are not a batch candidate). Until shapes are given by one
+   of them, a batch takes the first stage shape and, after every admission and
+   retirement, the magnetic shape a single solve of its total cells would take. */
 int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape, int32_t mag_shape);
 int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms);
 int lbfs_batch_tile_shapes_in_use(const lbfs_batch* b, int32_t* stage_shape, int32_t* mag_shape);

@@ -149,6 +149,14 @@ int validate(const lbfs_params* p)
     return LBFS_OK;
 }
 
+// the magnetic tile shape a step over `cells` cells takes unless shapes are given
+// (measured per step: 32 x 8 fastest on 128^2 and 256^2, 64 x 16 on 512^2 by 9%, 64 x 32
+// on 1024^2: a larger tile recomputes fewer halo cells once the tiles fill the GPU)
+int default_mag_shape(size_t cells)
+{
+    return cells > (size_t)512 * 512 ? 1 : (cells > ((size_t)1 << 17) ? 2 : 0);
+}
+
 Layout make_layout(const lbfs_params* p)
 {
     Layout L;
@@ -1114,10 +1122,8 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
         hipMemsetAsync(s->base + L.off_fields, 0, L.total - ALIGN - L.off_fields, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
-    // default shapes: the first stage shape; the magnetic shape by grid size (measured
-    // per step: 32 x 8 fastest on 128^2 and 256^2, 64 x 16 on 512^2 by 9%, 64 x 32 on 1024^2)
-    const size_t ncell = (size_t)p->nx * p->ny;
-    if (apply_shapes(s, 0, ncell > (size_t)512 * 512 ? 1 : (ncell > ((size_t)1 << 17) ? 2 : 0)) != LBFS_OK)
+    // default shapes: the first stage shape; the magnetic shape by grid size
+    if (apply_shapes(s, 0, default_mag_shape((size_t)p->nx * p->ny)) != LBFS_OK)
         return fail(LBFS_E_DEVICE);
 
     hipError_t e = s->f64()
@@ -1506,7 +1512,7 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     const size_t es = f64 ? 8 : 4, n = (size_t)q.nx * q.ny;
     // the tile shapes a solver of this size starts with
     const TileShape SS = stage_shape(f64, 0);
-    const int mshape = n > (size_t)512 * 512 ? 1 : (n > ((size_t)1 << 17) ? 2 : 0);
+    const int mshape = default_mag_shape(n);
     const TileShape MS = MAG_SHAPES[mshape];
     const int nts = count_tiles(q.nx, q.ny, SS), ntm = count_tiles(q.nx, q.ny, MS);
     // layout of the scratch for this problem
@@ -1853,6 +1859,7 @@ struct Slot {
 struct lbfs_batch {
     int32_t max_slots = 0, precision = 0, sweeps = 0;
     int stage_shape = 0, mag_shape = 0;   // tile shapes of every instance
+    bool shapes_given = false;            // set by lbfs_batch_set_tile_shapes or the autotuner
     double omega = 1.0;
     char* base = nullptr;
     size_t bytes = 0;
@@ -2040,6 +2047,31 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
     return LBFS_OK;
 }
 
+// a batch whose shapes were not given takes the magnetic shape of a step over its
+// total cells (with many instances the tiles fill the GPU as one large grid's do),
+// stepping down to smaller tiles while the shape's tiles would cover more than 15%
+// beyond the instances' cells (edges that are no multiple of the tile)
+static int batch_follow_size(lbfs_batch* b)
+{
+    if (b->shapes_given) return LBFS_OK;
+    size_t cells = 0;
+    for (const Slot& q : b->slots)
+        if (q.s) cells += (size_t)q.s->p.nx * q.s->p.ny;
+    auto covered = [&](int k) {
+        const TileShape S = MAG_SHAPES[k];
+        size_t a = 0;
+        for (const Slot& q : b->slots)
+            if (q.s) a += (size_t)count_tiles(q.s->p.nx, q.s->p.ny, S) * S.tx * S.ty;
+        return a;
+    };
+    int m = default_mag_shape(cells);   // 1 (64 x 32), 2 (64 x 16) or 0 (32 x 8)
+    while (m != 0 && (double)covered(m) > 1.15 * (double)cells) m = m == 1 ? 2 : 0;
+    if (m == b->mag_shape) return LBFS_OK;
+    const int rc = lbfs_batch_set_tile_shapes(b, b->stage_shape, m);
+    b->shapes_given = false;
+    return rc;
+}
+
 int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
 {
     if (!b) return LBFS_E_STATE;
@@ -2100,7 +2132,7 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     b->dirty = true;
     b->stepped_since_observe = true;
     *slot_out = slot;
-    return LBFS_OK;
+    return batch_follow_size(b);
 }
 
 int lbfs_batch_retire(lbfs_batch* b, int32_t slot)
@@ -2115,7 +2147,7 @@ int lbfs_batch_retire(lbfs_batch* b, int32_t slot)
     q = Slot{};
     b->dirty = true;
     b->stepped_since_observe = true;
-    return LBFS_OK;
+    return batch_follow_size(b);
 }
 
 int lbfs_batch_step(lbfs_batch* b, int32_t nsteps)
@@ -2239,6 +2271,7 @@ int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape_idx, int32_t m
     if (!b) return LBFS_E_STATE;
     if (stage_shape_idx < 0 || stage_shape_idx >= NSTAGE_SHAPES || mag_shape_idx < 0 || mag_shape_idx >= NMAG_SHAPES)
         return LBFS_E_INVAL;
+    b->shapes_given = true;
     HIPCHK(hipStreamSynchronize(b->stream));
     const bool mag_changed = mag_shape_idx != b->mag_shape;
     b->stage_shape = stage_shape_idx;
