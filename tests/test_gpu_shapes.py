@@ -173,6 +173,55 @@ def test_default_magnetic_shape_by_grid_size(edge, mag_shape):
     assert s.tile_shapes_in_use() == (0, mag_shape)
 
 
+def test_batch_magnetic_shape_follows_its_size_until_shapes_are_given():
+    """A batch without given shapes takes, after every admission and retirement, the
+    magnetic shape a single solve of its total cells would take, except where those tiles
+    would cover more than 15% beyond the instances' cells; given shapes stay. The tile
+    shapes change no field (checked bit for bit against a solve alone)."""
+    def prob(edge):
+        return wl.with_changes(wl.droplet_problem(edge, edge / 4.0, ste=0.1, bo_m=0.5, angle_deg=90.0,
+                                                  precision="fp32"), init_max=0)
+
+    def budget(probs):
+        return sum(lbfs.Batch.instance_bytes(p) for p in probs) + (1 << 20)
+
+    # 3 x 256^2 = 196608 cells: 64 x 16 (above 2^17); a fourth: 262144, still 64 x 16;
+    # a 320^2 one more: 364544, 64 x 32 (above 512^2)
+    big = [prob(256) for _ in range(4)] + [prob(320)]
+    b = lbfs.Batch(8, budget(big))
+    slots = [b.admit(p) for p in big[:2]]
+    assert b.tile_shapes_in_use() == (0, 0)
+    slots.append(b.admit(big[2]))
+    assert b.tile_shapes_in_use() == (0, 2)
+    slots.append(b.admit(big[3]))
+    slots.append(b.admit(big[4]))
+    assert b.tile_shapes_in_use() == (0, 1)
+    b.step(6)
+    b.retire(slots.pop())
+    b.retire(slots.pop())
+    assert b.tile_shapes_in_use() == (0, 2)
+    alone = lbfs.Solver(big[0])
+    alone.step(6)
+    for name in ("He", "p", "Mx", "My", "C", "phi", "S"):
+        assert np.array_equal(b.slot(slots[0]).get(name), alone.get(name)), name
+    alone.close()
+    b.close()
+    # 15 x 96^2 = 138240 cells, above 2^17, but 64 x 16 tiles cover 96 x 96 as 128 x 96
+    small = [prob(96) for _ in range(15)]
+    b = lbfs.Batch(16, budget(small))
+    for p in small:
+        b.admit(p)
+    assert b.tile_shapes_in_use() == (0, 0)
+    b.close()
+    # given shapes stay through later admissions
+    b = lbfs.Batch(8, budget(big))
+    b.set_tile_shapes(0, 0)
+    for p in big:
+        b.admit(p)
+    assert b.tile_shapes_in_use() == (0, 0)
+    b.close()
+
+
 def test_observables_follow_written_and_loaded_states():
     """Writing fields or loading a checkpoint changes what the next observe reports, for a
     single solve and for a batch member written through its borrowed handle."""
