@@ -2050,16 +2050,17 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
 // a batch whose shapes were not given takes the magnetic shape of a step over its
 // total cells (with many instances the tiles fill the GPU as one large grid's do),
 // stepping down to smaller tiles while the shape's tiles would cover more than 15%
-// beyond the instances' cells (edges that are no multiple of the tile)
-static int batch_follow_size(lbfs_batch* b)
+// beyond the instances' cells (edges that are no multiple of the tile); an instance of
+// nx x ny about to be admitted counts too
+static int batch_follow_size(lbfs_batch* b, int nx = 0, int ny = 0)
 {
     if (b->shapes_given) return LBFS_OK;
-    size_t cells = 0;
+    size_t cells = (size_t)nx * ny;
     for (const Slot& q : b->slots)
         if (q.s) cells += (size_t)q.s->p.nx * q.s->p.ny;
     auto covered = [&](int k) {
         const TileShape S = MAG_SHAPES[k];
-        size_t a = 0;
+        size_t a = nx > 0 ? (size_t)count_tiles(nx, ny, S) * S.tx * S.ty : 0;
         for (const Slot& q : b->slots)
             if (q.s) a += (size_t)count_tiles(q.s->p.nx, q.s->p.ny, S) * S.tx * S.ty;
         return a;
@@ -2094,6 +2095,9 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
             nm += q.s->L.cap_mag;
         }
     int rc = batch_reserve(b, ns, nm);
+    if (rc != LBFS_OK) return rc;
+    // the shapes with the new instance counted, before it takes them
+    rc = batch_follow_size(b, p->nx, p->ny);
     if (rc != LBFS_OK) return rc;
     const size_t need = align_up(L.total, ALIGN);
     size_t off = 0;
@@ -2132,7 +2136,7 @@ int lbfs_batch_admit(lbfs_batch* b, const lbfs_params* p, int32_t* slot_out)
     b->dirty = true;
     b->stepped_since_observe = true;
     *slot_out = slot;
-    return batch_follow_size(b);
+    return LBFS_OK;
 }
 
 int lbfs_batch_retire(lbfs_batch* b, int32_t slot)
