@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 VALU_PEAK_NONPACKED_TFLOPS = 78.6
 
-# Algorithmic work and traffic per cell and launch, the per-cell figures of the survey's
-# operation count of the definitional algorithm: about 780 FLOP per face for the nine
+# Algorithmic work and traffic per cell and launch, from an operation count of the
+# definitional algorithm: about 780 FLOP per face for the nine
 # surrounding equilibria, the Eq. 45 face state, the star distributions and the moments,
 # two faces per cell, plus about 250 of cell work, i.e. about 1.8k per cell and stage
 # (5.5k per cell-step); the magnetic phase about 1 % of a step. Bytes: one 4-byte FP32
@@ -292,7 +292,7 @@ def all_cores_rate(probs: list, budget_s: float, cores: int) -> dict:
 
 def all_cores_baseline(wl, budget_s: float, serve_edges=(96, 128)) -> dict:
     """The oracle on every host core (one single-thread solve per core) for the instance
-    mixes of the batch (configs[3]) and of the bounded serving run (its edges). Runs
+    mixes of the 64-instance batch (edges 64-256) and of the bounded serving run (its edges). Runs
     before the GPU is touched. Solves/s of the serving mix follows from this rate and the
     cell updates a served request needed on the GPU (filled in after the serving run)."""
     cores = cpu_cores()
@@ -339,7 +339,7 @@ def error_vs_oracle(source, solvers: dict, prob: dict) -> dict:
     state (the source solver's current state, read back; each solver receives it in its
     own storage precision). Per field: the relative L2 error against the field's own
     norm (for the potential, its perturbation phi - phi0), and the same with the floors
-    of the survey's reading A34 (He ~ L, C ~ 1, phi ~ H0 R, p ~ sigma/R, momentum ~
+    of the state's scales (He ~ L, C ~ 1, phi ~ H0 R, p ~ sigma/R, momentum ~
     rho_l cs^2 sigma / mu_l). The bound applies to the unfloored value."""
     import numpy as np
     from oracle import oracle as orc
@@ -374,7 +374,7 @@ def error_vs_oracle(source, solvers: dict, prob: dict) -> dict:
             if k in floor:
                 floored[k] = d / max(nb, floor[k] * math.sqrt(b.size))
         checked = [rel[k] for k in floor]
-        out[prec] = {"per_step_rel_l2": rel, "max": max(checked), "per_step_rel_l2_floored_a34": floored,
+        out[prec] = {"per_step_rel_l2": rel, "max": max(checked), "per_step_rel_l2_floored": floored,
                      "bound": 1e-5 if prec == "fp32" else 1e-10,
                      "note": "bound on the unfloored error of He, p, Mx, My, C and phi - phi0; "
                              "S (a difference of liquid fractions) is reported only"}
@@ -465,7 +465,7 @@ def freezing_fp32_vs_fp64(lbfs, wl, prob: dict) -> dict:
 def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict, mag_flops=None,
              mag_launches: int = 1, exclude=()) -> dict:
     """Roofline of the kernel kind with the largest mean duration among the sampled
-    steps. `achieved` is the survey's per-cell figure (ALG_FLOPS, or ALG_BYTES_FP32 times
+    steps. `achieved` is the algorithmic per-cell figure (ALG_FLOPS, or ALG_BYTES_FP32 times
     2 in FP64) times the cells of one launch over the mean launch duration; the bound is
     the kernel's (ALU for the stages, HBM for the magnetic phase), the other ceiling is
     given beside it. A magnetic phase of other than 4 sweeps (mag_launches launches per
@@ -500,7 +500,7 @@ def roofline(kern: dict, cells: int, precision: str, workload: str, shapes: dict
     roof.update({"kernel": dominant, "tile_shape": kernel_shape(dominant, shapes),
                  "mean_launch_us": kern[dominant][0] * 1e3,
                  "timed_launches": kern[dominant][1],
-                 "figures": "survey per-cell figures: 1.8k FLOP per cell and stage; 48/68/72 B per cell for "
+                 "figures": "algorithmic per-cell figures: 1.8k FLOP per cell and stage; 48/68/72 B per cell for "
                             "stages 1/2/3 and 52 B for 4 sweeps (FP32; x2 in FP64)",
                  "other_ceiling": hbm if BOUND[dominant] == "alu" else alu})
     return roof
@@ -522,20 +522,20 @@ def measured_valu(workload: str) -> float | None:
 
 
 def whole_step(cells: int, precision: str, ms_per_step: float, workload: str) -> dict:
-    """The whole step against the HBM peak: the survey's bytes per cell-step (63 field
+    """The whole step against the HBM peak: the algorithmic bytes per cell-step (63 field
     accesses of 4 B with perfect on-chip reuse; 8 B in FP64) and the least bytes of this
     layout (each kernel's fields once, the order parameter in FP64), over the measured
     time per step; and the issued VALU lane-operations per cell and stage when a counter
     summary of the current kernels exists."""
     scale = 2.0 if precision == "fp64" else 1.0
-    survey = sum(ALG_BYTES_FP32.values()) * scale
+    alg = sum(ALG_BYTES_FP32.values()) * scale
     least = sum(min_bytes(precision, k, workload) for k in MIN_BYTES[precision])
     step_s = ms_per_step * 1e-3
-    return {"survey_bytes_per_cell_step": survey, "least_bytes_per_cell_step": least,
-            "hbm_frac_survey_bytes": survey * cells / step_s / 1e9 / HBM_PEAK_GBS,
+    return {"algorithmic_bytes_per_cell_step": alg, "least_bytes_per_cell_step": least,
+            "hbm_frac_algorithmic_bytes": alg * cells / step_s / 1e9 / HBM_PEAK_GBS,
             "hbm_frac_least_bytes": least * cells / step_s / 1e9 / HBM_PEAK_GBS,
             "issued_valu_lane_ops_per_cell_stage": measured_valu(workload) if precision == "fp32" else None,
-            "survey_flop_per_cell_stage": ALG_FLOPS["stage1"]}
+            "algorithmic_flop_per_cell_stage": ALG_FLOPS["stage1"]}
 
 
 def kernel_fields(kern: dict) -> dict:
@@ -726,7 +726,7 @@ def run_single(args, torch, lbfs, wl, cpu_all=None) -> dict:
         out["serving"] = serving_leg(args, lbfs, wl, cpu_all)
     if not args.no_cpu_baseline and not args.no_freeze_check and args.mag_method == "sweeps" and \
             args.workload in ("droplet256", "droplet1024"):
-        # the freezing time of the 256^2 droplet (configs[1]) in FP32 and FP64 (about 10 s)
+        # the freezing time of the 256^2 droplet (R = 64, seeded field) in FP32 and FP64 (about 10 s)
         p256 = wl.droplet256()
         fz = freezing_fp32_vs_fp64(lbfs, wl, p256)
         fz["workload"] = p256["name"]

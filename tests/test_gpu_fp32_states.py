@@ -4,8 +4,8 @@
 Both sides take one step from the same state: the FP64 oracle from the state, the FP32
 path from the state rounded to its storage (He, p, momentum, potential and S in FP32,
 the order parameter in FP64). The bar is the relative L2 norm of the error of each
-field against that field's own norm, with no floor; the floored form of the survey's
-reading A34 is printed beside it. FP64 runs the same steps to rounding.
+field against that field's own norm, with no floor; the form floored by the state's
+scales is printed beside it. FP64 runs the same steps to rounding.
 
 The 64 x 64 states are those of the oracle's trajectory at a quarter, half and three
 quarters of its freezing time (tests/golden/freeze_time.json, written by the oracle):
@@ -35,7 +35,7 @@ def phi0(prob, nx, ny):
     return -p.h0 * (x * np.cos(th) + y * np.sin(th))
 
 
-def a34_floor(prob):
+def scale_floor(prob):
     p = orc.make_params(prob)
     R = prob["drop"][2]
     m = p.rho[1] / 3.0 * p.sigma / p.mu[1]
@@ -43,7 +43,7 @@ def a34_floor(prob):
 
 
 def one_step_errors(prob64, state):
-    """Relative L2 errors (unfloored, and floored per A34) of one FP32 and one FP64 GPU
+    """Relative L2 errors (unfloored, and floored by the state's scales) of one FP32 and one FP64 GPU
     step against one oracle step, all from `state`."""
     nx, ny = prob64["nx"], prob64["ny"]
     clock = state.get("_clock")
@@ -63,7 +63,7 @@ def one_step_errors(prob64, state):
         if clock:
             g.set_time(*clock)
         g.step(1)
-        fl = a34_floor(prob64)
+        fl = scale_floor(prob64)
         errs = {}
         for k in STATE:
             a = g.get(k) - (p0 if k == "phi" else 0.0)
