@@ -303,8 +303,9 @@ int lbfs_load_state(lbfs_solver* s, const void* host, size_t bytes);
  * kernel each have a small table of candidate tile shapes (cells per tile and threads
  * per workgroup); the results do not depend on the shape (each cell and face is
  * computed by the same arithmetic), only the time does. The first shape of each table
- * is the default, except for the magnetic kernel of a single solve: its third shape
- * (64 x 16) above 2^17 cells and its second (64 x 32) above 512 x 512 cells. */
+ * is the default, except above 2^17 cells for the magnetic kernel (its third shape,
+ * 64 x 16, and above 512 x 512 cells its second, 64 x 32) and above 512 x 512 cells for
+ * the FP64 stage kernels (their fifth shape, 12 x 7). */
 
 #define LBFS_MAX_SHAPES 8
 
@@ -332,8 +333,9 @@ int lbfs_tile_shapes_in_use(const lbfs_solver* s, int32_t* stage_shape, int32_t*
 /* Autotuner: time whole time steps (one untimed, then reps timed, kernels launched
    directly) from this solver's current state with every stage shape (at the current
    magnetic shape), then with every magnetic shape (at the fastest stage shape), and
-   keep the fastest of each: the default, shape 0, unless another is faster by more
-   than 2 %, the spread of such timings. Every candidate is timed twice, in a forward
+   keep the fastest of each: the default (the stage shape a solver of this size and
+   precision starts with, magnetic shape 0) unless another is faster by more than 2 %,
+   the spread of such timings. Every candidate is timed twice, in a forward
    and a backward pass over the list, and keeps the shorter time, so that a clock that
    still rises or falls favours no position in the list. Where the sweeps can run inside stage 1, that
    variant is timed too and chosen when its step beats the best step by 2 %. Before
@@ -444,8 +446,8 @@ int lbfs_batch_slot(lbfs_batch* b, int32_t slot, lbfs_solver** out);
 /* lbfs_set_tile_shapes and lbfs_autotune for a batch: one shape pair for all live
    instances (and those admitted later), timed on whole steps of every live instance
    (the sweeps inside stage 1 are not a batch candidate). Until shapes are given by one
-   of them, a batch takes the first stage shape and, after every admission and
-   retirement, the magnetic shape a single solve of its total cells would take. */
+   of them, a batch takes, after every admission and retirement, the stage and magnetic
+   shapes a single solve of its total cells and precision would take. */
 int lbfs_batch_set_tile_shapes(lbfs_batch* b, int32_t stage_shape, int32_t mag_shape);
 int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms);
 int lbfs_batch_tile_shapes_in_use(const lbfs_batch* b, int32_t* stage_shape, int32_t* mag_shape);

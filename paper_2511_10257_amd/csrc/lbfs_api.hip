@@ -157,6 +157,19 @@ int default_mag_shape(size_t cells)
     return cells > (size_t)512 * 512 ? 1 : (cells > ((size_t)1 << 17) ? 2 : 0);
 }
 
+// the stage tile shape a step over `cells` cells takes unless shapes are given: the
+// table's first, except in FP64 above 512^2, where 12 x 7 tiles (84 cells, still four
+// workgroups per CU) do fewer halo cells and idle face lanes per cell (measured per
+// step: 257.8 against 264.5 us for 10 x 8 on 1024^2, 1047.9 against 1078.2 on 2048^2;
+// 10 x 8 stays ahead on 256^2 and below)
+constexpr int F64_LARGE_STAGE_SHAPE = 4;
+static_assert(STAGE_SHAPES_F64[F64_LARGE_STAGE_SHAPE].tx == 12 && STAGE_SHAPES_F64[F64_LARGE_STAGE_SHAPE].ty == 7,
+              "the FP64 large-grid stage shape is 12 x 7");
+int default_stage_shape(bool f64, size_t cells)
+{
+    return f64 && cells > (size_t)512 * 512 ? F64_LARGE_STAGE_SHAPE : 0;
+}
+
 Layout make_layout(const lbfs_params* p)
 {
     Layout L;
@@ -1122,8 +1135,9 @@ static int init_solver(const lbfs_params* p, void* dev_buf, size_t bytes, void* 
         hipMemsetAsync(s->base + L.off_fields, 0, L.total - ALIGN - L.off_fields, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(LBFS_E_DEVICE);
-    // default shapes: the first stage shape; the magnetic shape by grid size
-    if (apply_shapes(s, 0, default_mag_shape((size_t)p->nx * p->ny)) != LBFS_OK)
+    // default shapes by precision and grid size
+    if (apply_shapes(s, default_stage_shape(s->f64(), (size_t)p->nx * p->ny),
+                     default_mag_shape((size_t)p->nx * p->ny)) != LBFS_OK)
         return fail(LBFS_E_DEVICE);
 
     hipError_t e = s->f64()
@@ -1511,8 +1525,8 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
     const bool f64 = q.precision == LBFS_FP64;
     const size_t es = f64 ? 8 : 4, n = (size_t)q.nx * q.ny;
     // the tile shapes a solver of this size starts with
-    const TileShape SS = stage_shape(f64, 0);
-    const int mshape = default_mag_shape(n);
+    const int sshape = default_stage_shape(f64, n), mshape = default_mag_shape(n);
+    const TileShape SS = stage_shape(f64, sshape);
     const TileShape MS = MAG_SHAPES[mshape];
     const int nts = count_tiles(q.nx, q.ny, SS), ntm = count_tiles(q.nx, q.ny, MS);
     // layout of the scratch for this problem
@@ -1568,7 +1582,7 @@ int lbfs_step_fields(const lbfs_params* p, void* const fields[7], int32_t nsteps
 
     Exec E;
     E.f64 = f64;
-    E.stage_shape = 0;
+    E.stage_shape = sshape;
     E.mag_shape = mshape;
     E.sweeps = q.sweeps;
     E.omega = q.sor_omega;
@@ -1639,16 +1653,16 @@ int time_launches(hipStream_t stream, int reps, F&& f, double* ms)
     return rc;
 }
 
-// a candidate replaces the best so far (initially the default, index 0) only when it is
-// faster by more than the run-to-run spread of such timings (2 %)
+// a candidate replaces the best so far (initially the default) only when it is faster
+// by more than the run-to-run spread of such timings (2 %)
 bool clearly_faster(double t, double best) { return t < 0.98 * best; }
 
 // Time candidates 0..n-1 with time_one(k, &ms) in two passes, forward then backward, and
 // keep each candidate's shorter time: a drifting clock (the GPU's, rising after the host
 // copies that restore the state) then favours neither end of the list. Returns the
-// index of the fastest, the default 0 unless a candidate is clearly faster.
+// index of the fastest, the default `def` unless a candidate is clearly faster.
 template <typename F>
-int time_candidates(int n, double* t, int& rc, F&& time_one)
+int time_candidates(int n, int def, double* t, int& rc, F&& time_one)
 {
     for (int pass = 0; pass < 2; pass++)
         for (int j = 0; j < n && rc == LBFS_OK; j++) {
@@ -1657,9 +1671,9 @@ int time_candidates(int n, double* t, int& rc, F&& time_one)
             rc = time_one(k, &ms);
             if (rc == LBFS_OK) t[k] = pass ? std::min(t[k], ms) : ms;
         }
-    int best = 0;
-    for (int k = 1; k < n && rc == LBFS_OK; k++)
-        if (clearly_faster(t[k], t[best])) best = k;
+    int best = def;
+    for (int k = 0; k < n && rc == LBFS_OK; k++)
+        if (k != def && clearly_faster(t[k], t[best])) best = k;
     return best;
 }
 
@@ -1759,11 +1773,12 @@ int lbfs_autotune(lbfs_solver* s, int32_t reps, int32_t* chosen, double* ms)
     };
     // stage shapes with the current magnetic shape, then magnetic shapes with the best
     // stage shape
-    const int best_s = time_candidates(NSTAGE_SHAPES, t, rc, [&](int k, double* ms) {
+    const int best_s = time_candidates(NSTAGE_SHAPES, default_stage_shape(s->f64(), (size_t)s->p.nx * s->p.ny), t,
+                                       rc, [&](int k, double* ms) {
         int r = apply_shapes(s, k, mag0);
         return r == LBFS_OK ? time_steps(ms) : r;
     });
-    const int best_m = time_candidates(NMAG_SHAPES, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
+    const int best_m = time_candidates(NMAG_SHAPES, 0, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
         int r = apply_shapes(s, best_s, k);
         return r == LBFS_OK ? time_steps(ms) : r;
     });
@@ -2047,8 +2062,8 @@ int lbfs_batch_create(int32_t max_slots, int32_t precision, int32_t sweeps, doub
     return LBFS_OK;
 }
 
-// a batch whose shapes were not given takes the magnetic shape of a step over its
-// total cells (with many instances the tiles fill the GPU as one large grid's do),
+// a batch whose shapes were not given takes the stage and magnetic shapes of a step
+// over its total cells (with many instances the tiles fill the GPU as one large grid's do),
 // stepping down to smaller tiles while the shape's tiles would cover more than 15%
 // beyond the instances' cells (edges that are no multiple of the tile); an instance of
 // nx x ny about to be admitted counts too
@@ -2067,8 +2082,9 @@ static int batch_follow_size(lbfs_batch* b, int nx = 0, int ny = 0)
     };
     int m = default_mag_shape(cells);   // 1 (64 x 32), 2 (64 x 16) or 0 (32 x 8)
     while (m != 0 && (double)covered(m) > 1.15 * (double)cells) m = m == 1 ? 2 : 0;
-    if (m == b->mag_shape) return LBFS_OK;
-    const int rc = lbfs_batch_set_tile_shapes(b, b->stage_shape, m);
+    const int st = default_stage_shape(b->precision == LBFS_FP64, cells);
+    if (m == b->mag_shape && st == b->stage_shape) return LBFS_OK;
+    const int rc = lbfs_batch_set_tile_shapes(b, st, m);
     b->shapes_given = false;
     return rc;
 }
@@ -2304,6 +2320,9 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
     if (E.ninst > 0) {
         // whole steps of every instance from host snapshots, as in lbfs_autotune
         const int phase0 = E.phase;
+        size_t cells = 0;
+        for (const Slot& q : b->slots)
+            if (q.s) cells += (size_t)q.s->p.nx * q.s->p.ny;
         std::vector<std::vector<char>> snap(b->slots.size());
         for (size_t i = 0; i < b->slots.size() && rc == LBFS_OK; i++)
             if (lbfs_solver* q = b->slots[i].s) {
@@ -2326,13 +2345,14 @@ int lbfs_batch_autotune(lbfs_batch* b, int32_t reps, int32_t* chosen, double* ms
             if (r == LBFS_OK) r = time_launches(E.stream, reps, [&] { return exec_enqueue_step(E); }, out);
             return r;
         };
-        best_s = time_candidates(NSTAGE_SHAPES, t, rc, [&](int k, double* ms) {
+        best_s = time_candidates(NSTAGE_SHAPES, default_stage_shape(b->precision == LBFS_FP64, cells), t, rc,
+                                 [&](int k, double* ms) {
             b->stage_shape = k;
             b->dirty = true;
             return time_steps(ms);
         });
         b->stage_shape = best_s;
-        best_m = time_candidates(NMAG_SHAPES, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
+        best_m = time_candidates(NMAG_SHAPES, 0, t + LBFS_MAX_SHAPES, rc, [&](int k, double* ms) {
             b->mag_shape = k;
             b->dirty = true;
             return time_steps(ms);

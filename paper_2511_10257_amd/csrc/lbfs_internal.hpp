@@ -13,7 +13,8 @@ namespace lbfs {
 
 // Tile shapes (cells) and workgroup sizes. The kernels loop over their tile plus halo
 // and over its faces, so any shape works; these are the candidates the autotuner times
-// (index 0, the default, was among the fastest on 1024^2 grids and on batches).
+// (index 0, the default but for FP64 grids above 512^2, was among the fastest on 1024^2
+// grids and on batches).
 // Stage kernels stage the tile plus a 3-cell halo.
 struct TileShape {
     int tx, ty, nt;
@@ -26,11 +27,13 @@ struct TileShape {
 // The face phase gives each wave faces of one axis: the x-faces ((TX+1) TY) and the
 // y-faces (TX (TY+1)) are each rounded up to whole waves, so 10 x 10 (110 + 110 faces on
 // four waves, a 256-cell halo region in one round, 22 KB of LDS in FP32: seven
-// workgroups and seven waves per SIMD) keeps the lanes busy; 7599 against 6804 MLUPS for
-// 10 x 8 (4 face waves for 178 faces) on a 1024^2 grid. In FP64 the 10 x 10 tile needs
-// 44 KB of LDS (three workgroups per CU); 10 x 8 needs 38 KB, so four fit, and the stage
-// kernel is held to 128 VGPRs for four waves per SIMD: 3642 against 3553 MLUPS for
-// 10 x 10 and 3386 for 12 x 8 on a 1024^2 grid. Loading the owned cell's values early
+// workgroups and seven waves per SIMD) keeps the lanes busy: a whole step on a 1024^2
+// grid takes 126 us against 137 us with 10 x 8 (4 face waves for 178 faces). In FP64 the
+// 10 x 10 tile needs 44 KB of LDS (three workgroups per CU); 10 x 8 needs 38 KB and
+// 12 x 7 40 KB, so four fit, and the stage kernel is held to 128 VGPRs for four waves
+// per SIMD. 10 x 8 is the FP64 default up to 512^2 cells, 12 x 7 above (a whole step on
+// 1024^2: 258 us against 265 us for 10 x 8 and 274 us for 12 x 8; on 256^2 10 x 8 is
+// ahead by 1.5%). Loading the owned cell's values early
 // hides their latency but holds registers through the face phase; whether that costs a
 // wave per SIMD depends on the shape, so both are candidates.
 constexpr int NSTAGE_SHAPES = 7;

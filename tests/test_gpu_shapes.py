@@ -173,6 +173,28 @@ def test_default_magnetic_shape_by_grid_size(edge, mag_shape):
     assert s.tile_shapes_in_use() == (0, mag_shape)
 
 
+@pytest.mark.parametrize("edge, shapes", [(256, (0, 0)), (512, (0, 2)), (513, (4, 1))])
+def test_default_fp64_stage_shape_by_grid_size(edge, shapes):
+    """FP64 solves above 512^2 cells start with 12 x 7 stage tiles, smaller ones with the
+    table's first; a batch of FP64 instances follows its total cells the same way."""
+    prob = wl.with_changes(wl.droplet_problem(edge, edge / 4.0, ste=0.1, bo_m=0.5, angle_deg=90.0,
+                                              precision="fp64"), init_max=0)
+    s = lbfs.Solver(prob)
+    assert s.tile_shapes_in_use() == shapes
+    tx, ty, _, _ = lbfs.tile_shapes("stage", "fp64")[shapes[0]]
+    assert (tx, ty) == ((12, 7) if edge > 512 else (10, 8))
+    s.close()
+    if edge == 512:
+        two = wl.with_changes(wl.droplet_problem(384, 96.0, ste=0.1, bo_m=0.5, angle_deg=90.0,
+                                                 precision="fp64"), init_max=0)
+        b = lbfs.Batch(4, 2 * lbfs.Batch.instance_bytes(two) + (1 << 20), precision="fp64")
+        b.admit(two)
+        assert b.tile_shapes_in_use()[0] == 0
+        b.admit(two)   # 2 x 384^2 = 294912 cells, above 512^2
+        assert b.tile_shapes_in_use()[0] == 4
+        b.close()
+
+
 def test_batch_magnetic_shape_follows_its_size_until_shapes_are_given():
     """A batch without given shapes takes, after every admission and retirement, the
     magnetic shape a single solve of its total cells would take, except where those tiles
