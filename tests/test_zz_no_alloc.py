@@ -59,6 +59,25 @@ def test_step_fields_equals_solver_steps_twice_second_smaller(precision):
         s.close()
 
 
+def test_step_fields_fp64_above_512_squared():
+    """An FP64 grid above 512^2 cells, where the stage kernels take 12 x 7 tiles in both
+    entry points, then a small one after it."""
+    big = wl.with_changes(wl.droplet_problem(520, 130.0, ste=0.1, bo_m=1.5, angle_deg=0.0, precision="fp64"),
+                          init_max=0)
+    small = wl.droplet_problem(64, 14.0, ste=0.15, bo_m=0.7, angle_deg=80.0, precision="fp64", ny=48)
+    for prob, nsteps in ((big, 3), (small, 4)):
+        s = lbfs.Solver(prob)
+        s.step(2)
+        start = native_state(s, prob)
+        s.step(nsteps)
+        ref = native_state(s, prob)
+        rc, got = step_fields(prob, start, nsteps)
+        assert rc == lbfs.LBFS_OK, lbfs.strerror(rc)
+        for k, (a, b) in enumerate(zip(got, ref)):
+            assert np.array_equal(a, b), (prob["nx"], prob["ny"], k, float(np.max(np.abs(a - b))))
+        s.close()
+
+
 def test_step_fields_refuses_what_does_not_fit():
     prob = wl.droplet_problem(1536, 384.0, ste=0.1, bo_m=1.0, angle_deg=0.0, precision="fp32")
     n = prob["nx"] * prob["ny"]
