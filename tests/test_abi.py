@@ -147,3 +147,27 @@ def test_tile_shape_tables():
     assert L.lbfs_tile_shape(0, 0, 99, None, None, None, None) == lbfs.LBFS_E_INVAL
     assert L.lbfs_set_tile_shapes(None, 0, 0) == lbfs.LBFS_E_STATE
     assert L.lbfs_autotune(None, 5, None, None) == lbfs.LBFS_E_STATE
+
+
+@pytest.mark.parametrize("compiler, std", [("gcc", "-std=c11"), ("g++", "-std=c++17")])
+def test_header_is_plain_iso_c_and_cpp(tmp_path, compiler, std):
+    """include/lbfs.h compiles alone as ISO C11 and as C++17 with every warning an error."""
+    src = tmp_path / ("h.c" if compiler == "gcc" else "h.cpp")
+    src.write_text('#include "lbfs.h"\nint lbfs_header_check(void) { return LBFS_OK + (int)LBFS_ABI_VERSION; }\n')
+    import subprocess
+    r = subprocess.run([compiler, std, "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_c_consumer_builds_against_the_library(tmp_path):
+    """The plain-C test program (the ABI driven from C, no Python) compiles and links
+    against liblbfs.so and the HIP runtime alone."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    import __graft_entry__ as ge
+    out = str(tmp_path / "c_consumer")
+    r = subprocess.run(ge.c_consumer_command(out), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert os.path.getsize(out) > 0
