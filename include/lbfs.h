@@ -374,7 +374,10 @@ void lbfs_destroy(lbfs_solver* s);
  * function allocates nothing. Every call on a device uses that device's one scratch:
  * calls that overlap on one device (other streams, other threads) race; calls on one
  * stream are ordered. Every value a step reads from the scratch is written earlier in
- * the same call. No observables are reduced (read them through a solver).
+ * the same call. No observables are reduced (read them through a solver). The call
+ * enqueues kernels and at most one device-to-device copy (no memset), so it can be
+ * captured into a HIP graph and replayed; the first call on a device looks up the
+ * scratch's address, so make one call (nsteps = 0 will do) before a capture.
  * LBFS_E_INVAL on invalid parameters, a NULL field, nsteps < 0, multigrid or
  * convergence control (mag_max_iters > 0); LBFS_E_NOMEM if the problem does not fit
  * the scratch; LBFS_E_DEVICE if a HIP call fails. */

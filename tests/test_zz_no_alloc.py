@@ -84,3 +84,42 @@ def test_step_fields_refuses_what_does_not_fit():
     arrays = [np.zeros((prob["ny"], prob["nx"]), dtype=np.float64 if k == 4 else np.float32) for k in range(7)]
     rc, _ = step_fields(prob, arrays, 1)
     assert rc == lbfs.LBFS_E_NOMEM and n * 64 > (80 << 20)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_step_fields_replayed_from_a_captured_graph(precision):
+    """The entry point captured into a HIP graph (the use it is for: no allocation, no
+    memset node, only kernel and copy nodes) and replayed four times, with eager work and
+    synchronisation between the replays: every replay equals the same steps taken by a
+    solver, bit for bit."""
+    prob = wl.droplet_problem(72, 16.0, ste=0.1, bo_m=1.2, angle_deg=45.0, precision=precision, ny=56)
+    nsteps = 3   # odd: each replay ends with the copy of the potential back to the caller's field
+    s = lbfs.Solver(prob)
+    s.step(4)
+    dev = [torch.from_numpy(a).to("cuda:0") for a in native_state(s, prob)]
+    ptrs = (C.c_void_p * 7)(*[t.data_ptr() for t in dev])
+    params = lbfs.make_params(prob)
+    # set-up outside the capture (the first call on a device finds the static scratch)
+    rc = lbfs.lib().lbfs_step_fields(C.byref(params), ptrs, 0, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == lbfs.LBFS_OK, lbfs.strerror(rc)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    codes = []
+    with torch.cuda.graph(g, stream=side):
+        codes.append(lbfs.lib().lbfs_step_fields(C.byref(params), ptrs, nsteps,
+                                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    assert codes == [lbfs.LBFS_OK], codes
+    torch.cuda.synchronize()
+    for replay in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        s.step(nsteps)
+        ref = native_state(s, prob)
+        scratch = torch.ones(1 << 20, device="cuda:0").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        for k, (t, r) in enumerate(zip(dev, ref)):
+            a = t.cpu().numpy()
+            assert np.array_equal(a, r), (replay, k, float(np.max(np.abs(a - r))))
+        assert float(scratch) == float(1 << 20)
+    s.close()
